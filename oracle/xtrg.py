@@ -1,0 +1,321 @@
+"""XTRG beta-doubling with variational MPO-product compression (FP64 oracle).
+
+Test infrastructure: see the package docstring.  Follows, in order:
+
+* Sec. II.C, Eqs. (rhoinit) and (rho:scale2): rho_n = rho_{n-1} * rho_{n-1},
+  tau_n = 2^n tau0, starting from rho(tau0) at tiny tau0.
+* Sec. II.D, Eq. (RhoTau) and App. C.2: rho(tau0) as the truncated
+  Maclaurin series sum_k (-tau0)^k/k! H^k; order 1 is I - tau0 H, exact at
+  the bond dimension of H.
+* Sec. II.E: truncate by a fixed number of kept states, never by discarded
+  weight.
+* App. D.1, Eqs. (MPO:prod), (LSEProd), Fig. VMPO: minimise
+  ||A*B - C||_F^2 by two-site sweeps.  For C canonical about (i, i+1) the
+  local solution is C_i C_{i+1} = C_E, the generalized overlap of A*B with
+  the environments of C; the environments are grown in three substeps per
+  site (Fig. VMPO(c)); C_E is split by an SVD, U goes to C_i and Lambda V^T
+  to C_{i+1} in a left-to-right sweep, Lambda joins U in a right-to-left
+  sweep (Fig. VMPO(d)); a few full sweeps suffice.
+* Sec. II.C: Z(2 tau_n) = Tr(rho_n^T rho_n) = ||rho_n||_F^2.
+* Eq. (ThermalQuan): f, u, c_V.
+* Sec. V.A, Eq. (purif): entanglement of the vectorised MPO.
+
+Readings where the paper is silent (the same rules are used by the GPU
+library, implemented independently):
+* initial guess of C is rho_n itself (same bonds, right-canonical);
+* n_sweeps full sweeps, no tolerance exit; a bond at the end of a
+  half-sweep is not optimised twice (its C_E would be identical), it is
+  only re-gauged for the next direction;
+* keep k <= D states, backing off to the largest k >= D/2 with a relative
+  gap sigma_k - sigma_{k+1} > deg_rtol * sigma_k so that a (numerically)
+  degenerate multiplet is never split; singular values below
+  sv_floor * sigma_1 count as zero;
+* rho_n is stored normalised, rho_n = exp(lambda_n) * rhohat_n with
+  ||rhohat_n||_F = 1 and lambda_n in FP64.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, List, Sequence
+
+import numpy as np
+
+from . import mpo as M
+
+
+# --------------------------------------------------------------------------
+# Truncation rule (Sec. II.E: a fixed number of states; multiplet-safe cut)
+# --------------------------------------------------------------------------
+
+def keep_count(S: np.ndarray, D: int, deg_rtol: float, sv_floor: float) -> int:
+    """Number of singular values kept out of the descending list S."""
+    if S.size == 0 or not S[0] > 0:
+        return 1
+    r = int(np.count_nonzero(S > sv_floor * S[0]))
+    r = max(r, 1)
+    if r <= D:
+        return r
+    lo = max(1, (D + 1) // 2)
+    for k in range(D, lo - 1, -1):
+        if S[k - 1] - S[k] > deg_rtol * S[k - 1]:
+            return k
+    return D
+
+
+# --------------------------------------------------------------------------
+# Initial state (Eq. RhoTau; App. C.2)
+# --------------------------------------------------------------------------
+
+def series_rho(n, bonds, jxy, jz, tau0: float, order: int) -> List[np.ndarray]:
+    """Exact MPO of sum_{k<=order} (-tau0)^k/k! H^k.
+
+    The order-fold product of the open automaton has, at its right end,
+    the product space of 'start'/'stop' states of each factor; a factor that
+    ended in 'start' contributed I, one that ended in 'stop' contributed H.
+    Weighting every string with m 'stop' entries by omega_m / C(order, m)
+    yields sum_m omega_m H^m (App. B.1 boundary states, App. C.2 for m<=1).
+    """
+    if order < 1:
+        raise ValueError("order >= 1")
+    Wopen = M.xxz_automaton(n, bonds, jxy, jz)
+    P = Wopen
+    for _ in range(order - 1):
+        P = M.product(P, Wopen)
+    left = np.zeros(2 ** order)
+    left[0] = 1.0                                      # all factors in 'start'
+    right = np.zeros(2 ** order)
+    for idx in range(2 ** order):
+        m = bin(idx).count("1")                       # number of 'stop' factors
+        omega = (-tau0) ** m / math.factorial(m)
+        right[idx] = omega / math.comb(order, m)
+    return M.cap(P, left, right)
+
+
+def init_rho(n, bonds, jxy, jz, tau0: float, order: int, rel_floor: float = 1e-14):
+    """rho(tau0) normalised and right-canonical, with lambda_0 = ln||rho||_F.
+
+    The exact series MPO is compressed without loss (QR sweep, then an SVD
+    sweep dropping singular values <= rel_floor*sigma_1, i.e. exact zeros)."""
+    W = series_rho(n, bonds, jxy, jz, tau0, order)
+    W = M.svd_compress(W, D=10 ** 9, rel_floor=rel_floor)
+    nrm = float(np.linalg.norm(W[0]))                 # right-canonical: norm on site 0
+    W[0] = W[0] / nrm
+    return W, math.log(nrm)
+
+
+# --------------------------------------------------------------------------
+# Environments (Fig. VMPO(a), (c))
+# --------------------------------------------------------------------------
+
+def left_block(L: np.ndarray, A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """First two substeps of Fig. VMPO(c): Lb[c,s,a',s'',b'] =
+    sum_{a,b,s'} L[c,a,b] A[a,s,s',a'] B[b,s',s'',b']."""
+    T1 = np.einsum("cab,astp->cbstp", L, A, optimize=True)        # O(Da^2 Db Dc)
+    Lb = np.einsum("cbstp,btuq->cspuq", T1, B, optimize=True)     # O(Da Db^2 Dc)
+    return Lb
+
+
+def left_env(Lb: np.ndarray, C: np.ndarray) -> np.ndarray:
+    """Third substep: L'[c',a',b'] = sum_{c,s,s''} Lb[c,s,a',s'',b'] C[c,s,s'',c']."""
+    return np.einsum("cspuq,csur->rpq", Lb, C, optimize=True)      # O(Da Db Dc^2)
+
+
+def right_block(R: np.ndarray, A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """Mirror of left_block: Rb[a,b,t,t'',c''] =
+    sum_{a'',b'',t'} A[a,t,t',a''] B[b,t',t'',b''] R[c'',a'',b'']."""
+    U1 = np.einsum("atvp,cpq->atvqc", A, R, optimize=True)
+    Rb = np.einsum("atvqc,bvwq->abtwc", U1, B, optimize=True)
+    return Rb
+
+
+def right_env(Rb: np.ndarray, C: np.ndarray) -> np.ndarray:
+    """R[c,a,b] = sum_{t,t'',c''} Rb[a,b,t,t'',c''] C[c,t,t'',c'']."""
+    return np.einsum("abtwe,ctwe->cab", Rb, C, optimize=True)
+
+
+def two_site_overlap(Lb: np.ndarray, Rb: np.ndarray) -> np.ndarray:
+    """Generalized overlap C_E (Eq. LSEProd, Fig. VMPO(a)) as a matrix with
+    rows (c, s, s'') and columns (t, t'', c'')."""
+    th = np.einsum("cspuq,pqtwe->csutwe", Lb, Rb, optimize=True)
+    c, s, u, t, w, e = th.shape
+    return th.reshape(c * s * u, t * w * e)
+
+
+def sweep_schedule(n: int, n_sweeps: int):
+    """Bonds visited by n_sweeps full sweeps: a list of (bond, direction,
+    is_last_of_half_sweep).  The bond that ends a half-sweep is not visited
+    again at the start of the next one."""
+    out = []
+    for h in range(2 * n_sweeps):
+        if h % 2 == 0:
+            bonds = list(range(0 if h == 0 else 1, n - 1))
+            d = +1
+        else:
+            bonds = list(range(n - 3, -1, -1))
+            d = -1
+        for j, b in enumerate(bonds):
+            out.append((b, d, j == len(bonds) - 1))
+    return out
+
+
+@dataclasses.dataclass
+class CompressInfo:
+    dlog_norm: float
+    sv: List[np.ndarray]
+    kept: List[int]
+    discarded: List[float]
+    steps: int
+    flops: float
+
+    @property
+    def trunc_err_max(self) -> float:
+        return max(self.discarded) if self.discarded else 0.0
+
+
+def square_compress(rho: List[np.ndarray], D: int, n_sweeps: int = 4,
+                    deg_rtol: float = 1e-6, sv_floor: float = 1e-14):
+    """One doubling: C ~ rho*rho, compressed variationally to bond <= D.
+
+    ``rho`` must be right-canonical with ||rho||_F = 1.  Returns the new
+    normalised right-canonical MPO and a CompressInfo with ln c, where
+    c = ||C||_F before normalisation, so lambda_{n+1} = 2 lambda_n + ln c.
+    """
+    n = len(rho)
+    if n < 2:
+        raise ValueError("need at least two sites")
+    A = B = rho
+    C = [w.copy() for w in rho]                         # initial guess
+    one = np.ones((1, 1, 1))
+    L: List[np.ndarray] = [None] * (n + 1)
+    R: List[np.ndarray] = [None] * (n + 2)
+    L[0] = one
+    R[n] = one
+    for j in range(n - 1, 1, -1):                       # R_{n-1} .. R_2
+        R[j] = right_env(right_block(R[j + 1], A[j], B[j]), C[j])
+    sv = [np.zeros(0)] * (n - 1)
+    kept = [1] * (n - 1)
+    disc = [0.0] * (n - 1)
+    flops = 0.0
+    S_last = None
+    sched = sweep_schedule(n, n_sweeps)
+    for step, (i, d, last) in enumerate(sched):
+        Lb = left_block(L[i], A[i], B[i])
+        Rb = right_block(R[i + 2], A[i + 1], B[i + 1])
+        th = two_site_overlap(Lb, Rb)
+        flops += _step_flops(L[i].shape, A[i].shape[3], B[i].shape[3], R[i + 2].shape)
+        U, S, Vt = np.linalg.svd(th, full_matrices=False)
+        k = keep_count(S, D, deg_rtol, sv_floor)
+        tot = float(np.sum(S * S))
+        sv[i] = S.copy()
+        kept[i] = k
+        disc[i] = float(np.sum(S[k:] ** 2) / tot) if tot > 0 else 0.0
+        Dc = L[i].shape[0]
+        Dc2 = R[i + 2].shape[0]
+        go_right = (d > 0) != (last and step != len(sched) - 1)
+        if step == len(sched) - 1:
+            go_right = False
+        if go_right:
+            C[i] = U[:, :k].reshape(Dc, 2, 2, k)
+            C[i + 1] = (S[:k, None] * Vt[:k]).reshape(k, 2, 2, Dc2)
+            L[i + 1] = left_env(Lb, C[i])
+        else:
+            C[i + 1] = Vt[:k].reshape(k, 2, 2, Dc2)
+            C[i] = (U[:, :k] * S[:k]).reshape(Dc, 2, 2, k)
+            R[i + 1] = right_env(Rb, C[i + 1])
+        S_last = S[:k]
+    c = float(np.sqrt(np.sum(S_last * S_last)))
+    C[0] = C[0] / c
+    return C, CompressInfo(math.log(c), sv, kept, disc, len(sched), flops)
+
+
+def _step_flops(Lshape, Da2, Db2, Rshape) -> float:
+    """Algorithmic flops of one two-site step with the static side built:
+    left block (2 substeps), C_E, left/right environment advance.  Uses the
+    actual bond dimensions (d = 2)."""
+    Dc, Da, Db = Lshape
+    Dc2, Da3, Db3 = Rshape
+    d = 2
+    k1 = 2.0 * Dc * Db * Da * d * d * Da2
+    k2 = 2.0 * Dc * d * Da2 * Db * d * d * Db2
+    th = 2.0 * (Dc * d * d) * (Da2 * Db2) * (d * d * Dc2)
+    k3 = 2.0 * Da2 * Db2 * (Dc * d * d) * Dc
+    return k1 + k2 + th + k3
+
+
+# --------------------------------------------------------------------------
+# Observables (Eq. ThermalQuan; Sec. II.C for beta = 2 tau_n)
+# --------------------------------------------------------------------------
+
+def observables(rho: List[np.ndarray], lam: float, tau: float, H: List[np.ndarray],
+                n_sites: int) -> Dict[str, Dict[str, float]]:
+    """f, u, c per site at beta = tau (Z = Tr rho) and at beta = 2 tau
+    (Z = Tr rho^T rho).  ``rho`` is the normalised MPO, rho_true = e^lam rho."""
+    out = {}
+    tr = M.trace(rho)
+    e1 = M.trace_of_product(H, rho) / tr
+    e2 = M.trace_of_product(H, H, rho) / tr
+    b = tau
+    lnZ = lam + math.log(tr)
+    out["tau"] = dict(beta=b, lnZ=lnZ, f=-lnZ / (n_sites * b), u=e1 / n_sites,
+                      c=b * b * (e2 - e1 * e1) / n_sites, tr=tr)
+    rt = M.transpose(rho)
+    nrm = M.inner(rho, rho)
+    g1 = M.trace_of_product(H, rt, rho) / nrm
+    g2 = M.trace_of_product(H, H, rt, rho) / nrm
+    b = 2 * tau
+    lnZ = 2 * lam + math.log(nrm)
+    out["2tau"] = dict(beta=b, lnZ=lnZ, f=-lnZ / (n_sites * b), u=g1 / n_sites,
+                       c=b * b * (g2 - g1 * g1) / n_sites, norm2=nrm)
+    return out
+
+
+def entanglement(rho: List[np.ndarray]) -> np.ndarray:
+    """Von Neumann entropy of the normalised superstate |rho> (Eq. purif)
+    across every bond: QR sweep left-to-right, then SVD sweep right-to-left;
+    the singular values at bond (i-1, i) are the Schmidt coefficients."""
+    W = M.left_canonicalize(rho)
+    n = len(W)
+    out = np.zeros(n - 1)
+    for i in range(n - 1, 0, -1):
+        Dl, d1, d2, Dr = W[i].shape
+        U, S, Vt = np.linalg.svd(W[i].reshape(Dl, d1 * d2 * Dr), full_matrices=False)
+        W[i] = Vt.reshape(-1, d1, d2, Dr)
+        W[i - 1] = np.einsum("astb,bk->astk", W[i - 1], U * S)
+        p = S * S
+        p = p / p.sum()
+        p = p[p > 0]
+        out[i - 1] = float(-np.sum(p * np.log(p)))
+    return out
+
+
+# --------------------------------------------------------------------------
+# Driver
+# --------------------------------------------------------------------------
+
+def run(n, bonds, jxy, jz, tau0: float, n_doublings: int, D: int, order: int = 1,
+        n_sweeps: int = 4, deg_rtol: float = 1e-6, sv_floor: float = 1e-14,
+        with_entropy: bool = False, keep_states: bool = False):
+    """Full XTRG run; returns a list of per-doubling records."""
+    H = M.hamiltonian(n, bonds, jxy, jz)
+    rho, lam = init_rho(n, bonds, jxy, jz, tau0, order)
+    recs = []
+    tau = tau0
+    rec = dict(n=0, tau=tau, lam=lam, obs=observables(rho, lam, tau, H, n), bond_dims=M.bond_dims(rho))
+    if with_entropy:
+        rec["S_E"] = entanglement(rho)
+    if keep_states:
+        rec["rho"] = rho
+    recs.append(rec)
+    for k in range(1, n_doublings + 1):
+        rho, info = square_compress(rho, D, n_sweeps, deg_rtol, sv_floor)
+        lam = 2 * lam + info.dlog_norm
+        tau = 2 * tau
+        rec = dict(n=k, tau=tau, lam=lam, obs=observables(rho, lam, tau, H, n),
+                   bond_dims=M.bond_dims(rho), info=info)
+        if with_entropy:
+            rec["S_E"] = entanglement(rho)
+        if keep_states:
+            rec["rho"] = rho
+        recs.append(rec)
+    return recs
