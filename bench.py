@@ -1,0 +1,178 @@
+"""Throughput of the XTRG doubling step on one MI355X.
+
+One step = one beta-doubling of the L = 64 Heisenberg chain (tau0 = 2^-12,
+linear start) at bond dimension D = 256, i.e. the whole hot path: the
+static right blocks, n_sweeps two-site sweeps (left/right blocks, the
+two-site overlap C_E, SVD truncation, projection, environment advance) and
+the normalisation.  The untimed warm-up doublings grow the bonds from the
+start state until they reach D (plus --warmup more), so every timed step
+runs at the saturated bond dimension.  The metric counts the algorithmic
+flops of the contractions (64 D^4 per uniform two-site step, counted with
+the actual bond dimensions) divided by the wall time of the timed steps.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--D 256] [--sweeps 2]
+
+Prints one JSON line.  Only one GPU is used: --gpus above 1 exits.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--workload", default="chain64")
+    ap.add_argument("--D", type=int, default=256)
+    ap.add_argument("--sweeps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    return ap.parse_args()
+
+
+def cpu_baseline(sites, D, n_steps):
+    """Time the FP64 oracle's two-site step (left block, right block, C_E,
+    SVD, environment advance) on a bounded sample: n_steps steps at the
+    centre bond of the saturated MPO, with seeded environments of the
+    shapes the step sees.  Returns (TFLOP/s, seconds, flops, threads)."""
+    import numpy as np
+    from oracle import xtrg as OX
+
+    L = len(sites)
+    i = L // 2 - 1
+    A_i, A_j = sites[i], sites[i + 1]
+    Dl, Dm, Dr = A_i.shape[0], A_i.shape[3], A_j.shape[3]
+    rng = np.random.default_rng(0)
+    E = rng.standard_normal((min(D, Dl), Dl, Dl))
+    R = rng.standard_normal((min(D, Dr), Dr, Dr))
+    flops = 0.0
+    t0 = time.perf_counter()
+    for _ in range(n_steps):
+        Lb = OX.left_block(E, A_i, A_i)
+        Rb = OX.right_block(R, A_j, A_j)
+        th = OX.two_site_overlap(Lb, Rb)
+        U, S, Vt = np.linalg.svd(th, full_matrices=False)
+        k = min(D, U.shape[1])
+        C_i = U[:, :k].reshape(E.shape[0], 2, 2, k)
+        OX.left_env(Lb, C_i)
+        flops += OX._step_flops(E.shape, Dm, Dm, R.shape)
+    dt = time.perf_counter() - t0
+    threads = os.environ.get("OPENBLAS_NUM_THREADS") or os.environ.get("OMP_NUM_THREADS") or "default"
+    return flops / dt / 1e12, dt, flops, threads
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); independent chains would shard "
+              "across GPUs without communication, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads as W
+    from paper_1801_00142_amd import Context
+
+    wl = W.workload(args.workload, args.D)
+    lat = wl.lattice
+    ctx = Context(0)
+    H = ctx.hamiltonian_xxz(lat.n_sites, lat.bonds, lat.jxy, lat.jz)
+    rho, lam = ctx.init_rho(H, wl.tau0, wl.init_order)
+    tau = wl.tau0
+    n_done = 0
+    # warm-up: grow the bonds to D, then --warmup more doublings
+    t_w = time.perf_counter()
+    saturated_at = None
+    while True:
+        new, info = ctx.square_compress(rho, args.D, args.sweeps)
+        rho.close()
+        rho = new
+        lam = 2 * lam + info["dlog_norm"]      # lambda_{n+1} = 2 lambda_n + ln c
+        tau *= 2
+        n_done += 1
+        if saturated_at is None and info["D_kept_max"] >= args.D:
+            saturated_at = n_done
+        if saturated_at is not None and n_done >= saturated_at + args.warmup:
+            break
+        if n_done >= wl.n_doublings:
+            break
+    warm_s = time.perf_counter() - t_w
+
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_report()                       # reset
+    flops = 0.0
+    steps_2site = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        new, info = ctx.square_compress(rho, args.D, args.sweeps)
+        rho.close()
+        rho = new
+        flops += info["flops"]
+        steps_2site += info["steps"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = ctx.profile_report()
+    ctx.profile(False)
+
+    value = flops / dt / 1e12
+    th = prof["theta_gemm"]
+    th_avg_s = th["ms"] / max(th["calls"], 1) / 1e3
+    th_flops = th["flops"] / max(th["calls"], 1)
+    achieved = th_flops / th_avg_s / 1e12 if th_avg_s > 0 else 0.0
+    total_ms = sum(v["ms"] for v in prof.values())
+    shares = {k: round(v["ms"] / total_ms, 4) if total_ms else 0.0 for k, v in prof.items()}
+
+    out = {
+        "metric": "TFLOP/s in MPO product-compression sweeps at D=256",
+        "value": round(value, 4),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{lat.name} Heisenberg, tau0=2^-12, D={args.D}, {args.sweeps} sweeps/doubling",
+                   "L": lat.n_sites, "D": args.D, "n_sweeps": args.sweeps,
+                   "two_site_steps_per_doubling": steps_2site // max(args.steps, 1),
+                   "warmup_doublings": n_done, "saturated_after": saturated_at},
+        "sweeps_per_s": round(args.steps * args.sweeps / dt, 4),
+        "phase_share": shares,
+        "roofline": {"bound": "mfma", "kernel": "two-site overlap C_E (dgemm_kernel<...,1>)",
+                     "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                     "launches": th["calls"], "avg_launch_ms": round(th_avg_s * 1e3, 4),
+                     "flops_per_launch": th_flops},
+    }
+    if not args.no_cpu_baseline:
+        sites = rho.to_host()
+        tf, cdt, cfl, threads = cpu_baseline(sites, args.D, args.cpu_steps)
+        out["cpu_baseline"] = {"value": round(tf, 5), "unit": "TFLOP/s",
+                               "cores": len(os.sched_getaffinity(0)), "blas_threads": threads,
+                               "kind": "oracle", "seconds": round(cdt, 2),
+                               "sample": f"{args.cpu_steps} two-site steps (left/right block, C_E, LAPACK SVD, "
+                                         f"environment) at the centre bond of the saturated D={args.D} MPO, "
+                                         "seeded environments"}
+    rho.close()
+    H.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,164 @@
+/*
+ * xtrg.h -- C ABI of the MI355X XTRG library (libxtrg.so).
+ *
+ * XTRG (exponential thermal tensor renormalization group) cools a thermal
+ * state by repeated squaring, rho(2 tau) = rho(tau) * rho(tau), with the
+ * product of two matrix product operators (MPOs) compressed back to a bond
+ * dimension D by variational two-site sweeps (paper: Sec. II.C, Eqs.
+ * (rhoinit), (rho:scale2); App. D.1, Eqs. (MPO:prod), (LSEProd), Fig. VMPO).
+ *
+ * Conventions for every call:
+ *  - Return value: XTRG_OK (0) on success, a negative XTRG_E* code on
+ *    failure.  No C++ exception and no abort crosses this interface; the
+ *    message of the last failure on a context is xtrg_last_error(ctx).
+ *  - Ownership: the library owns all device memory behind xtrg_ctx and
+ *    xtrg_mpo handles.  Every *_out handle is newly created and must be
+ *    released by the caller with xtrg_mpo_destroy / xtrg_ctx_destroy.
+ *    Input handles are never modified.  Host arrays are caller-owned and
+ *    are only read or written during the call.
+ *  - Threading: a context serialises its work on one HIP stream; use one
+ *    context per host thread.
+ *  - Numbers: FP64 at the interface.  MPO site tensors are real, row-major
+ *    [D_left][d][d][D_right] with W[a][s][s'][a'] = <s| W_{a a'} |s'>
+ *    (row = output index, column = input index), d = 2 (spin 1/2), and the
+ *    outermost bonds have dimension 1.
+ */
+#ifndef XTRG_H
+#define XTRG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct xtrg_ctx_s* xtrg_ctx;
+typedef struct xtrg_mpo_s* xtrg_mpo;
+
+enum {
+  XTRG_OK = 0,
+  XTRG_EINVAL = -1,   /* bad argument (null pointer, size, shape) */
+  XTRG_ENOMEM = -2,   /* device allocation failed or HBM budget exceeded */
+  XTRG_EDEVICE = -3,  /* HIP runtime error */
+  XTRG_ENUMERIC = -4, /* NaN/Inf, non-positive norm or trace, SVD not converged */
+  XTRG_EBUSY = -5
+};
+
+enum { XTRG_FP64 = 0 };
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
+ * (e.g. torch.cuda.current_stream().cuda_stream) or NULL for the null
+ * stream.  `hbm_budget` bounds the bytes the context may hold (0 = no
+ * bound); an allocation beyond it fails with XTRG_ENOMEM. */
+int xtrg_ctx_create(int device, void* hip_stream, size_t hbm_budget, xtrg_ctx* out);
+int xtrg_ctx_destroy(xtrg_ctx ctx);
+/* Message of the last failure on ctx ("" if none).  Owned by ctx. */
+const char* xtrg_last_error(xtrg_ctx ctx);
+/* Device bytes currently held by ctx (MPOs + workspaces). */
+size_t xtrg_ctx_bytes(xtrg_ctx ctx);
+
+/* Hamiltonian MPO of the spin-1/2 XXZ model on an arbitrary bond list,
+ * H = sum_b jxy_b (Sx Sx + Sy Sy) + jz_b Sz Sz
+ *   = sum_b jxy_b/2 (S+ S- + S- S+) + jz_b Sz Sz   (real form, App. F),
+ * built by the automaton construction of App. B.1: virtual states start,
+ * stop and one state per operator still pending across a cut, so
+ * D_H = 2 + 3 * (max number of sites with an open bond across a cut).
+ * bonds: 2*n_bonds site indices (0-based, in the 1D MPO ordering), i != j.
+ * The handle also keeps the un-capped right end (start/stop open) for
+ * xtrg_init_rho. */
+int xtrg_hamiltonian_xxz(xtrg_ctx ctx, int n_sites, int n_bonds, const int* bonds,
+                         const double* jxy, const double* jz, xtrg_mpo* H_out);
+
+/* Upload an MPO.  bond_dims: L+1 entries (first and last must be 1);
+ * site_tensors[i]: host array of bond_dims[i]*d*d*bond_dims[i+1] doubles. */
+int xtrg_mpo_from_host(xtrg_ctx ctx, int L, int d, const int* bond_dims,
+                       const double* const* site_tensors, xtrg_mpo* out);
+/* Number of sites and bond dimensions (bond_dims: L+1 entries, caller-sized). */
+int xtrg_mpo_shape(xtrg_mpo mpo, int* L, int* bond_dims);
+/* Download an MPO into caller-allocated host arrays sized from xtrg_mpo_shape. */
+int xtrg_mpo_to_host(xtrg_mpo mpo, double* const* site_tensors);
+int xtrg_mpo_destroy(xtrg_mpo mpo);
+
+/* Initial state rho(tau0) = sum_{k<=order} (-tau0)^k/k! H^k (Eq. RhoTau;
+ * order 1 is the linear start I - tau0 H of App. C.2, exact at bond D_H).
+ * H must come from xtrg_hamiltonian_xxz.  order is 1 or 2.  The result is
+ * compressed without loss (numerically zero singular values dropped, never
+ * more than D0_max kept if D0_max > 0), right-canonical and normalised:
+ * rho(tau0) = exp(*log_norm) * rho_out with ||rho_out||_F = 1. */
+int xtrg_init_rho(xtrg_ctx ctx, xtrg_mpo H, double tau0, int order, int D0_max,
+                  xtrg_mpo* rho_out, double* log_norm);
+
+/* Options of one doubling. */
+typedef struct {
+  int D_max;         /* bond dimension budget D (> 0) */
+  int n_sweeps;      /* full sweeps (left-to-right then right-to-left), >= 1 */
+  int precision;     /* XTRG_FP64 */
+  double degen_rtol; /* multiplet-safe cut: back off to a gap > degen_rtol*sigma_k (1e-6) */
+  double sv_floor;   /* singular values <= sv_floor*sigma_1 count as zero (1e-14) */
+} xtrg_compress_opts;
+
+/* Diagnostics of one doubling. */
+typedef struct {
+  double dlog_norm;     /* ln c, c = ||C||_F before normalisation */
+  double trunc_err_max; /* max over bonds of discarded weight sum_{k>kept} s_k^2 / sum s_k^2 */
+  int sweeps_done;
+  int D_kept_max;
+  int steps;            /* two-site steps performed */
+  double flops;         /* algorithmic flops of the contractions (64 D^4 per uniform step) */
+  double* sv;           /* optional, caller-sized (L-1)*sv_stride: per-bond sigma of the last visit */
+  int sv_stride;        /* entries per bond in sv (values beyond the bond's count are zero) */
+} xtrg_compress_info;
+
+/* One XTRG doubling (Eqs. rhoinit, rho:scale2): rho_out ~ rho_in * rho_in
+ * compressed to bond <= D_max by n_sweeps variational two-site sweeps
+ * (App. D.1, Eq. LSEProd, Fig. VMPO).  rho_in must be normalised and
+ * right-canonical (as returned by xtrg_init_rho or this call).  The result
+ * is normalised and right-canonical; lambda_{n+1} = 2 lambda_n + info->dlog_norm.
+ * Initial guess: rho_in.  Truncation: at most D_max states per bond, backed
+ * off to the largest k >= D_max/2 with sigma_k - sigma_{k+1} > degen_rtol*sigma_k
+ * (never split a degenerate multiplet); sigma <= sv_floor*sigma_1 dropped. */
+int xtrg_square_compress(xtrg_ctx ctx, xtrg_mpo rho_in, const xtrg_compress_opts* opts,
+                         xtrg_mpo* rho_out, xtrg_compress_info* info);
+
+/* Thermodynamics of a normalised MPO rho (rho_true = exp(log_norm) rho),
+ * Eq. (ThermalQuan): f = -ln Z/(N beta), u = <H>/N, c = beta^2 (<H^2> - <H>^2)/N.
+ * at_tau : beta = tau_n, Z = Tr rho.
+ * at_2tau: beta = 2 tau_n, Z = Tr rho^T rho = ||rho||_F^2 (Sec. II.C).
+ * S_E_per_bond (optional, L-1 entries): von Neumann entropy of the
+ * normalised vectorised MPO across every bond (Eq. purif), at beta = 2 tau_n. */
+typedef struct {
+  double beta, lnZ, f, u, c;
+  double tr_rho;      /* Tr rho (at_tau) or ||rho||_F^2 (at_2tau) of the normalised MPO */
+  double S_E_center, S_E_max;
+} xtrg_obs;
+
+int xtrg_observables(xtrg_ctx ctx, xtrg_mpo rho, double log_norm, double tau_n, xtrg_mpo H,
+                     int n_sites, xtrg_obs* at_tau, xtrg_obs* at_2tau, double* S_E_per_bond);
+
+/* Timing of the doubling's phases (two-site overlap GEMM, left/right block
+ * GEMMs, environment GEMMs, SVD, split/projection) with HIP events on the
+ * context stream.  xtrg_profile_report writes a JSON object
+ * {"theta_gemm": {"ms", "calls", "flops", "bytes"}, ...} accumulated since
+ * the last report into buf (cap bytes) and resets the counters. */
+int xtrg_profile_enable(xtrg_ctx ctx, int on);
+int xtrg_profile_report(xtrg_ctx ctx, char* buf, size_t cap);
+
+/* Kernel-level entry points (device pointers, FP64, on the context stream).
+ * Used by the parity tests of the individual kernels.
+ *
+ * xtrg_dgemm: C = A * B with A (M x K) stored row-major (lda) or, if transA,
+ * as K x M row-major; B (K x N) row-major (ldb) or, if transB, as N x K;
+ * C (M x N) row-major (ldc).  Inputs and output must not alias. */
+int xtrg_dgemm(xtrg_ctx ctx, int M, int N, int K, int transA, int transB,
+               const double* A, long lda, const double* B, long ldb, double* C, long ldc);
+/* xtrg_dsvd_left: singular values of the len x p matrix Y stored
+ * column-major (column j at Y + j*len, device), descending, into sigma
+ * (device, p entries), and the left singular vectors of the first k of them
+ * into U (device, column-major len x k).  Y is not modified.  One-sided
+ * (Hestenes) Jacobi with column blocks. */
+int xtrg_dsvd_left(xtrg_ctx ctx, int len, int p, const double* Y, double* sigma, int k, double* U);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XTRG_H */

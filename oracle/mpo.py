@@ -220,7 +220,8 @@ def svd_compress(W: List[np.ndarray], D: int, rel_floor: float = 1e-14) -> List[
         Dl, d1, d2, Dr = W[i].shape
         M = W[i].reshape(Dl, d1 * d2 * Dr)
         U, S, Vt = np.linalg.svd(M, full_matrices=False)
-        k = min(D, int(np.sum(S > rel_floor * S[0]))) if S[0] > 0 else 1
+        noise = 40.0 * 2.220446049250313e-16 * np.sqrt(max(M.shape)) * np.linalg.norm(M)
+        k = min(D, int(np.sum(S > max(rel_floor * S[0], noise)))) if S[0] > 0 else 1
         k = max(k, 1)
         W[i] = Vt[:k].reshape(k, d1, d2, Dr)
         W[i - 1] = np.einsum("astb,bk->astk", W[i - 1], U[:, :k] * S[:k])

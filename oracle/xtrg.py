@@ -29,7 +29,8 @@ library, implemented independently):
 * keep k <= D states, backing off to the largest k >= D/2 with a relative
   gap sigma_k - sigma_{k+1} > deg_rtol * sigma_k so that a (numerically)
   degenerate multiplet is never split; singular values below
-  sv_floor * sigma_1 count as zero;
+  sv_floor * sigma_1, or below the rounding noise of C_E
+  (40 eps sqrt(max dim) ||C_E||_F), count as zero;
 * rho_n is stored normalised, rho_n = exp(lambda_n) * rhohat_n with
   ||rhohat_n||_F = 1 and lambda_n in FP64.
 """
@@ -48,11 +49,22 @@ from . import mpo as M
 # Truncation rule (Sec. II.E: a fixed number of states; multiplet-safe cut)
 # --------------------------------------------------------------------------
 
-def keep_count(S: np.ndarray, D: int, deg_rtol: float, sv_floor: float) -> int:
+EPS = 2.220446049250313e-16
+
+
+def noise_floor(M: np.ndarray) -> float:
+    """Rounding-noise level of a matrix: singular values below
+    40 eps sqrt(max(m, n)) ||M||_F are resolved to less than ~10% by any
+    FP64 factorisation and count as zero (reading of the 'numerically
+    zero' case the paper leaves open)."""
+    return 40.0 * EPS * float(np.sqrt(max(M.shape))) * float(np.linalg.norm(M))
+
+
+def keep_count(S: np.ndarray, D: int, deg_rtol: float, sv_floor: float, abs_floor: float = 0.0) -> int:
     """Number of singular values kept out of the descending list S."""
     if S.size == 0 or not S[0] > 0:
         return 1
-    r = int(np.count_nonzero(S > sv_floor * S[0]))
+    r = int(np.count_nonzero(S > max(sv_floor * S[0], abs_floor)))
     r = max(r, 1)
     if r <= D:
         return r
@@ -205,7 +217,7 @@ def square_compress(rho: List[np.ndarray], D: int, n_sweeps: int = 4,
         th = two_site_overlap(Lb, Rb)
         flops += _step_flops(L[i].shape, A[i].shape[3], B[i].shape[3], R[i + 2].shape)
         U, S, Vt = np.linalg.svd(th, full_matrices=False)
-        k = keep_count(S, D, deg_rtol, sv_floor)
+        k = keep_count(S, D, deg_rtol, sv_floor, noise_floor(th))
         tot = float(np.sum(S * S))
         sv[i] = S.copy()
         kept[i] = k

@@ -1,0 +1,1114 @@
+// C ABI of the library: contexts, MPO handles, the automaton Hamiltonian,
+// the series start, one XTRG doubling (variational product compression)
+// and the thermodynamic observables.  Host code here only orchestrates:
+// every tensor operation is a kernel on the context stream.
+#include "xtrg.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "internal.h"
+
+using xtrg::Error;
+using xtrg::Gemm;
+
+// ---------------------------------------------------------------------------
+// Context and device memory
+// ---------------------------------------------------------------------------
+
+struct DevBuf {
+  double* p = nullptr;
+  size_t cap = 0;  // doubles
+};
+
+struct xtrg_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t budget = 0;
+  size_t bytes = 0;
+  std::string err;
+  std::map<std::string, DevBuf> ws;   // named, grow-only workspaces
+  double* scratch = nullptr;          // 2048 doubles: reductions, small vectors
+
+  // Optional timing of the doubling's phases with HIP events on `stream`.
+  struct Prof {
+    int cat;
+    hipEvent_t a, b;
+    double flops, bytes;
+  };
+  bool prof = false;
+  std::vector<Prof> prof_recs;
+
+  double* alloc(size_t n) {
+    const size_t b = std::max<size_t>(n, 1) * sizeof(double);
+    if (budget && bytes + b > budget)
+      throw Error(XTRG_ENOMEM, "HBM budget exceeded (" + std::to_string(bytes + b) + " > " +
+                                   std::to_string(budget) + " bytes)");
+    double* p = nullptr;
+    if (hipMalloc(&p, b) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(XTRG_ENOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed");
+    }
+    bytes += b;
+    return p;
+  }
+  void release(double* p, size_t n) {
+    if (!p) return;
+    // work queued on the stream may still read p
+    if (stream) (void)hipStreamSynchronize(stream);
+    else (void)hipDeviceSynchronize();
+    (void)hipFree(p);
+    bytes -= std::max<size_t>(n, 1) * sizeof(double);
+  }
+  double* need(const std::string& name, size_t n) {
+    DevBuf& d = ws[name];
+    if (d.cap < n) {
+      release(d.p, d.cap);
+      d.p = nullptr;
+      d.cap = 0;
+      d.p = alloc(n);
+      d.cap = n;
+    }
+    return d.p;
+  }
+};
+
+struct Site {
+  double* p = nullptr;
+  size_t n = 0;
+};
+
+struct xtrg_mpo_s {
+  xtrg_ctx ctx = nullptr;
+  int L = 0;
+  std::vector<int> dims;      // L+1
+  std::vector<Site> site;     // device [Dl][2][2][Dr]
+  // Hamiltonians built here keep the un-capped right end ([Dl][2][2][2],
+  // last index: start, stop) on the host for the series start.
+  bool has_open = false;
+  std::vector<double> open_last;
+
+  ~xtrg_mpo_s() {
+    for (auto& s : site) ctx->release(s.p, s.n);
+  }
+  size_t elems(int i) const { return (size_t)dims[i] * 4 * dims[i + 1]; }
+};
+
+namespace {
+
+// Phases of the doubling step timed by the profiler.
+enum { P_THETA = 0, P_BLOCK, P_ENV, P_SVD, P_SPLIT, P_NCAT };
+const char* const kPhase[P_NCAT] = {"theta_gemm", "block_gemm", "env_gemm", "svd", "split"};
+
+// RAII event pair around the work enqueued in its scope.
+struct Timed {
+  xtrg_ctx c;
+  xtrg_ctx_s::Prof r{};
+  Timed(xtrg_ctx ctx, int cat, double flops, double bytes) : c(ctx) {
+    if (!c->prof) return;
+    r.cat = cat;
+    r.flops = flops;
+    r.bytes = bytes;
+    XTRG_HIP(hipEventCreate(&r.a));
+    XTRG_HIP(hipEventCreate(&r.b));
+    XTRG_HIP(hipEventRecord(r.a, c->stream));
+  }
+  ~Timed() {
+    if (!c->prof) return;
+    (void)hipEventRecord(r.b, c->stream);
+    c->prof_recs.push_back(r);
+  }
+};
+
+template <class F>
+int guarded(xtrg_ctx ctx, F&& f) {
+  try {
+    f();
+    if (ctx) ctx->err.clear();
+    return XTRG_OK;
+  } catch (const Error& e) {
+    if (ctx) ctx->err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    if (ctx) ctx->err = e.what();
+    return XTRG_EINVAL;
+  } catch (...) {
+    if (ctx) ctx->err = "unknown error";
+    return XTRG_EINVAL;
+  }
+}
+
+void set_device(xtrg_ctx c) { XTRG_HIP(hipSetDevice(c->device)); }
+
+std::unique_ptr<xtrg_mpo_s> new_mpo(xtrg_ctx c, const std::vector<int>& dims) {
+  auto m = std::make_unique<xtrg_mpo_s>();
+  m->ctx = c;
+  m->L = (int)dims.size() - 1;
+  m->dims = dims;
+  m->site.resize(m->L);
+  for (int i = 0; i < m->L; ++i) {
+    m->site[i].n = m->elems(i);
+    m->site[i].p = c->alloc(m->site[i].n);
+  }
+  return m;
+}
+
+void upload(xtrg_ctx c, double* dst, const double* src, size_t n) {
+  XTRG_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+}
+
+double read_scalar(xtrg_ctx c, const double* d) {
+  double h = 0.0;
+  XTRG_HIP(hipMemcpyAsync(&h, d, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  XTRG_HIP(hipStreamSynchronize(c->stream));
+  return h;
+}
+
+void gemm(xtrg_ctx c, const Gemm& g) {
+  const size_t w = xtrg::gemm_splitk_work(g);
+  double* work = w ? c->need("splitk", w) : nullptr;
+  xtrg::gemm(g, c->stream, work, w);
+}
+
+// Plain row-major C[MxN] = op(A) op(B).
+Gemm plain(int M, int N, int K, const double* A, long lda, bool tA, const double* B, long ldb, bool tB,
+           double* C, long ldc) {
+  Gemm g;
+  g.M = M; g.N = N; g.K = K;
+  g.A = A; g.lda = lda; g.transA = tA;
+  g.B = B; g.ldb = ldb; g.transB = tB;
+  g.C = C; g.ldc = ldc;
+  return g;
+}
+
+// ---------------------------------------------------------------------------
+// Automaton Hamiltonian MPO (App. B.1)
+// ---------------------------------------------------------------------------
+
+struct Automaton {
+  int n = 0;
+  std::vector<int> dims;                 // n+1 open dims (2 at both ends)
+  std::vector<std::vector<double>> T;    // [Dl][2][2][Dr]
+};
+
+Automaton build_automaton(int n, int nb, const int* bonds, const double* jxy, const double* jz) {
+  std::map<std::pair<int, int>, std::pair<double, double>> coup;
+  for (int b = 0; b < nb; ++b) {
+    int i = bonds[2 * b], j = bonds[2 * b + 1];
+    if (i < 0 || j < 0 || i >= n || j >= n || i == j) throw Error(XTRG_EINVAL, "bad bond index");
+    if (i > j) std::swap(i, j);
+    auto& v = coup[{i, j}];
+    v.first += jxy[b];
+    v.second += jz[b];
+  }
+  // pending[p]: sites i <= p with a partner j > p (interaction terms open across cut p)
+  std::vector<std::vector<int>> pend(std::max(n - 1, 0));
+  for (int p = 0; p + 1 < n; ++p) {
+    std::vector<int> s;
+    for (auto& kv : coup)
+      if (kv.first.first <= p && p < kv.first.second) s.push_back(kv.first.first);
+    std::sort(s.begin(), s.end());
+    s.erase(std::unique(s.begin(), s.end()), s.end());
+    pend[p] = s;
+  }
+  auto chan = [&](int cut, int site, int a) {
+    const auto& P = pend[cut];
+    const int k = (int)(std::lower_bound(P.begin(), P.end(), site) - P.begin());
+    return 2 + 3 * k + a;
+  };
+  // local operators: basis (up, down); S+ = |up><down|
+  const double Sp[2][2] = {{0, 1}, {0, 0}}, Sm[2][2] = {{0, 0}, {1, 0}}, Sz[2][2] = {{0.5, 0}, {0, -0.5}};
+  const double Id[2][2] = {{1, 0}, {0, 1}};
+  const double (*open_op[3])[2] = {Sp, Sm, Sz};
+  const double (*close_op[3])[2] = {Sm, Sp, Sz};
+
+  Automaton A;
+  A.n = n;
+  A.dims.resize(n + 1);
+  A.dims[0] = 2;
+  A.dims[n] = 2;
+  for (int p = 0; p + 1 < n; ++p) A.dims[p + 1] = 2 + 3 * (int)pend[p].size();
+  A.T.resize(n);
+  for (int p = 0; p < n; ++p) {
+    const int Dl = A.dims[p], Dr = A.dims[p + 1];
+    std::vector<double> T((size_t)Dl * 4 * Dr, 0.0);
+    auto put = [&](int a, int b, const double (*op)[2], double cf) {
+      for (int s = 0; s < 2; ++s)
+        for (int t = 0; t < 2; ++t) T[(((size_t)a * 2 + s) * 2 + t) * Dr + b] += cf * op[s][t];
+    };
+    put(0, 0, Id, 1.0);  // start -> start
+    put(1, 1, Id, 1.0);  // stop -> stop
+    if (p + 1 < n && std::binary_search(pend[p].begin(), pend[p].end(), p))
+      for (int a = 0; a < 3; ++a) put(0, chan(p, p, a), open_op[a], 1.0);   // open at site p
+    if (p > 0) {
+      for (int i : pend[p - 1]) {
+        if (p + 1 < n && std::binary_search(pend[p].begin(), pend[p].end(), i))
+          for (int a = 0; a < 3; ++a) put(chan(p - 1, i, a), chan(p, i, a), Id, 1.0);  // carry
+        auto it = coup.find({i, p});
+        if (it != coup.end()) {                                                   // close at p
+          const double cf[3] = {0.5 * it->second.first, 0.5 * it->second.first, it->second.second};
+          for (int a = 0; a < 3; ++a) put(chan(p - 1, i, a), 1, close_op[a], cf[a]);
+        }
+      }
+    }
+    A.T[p] = std::move(T);
+  }
+  return A;
+}
+
+// Cap the outer bonds: left with e_start, right with the vector `r` (length 2).
+std::vector<std::vector<double>> cap(const Automaton& A, const double r[2], std::vector<int>* dims) {
+  const int n = A.n;
+  std::vector<std::vector<double>> S(n);
+  dims->assign(n + 1, 0);
+  for (int p = 0; p < n; ++p) (*dims)[p] = A.dims[p];
+  (*dims)[n] = 1;
+  (*dims)[0] = 1;
+  for (int p = 0; p < n; ++p) {
+    const int Dl = A.dims[p], Dr = A.dims[p + 1];
+    const int dl = (p == 0) ? 1 : Dl, dr = (p == n - 1) ? 1 : Dr;
+    std::vector<double> T((size_t)dl * 4 * dr, 0.0);
+    for (int a = 0; a < dl; ++a)
+      for (int st = 0; st < 4; ++st)
+        for (int b = 0; b < dr; ++b) {
+          double v;
+          if (p == n - 1) {
+            v = 0.0;
+            for (int q = 0; q < 2; ++q) v += A.T[p][((size_t)a * 4 + st) * Dr + q] * r[q];
+          } else {
+            v = A.T[p][((size_t)a * 4 + st) * Dr + b];
+          }
+          T[((size_t)a * 4 + st) * dr + b] = v;   // p == 0: a = 0 is the start row
+        }
+    S[p] = std::move(T);
+  }
+  return S;
+}
+
+// ---------------------------------------------------------------------------
+// Canonical forms by SVD sweeps (all on device)
+// ---------------------------------------------------------------------------
+
+// Number of kept singular values: the rule of the doubling step.
+// S descending; values <= max(floor * S[0], abs_floor) count as zero.
+int keep_count(const std::vector<double>& S, int D, double deg_rtol, double floor, double abs_floor) {
+  if (S.empty() || !(S[0] > 0)) return 1;
+  const double f = std::max(floor * S[0], abs_floor);
+  int r = 0;
+  for (double v : S)
+    if (v > f) ++r;
+  r = std::max(r, 1);
+  if (r <= D) return r;
+  const int lo = std::max(1, (D + 1) / 2);
+  for (int k = D; k >= lo; --k)
+    if (S[k - 1] - S[k] > deg_rtol * S[k - 1]) return k;
+  return D;
+}
+
+std::vector<double> read_vec(xtrg_ctx c, const double* d, size_t n) {
+  std::vector<double> h(n);
+  if (n) {
+    XTRG_HIP(hipMemcpyAsync(h.data(), d, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    XTRG_HIP(hipStreamSynchronize(c->stream));
+  }
+  return h;
+}
+
+// Absolute rounding-noise floor of the matrix last decomposed in `work`.
+double noise_floor(xtrg_ctx c, const double* work, int len, int p) {
+  const double f2 = read_vec(c, xtrg::svd_fro2(work, len, p), 1)[0];
+  return xtrg::svd_keep_rel(len, p) * std::sqrt(std::max(f2, 0.0));
+}
+
+// Enforce orthonormal columns on the len x k isometry U by Newton-Schulz
+// polar iterations U <- U (3I - U^T U)/2: the column space is kept and the
+// deviation from orthonormality e goes to (3/4) e^2 per iteration.  U is
+// stored row-major [len][k] (rowmajor) or as U^T row-major [k][len].  The
+// Jacobi columns of tiny singular values are orthogonal only to the
+// rounding noise of the large ones; this restores the canonical form.
+void orthonormalize(xtrg_ctx c, double* U, int len, int k, bool rowmajor) {
+  if (k <= 0 || len <= 0) return;
+  double* X = c->need("ns_X", (size_t)k * k);
+  double* T = c->need("ns_T", (size_t)len * k);
+  for (int it = 0; it < 4; ++it) {
+    if (rowmajor) {
+      gemm(c, plain(k, k, len, U, k, true, U, k, false, X, k));        // U^T U
+      gemm(c, plain(len, k, k, U, k, false, X, k, false, T, k));       // U (U^T U)
+    } else {
+      gemm(c, plain(k, k, len, U, len, false, U, len, true, X, k));    // U^T U from U^T
+      gemm(c, plain(k, len, k, X, k, false, U, len, false, T, len));   // (U^T U) U^T
+    }
+    xtrg::axpby(U, 1.5, T, -0.5, (size_t)len * k, c->stream);
+  }
+}
+
+// Replace site i's buffer by a new one of n doubles.
+double* reshape_site(xtrg_mpo m, int i, size_t n) {
+  xtrg_ctx c = m->ctx;
+  if (m->site[i].n < n) {
+    c->release(m->site[i].p, m->site[i].n);
+    m->site[i].p = c->alloc(n);
+    m->site[i].n = n;
+  }
+  return m->site[i].p;
+}
+
+// Left-to-right: site i = U (left-isometric), R = S V^T pushed into site i+1.
+// Singular values <= floor * s_1 are dropped (floor = 0 keeps all nonzero).
+void left_sweep(xtrg_mpo m, double floor, std::vector<std::vector<double>>* sv) {
+  xtrg_ctx c = m->ctx;
+  hipStream_t s = c->stream;
+  for (int i = 0; i + 1 < m->L; ++i) {
+    const int Dl = m->dims[i], Dr = m->dims[i + 1], Dn = m->dims[i + 2];
+    const int rows = Dl * 4;
+    double* Y = c->need("cs_Y", (size_t)rows * Dr);
+    xtrg::transpose(Y, rows, m->site[i].p, Dr, Dr, rows, s);          // Y col-major (rows x Dr)
+    // note: transpose(dst, ldd, src, lds, R, C) reads src column-major (C cols of R);
+    // the site matrix [rows][Dr] row-major is (Dr x rows) column-major.
+    double* work = c->need("cs_work", xtrg::svd_work(rows, Dr));
+    xtrg::svd_left(rows, Dr, Y, nullptr, 0, nullptr, 0, 0, work, s, nullptr);
+    std::vector<double> S = read_vec(c, xtrg::svd_sorted_values(work, rows, Dr), Dr);
+    const int lim = std::min(rows, Dr);
+    S.resize(lim);
+    const double nf = noise_floor(c, work, rows, Dr);
+    int k = 0;
+    for (double v : S)
+      if (v > floor * S[0] && v > nf && v > 0) ++k;
+    k = std::max(k, 1);
+    if (sv) sv->push_back(S);
+    double* U = c->need("cs_U", (size_t)rows * k);
+    xtrg::svd_gather(rows, Dr, work, k, U, k, 1, s);                   // U row-major [rows][k]
+    orthonormalize(c, U, rows, k, true);
+    double* R = c->need("cs_R", (size_t)k * Dr);
+    gemm(c, plain(k, Dr, rows, U, k, true, m->site[i].p, Dr, false, R, Dr));   // R = U^T M
+    double* Nn = c->need("cs_N", (size_t)k * 4 * Dn);
+    gemm(c, plain(k, 4 * Dn, Dr, R, Dr, false, m->site[i + 1].p, 4 * Dn, false, Nn, 4 * Dn));
+    xtrg::copy(reshape_site(m, i, (size_t)rows * k), U, (size_t)rows * k, s);
+    xtrg::copy(reshape_site(m, i + 1, (size_t)k * 4 * Dn), Nn, (size_t)k * 4 * Dn, s);
+    m->dims[i + 1] = k;
+  }
+}
+
+// Right-to-left: site i = V^T (right-isometric), U S pushed into site i-1.
+// Keeps at most Dmax (if > 0) and drops values <= floor * s_1.  Records the
+// singular values of every bond (bond i-1 | i) in sv (indexed by bond).
+void right_sweep(xtrg_mpo m, double floor, int Dmax, std::vector<std::vector<double>>* sv) {
+  xtrg_ctx c = m->ctx;
+  hipStream_t s = c->stream;
+  if (sv) sv->assign(std::max(m->L - 1, 0), {});
+  for (int i = m->L - 1; i >= 1; --i) {
+    const int Dl = m->dims[i], Dr = m->dims[i + 1], Dp = m->dims[i - 1];
+    const int len = 4 * Dr;
+    double* work = c->need("cs_work", xtrg::svd_work(len, Dl));
+    xtrg::svd_left(len, Dl, m->site[i].p, nullptr, 0, nullptr, 0, 0, work, s, nullptr);
+    std::vector<double> S = read_vec(c, xtrg::svd_sorted_values(work, len, Dl), Dl);
+    S.resize(std::min(len, Dl));
+    const double nf = noise_floor(c, work, len, Dl);
+    int k = 0;
+    for (double v : S)
+      if (v > floor * S[0] && v > nf && v > 0) ++k;
+    k = std::max(k, 1);
+    if (Dmax > 0) k = std::min(k, Dmax);
+    if (sv) (*sv)[i - 1] = S;
+    double* V = c->need("cs_V", (size_t)len * k);
+    xtrg::svd_gather(len, Dl, work, k, V, len, 0, s);                 // V col-major = V^T row-major [k][len]
+    orthonormalize(c, V, len, k, false);
+    double* US = c->need("cs_R", (size_t)Dl * k);
+    gemm(c, plain(Dl, k, len, m->site[i].p, len, false, V, len, true, US, k));   // U S = M V
+    double* Pn = c->need("cs_N", (size_t)Dp * 4 * k);
+    gemm(c, plain(Dp * 4, k, Dl, m->site[i - 1].p, Dl, false, US, k, false, Pn, k));
+    xtrg::copy(reshape_site(m, i, (size_t)k * len), V, (size_t)k * len, s);
+    xtrg::copy(reshape_site(m, i - 1, (size_t)Dp * 4 * k), Pn, (size_t)Dp * 4 * k, s);
+    m->dims[i] = k;
+  }
+}
+
+double site_norm(xtrg_mpo m, int i) {
+  xtrg_ctx c = m->ctx;
+  xtrg::sumsq(m->site[i].p, m->elems(i), c->scratch, c->scratch + 1024, c->stream);
+  return std::sqrt(read_scalar(c, c->scratch));
+}
+
+std::unique_ptr<xtrg_mpo_s> clone(xtrg_mpo src) {
+  auto m = new_mpo(src->ctx, src->dims);
+  for (int i = 0; i < src->L; ++i) xtrg::copy(m->site[i].p, src->site[i].p, src->elems(i), src->ctx->stream);
+  return m;
+}
+
+// ---------------------------------------------------------------------------
+// The doubling step (App. D.1, Fig. VMPO)
+// ---------------------------------------------------------------------------
+
+struct Step {
+  int bond;
+  int dir;        // +1 left-to-right, -1 right-to-left
+  bool last;      // last bond of its half-sweep
+};
+
+std::vector<Step> schedule(int n, int n_sweeps) {
+  std::vector<Step> out;
+  for (int h = 0; h < 2 * n_sweeps; ++h) {
+    std::vector<int> bonds;
+    if (h % 2 == 0)
+      for (int b = (h == 0 ? 0 : 1); b <= n - 2; ++b) bonds.push_back(b);
+    else
+      for (int b = n - 3; b >= 0; --b) bonds.push_back(b);
+    for (size_t j = 0; j < bonds.size(); ++j)
+      out.push_back({bonds[j], h % 2 == 0 ? 1 : -1, j + 1 == bonds.size()});
+  }
+  return out;
+}
+
+struct Doubler {
+  xtrg_ctx c;
+  int L;
+  std::vector<int> Da;                  // bonds of A = B = rho
+  std::vector<int> Dc;                  // bonds of C
+  std::vector<int> cap;                 // largest possible bond of C
+  std::vector<const double*> A;         // rho sites
+  std::vector<double*> Bp;              // rho sites with the physical indices swapped
+  std::vector<DevBuf> slot;             // Lb_i or Rb_i
+  std::vector<Site> C;                  // output sites (capacity at cap)
+
+  double* slot_need(int i, size_t n) {
+    DevBuf& d = slot[i];
+    if (d.cap < n) {
+      c->release(d.p, d.cap);
+      d.p = c->alloc(n);
+      d.cap = n;
+    }
+    return d.p;
+  }
+
+  // Lb[(c,s,s'')][(a',b')] = sum_{a,b,s'} E[c][a][b] A_i[a][s][s'][a'] A_i[b][s'][s''][b']
+  void left_block(int i, const double* E, double* out) {
+    const int dc = Dc[i], da = Da[i], db = Da[i], da2 = Da[i + 1], db2 = Da[i + 1];
+    double* X = c->need("X", (size_t)dc * 4 * db * da2);
+    Gemm g1;   // X[c][s][b][(s',a')] = sum_a E[c][a][b] A[a][s][(s',a')]   batch (c, s)
+    g1.M = db; g1.N = 2 * da2; g1.K = da;
+    g1.transA = 1; g1.A = E; g1.lda = db;
+    g1.B = A[i]; g1.ldb = 4 * da2;
+    g1.C = X; g1.ldc = 2 * da2;
+    g1.nb[0] = dc; g1.nb[1] = 2;
+    g1.sA[0] = (long)da * db;
+    g1.sB[1] = 2L * da2;
+    g1.sC[0] = 4L * db * da2; g1.sC[1] = 2L * db * da2;
+    gemm(c, g1);
+    Gemm g2;   // Lb[c][s][s''][a'][b'] = sum_{(b,s')} X[c][s][(b,s')][a'] B[(b,s')][s''][b']  batch (c,s,s'')
+    g2.M = da2; g2.N = db2; g2.K = 2 * db;
+    g2.transA = 1; g2.A = X; g2.lda = da2;
+    g2.B = A[i]; g2.ldb = 2 * db2;
+    g2.C = out; g2.ldc = db2;
+    g2.nb[0] = dc; g2.nb[1] = 2; g2.nb[2] = 2;
+    g2.sA[0] = 4L * db * da2; g2.sA[1] = 2L * db * da2;
+    g2.sB[2] = db2;
+    g2.sC[0] = 4L * da2 * db2; g2.sC[1] = 2L * da2 * db2; g2.sC[2] = (long)da2 * db2;
+    gemm(c, g2);
+  }
+
+  // Rb[(a,b)][(t,t'',c'')] = sum_{a'',b'',t'} A_j[a][t][t'][a''] A_j[b][t'][t''][b''] F[a''][b''][c'']
+  void right_block(int j, const double* F, double* out) {
+    const int da = Da[j], db = Da[j], da2 = Da[j + 1], db2 = Da[j + 1], dc2 = Dc[j + 1];
+    double* Z = c->need("X", (size_t)4 * da * db2 * dc2);
+    gemm(c, plain(4 * da, db2 * dc2, da2, A[j], da2, false, F, (long)db2 * dc2, false, Z, (long)db2 * dc2));
+    Gemm g;    // batch (a, t, t''): Rb[a][b][t][t''][c''] = sum_{(t',b'')} Bp[b][t''][(t',b'')] Z[a][t][(t',b'')][c'']
+    g.M = db; g.N = dc2; g.K = 2 * db2;
+    g.A = Bp[j]; g.lda = 4 * db2;
+    g.B = Z; g.ldb = dc2;
+    g.C = out; g.ldc = 4 * dc2;
+    g.nb[0] = da; g.nb[1] = 2; g.nb[2] = 2;
+    g.sA[2] = 2L * db2;
+    g.sB[0] = 4L * db2 * dc2; g.sB[1] = 2L * db2 * dc2;
+    g.sC[0] = 4L * db * dc2; g.sC[1] = 2L * dc2; g.sC[2] = dc2;
+    gemm(c, g);
+  }
+
+  static double step_flops(int dc, int da, int db, int da2, int db2, int dc2) {
+    const double k1 = 2.0 * dc * db * da * 4 * da2;
+    const double k2 = 2.0 * dc * 2 * da2 * db * 4 * db2;
+    const double th = 2.0 * (4.0 * dc) * ((double)da2 * db2) * (4.0 * dc2);
+    const double k3 = 2.0 * da2 * db2 * (4.0 * dc) * dc;
+    return k1 + k2 + th + k3;
+  }
+};
+
+void square_compress_impl(xtrg_ctx c, xtrg_mpo in, const xtrg_compress_opts& o, xtrg_mpo* out,
+                          xtrg_compress_info* info) {
+  const int L = in->L;
+  if (L < 2) throw Error(XTRG_EINVAL, "square_compress needs at least two sites");
+  if (o.D_max < 1 || o.n_sweeps < 1) throw Error(XTRG_EINVAL, "D_max and n_sweeps must be >= 1");
+  if (o.precision != XTRG_FP64) throw Error(XTRG_EINVAL, "only XTRG_FP64 is available");
+  hipStream_t s = c->stream;
+  Doubler d;
+  d.c = c;
+  d.L = L;
+  d.Da = in->dims;
+  d.Dc = in->dims;                         // initial guess C = rho (right-canonical)
+  d.cap.resize(L + 1);
+  for (int i = 0; i <= L; ++i) {
+    double cp = 1.0;
+    for (int q = 0; q < std::min(i, L - i) && cp < 1e9; ++q) cp *= 4.0;
+    d.cap[i] = (int)std::min<double>(cp, (double)std::max(o.D_max, in->dims[i]));
+  }
+  d.A.resize(L);
+  d.Bp.resize(L);
+  d.C.resize(L);
+  d.slot.resize(L);
+  for (int i = 0; i < L; ++i) {
+    d.A[i] = in->site[i].p;
+    d.Bp[i] = c->need("Bp" + std::to_string(i), in->elems(i));
+    xtrg::swap_phys(d.Bp[i], in->site[i].p, in->dims[i], in->dims[i + 1], s);
+    d.C[i].n = (size_t)d.cap[i] * 4 * d.cap[i + 1];
+    d.C[i].p = c->need("C" + std::to_string(i), d.C[i].n);
+    xtrg::copy(d.C[i].p, in->site[i].p, in->elems(i), s);
+  }
+  size_t env_max = 1;
+  for (int i = 0; i <= L; ++i) env_max = std::max(env_max, (size_t)d.cap[i] * d.Da[i] * d.Da[i]);
+  double* E = c->need("E", env_max);
+  double* F = c->need("F", env_max);
+  xtrg::fill(E, 1.0, 1, s);
+  xtrg::fill(F, 1.0, 1, s);
+  auto lb_size = [&](int i) { return (size_t)4 * d.cap[i] * d.Da[i + 1] * d.Da[i + 1]; };
+  auto rb_size = [&](int j) { return (size_t)d.Da[j] * d.Da[j] * 4 * d.cap[j + 1]; };
+
+  // static right blocks Rb_j, j = L-1 .. 1, from C = rho (the first
+  // left-to-right half-sweep reads Rb_{i+1} for every bond i)
+  for (int j = L - 1; j >= 1; --j) {
+    double* Rb = d.slot_need(j, std::max(lb_size(j), rb_size(j)));
+    d.right_block(j, F, Rb);
+    if (j == 1) break;
+    const int mR = 4 * d.Dc[j + 1];
+    const int k = d.Dc[j];
+    gemm(c, plain(d.Da[j] * d.Da[j], k, mR, Rb, mR, false, d.C[j].p, mR, true, F, k));
+  }
+
+  const auto sched = schedule(L, o.n_sweeps);
+  std::vector<std::vector<double>> sv(L - 1);
+  std::vector<int> kept(L - 1, 1);
+  std::vector<double> disc(L - 1, 0.0);
+  double flops = 0.0;
+  double last_norm = 0.0;
+  for (size_t st = 0; st < sched.size(); ++st) {
+    const int i = sched[st].bond;
+    const bool final_step = st + 1 == sched.size();
+    bool gauge_right = (sched[st].dir > 0) != (sched[st].last && !final_step);
+    if (final_step) gauge_right = false;
+    double* Lb;
+    double* Rb;
+    const int mL = 4 * d.Dc[i], mR = 4 * d.Dc[i + 2];
+    const int Kt = d.Da[i + 1] * d.Da[i + 1];
+    const double sflops = Doubler::step_flops(d.Dc[i], d.Da[i], d.Da[i], d.Da[i + 1], d.Da[i + 1], d.Dc[i + 2]);
+    flops += sflops;
+    {
+      // left block: 8 Dc Da Db Da' + 16 Dc Da' Db Db' (two substeps of Fig. VMPO(c));
+      // the right block mirrors it with the right bond of C
+      double fb;
+      if (sched[st].dir > 0)
+        fb = 8.0 * d.Dc[i] * d.Da[i] * (double)d.Da[i] * d.Da[i + 1] +
+             16.0 * d.Dc[i] * d.Da[i + 1] * (double)d.Da[i] * d.Da[i + 1];
+      else
+        fb = 8.0 * d.Dc[i + 2] * d.Da[i + 2] * (double)d.Da[i + 2] * d.Da[i + 1] +
+             16.0 * d.Dc[i + 2] * d.Da[i + 1] * (double)d.Da[i + 2] * d.Da[i + 1];
+      Timed tm(c, P_BLOCK, fb, 0.0);
+      if (sched[st].dir > 0) {
+        Lb = d.slot_need(i, std::max(lb_size(i), rb_size(i)));
+        d.left_block(i, E, Lb);
+        Rb = d.slot[i + 1].p;
+      } else {
+        Rb = d.slot_need(i + 1, std::max(lb_size(i + 1), rb_size(i + 1)));
+        d.right_block(i + 1, F, Rb);
+        Lb = d.slot[i].p;
+      }
+    }
+    double* th = c->need("theta", (size_t)mL * mR);
+    const int len = gauge_right ? mL : mR, p = gauge_right ? mR : mL;
+    {
+      Timed tm(c, P_THETA, 2.0 * mL * (double)mR * Kt, 8.0 * ((double)mL * Kt + (double)Kt * mR + (double)mL * mR));
+      Gemm g = gauge_right ? plain(mR, mL, Kt, Rb, mR, true, Lb, Kt, true, th, mL)    // theta column-major
+                           : plain(mL, mR, Kt, Lb, Kt, false, Rb, mR, false, th, mR);  // theta row-major
+      g.tag = 1;
+      gemm(c, g);
+    }
+    double* work = c->need("svd", xtrg::svd_work(len, p));
+    {
+      Timed tm(c, P_SVD, 0.0, 8.0 * len * (double)p);
+      xtrg::svd_left(len, p, th, nullptr, 0, nullptr, 0, 0, work, s, nullptr);
+    }
+    std::vector<double> S = read_vec(c, xtrg::svd_sorted_values(work, len, p), p);
+    S.resize(std::min(mL, mR));
+    for (double v : S)
+      if (!std::isfinite(v)) throw Error(XTRG_ENUMERIC, "non-finite singular value");
+    const int k = keep_count(S, o.D_max, o.degen_rtol, o.sv_floor, noise_floor(c, work, len, p));
+    double tot = 0.0, kw = 0.0;
+    for (size_t q = 0; q < S.size(); ++q) {
+      tot += S[q] * S[q];
+      if ((int)q < k) kw += S[q] * S[q];
+    }
+    if (!(tot > 0)) throw Error(XTRG_ENUMERIC, "zero two-site tensor");
+    sv[i] = S;
+    kept[i] = k;
+    disc[i] = (tot - kw) / tot;
+    last_norm = std::sqrt(kw);
+    double* Ci = d.C[i].p;
+    double* Cn = d.C[i + 1].p;
+    if (gauge_right) {
+      {
+        Timed tm(c, P_SPLIT, 2.0 * k * (double)mL * mR, 0.0);
+        xtrg::svd_gather(len, p, work, k, Ci, k, 1, s);                                 // C_i = U [mL][k]
+        orthonormalize(c, Ci, mL, k, true);
+        gemm(c, plain(k, mR, mL, Ci, k, true, th, mL, true, Cn, mR));                  // C_{i+1} = U^T theta
+      }
+      Timed tm(c, P_ENV, 2.0 * k * (double)Kt * mL, 8.0 * ((double)mL * Kt + (double)k * Kt));
+      gemm(c, plain(k, Kt, mL, Ci, k, true, Lb, Kt, false, E, Kt));                    // E_{i+1} = C_i^T Lb
+    } else {
+      {
+        Timed tm(c, P_SPLIT, 2.0 * k * (double)mL * mR, 0.0);
+        xtrg::svd_gather(len, p, work, k, Cn, len, 0, s);                              // C_{i+1} = V^T [k][mR]
+        orthonormalize(c, Cn, mR, k, false);
+        gemm(c, plain(mL, k, mR, th, mR, false, Cn, mR, true, Ci, k));                 // C_i = theta V
+      }
+      Timed tm(c, P_ENV, 2.0 * k * (double)Kt * mR, 8.0 * ((double)mR * Kt + (double)k * Kt));
+      gemm(c, plain(d.Da[i + 1] * d.Da[i + 1], k, mR, Rb, mR, false, Cn, mR, true, F, k));  // F_{i+1}
+    }
+    d.Dc[i + 1] = k;
+  }
+  // normalise: the centre is site 0 after the final right-to-left step
+  const double cnorm = last_norm;
+  xtrg::scale(d.C[0].p, 1.0 / cnorm, (size_t)4 * d.Dc[1], s);
+  auto m = new_mpo(c, d.Dc);
+  for (int i = 0; i < L; ++i) xtrg::copy(m->site[i].p, d.C[i].p, m->elems(i), s);
+  XTRG_HIP(hipStreamSynchronize(s));
+  // free the per-site caches of this call (slots); keep the named workspaces
+  for (auto& b : d.slot) c->release(b.p, b.cap);
+  if (info) {
+    info->dlog_norm = std::log(cnorm);
+    info->trunc_err_max = *std::max_element(disc.begin(), disc.end());
+    info->sweeps_done = o.n_sweeps;
+    info->D_kept_max = *std::max_element(d.Dc.begin(), d.Dc.end());
+    info->steps = (int)sched.size();
+    info->flops = flops;
+    if (info->sv && info->sv_stride > 0)
+      for (int b = 0; b < L - 1; ++b)
+        for (int q = 0; q < info->sv_stride; ++q)
+          info->sv[(size_t)b * info->sv_stride + q] = q < (int)sv[b].size() ? sv[b][q] : 0.0;
+  }
+  *out = m.release();
+}
+
+// ---------------------------------------------------------------------------
+// Observables: traces of MPO products by environment contractions
+// ---------------------------------------------------------------------------
+
+struct Named {
+  std::vector<std::string> name;
+  std::vector<int> ext;
+  long size() const {
+    long n = 1;
+    for (int e : ext) n *= e;
+    return n;
+  }
+  long stride(const std::string& nm) const {   // sum over repeated names (diagonal)
+    long st = 1, out = 0;
+    for (int d = (int)name.size() - 1; d >= 0; --d) {
+      if (name[d] == nm) out += st;
+      st *= ext[d];
+    }
+    return out;
+  }
+  int extent(const std::string& nm) const {
+    for (size_t d = 0; d < name.size(); ++d)
+      if (name[d] == nm) return ext[d];
+    throw Error(XTRG_EINVAL, "internal: no dim " + nm);
+  }
+};
+
+// out (row-major in `outd` order) = sum over `sum` of T * W
+void contract_named(const Named& T, const double* Tp, const Named& W, const double* Wp, const Named& outd,
+                    double* outp, const std::vector<std::string>& sum, hipStream_t s) {
+  xtrg::Contract k;
+  k.n_out = (int)outd.name.size();
+  if (k.n_out > 6 || sum.size() > 3) throw Error(XTRG_EINVAL, "internal: contraction too wide");
+  for (int d = 0; d < k.n_out; ++d) {
+    k.oe[d] = outd.ext[d];
+    k.ots[d] = T.stride(outd.name[d]);
+    k.ows[d] = W.stride(outd.name[d]);
+  }
+  k.n_c = (int)sum.size();
+  for (size_t q = 0; q < sum.size(); ++q) {
+    int e = 0;
+    for (size_t d = 0; d < T.name.size(); ++d)
+      if (T.name[d] == sum[q]) e = T.ext[d];
+    if (!e) e = W.extent(sum[q]);
+    k.ce[q] = e;
+    k.cts[q] = T.stride(sum[q]);
+    k.cws[q] = W.stride(sum[q]);
+  }
+  k.T = Tp;
+  k.W = Wp;
+  k.out = outp;
+  xtrg::contract(k, s);
+}
+
+// Tr(M_1 M_2 ... M_k) for k <= 4; trans[j]: use M_j^T.
+double trace_chain(xtrg_ctx c, const std::vector<xtrg_mpo>& M, const std::vector<bool>& trans) {
+  const int k = (int)M.size();
+  const int L = M[0]->L;
+  hipStream_t s = c->stream;
+  auto bname = [](const char* p, int j) { return std::string(p) + std::to_string(j); };
+  size_t cap = 1;   // largest intermediate: open a's of site i, b's of site i+1, two physical indices
+  for (int i = 0; i < L; ++i)
+    for (int j = 0; j < k; ++j) {
+      size_t e = 4;
+      for (int q = 0; q < k; ++q) e *= (size_t)(q > j ? M[q]->dims[i] : M[q]->dims[i + 1]);
+      cap = std::max(cap, e);
+    }
+  double* bufA = c->need("tr_a", cap);
+  double* bufB = c->need("tr_b", cap);
+  Named E;
+  for (int j = 0; j < k; ++j) {
+    E.name.push_back(bname("a", j));
+    E.ext.push_back(1);
+  }
+  xtrg::fill(bufA, 1.0, 1, s);
+  double* cur = bufA;
+  double* nxt = bufB;
+  for (int i = 0; i < L; ++i) {
+    // T_0 = E with dims a_0..a_{k-1}
+    Named T = E;
+    for (int j = 0; j < k; ++j) {
+      Named W;
+      const int Dl = M[j]->dims[i], Dr = M[j]->dims[i + 1];
+      // physical: output index s_j, input index s_{j+1}; transposed swaps them
+      const std::string so = "s" + std::to_string(j);
+      const std::string si = (j + 1 < k) ? "s" + std::to_string(j + 1) : "s0";
+      W.name = {bname("a", j), trans[j] ? si : so, trans[j] ? so : si, bname("b", j)};
+      W.ext = {Dl, 2, 2, Dr};
+      Named O;
+      std::vector<std::string> sum = {bname("a", j)};
+      if (j > 0) sum.push_back(so);
+      if (j + 1 == k && k > 1) sum.push_back("s0");
+      if (k == 1) sum.push_back("s0");           // W has s0 twice: the diagonal
+      // output dims: remaining a's, s0 (if still open), b_0..b_j, s_{j+1} (if open)
+      for (int q = j + 1; q < k; ++q) {
+        O.name.push_back(bname("a", q));
+        O.ext.push_back(M[q]->dims[i]);
+      }
+      if (j + 1 < k) {
+        O.name.push_back("s0");
+        O.ext.push_back(2);
+      }
+      for (int q = 0; q <= j; ++q) {
+        O.name.push_back(bname("b", q));
+        O.ext.push_back(M[q]->dims[i + 1]);
+      }
+      if (j + 1 < k) {
+        O.name.push_back(si);
+        O.ext.push_back(2);
+      }
+      if (j == 0 && k > 1) {
+        // s0 is an output index of W_0 here, not summed
+      }
+      contract_named(T, cur, W, M[j]->site[i].p, O, nxt, sum, s);
+      std::swap(cur, nxt);
+      T = O;
+    }
+    // rename b -> a for the next site
+    E = T;
+    for (auto& nm : E.name) nm[0] = 'a';
+  }
+  return read_scalar(c, cur);
+}
+
+void observables_impl(xtrg_ctx c, xtrg_mpo rho, double lam, double tau, xtrg_mpo H, int n_sites,
+                      xtrg_obs* at_tau, xtrg_obs* at_2tau, double* SE) {
+  if (H->L != rho->L) throw Error(XTRG_EINVAL, "H and rho differ in length");
+  if (n_sites <= 0) n_sites = rho->L;
+  const double N = n_sites;
+  if (at_tau) {
+    const double tr = trace_chain(c, {rho}, {false});
+    if (!(tr > 0)) throw Error(XTRG_ENUMERIC, "Tr rho <= 0");
+    const double e1 = trace_chain(c, {H, rho}, {false, false}) / tr;
+    const double e2 = trace_chain(c, {H, H, rho}, {false, false, false}) / tr;
+    const double b = tau, lnZ = lam + std::log(tr);
+    *at_tau = xtrg_obs{b, lnZ, -lnZ / (N * b), e1 / N, b * b * (e2 - e1 * e1) / N, tr, 0.0, 0.0};
+  }
+  double Sc = 0.0, Smax = 0.0;
+  if (SE || at_2tau) {
+    auto m = clone(rho);
+    left_sweep(m.get(), 0.0, nullptr);
+    std::vector<std::vector<double>> sv;
+    right_sweep(m.get(), 0.0, 0, &sv);
+    for (int bnd = 0; bnd + 1 < rho->L; ++bnd) {
+      double tot = 0.0;
+      for (double v : sv[bnd]) tot += v * v;
+      double e = 0.0;
+      for (double v : sv[bnd]) {
+        const double q = v * v / tot;
+        if (q > 0) e -= q * std::log(q);
+      }
+      if (SE) SE[bnd] = e;
+      Smax = std::max(Smax, e);
+      if (bnd == (rho->L - 1) / 2) Sc = e;
+    }
+  }
+  if (at_2tau) {
+    const double nrm = trace_chain(c, {rho, rho}, {true, false});
+    if (!(nrm > 0)) throw Error(XTRG_ENUMERIC, "||rho|| = 0");
+    const double g1 = trace_chain(c, {H, rho, rho}, {false, true, false}) / nrm;
+    const double g2 = trace_chain(c, {H, H, rho, rho}, {false, false, true, false}) / nrm;
+    const double b = 2 * tau, lnZ = 2 * lam + std::log(nrm);
+    *at_2tau = xtrg_obs{b, lnZ, -lnZ / (N * b), g1 / N, b * b * (g2 - g1 * g1) / N, nrm, Sc, Smax};
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+int xtrg_ctx_create(int device, void* hip_stream, size_t hbm_budget, xtrg_ctx* out) {
+  if (!out) return XTRG_EINVAL;
+  *out = nullptr;
+  auto c = new xtrg_ctx_s();
+  c->device = device;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  c->budget = hbm_budget;
+  const int rc = guarded(c, [&] {
+    int n = 0;
+    XTRG_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) throw Error(XTRG_EINVAL, "no such device");
+    set_device(c);
+    c->scratch = c->alloc(2048);
+  });
+  if (rc != XTRG_OK) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return XTRG_OK;
+}
+
+int xtrg_ctx_destroy(xtrg_ctx c) {
+  if (!c) return XTRG_EINVAL;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  for (auto& kv : c->ws) c->release(kv.second.p, kv.second.cap);
+  c->release(c->scratch, 2048);
+  delete c;
+  return XTRG_OK;
+}
+
+const char* xtrg_last_error(xtrg_ctx c) { return c ? c->err.c_str() : "null context"; }
+
+size_t xtrg_ctx_bytes(xtrg_ctx c) { return c ? c->bytes : 0; }
+
+int xtrg_hamiltonian_xxz(xtrg_ctx c, int n_sites, int n_bonds, const int* bonds, const double* jxy,
+                         const double* jz, xtrg_mpo* H_out) {
+  if (!c || !H_out || n_sites < 2 || n_bonds < 0 || (n_bonds > 0 && (!bonds || !jxy || !jz)))
+    return XTRG_EINVAL;
+  return guarded(c, [&] {
+    set_device(c);
+    Automaton A = build_automaton(n_sites, n_bonds, bonds, jxy, jz);
+    const double r[2] = {0.0, 1.0};   // stop state: H
+    std::vector<int> dims;
+    auto S = cap(A, r, &dims);
+    auto m = new_mpo(c, dims);
+    for (int i = 0; i < n_sites; ++i) upload(c, m->site[i].p, S[i].data(), S[i].size());
+    m->has_open = true;
+    m->open_last = A.T[n_sites - 1];
+    XTRG_HIP(hipStreamSynchronize(c->stream));
+    *H_out = m.release();
+  });
+}
+
+int xtrg_mpo_from_host(xtrg_ctx c, int L, int d, const int* bond_dims, const double* const* site_tensors,
+                       xtrg_mpo* out) {
+  if (!c || !out || L < 1 || d != 2 || !bond_dims || !site_tensors) return XTRG_EINVAL;
+  return guarded(c, [&] {
+    set_device(c);
+    std::vector<int> dims(bond_dims, bond_dims + L + 1);
+    if (dims[0] != 1 || dims[L] != 1) throw Error(XTRG_EINVAL, "outer bonds must be 1");
+    for (int v : dims)
+      if (v < 1) throw Error(XTRG_EINVAL, "bond dimension < 1");
+    auto m = new_mpo(c, dims);
+    for (int i = 0; i < L; ++i) {
+      if (!site_tensors[i]) throw Error(XTRG_EINVAL, "null site tensor");
+      upload(c, m->site[i].p, site_tensors[i], m->elems(i));
+    }
+    XTRG_HIP(hipStreamSynchronize(c->stream));
+    *out = m.release();
+  });
+}
+
+int xtrg_mpo_shape(xtrg_mpo m, int* L, int* bond_dims) {
+  if (!m) return XTRG_EINVAL;
+  if (L) *L = m->L;
+  if (bond_dims) std::copy(m->dims.begin(), m->dims.end(), bond_dims);
+  return XTRG_OK;
+}
+
+int xtrg_mpo_to_host(xtrg_mpo m, double* const* site_tensors) {
+  if (!m || !site_tensors) return XTRG_EINVAL;
+  xtrg_ctx c = m->ctx;
+  return guarded(c, [&] {
+    set_device(c);
+    for (int i = 0; i < m->L; ++i) {
+      if (!site_tensors[i]) throw Error(XTRG_EINVAL, "null site tensor");
+      XTRG_HIP(hipMemcpyAsync(site_tensors[i], m->site[i].p, m->elems(i) * sizeof(double),
+                              hipMemcpyDeviceToHost, c->stream));
+    }
+    XTRG_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+int xtrg_mpo_destroy(xtrg_mpo m) {
+  if (!m) return XTRG_EINVAL;
+  (void)hipSetDevice(m->ctx->device);
+  (void)hipStreamSynchronize(m->ctx->stream);
+  delete m;
+  return XTRG_OK;
+}
+
+int xtrg_init_rho(xtrg_ctx c, xtrg_mpo H, double tau0, int order, int D0_max, xtrg_mpo* rho_out,
+                  double* log_norm) {
+  if (!c || !H || !rho_out || !log_norm || !(tau0 > 0) || order < 1 || order > 2) return XTRG_EINVAL;
+  if (!H->has_open) return XTRG_EINVAL;
+  return guarded(c, [&] {
+    set_device(c);
+    hipStream_t s = c->stream;
+    const int L = H->L;
+    // The right end of the automaton is left open over {start, stop}; a
+    // right boundary r selects r_start * I + r_stop * H (App. B.1, App. C.2).
+    std::unique_ptr<xtrg_mpo_s> m;
+    if (order == 1) {
+      std::vector<int> dims = H->dims;
+      m = new_mpo(c, dims);
+      for (int i = 0; i + 1 < L; ++i) xtrg::copy(m->site[i].p, H->site[i].p, H->elems(i), s);
+      const int Dl = H->dims[L - 1];
+      std::vector<double> last((size_t)Dl * 4);
+      for (size_t q = 0; q < last.size(); ++q)
+        last[q] = H->open_last[2 * q + 0] * 1.0 + H->open_last[2 * q + 1] * (-tau0);
+      upload(c, m->site[L - 1].p, last.data(), last.size());
+    } else {
+      // exact product of two automata; each factor ends in start (I) or stop (H):
+      // weights r[(x,y)] with x,y in {start, stop} give I - tau H + tau^2/2 H^2
+      std::vector<int> dims(L + 1);
+      for (int i = 0; i <= L; ++i) dims[i] = H->dims[i] * H->dims[i];
+      dims[L] = 1;
+      m = new_mpo(c, dims);
+      for (int i = 0; i + 1 < L; ++i)
+        xtrg::site_product(m->site[i].p, H->site[i].p, H->dims[i], H->dims[i + 1], H->site[i].p, H->dims[i],
+                           H->dims[i + 1], s);
+      const int Dl = H->dims[L - 1];
+      double* openp = c->need("init_open", (size_t)Dl * 4 * 2);
+      upload(c, openp, H->open_last.data(), H->open_last.size());
+      double* prod = c->need("init_prod", (size_t)Dl * Dl * 4 * 4);
+      xtrg::site_product(prod, openp, Dl, 2, openp, Dl, 2, s);     // [(a,b)][s][u][(x,y)]
+      const double r[4] = {1.0, -0.5 * tau0, -0.5 * tau0, 0.5 * tau0 * tau0};
+      double* rv = c->need("init_r", 4);
+      upload(c, rv, r, 4);
+      gemm(c, plain(Dl * Dl * 4, 1, 4, prod, 4, false, rv, 1, false, m->site[L - 1].p, 1));
+    }
+    // lossless compression to canonical form: exact zeros dropped
+    left_sweep(m.get(), 1e-14, nullptr);
+    right_sweep(m.get(), 1e-14, D0_max, nullptr);
+    const double nrm = site_norm(m.get(), 0);
+    if (!(nrm > 0) || !std::isfinite(nrm)) throw Error(XTRG_ENUMERIC, "rho(tau0) has zero norm");
+    xtrg::scale(m->site[0].p, 1.0 / nrm, m->elems(0), s);
+    XTRG_HIP(hipStreamSynchronize(s));
+    *log_norm = std::log(nrm);
+    // shrink the buffers to the final shapes
+    auto fin = clone(m.get());
+    XTRG_HIP(hipStreamSynchronize(s));
+    *rho_out = fin.release();
+  });
+}
+
+int xtrg_square_compress(xtrg_ctx c, xtrg_mpo rho_in, const xtrg_compress_opts* opts, xtrg_mpo* rho_out,
+                         xtrg_compress_info* info) {
+  if (!c || !rho_in || !opts || !rho_out) return XTRG_EINVAL;
+  return guarded(c, [&] {
+    set_device(c);
+    square_compress_impl(c, rho_in, *opts, rho_out, info);
+  });
+}
+
+int xtrg_observables(xtrg_ctx c, xtrg_mpo rho, double log_norm, double tau_n, xtrg_mpo H, int n_sites,
+                     xtrg_obs* at_tau, xtrg_obs* at_2tau, double* S_E_per_bond) {
+  if (!c || !rho || !H || !(tau_n > 0)) return XTRG_EINVAL;
+  return guarded(c, [&] {
+    set_device(c);
+    observables_impl(c, rho, log_norm, tau_n, H, n_sites, at_tau, at_2tau, S_E_per_bond);
+  });
+}
+
+int xtrg_profile_enable(xtrg_ctx c, int on) {
+  if (!c) return XTRG_EINVAL;
+  c->prof = on != 0;
+  return XTRG_OK;
+}
+
+int xtrg_profile_report(xtrg_ctx c, char* buf, size_t cap) {
+  if (!c || !buf || cap == 0) return XTRG_EINVAL;
+  return guarded(c, [&] {
+    set_device(c);
+    XTRG_HIP(hipStreamSynchronize(c->stream));
+    double ms[P_NCAT] = {0}, fl[P_NCAT] = {0}, by[P_NCAT] = {0};
+    long n[P_NCAT] = {0};
+    for (auto& r : c->prof_recs) {
+      float t = 0.f;
+      XTRG_HIP(hipEventElapsedTime(&t, r.a, r.b));
+      ms[r.cat] += t;
+      fl[r.cat] += r.flops;
+      by[r.cat] += r.bytes;
+      n[r.cat] += 1;
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    c->prof_recs.clear();
+    std::string out = "{";
+    for (int q = 0; q < P_NCAT; ++q) {
+      char tmp[256];
+      std::snprintf(tmp, sizeof tmp, "%s\"%s\": {\"ms\": %.6f, \"calls\": %ld, \"flops\": %.6e, \"bytes\": %.6e}",
+                    q ? ", " : "", kPhase[q], ms[q], n[q], fl[q], by[q]);
+      out += tmp;
+    }
+    out += "}";
+    if (out.size() + 1 > cap) throw Error(XTRG_EINVAL, "profile report buffer too small");
+    std::memcpy(buf, out.c_str(), out.size() + 1);
+  });
+}
+
+int xtrg_dgemm(xtrg_ctx c, int M, int N, int K, int transA, int transB, const double* A, long lda,
+               const double* B, long ldb, double* C, long ldc) {
+  if (!c || M < 0 || N < 0 || K < 0 || (M * (long)N > 0 && (!A || !B || !C))) return XTRG_EINVAL;
+  return guarded(c, [&] {
+    set_device(c);
+    gemm(c, plain(M, N, K, A, lda, transA != 0, B, ldb, transB != 0, C, ldc));
+    XTRG_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+int xtrg_dsvd_left(xtrg_ctx c, int len, int p, const double* Y, double* sigma, int k, double* U) {
+  if (!c || len < 0 || p < 0 || k < 0 || k > p || (len * (long)p > 0 && !Y)) return XTRG_EINVAL;
+  return guarded(c, [&] {
+    set_device(c);
+    double* work = c->need("svd", xtrg::svd_work(len, p));
+    xtrg::svd_left(len, p, Y, sigma, k, U, len, 0, work, c->stream, nullptr);
+    if (k > 0 && U) orthonormalize(c, U, len, k, false);
+    XTRG_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,234 @@
+// Batched strided FP64 GEMM on CDNA4 matrix cores (v_mfma_f64_16x16x4f64).
+//
+// Workgroup = 4 waves (256 threads) in a 2 x 2 arrangement; each wave owns a
+// (BM/2) x (BN/2) block of C made of 16 x 16 MFMA tiles.  K is consumed in
+// steps of 16: the A and B tiles are staged through LDS with k as the slow
+// index so that every MFMA operand read is 16 consecutive doubles per lane
+// group.  The next K tile is fetched into registers while the current one
+// is multiplied.
+#include "internal.h"
+
+namespace xtrg {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int BK = 16;
+
+// TAG only separates kernel symbols (1 = two-site overlap C_E) for profilers.
+template <int BM, int BN, bool TA, bool TB, int TAG>
+__global__ __launch_bounds__(256) void dgemm_kernel(Gemm g, int splitk, int kchunk, double* work) {
+  constexpr int WM = BM / 2, WN = BN / 2;     // wave tile
+  constexpr int TM = WM / 16, TN = WN / 16;   // MFMA tiles per wave
+  constexpr int LA = BM * BK / 256;           // doubles of A per thread per K tile
+  constexpr int LB = BN * BK / 256;
+  constexpr int PAD = 4;
+  __shared__ double As[BK][BM + PAD];
+  __shared__ double Bs[BK][BN + PAD];
+
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  int z = blockIdx.z;
+  const int ks = z % splitk;
+  z /= splitk;
+  const int b2 = z % g.nb[2];
+  const int b1 = (z / g.nb[2]) % g.nb[1];
+  const int b0 = z / (g.nb[2] * g.nb[1]);
+  const double* __restrict__ A = g.A + b0 * g.sA[0] + b1 * g.sA[1] + b2 * g.sA[2];
+  const double* __restrict__ B = g.B + b0 * g.sB[0] + b1 * g.sB[1] + b2 * g.sB[2];
+
+  const int m0 = blockIdx.y * BM;
+  const int n0 = blockIdx.x * BN;
+  const int kbeg = ks * kchunk;
+  const int kend = min(g.K, kbeg + kchunk);
+  const int M = g.M, N = g.N;
+
+  double ra[LA], rb[LB];
+
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int c = 0; c < LA / 4; ++c) {
+      if (!TA) {            // A[m*lda + k]: thread -> (row, 4 consecutive k)
+        const int m = m0 + (t >> 2) + 64 * c;
+        const int k = k0 + (t & 3) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          ra[4 * c + j] = (m < M && k + j < kend) ? A[(long)m * g.lda + k + j] : 0.0;
+      } else {              // A[k*lda + m]: thread -> (k row, 4 consecutive m)
+        const int k = k0 + (t >> 4);
+        const int m = m0 + (t & 15) * 4 + 64 * c;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          ra[4 * c + j] = (k < kend && m + j < M) ? A[(long)k * g.lda + m + j] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < LB / 4; ++c) {
+      if (!TB) {            // B[k*ldb + n]
+        const int k = k0 + (t >> 4);
+        const int n = n0 + (t & 15) * 4 + 64 * c;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          rb[4 * c + j] = (k < kend && n + j < N) ? B[(long)k * g.ldb + n + j] : 0.0;
+      } else {              // B[n*ldb + k]
+        const int n = n0 + (t >> 2) + 64 * c;
+        const int k = k0 + (t & 3) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          rb[4 * c + j] = (n < N && k + j < kend) ? B[(long)n * g.ldb + k + j] : 0.0;
+      }
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int c = 0; c < LA / 4; ++c) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (!TA) As[(t & 3) * 4 + j][(t >> 2) + 64 * c] = ra[4 * c + j];
+        else     As[t >> 4][(t & 15) * 4 + 64 * c + j] = ra[4 * c + j];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < LB / 4; ++c) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (!TB) Bs[t >> 4][(t & 15) * 4 + 64 * c + j] = rb[4 * c + j];
+        else     Bs[(t & 3) * 4 + j][(t >> 2) + 64 * c] = rb[4 * c + j];
+      }
+    }
+  };
+
+  d4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const int lr = lane & 15, lk = lane >> 4;
+  if (kbeg < kend) {
+    load(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+      __syncthreads();
+      stash();
+      __syncthreads();
+      if (k0 + BK < kend) load(k0 + BK);
+#pragma unroll
+      for (int kk = 0; kk < BK / 4; ++kk) {
+        double a[TM], b[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) a[i] = As[kk * 4 + lk][wm * WM + i * 16 + lr];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) b[j] = Bs[kk * 4 + lk][wn * WN + j * 16 + lr];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+    }
+  }
+
+  // Output of v_mfma_f64_16x16x4f64: register r of lane l holds row l/16 + 4r,
+  // column l%16 of the 16x16 tile.
+  double* __restrict__ C;
+  long ldc;
+  if (splitk > 1) {
+    C = work + (long)ks * M * N;
+    ldc = N;
+  } else {
+    C = g.C + b0 * g.sC[0] + b1 * g.sC[1] + b2 * g.sC[2];
+    ldc = g.ldc;
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int col = n0 + wn * WN + j * 16 + lr;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * WM + i * 16 + lk + 4 * r;
+        if (row < M && col < N) C[(long)row * ldc + col] = acc[i][j][r];
+      }
+    }
+}
+
+// Deterministic split-K reduction: C[row*ldc + col] = sum_ks work[ks][row][col].
+__global__ void splitk_reduce(const double* __restrict__ work, int splitk, int M, int N,
+                              double* __restrict__ C, long ldc) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long MN = (long)M * N;
+  if (idx >= MN) return;
+  double s = 0.0;
+  for (int k = 0; k < splitk; ++k) s += work[k * MN + idx];
+  const int row = (int)(idx / N), col = (int)(idx % N);
+  C[(long)row * ldc + col] = s;
+}
+
+namespace {
+
+template <int BM, int BN, int TAG>
+void launch(const Gemm& g, int splitk, int kchunk, double* work, hipStream_t s) {
+  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.nb[0] * g.nb[1] * g.nb[2] * splitk);
+  dim3 block(256);
+  if (!g.transA && !g.transB)
+    hipLaunchKernelGGL((dgemm_kernel<BM, BN, false, false, TAG>), grid, block, 0, s, g, splitk, kchunk, work);
+  else if (g.transA && !g.transB)
+    hipLaunchKernelGGL((dgemm_kernel<BM, BN, true, false, TAG>), grid, block, 0, s, g, splitk, kchunk, work);
+  else if (!g.transA && g.transB)
+    hipLaunchKernelGGL((dgemm_kernel<BM, BN, false, true, TAG>), grid, block, 0, s, g, splitk, kchunk, work);
+  else
+    hipLaunchKernelGGL((dgemm_kernel<BM, BN, true, true, TAG>), grid, block, 0, s, g, splitk, kchunk, work);
+  XTRG_HIP(hipGetLastError());
+}
+
+int choose_splitk(const Gemm& g, bool big) {
+  const long batch = (long)g.nb[0] * g.nb[1] * g.nb[2];
+  if (batch != 1) return 1;
+  const int bm = big ? 128 : 64, bn = big ? 128 : 64;
+  const long tiles = (long)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);
+  const long target = 1024;   // workgroups to fill 256 CUs several times over
+  if (tiles >= target || g.K < 1024) return 1;
+  long sk = (target + tiles - 1) / tiles;
+  sk = std::min<long>(sk, g.K / 512);
+  sk = std::min<long>(sk, 64);
+  return (int)std::max<long>(sk, 1);
+}
+
+bool use_big(const Gemm& g) { return g.M >= 128 && g.N >= 128; }
+
+}  // namespace
+
+size_t gemm_splitk_work(const Gemm& g) {
+  const int sk = choose_splitk(g, use_big(g));
+  return sk > 1 ? (size_t)sk * g.M * g.N : 0;
+}
+
+void gemm(const Gemm& g, hipStream_t s, double* work, size_t work_cap) {
+  if (g.M <= 0 || g.N <= 0) return;
+  const bool big = use_big(g);
+  int sk = choose_splitk(g, big);
+  if (sk > 1 && (work == nullptr || work_cap < (size_t)sk * g.M * g.N)) sk = 1;
+  if (g.K <= 0) sk = 1;
+  int kchunk = g.K;
+  if (sk > 1) {
+    kchunk = ((g.K + sk - 1) / sk + BK - 1) / BK * BK;
+    sk = (g.K + kchunk - 1) / kchunk;
+  }
+  if (g.tag == 1) {
+    if (big) launch<128, 128, 1>(g, sk, kchunk, work, s);
+    else launch<64, 64, 1>(g, sk, kchunk, work, s);
+  } else {
+    if (big) launch<128, 128, 0>(g, sk, kchunk, work, s);
+    else launch<64, 64, 0>(g, sk, kchunk, work, s);
+  }
+  if (sk > 1) {
+    const long MN = (long)g.M * g.N;
+    hipLaunchKernelGGL(splitk_reduce, dim3((MN + 255) / 256), dim3(256), 0, s, work, sk, g.M, g.N,
+                       g.C, g.ldc);
+    XTRG_HIP(hipGetLastError());
+  }
+}
+
+}  // namespace xtrg

@@ -1,0 +1,106 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace xtrg {
+
+// Error carried to the C ABI boundary and turned into a status code there.
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define XTRG_HIP(call)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      throw ::xtrg::Error(-3, std::string(#call) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+// Batched, strided GEMM on FP64 MFMA:  C[b] = A[b] * B[b]
+//   A element (m, k): transA ? A[k*lda + m] : A[m*lda + k]
+//   B element (k, n): transB ? B[n*ldb + k] : B[k*ldb + n]
+//   C element (m, n): C[m*ldc + n]
+// The batch index is split into up to three levels b = (b0*nb1 + b1)*nb2 + b2,
+// each with its own offset stride for A, B and C.
+struct Gemm {
+  int M = 0, N = 0, K = 0;
+  int transA = 0, transB = 0;
+  long lda = 0, ldb = 0, ldc = 0;
+  int nb[3] = {1, 1, 1};
+  long sA[3] = {0, 0, 0}, sB[3] = {0, 0, 0}, sC[3] = {0, 0, 0};
+  const double* A = nullptr;
+  const double* B = nullptr;
+  double* C = nullptr;
+  int tag = 0;   // 1: the two-site overlap C_E (its own kernel symbol for profiling)
+};
+
+// Launch; split-K (for small M*N and large K, unbatched only) uses `work`
+// (device, >= splitk*M*N doubles) and a deterministic reduction.
+void gemm(const Gemm& g, hipStream_t s, double* work = nullptr, size_t work_cap = 0);
+size_t gemm_splitk_work(const Gemm& g);
+
+// One-sided block Jacobi SVD of Y (len x p, column-major, device).
+// On return sigma (device, p) holds the singular values descending and,
+// if k > 0, U (device, column-major len x k, leading dim ldu) the leading
+// left singular vectors.  `work` must hold svd_work(len, p) doubles.
+size_t svd_work(int len, int p);
+// kneed: pairs of columns that both rank at or beyond kneed (by norm) are not
+// rotated -- they are discarded by the caller's truncation (kneed <= 0: all).
+void svd_left(int len, int p, const double* Y, double* sigma, int k, double* U, long ldu,
+              int u_rowmajor, double* work, hipStream_t s, int* sweeps_out, int kneed = 0);
+
+// Two-stage use: svd_left with k = 0, read the sorted values, then gather.
+void svd_gather(int len, int p, double* work, int k, double* U, long ldu, int u_rowmajor, hipStream_t s);
+const double* svd_sorted_values(const double* work, int len, int p);
+// ||Y||_F^2 (device scalar in work) and the relative rounding-noise level:
+// singular values below svd_noise_rel(len, p) * ||Y||_F are numerically zero
+// (not resolvable by any FP64 factorisation of Y) and are never kept.
+const double* svd_fro2(const double* work, int len, int p);
+double svd_noise_rel(int len, int p);
+// Smallest singular value (relative to ||Y||_F) whose vector the Jacobi
+// keeps orthogonal to the larger ones to better than ~10% (the rotation of a
+// pair stops once its overlap is below the rounding noise 4 sqrt(n) eps
+// ||Y||_F |z|); values below svd_keep_rel(len, p) * ||Y||_F are not kept.
+double svd_keep_rel(int len, int p);
+
+// Small elementwise / reduction kernels (misc.hip).
+void copy(double* dst, const double* src, size_t n, hipStream_t s);
+void fill(double* dst, double v, size_t n, hipStream_t s);
+void scale(double* x, double a, size_t n, hipStream_t s);
+// y = a*y + b*x
+void axpby(double* y, double a, const double* x, double b, size_t n, hipStream_t s);
+// dst[r*ldd + c] = src[c*lds + r] for r < rows, c < cols
+void transpose(double* dst, long ldd, const double* src, long lds, int rows, int cols, hipStream_t s);
+// swap the two physical indices of a site tensor [Dl][2][2][Dr]
+void swap_phys(double* dst, const double* src, int Dl, int Dr, hipStream_t s);
+// sum of squares into *out (device double), deterministic; part: 1024 doubles scratch
+void sumsq(const double* x, size_t n, double* out, double* part, hipStream_t s);
+// C[(a,b), s, u, (a',b')] = sum_t A[a,s,t,a'] B[b,t,u,b'] (exact MPO product site)
+void site_product(double* C, const double* A, int Dla, int Dra, const double* B, int Dlb, int Drb,
+                  hipStream_t s);
+// out[a][a'] = sum_s W[a][s][s][a']
+void phys_trace(double* out, const double* W, int Dl, int Dr, hipStream_t s);
+
+// Generic pairwise contraction (observables): see misc.hip.
+struct Contract {
+  int n_out = 0;            // <= 6 output dims (row-major, in this order)
+  int oe[6] = {1, 1, 1, 1, 1, 1};
+  long ots[6] = {0}, ows[6] = {0};  // stride of each output dim in T and in W
+  int n_c = 0;              // <= 3 contracted dims
+  int ce[3] = {1, 1, 1};
+  long cts[3] = {0}, cws[3] = {0};
+  const double* T = nullptr;
+  const double* W = nullptr;
+  double* out = nullptr;
+};
+void contract(const Contract& c, hipStream_t s);
+
+}  // namespace xtrg

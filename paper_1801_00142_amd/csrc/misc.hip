@@ -1,0 +1,206 @@
+// Small elementwise, permutation and reduction kernels (memory-bound; one
+// thread per element, grid-stride loops).
+#include "internal.h"
+
+#include <algorithm>
+
+namespace xtrg {
+
+namespace {
+
+constexpr int kT = 256;
+
+inline dim3 grid_for(size_t n) {
+  size_t b = (n + kT - 1) / kT;
+  if (b > 65535u * 8u) b = 65535u * 8u;
+  return dim3((unsigned)(b ? b : 1));
+}
+
+__global__ void k_fill(double* __restrict__ d, double v, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    d[i] = v;
+}
+
+__global__ void k_scale(double* __restrict__ d, double a, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    d[i] *= a;
+}
+
+__global__ void k_axpby(double* __restrict__ y, double a, const double* __restrict__ x, double b, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = a * y[i] + b * x[i];
+}
+
+__global__ void k_transpose(double* __restrict__ dst, long ldd, const double* __restrict__ src, long lds,
+                            int rows, int cols) {
+  __shared__ double tile[32][33];
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  for (int y = threadIdx.y; y < 32; y += 8) {
+    const int c = c0 + y, r = r0 + threadIdx.x;       // read src column-major: src[c*lds + r]
+    tile[y][threadIdx.x] = (c < cols && r < rows) ? src[(long)c * lds + r] : 0.0;
+  }
+  __syncthreads();
+  for (int y = threadIdx.y; y < 32; y += 8) {
+    const int r = r0 + y, c = c0 + threadIdx.x;       // write dst row-major: dst[r*ldd + c]
+    if (r < rows && c < cols) dst[(long)r * ldd + c] = tile[threadIdx.x][y];
+  }
+}
+
+__global__ void k_swap_phys(double* __restrict__ dst, const double* __restrict__ src, int Dl, int Dr) {
+  const long n = (long)Dl * 4 * Dr;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const long ar = i % Dr;
+    const long q = i / Dr;
+    const int t = (int)(q % 2), s = (int)((q / 2) % 2);
+    const long al = q / 4;
+    dst[((al * 2 + t) * 2 + s) * Dr + ar] = src[i];
+  }
+}
+
+// Fixed-order block sums, then one block adds the partials: deterministic.
+__global__ void k_sumsq_partial(const double* __restrict__ x, size_t n, double* __restrict__ part) {
+  __shared__ double sm[kT];
+  double s = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    s = fma(x[i], x[i], s);
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = kT / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+__global__ void k_sum_final(const double* __restrict__ part, int n, double* __restrict__ out) {
+  __shared__ double sm[kT];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += kT) s += part[i];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = kT / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sm[0];
+}
+
+__global__ void k_site_product(double* __restrict__ C, const double* __restrict__ A, int Dla, int Dra,
+                               const double* __restrict__ B, int Dlb, int Drb) {
+  // C[(a,b), s, u, (a',b')] = sum_t A[a,s,t,a'] B[b,t,u,b']
+  const long n = (long)Dla * Dlb * 4 * Dra * Drb;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    long q = i;
+    const int bp = (int)(q % Drb); q /= Drb;
+    const int ap = (int)(q % Dra); q /= Dra;
+    const int u = (int)(q % 2); q /= 2;
+    const int s = (int)(q % 2); q /= 2;
+    const int b = (int)(q % Dlb); q /= Dlb;
+    const int a = (int)q;
+    double v = 0.0;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+      v += A[(((long)a * 2 + s) * 2 + t) * Dra + ap] * B[(((long)b * 2 + t) * 2 + u) * Drb + bp];
+    C[i] = v;
+  }
+}
+
+__global__ void k_phys_trace(double* __restrict__ out, const double* __restrict__ W, int Dl, int Dr) {
+  const long n = (long)Dl * Dr;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const long a = i / Dr, ap = i % Dr;
+    out[i] = W[((a * 2 + 0) * 2 + 0) * Dr + ap] + W[((a * 2 + 1) * 2 + 1) * Dr + ap];
+  }
+}
+
+__global__ void k_contract(Contract c, long n_out_total) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n_out_total; i += (long)gridDim.x * blockDim.x) {
+    long q = i, bt = 0, bw = 0;
+    for (int d = c.n_out - 1; d >= 0; --d) {
+      const long v = q % c.oe[d];
+      q /= c.oe[d];
+      bt += v * c.ots[d];
+      bw += v * c.ows[d];
+    }
+    double acc = 0.0;
+    for (int i0 = 0; i0 < c.ce[0]; ++i0)
+      for (int i1 = 0; i1 < c.ce[1]; ++i1)
+        for (int i2 = 0; i2 < c.ce[2]; ++i2) {
+          const long ot = bt + i0 * c.cts[0] + i1 * c.cts[1] + i2 * c.cts[2];
+          const long ow = bw + i0 * c.cws[0] + i1 * c.cws[1] + i2 * c.cws[2];
+          acc = fma(c.T[ot], c.W[ow], acc);
+        }
+    c.out[i] = acc;
+  }
+}
+
+}  // namespace
+
+void copy(double* dst, const double* src, size_t n, hipStream_t s) {
+  if (n) XTRG_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+}
+
+void fill(double* dst, double v, size_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_fill, grid_for(n), dim3(kT), 0, s, dst, v, n);
+  XTRG_HIP(hipGetLastError());
+}
+
+void scale(double* x, double a, size_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_scale, grid_for(n), dim3(kT), 0, s, x, a, n);
+  XTRG_HIP(hipGetLastError());
+}
+
+void axpby(double* y, double a, const double* x, double b, size_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_axpby, grid_for(n), dim3(kT), 0, s, y, a, x, b, n);
+  XTRG_HIP(hipGetLastError());
+}
+
+void transpose(double* dst, long ldd, const double* src, long lds, int rows, int cols, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  dim3 g((cols + 31) / 32, (rows + 31) / 32);
+  hipLaunchKernelGGL(k_transpose, g, dim3(32, 8), 0, s, dst, ldd, src, lds, rows, cols);
+  XTRG_HIP(hipGetLastError());
+}
+
+void swap_phys(double* dst, const double* src, int Dl, int Dr, hipStream_t s) {
+  const size_t n = (size_t)Dl * 4 * Dr;
+  if (!n) return;
+  hipLaunchKernelGGL(k_swap_phys, grid_for(n), dim3(kT), 0, s, dst, src, Dl, Dr);
+  XTRG_HIP(hipGetLastError());
+}
+
+void sumsq(const double* x, size_t n, double* out, double* part, hipStream_t s) {
+  unsigned nb = (unsigned)std::min<size_t>(1024, (n + kT - 1) / kT);
+  if (nb == 0) nb = 1;
+  hipLaunchKernelGGL(k_sumsq_partial, dim3(nb), dim3(kT), 0, s, x, n, part);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kT), 0, s, part, (int)nb, out);
+  XTRG_HIP(hipGetLastError());
+}
+
+void site_product(double* C, const double* A, int Dla, int Dra, const double* B, int Dlb, int Drb,
+                  hipStream_t s) {
+  const size_t n = (size_t)Dla * Dlb * 4 * Dra * Drb;
+  if (!n) return;
+  hipLaunchKernelGGL(k_site_product, grid_for(n), dim3(kT), 0, s, C, A, Dla, Dra, B, Dlb, Drb);
+  XTRG_HIP(hipGetLastError());
+}
+
+void phys_trace(double* out, const double* W, int Dl, int Dr, hipStream_t s) {
+  const size_t n = (size_t)Dl * Dr;
+  if (!n) return;
+  hipLaunchKernelGGL(k_phys_trace, grid_for(n), dim3(kT), 0, s, out, W, Dl, Dr);
+  XTRG_HIP(hipGetLastError());
+}
+
+void contract(const Contract& c, hipStream_t s) {
+  long n = 1;
+  for (int d = 0; d < c.n_out; ++d) n *= c.oe[d];
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_contract, grid_for((size_t)n), dim3(kT), 0, s, c, n);
+  XTRG_HIP(hipGetLastError());
+}
+
+}  // namespace xtrg

@@ -1,0 +1,273 @@
+"""ctypes binding of libxtrg.so (argument marshalling only).
+
+Every tensor operation runs in the HIP library; this module converts Python
+and NumPy arguments to the C ABI of include/xtrg.h and back.  It raises
+immediately if the compiled library is absent: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import weakref
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libxtrg.so")
+_lib = None
+
+XTRG_FP64 = 0
+
+
+class XtrgError(RuntimeError):
+    pass
+
+
+class CompressOpts(C.Structure):
+    _fields_ = [("D_max", C.c_int), ("n_sweeps", C.c_int), ("precision", C.c_int),
+                ("degen_rtol", C.c_double), ("sv_floor", C.c_double)]
+
+
+class CompressInfo(C.Structure):
+    _fields_ = [("dlog_norm", C.c_double), ("trunc_err_max", C.c_double), ("sweeps_done", C.c_int),
+                ("D_kept_max", C.c_int), ("steps", C.c_int), ("flops", C.c_double),
+                ("sv", C.POINTER(C.c_double)), ("sv_stride", C.c_int)]
+
+
+class Obs(C.Structure):
+    _fields_ = [("beta", C.c_double), ("lnZ", C.c_double), ("f", C.c_double), ("u", C.c_double),
+                ("c", C.c_double), ("tr_rho", C.c_double), ("S_E_center", C.c_double),
+                ("S_E_max", C.c_double)]
+
+
+def load_library(path: Optional[str] = None):
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or _LIB_PATH
+    if not os.path.exists(p):
+        raise XtrgError(f"{p} is missing: build it with `python -m paper_1801_00142_amd.build`")
+    lib = C.CDLL(p)
+    vp, ip, dp = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double)
+    sig = {
+        "xtrg_ctx_create": (C.c_int, [C.c_int, vp, C.c_size_t, C.POINTER(vp)]),
+        "xtrg_ctx_destroy": (C.c_int, [vp]),
+        "xtrg_last_error": (C.c_char_p, [vp]),
+        "xtrg_ctx_bytes": (C.c_size_t, [vp]),
+        "xtrg_hamiltonian_xxz": (C.c_int, [vp, C.c_int, C.c_int, ip, dp, dp, C.POINTER(vp)]),
+        "xtrg_mpo_from_host": (C.c_int, [vp, C.c_int, C.c_int, ip, C.POINTER(dp), C.POINTER(vp)]),
+        "xtrg_mpo_shape": (C.c_int, [vp, ip, ip]),
+        "xtrg_mpo_to_host": (C.c_int, [vp, C.POINTER(dp)]),
+        "xtrg_mpo_destroy": (C.c_int, [vp]),
+        "xtrg_init_rho": (C.c_int, [vp, vp, C.c_double, C.c_int, C.c_int, C.POINTER(vp), dp]),
+        "xtrg_square_compress": (C.c_int, [vp, vp, C.POINTER(CompressOpts), C.POINTER(vp),
+                                           C.POINTER(CompressInfo)]),
+        "xtrg_observables": (C.c_int, [vp, vp, C.c_double, C.c_double, vp, C.c_int, C.POINTER(Obs),
+                                       C.POINTER(Obs), dp]),
+        "xtrg_dgemm": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, vp, C.c_long, vp,
+                                 C.c_long, vp, C.c_long]),
+        "xtrg_dsvd_left": (C.c_int, [vp, C.c_int, C.c_int, vp, vp, C.c_int, vp]),
+        "xtrg_profile_enable": (C.c_int, [vp, C.c_int]),
+        "xtrg_profile_report": (C.c_int, [vp, C.c_char_p, C.c_size_t]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols() -> List[str]:
+    return ["xtrg_ctx_create", "xtrg_ctx_destroy", "xtrg_last_error", "xtrg_ctx_bytes",
+            "xtrg_hamiltonian_xxz", "xtrg_mpo_from_host", "xtrg_mpo_shape", "xtrg_mpo_to_host",
+            "xtrg_mpo_destroy", "xtrg_init_rho", "xtrg_square_compress", "xtrg_observables",
+            "xtrg_dgemm", "xtrg_dsvd_left", "xtrg_profile_enable", "xtrg_profile_report"]
+
+
+class MPO:
+    def __init__(self, ctx: "Context", handle):
+        self.ctx = ctx
+        self.h = handle
+        ctx._live.add(self)
+
+    def shape(self):
+        L = C.c_int()
+        _check(self.ctx, _lib.xtrg_mpo_shape(self.h, C.byref(L), None))
+        dims = (C.c_int * (L.value + 1))()
+        _check(self.ctx, _lib.xtrg_mpo_shape(self.h, None, dims))
+        return L.value, list(dims)
+
+    @property
+    def bond_dims(self):
+        return self.shape()[1]
+
+    def to_host(self) -> List[np.ndarray]:
+        L, dims = self.shape()
+        arrs = [np.empty((dims[i], 2, 2, dims[i + 1]), dtype=np.float64) for i in range(L)]
+        ptrs = (C.POINTER(C.c_double) * L)(*[a.ctypes.data_as(C.POINTER(C.c_double)) for a in arrs])
+        _check(self.ctx, _lib.xtrg_mpo_to_host(self.h, ptrs))
+        return arrs
+
+    def close(self):
+        # an MPO is released before its context; after Context.close() the
+        # handle is already gone
+        if self.h and self.ctx.h:
+            _lib.xtrg_mpo_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _check(ctx, rc):
+    if rc != 0:
+        msg = _lib.xtrg_last_error(ctx.h if ctx is not None else None)
+        raise XtrgError(f"xtrg error {rc}: {msg.decode() if msg else ''}")
+
+
+class Context:
+    def __init__(self, device: int = 0, stream: Optional[int] = None, hbm_budget: int = 0):
+        load_library()
+        h = C.c_void_p()
+        rc = _lib.xtrg_ctx_create(device, C.c_void_p(stream) if stream else None, hbm_budget, C.byref(h))
+        if rc != 0:
+            raise XtrgError(f"xtrg_ctx_create failed ({rc})")
+        self.h = h
+        self._live = weakref.WeakSet()
+
+    def close(self):
+        if self.h:
+            for m in list(self._live):
+                m.close()
+            _lib.xtrg_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def bytes(self) -> int:
+        return int(_lib.xtrg_ctx_bytes(self.h))
+
+    def hamiltonian_xxz(self, n_sites: int, bonds: Sequence, jxy: Sequence[float], jz: Sequence[float]) -> MPO:
+        b = np.ascontiguousarray(np.array(bonds, dtype=np.int32).reshape(-1))
+        a = np.ascontiguousarray(np.array(jxy, dtype=np.float64))
+        z = np.ascontiguousarray(np.array(jz, dtype=np.float64))
+        h = C.c_void_p()
+        _check(self, _lib.xtrg_hamiltonian_xxz(self.h, n_sites, len(a), b.ctypes.data_as(C.POINTER(C.c_int)),
+                                               a.ctypes.data_as(C.POINTER(C.c_double)),
+                                               z.ctypes.data_as(C.POINTER(C.c_double)), C.byref(h)))
+        return MPO(self, h)
+
+    def mpo_from_host(self, sites: Sequence[np.ndarray]) -> MPO:
+        sites = [np.ascontiguousarray(s, dtype=np.float64) for s in sites]
+        L = len(sites)
+        dims = (C.c_int * (L + 1))(*([sites[0].shape[0]] + [s.shape[3] for s in sites]))
+        ptrs = (C.POINTER(C.c_double) * L)(*[s.ctypes.data_as(C.POINTER(C.c_double)) for s in sites])
+        h = C.c_void_p()
+        _check(self, _lib.xtrg_mpo_from_host(self.h, L, 2, dims, ptrs, C.byref(h)))
+        return MPO(self, h)
+
+    def init_rho(self, H: MPO, tau0: float, order: int = 1, D0_max: int = 0):
+        h = C.c_void_p()
+        lam = C.c_double()
+        _check(self, _lib.xtrg_init_rho(self.h, H.h, tau0, order, D0_max, C.byref(h), C.byref(lam)))
+        return MPO(self, h), lam.value
+
+    def square_compress(self, rho: MPO, D_max: int, n_sweeps: int = 4, degen_rtol: float = 1e-6,
+                        sv_floor: float = 1e-14, sv_stride: int = 0):
+        o = CompressOpts(D_max, n_sweeps, XTRG_FP64, degen_rtol, sv_floor)
+        info = CompressInfo()
+        L = rho.shape()[0]
+        buf = None
+        if sv_stride > 0:
+            buf = np.zeros((L - 1, sv_stride))
+            info.sv = buf.ctypes.data_as(C.POINTER(C.c_double))
+            info.sv_stride = sv_stride
+        h = C.c_void_p()
+        _check(self, _lib.xtrg_square_compress(self.h, rho.h, C.byref(o), C.byref(h), C.byref(info)))
+        out = dict(dlog_norm=info.dlog_norm, trunc_err_max=info.trunc_err_max, sweeps=info.sweeps_done,
+                   D_kept_max=info.D_kept_max, steps=info.steps, flops=info.flops)
+        if buf is not None:
+            out["sv"] = buf
+        return MPO(self, h), out
+
+    def observables(self, rho: MPO, log_norm: float, tau: float, H: MPO, n_sites: int,
+                    entropy: bool = True) -> Dict[str, Dict[str, float]]:
+        a, b = Obs(), Obs()
+        L = rho.shape()[0]
+        se = np.zeros(max(L - 1, 1)) if entropy else None
+        _check(self, _lib.xtrg_observables(self.h, rho.h, log_norm, tau, H.h, n_sites, C.byref(a), C.byref(b),
+                                           se.ctypes.data_as(C.POINTER(C.c_double)) if entropy else None))
+        fa = {k: getattr(a, k) for k, _ in Obs._fields_}
+        fb = {k: getattr(b, k) for k, _ in Obs._fields_}
+        fa["tr"] = fa.pop("tr_rho")
+        fb["norm2"] = fb.pop("tr_rho")
+        out = {"tau": fa, "2tau": fb}
+        if entropy:
+            out["S_E"] = se[: L - 1]
+        return out
+
+    def profile(self, on: bool = True):
+        _check(self, _lib.xtrg_profile_enable(self.h, int(on)))
+
+    def profile_report(self) -> Dict[str, Dict[str, float]]:
+        import json
+        buf = C.create_string_buffer(4096)
+        _check(self, _lib.xtrg_profile_report(self.h, buf, 4096))
+        return json.loads(buf.value.decode())
+
+    # kernel-level entry points (device pointers as Python ints)
+    def dgemm(self, M, N, K, transA, transB, A, lda, B, ldb, Cp, ldc):
+        _check(self, _lib.xtrg_dgemm(self.h, M, N, K, int(transA), int(transB), C.c_void_p(A), lda,
+                                     C.c_void_p(B), ldb, C.c_void_p(Cp), ldc))
+
+    def dsvd_left(self, length, p, Y, sigma, k=0, U=None):
+        _check(self, _lib.xtrg_dsvd_left(self.h, length, p, C.c_void_p(Y), C.c_void_p(sigma), k,
+                                         C.c_void_p(U) if U else None))
+
+
+def run(ctx: Context, n_sites: int, bonds, jxy, jz, tau0: float, n_doublings: int, D: int, order: int = 1,
+        n_sweeps: int = 4, degen_rtol: float = 1e-6, sv_floor: float = 1e-14, observe: bool = True,
+        entropy: bool = False):
+    """Full XTRG run through the library: rho(tau0), then n_doublings doublings;
+    returns per-doubling records (observables at beta = tau_n and 2 tau_n)."""
+    H = ctx.hamiltonian_xxz(n_sites, bonds, jxy, jz)
+    rho, lam = ctx.init_rho(H, tau0, order)
+    tau = tau0
+    recs = []
+
+    def rec(n, info=None):
+        r = dict(n=n, tau=tau, lam=lam, bond_dims=rho.bond_dims)
+        if observe:
+            r["obs"] = ctx.observables(rho, lam, tau, H, n_sites, entropy=entropy)
+        if info is not None:
+            r["info"] = info
+        return r
+
+    recs.append(rec(0))
+    for n in range(1, n_doublings + 1):
+        new, info = ctx.square_compress(rho, D, n_sweeps, degen_rtol, sv_floor)
+        rho.close()
+        rho = new
+        lam = 2 * lam + info["dlog_norm"]
+        tau = 2 * tau
+        recs.append(rec(n, info))
+    rho.close()
+    H.close()
+    return recs

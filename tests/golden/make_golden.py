@@ -1,0 +1,44 @@
+"""Write the stored oracle results used by the GPU parity tests.
+
+Runs only the FP64 oracle (oracle/) on the seeded workloads of workloads.py
+and stores f, u, c, ln Z at every beta of the doubling grid, plus the bond
+dimensions, as JSON.  Usage:  python tests/golden/make_golden.py [name ...]
+"""
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import workloads as W  # noqa: E402
+from oracle import xtrg  # noqa: E402
+
+CASES = {
+    # the L=10 chain workload: 2nd-order start at tau0 = 2^-10, 14 doublings, D = 64
+    "chain10_D64": dict(workload="chain10", D=64, n_sweeps=4),
+}
+
+
+def main(names):
+    for name in names:
+        cfg = CASES[name]
+        wl = W.workload(cfg["workload"], cfg["D"])
+        lat = wl.lattice
+        t0 = time.time()
+        recs = xtrg.run(lat.n_sites, lat.bonds, lat.jxy, lat.jz, wl.tau0, wl.n_doublings, wl.D,
+                        order=wl.init_order, n_sweeps=cfg["n_sweeps"])
+        out = dict(case=name, workload=cfg["workload"], D=wl.D, n_sweeps=cfg["n_sweeps"], tau0=wl.tau0,
+                   order=wl.init_order, n_doublings=wl.n_doublings, n_sites=lat.n_sites,
+                   seconds=time.time() - t0, records=[])
+        for r in recs:
+            out["records"].append(dict(n=r["n"], tau=r["tau"], lam=r["lam"], bond_dims=r["bond_dims"],
+                                       tau_obs=r["obs"]["tau"], two_tau_obs=r["obs"]["2tau"]))
+        with open(os.path.join(HERE, f"oracle_{name}.json"), "w") as f:
+            json.dump(out, f, indent=1)
+        print(name, f"{out['seconds']:.1f}s")
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or list(CASES))

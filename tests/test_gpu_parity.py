@@ -1,0 +1,237 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Tolerances: the FP64 path must reproduce the oracle's free energy per site
+to 1e-9 relative at the same D; kernel-level results are compared element
+by element with FP64 rounding-level bounds stated per test.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import ed
+from oracle import mpo as M
+from oracle import xtrg as OX
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1801_00142_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+# ---------------------------------------------------------------- kernels
+
+@pytest.mark.parametrize("M_,N_,K_", [(1, 1, 1), (17, 33, 5), (64, 64, 16), (130, 257, 70),
+                                      (300, 129, 1000), (128, 128, 8192), (5, 700, 3)])
+@pytest.mark.parametrize("tA,tB", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_dgemm_matches_fp64_matmul(ctx, M_, N_, K_, tA, tB):
+    import torch
+    rng = np.random.default_rng(M_ * 7 + N_ * 3 + K_ + 11 * tA + 13 * tB)
+    A = rng.standard_normal((K_, M_) if tA else (M_, K_))
+    B = rng.standard_normal((N_, K_) if tB else (K_, N_))
+    want = (A.T if tA else A) @ (B.T if tB else B)
+    dA, dB = _dev(A), _dev(B)
+    dC = torch.full((M_, N_), float("nan"), dtype=torch.float64, device="cuda")
+    ctx.dgemm(M_, N_, K_, tA, tB, dA.data_ptr(), A.shape[1], dB.data_ptr(), B.shape[1], dC.data_ptr(), N_)
+    torch.cuda.synchronize()
+    got = dC.cpu().numpy()
+    bound = 1e-14 * K_ * np.abs(A).max() * np.abs(B).max() + 1e-300
+    assert np.abs(got - want).max() <= 4 * bound
+
+
+@pytest.mark.parametrize("length,p", [(1, 1), (5, 3), (3, 5), (64, 64), (100, 37), (37, 100), (300, 256),
+                                      (1024, 64)])
+def test_svd_graded_spectrum(ctx, length, p):
+    """Singular values to absolute accuracy ~eps*sigma_1 on a graded
+    spectrum spanning 14 decades; orthonormal singular vectors."""
+    import torch
+    rng = np.random.default_rng(length * 1000 + p)
+    r = min(length, p)
+    U0, _ = np.linalg.qr(rng.standard_normal((length, r)))
+    V0, _ = np.linalg.qr(rng.standard_normal((p, r)))
+    s0 = 10.0 ** -np.linspace(0, 14, r)
+    Y = (U0 * s0) @ V0.T                     # column-major storage of a len x p matrix
+    dY = _dev(Y.T.copy())                    # rows of Y.T = columns of Y
+    sig = torch.zeros(p, dtype=torch.float64, device="cuda")
+    k = max(1, r // 2)
+    dU = torch.zeros((k, length), dtype=torch.float64, device="cuda")
+    ctx.dsvd_left(length, p, dY.data_ptr(), sig.data_ptr(), k, dU.data_ptr())
+    torch.cuda.synchronize()
+    s = sig.cpu().numpy()
+    s_ref = np.linalg.svd(Y, compute_uv=False)
+    assert np.abs(s[:r] - s_ref[:r]).max() <= 100 * 2.2e-16 * s_ref[0] * math.sqrt(max(length, p))
+    assert np.all(np.abs(s[r:]) <= 100 * 2.2e-16 * s_ref[0] * math.sqrt(max(length, p)))
+    U = dU.cpu().numpy().T                   # column-major len x k
+    assert np.abs(U.T @ U - np.eye(k)).max() < 1e-12
+    # the leading, well separated directions agree with LAPACK up to sign
+    Ur = np.linalg.svd(Y, full_matrices=False)[0]
+    good = [j for j in range(k) if s_ref[j] > 1e-6 * s_ref[0]]
+    for j in good:
+        assert abs(abs(U[:, j] @ Ur[:, j]) - 1) < 1e-8
+
+
+def test_svd_rank_deficient(ctx):
+    """Exact rank 21 in a 64 x 64 matrix: the values beyond the rank are
+    below the keep floor (40 eps sqrt(64) ||Y||_F), the leading ones exact."""
+    import torch
+    rng = np.random.default_rng(5)
+    Y = rng.standard_normal((64, 21)) @ rng.standard_normal((21, 64))
+    sig = torch.zeros(64, dtype=torch.float64, device="cuda")
+    ctx.dsvd_left(64, 64, _dev(Y.T.copy()).data_ptr(), sig.data_ptr(), 0, None)
+    torch.cuda.synchronize()
+    s = sig.cpu().numpy()
+    s_ref = np.linalg.svd(Y, compute_uv=False)
+    noise = 1.01 * 40 * 2.220446049250313e-16 * 8 * np.linalg.norm(Y)
+    assert np.abs(s[:21] - s_ref[:21]).max() < 1e-12 * s_ref[0]
+    assert np.all(s[21:] < noise)
+
+
+# ---------------------------------------------------------------- Hamiltonian, start
+
+@pytest.mark.parametrize("lat", [W.chain(6), W.random_couplings(W.chain(7), 3), W.square_cylinder(3, 3),
+                                 W.triangular_yc(3, 3), W.with_couplings(W.chain(5), 1.0, 1.6)],
+                         ids=lambda l: l.name)
+def test_hamiltonian_mpo_matches_ed(ctx, lat):
+    H = ctx.hamiltonian_xxz(lat.n_sites, lat.bonds, lat.jxy, lat.jz)
+    got = M.to_dense(H.to_host())
+    assert np.abs(got - ed.xxz_dense(lat.n_sites, lat.bonds, lat.jxy, lat.jz)).max() < 1e-14
+    assert max(H.bond_dims) == max(M.automaton_bond_dims(lat.n_sites, lat.bonds))
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_init_rho_matches_series(ctx, order):
+    lat = W.random_couplings(W.chain(6), 5)
+    tau = 0.05
+    H = ctx.hamiltonian_xxz(lat.n_sites, lat.bonds, lat.jxy, lat.jz)
+    rho, lam = ctx.init_rho(H, tau, order)
+    want = M.to_dense(OX.series_rho(lat.n_sites, lat.bonds, lat.jxy, lat.jz, tau, order))
+    sites = rho.to_host()
+    assert np.abs(M.to_dense(sites) * math.exp(lam) - want).max() < 1e-13
+    assert abs(M.norm(sites) - 1) < 1e-13
+    for w in sites[1:]:
+        m = w.reshape(w.shape[0], -1)
+        assert np.abs(m @ m.T - np.eye(w.shape[0])).max() < 1e-12
+    # same exact bond dimensions as the oracle's lossless compression
+    ref, _ = OX.init_rho(lat.n_sites, lat.bonds, lat.jxy, lat.jz, tau, order)
+    assert rho.bond_dims == M.bond_dims(ref)
+
+
+# ---------------------------------------------------------------- the doubling step
+
+def test_untruncated_doubling_is_exact(ctx):
+    """Brute force: below the bond budget the doubling returns rho*rho exactly."""
+    lat = W.random_couplings(W.chain(5), 4)
+    H = ctx.hamiltonian_xxz(lat.n_sites, lat.bonds, lat.jxy, lat.jz)
+    rho, lam = ctx.init_rho(H, 0.2, 2)
+    for _ in range(3):
+        R = M.to_dense(rho.to_host())
+        new, info = ctx.square_compress(rho, 1000, n_sweeps=2)
+        got = M.to_dense(new.to_host()) * math.exp(info["dlog_norm"])
+        assert np.linalg.norm(got - R @ R) < 1e-13 * np.linalg.norm(R @ R)
+        rho = new
+
+
+def test_two_sites_and_D1(ctx):
+    """Edge cases: the shortest chain (one bond), and the harshest budget D = 1."""
+    lat = W.chain(2)
+    H = ctx.hamiltonian_xxz(2, lat.bonds, lat.jxy, lat.jz)
+    rho, lam = ctx.init_rho(H, 0.1, 2)
+    R = M.to_dense(rho.to_host())
+    new, info = ctx.square_compress(rho, 64, n_sweeps=1)
+    assert np.abs(M.to_dense(new.to_host()) * math.exp(info["dlog_norm"]) - R @ R).max() < 1e-14
+    lat = W.chain(6)
+    H = ctx.hamiltonian_xxz(6, lat.bonds, lat.jxy, lat.jz)
+    rho, lam = ctx.init_rho(H, 0.1, 1)
+    new, info = ctx.square_compress(rho, 1, n_sweeps=2)
+    assert max(new.bond_dims) == 1
+    ref, rinfo = OX.square_compress(OX.init_rho(6, lat.bonds, lat.jxy, lat.jz, 0.1, 1)[0], 1, 2)
+    assert abs(info["dlog_norm"] - rinfo.dlog_norm) < 1e-12
+
+
+def test_no_bonds_identity(ctx):
+    """H = 0 (no bonds): rho stays proportional to the identity."""
+    H = ctx.hamiltonian_xxz(4, [], [], [])
+    rho, lam = ctx.init_rho(H, 0.3, 1)
+    new, info = ctx.square_compress(rho, 8, n_sweeps=1)
+    got = M.to_dense(new.to_host())
+    assert np.abs(got - np.eye(16) * got[0, 0]).max() < 1e-14
+
+
+def test_error_paths(ctx):
+    from paper_1801_00142_amd import XtrgError
+    lat = W.chain(4)
+    H = ctx.hamiltonian_xxz(4, lat.bonds, lat.jxy, lat.jz)
+    rho, lam = ctx.init_rho(H, 0.1, 1)
+    with pytest.raises(XtrgError):
+        ctx.square_compress(rho, 0)
+    with pytest.raises(XtrgError):
+        ctx.init_rho(H, 0.1, 3)
+    with pytest.raises(XtrgError):
+        ctx.hamiltonian_xxz(4, [(0, 9)], [1.0], [1.0])
+    H5 = ctx.hamiltonian_xxz(5, W.chain(5).bonds, [1.0] * 4, [1.0] * 4)
+    with pytest.raises(XtrgError):
+        ctx.observables(rho, lam, 0.1, H5, 4)
+
+
+def _compare_runs(gpu, ora, n_sites, rtol):
+    for g, o in zip(gpu, ora):
+        for key in ("tau", "2tau"):
+            fg, fo = g["obs"][key]["f"], o["obs"][key]["f"]
+            assert abs(fg - fo) <= rtol * abs(fo), (g["n"], key, fg, fo)
+            ug, uo = g["obs"][key]["u"], o["obs"][key]["u"]
+            assert abs(ug - uo) <= rtol * max(abs(uo), 1e-3), (g["n"], key, ug, uo)
+
+
+@pytest.mark.parametrize("case", [
+    dict(lat=W.chain(10), tau0=2.0 ** -10, n=10, D=32, order=2),
+    dict(lat=W.with_couplings(W.chain(9), 1.0, 1.5), tau0=2.0 ** -8, n=9, D=24, order=1),
+    dict(lat=W.square_cylinder(3, 3), tau0=2.0 ** -8, n=8, D=40, order=1),
+], ids=["chain10_D32", "xxz9_D24", "sq3x3_D40"])
+def test_run_matches_oracle(ctx, case):
+    from paper_1801_00142_amd import run
+    lat = case["lat"]
+    args = (lat.n_sites, lat.bonds, lat.jxy, lat.jz, case["tau0"], case["n"], case["D"])
+    gpu = run(ctx, *args, order=case["order"], n_sweeps=2, entropy=True)
+    ora = OX.run(*args, order=case["order"], n_sweeps=2, with_entropy=True)
+    _compare_runs(gpu, ora, lat.n_sites, 1e-9)
+    for g, o in zip(gpu, ora):
+        assert np.abs(g["obs"]["S_E"] - o["S_E"]).max() < 1e-8
+        assert max(g["bond_dims"]) <= case["D"]
+
+
+def test_chain10_full_against_stored_oracle(ctx):
+    """The L = 10 chain workload (2nd-order start, tau0 = 2^-10, 14 doublings
+    to beta = 16, D = 64, 4 sweeps) against the stored oracle run."""
+    path = os.path.join(GOLD, "oracle_chain10_D64.json")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle run missing (tests/golden/make_golden.py)")
+    ref = json.load(open(path))
+    from paper_1801_00142_amd import run
+    lat = W.workload("chain10").lattice
+    gpu = run(ctx, lat.n_sites, lat.bonds, lat.jxy, lat.jz, ref["tau0"], ref["n_doublings"], ref["D"],
+              order=ref["order"], n_sweeps=ref["n_sweeps"])
+    for g, o in zip(gpu, ref["records"]):
+        for key, okey in (("tau", "tau_obs"), ("2tau", "two_tau_obs")):
+            fg, fo = g["obs"][key]["f"], o[okey]["f"]
+            assert abs(fg - fo) <= 1e-9 * abs(fo), (g["n"], key, fg, fo)
+    # and against exact diagonalisation, within the series + truncation error
+    E = ed.spectrum(lat.n_sites, lat.bonds, lat.jxy, lat.jz)
+    o = gpu[-1]["obs"]["2tau"]
+    assert abs(o["f"] - ed.thermo(E, o["beta"], lat.n_sites)[0]) < 5e-6
