@@ -127,6 +127,8 @@ def main():
     ctx.profile(False)
 
     value = flops / dt / 1e12
+    svd_calls = prof.pop("svd_calls", 0)
+    svd_sweeps = prof.pop("svd_sweeps", 0)
     th = prof["theta_gemm"]
     th_avg_s = th["ms"] / max(th["calls"], 1) / 1e3
     th_flops = th["flops"] / max(th["calls"], 1)
@@ -153,6 +155,7 @@ def main():
                    "warmup_doublings": n_done, "saturated_after": saturated_at},
         "sweeps_per_s": round(args.steps * args.sweeps / dt, 4),
         "phase_share": shares,
+        "svd_sweeps_avg": round(svd_sweeps / max(svd_calls, 1), 2),
         "roofline": {"bound": "mfma", "kernel": "two-site overlap C_E (dgemm_kernel<...,1>)",
                      "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,

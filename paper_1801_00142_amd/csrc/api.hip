@@ -45,6 +45,7 @@ struct xtrg_ctx_s {
   };
   bool prof = false;
   std::vector<Prof> prof_recs;
+  long svd_calls = 0, svd_sweeps = 0;
 
   double* alloc(size_t n) {
     const size_t b = std::max<size_t>(n, 1) * sizeof(double);
@@ -639,7 +640,10 @@ void square_compress_impl(xtrg_ctx c, xtrg_mpo in, const xtrg_compress_opts& o, 
     double* work = c->need("svd", xtrg::svd_work(len, p));
     {
       Timed tm(c, P_SVD, 0.0, 8.0 * len * (double)p);
-      xtrg::svd_left(len, p, th, nullptr, 0, nullptr, 0, 0, work, s, nullptr);
+      int sw = 0;
+      xtrg::svd_left(len, p, th, nullptr, 0, nullptr, 0, 0, work, s, &sw);
+      c->svd_calls += 1;
+      c->svd_sweeps += sw;
     }
     std::vector<double> S = read_vec(c, xtrg::svd_sorted_values(work, len, p), p);
     S.resize(std::min(mL, mR));
@@ -1084,7 +1088,10 @@ int xtrg_profile_report(xtrg_ctx c, char* buf, size_t cap) {
                     q ? ", " : "", kPhase[q], ms[q], n[q], fl[q], by[q]);
       out += tmp;
     }
-    out += "}";
+    char tail[128];
+    std::snprintf(tail, sizeof tail, ", \"svd_calls\": %ld, \"svd_sweeps\": %ld}", c->svd_calls, c->svd_sweeps);
+    out += tail;
+    c->svd_calls = c->svd_sweeps = 0;
     if (out.size() + 1 > cap) throw Error(XTRG_EINVAL, "profile report buffer too small");
     std::memcpy(buf, out.c_str(), out.size() + 1);
   });
@@ -1105,7 +1112,10 @@ int xtrg_dsvd_left(xtrg_ctx c, int len, int p, const double* Y, double* sigma, i
   return guarded(c, [&] {
     set_device(c);
     double* work = c->need("svd", xtrg::svd_work(len, p));
-    xtrg::svd_left(len, p, Y, sigma, k, U, len, 0, work, c->stream, nullptr);
+    int sw = 0;
+    xtrg::svd_left(len, p, Y, sigma, k, U, len, 0, work, c->stream, &sw);
+    c->svd_calls += 1;
+    c->svd_sweeps += sw;
     if (k > 0 && U) orthonormalize(c, U, len, k, false);
     XTRG_HIP(hipStreamSynchronize(c->stream));
   });

@@ -52,10 +52,8 @@ size_t gemm_splitk_work(const Gemm& g);
 // if k > 0, U (device, column-major len x k, leading dim ldu) the leading
 // left singular vectors.  `work` must hold svd_work(len, p) doubles.
 size_t svd_work(int len, int p);
-// kneed: pairs of columns that both rank at or beyond kneed (by norm) are not
-// rotated -- they are discarded by the caller's truncation (kneed <= 0: all).
 void svd_left(int len, int p, const double* Y, double* sigma, int k, double* U, long ldu,
-              int u_rowmajor, double* work, hipStream_t s, int* sweeps_out, int kneed = 0);
+              int u_rowmajor, double* work, hipStream_t s, int* sweeps_out);
 
 // Two-stage use: svd_left with k = 0, read the sorted values, then gather.
 void svd_gather(int len, int p, double* work, int k, double* U, long ldu, int u_rowmajor, hipStream_t s);

@@ -3,17 +3,19 @@
 // The columns of Y (len x p, column-major) are made mutually orthogonal by
 // plane rotations from the right, Y V = Z.  The column norms of Z are the
 // singular values and the normalised columns the left singular vectors.
-// Columns are grouped into blocks of b; each outer round pairs every block
-// with one other block (round-robin tournament, all pairs met once per
-// sweep), one workgroup per block pair holds its 2b columns in LDS and runs
-// one inner sweep of rotations over them.  Sweeps repeat until the largest
-// cosine |z_i . z_j| / (|z_i| |z_j|) seen in a sweep is below tol.
+// Columns are grouped into blocks of 4 by norm rank; each outer round pairs
+// every block with one other block (round-robin tournament, all pairs met
+// once per sweep) and one workgroup per block pair orthogonalises its 8
+// columns (8 x 8 Gram from the columns, one sweep of small Jacobi on it,
+// one rotation pass).  Sweeps repeat until no pair in a sweep needs a
+// rotation.
 //
-// Accuracy: the rotations act on the columns themselves (no Gram matrix is
-// formed), so singular values and vectors are resolved to absolute
-// accuracy ~ eps * sigma_1, which the thermal-state compression needs:
-// components far below sqrt(eps) * sigma_1 carry the high-order terms of
-// the series start and must not be lost.
+// Accuracy: the Gram entries are recomputed from the rotated columns at
+// every visit and the stopping test is on those fresh cosines, so singular
+// values and vectors are resolved to absolute accuracy ~ eps * sigma_1, which
+// the thermal-state compression needs: components far below
+// sqrt(eps) * sigma_1 carry the high-order terms of the series start and
+// must not be lost (a Gram matrix of the whole Y would lose them).
 #include "internal.h"
 
 #include <algorithm>
@@ -47,106 +49,179 @@ __host__ __device__ inline void rr_pair(int n, int r, int q, int* i, int* j) {
   }
 }
 
-// Block pairing works on ranks: rank q is the column with the q-th largest
-// norm at the start of the sweep (perm[q]), so each block holds columns of
-// similar norm (sorted one-sided Jacobi converges in fewer sweeps on graded
-// spectra).  Pairs are skipped when a column is numerically zero
-// (|z|^2 <= zth) or when both columns rank at or beyond kneed (both will be
-// discarded by the truncation that follows).
-__global__ __launch_bounds__(kThreads) void jacobi_round(double* __restrict__ Y, int len, int p, int b,
-                                                          int nbk, int r, double tol,
-                                                          const int* __restrict__ perm,
+// One outer round of one-sided block Jacobi.  Block pairing works on
+// ranks: rank q is the column with the q-th largest norm at the start of the
+// sweep (perm[q]), so each block holds columns of similar norm.  A
+// workgroup owns one block pair (kNC = 8 columns): every thread keeps its R
+// rows of the 8 columns in registers, the 8 x 8 Gram matrix of the pair is
+// formed from the columns themselves (fresh dot products every visit),
+// one cyclic two-sided Jacobi sweep is run on that small matrix, and the
+// accumulated 8 x 8 rotation W is applied to the columns in one pass
+// (Z <- Z W).  The convergence measure is the largest cosine
+// |z_i . z_j| / (|z_i| |z_j|) of the fresh Gram that exceeds tol; columns
+// with |z|^2 <= zth are numerically zero and take no part.
+constexpr int kNC = 8;
+constexpr int kPairs = kNC * (kNC + 1) / 2;   // 36 Gram entries
+
+template <int R>
+__global__ __launch_bounds__(kThreads) void jacobi_round(double* __restrict__ Y, int len, int p, int nbk, int r,
+                                                          double tol, const int* __restrict__ perm,
                                                           const double* __restrict__ fro2, double zrel2,
-                                                          double noise_coef, int kneed,
                                                           unsigned long long* __restrict__ offmax) {
-  extern __shared__ double cols[];     // [2b][len]
-  __shared__ int colid[32];
+  constexpr int b = kNC / 2;
+  __shared__ int colid[kNC];
+  __shared__ double red[kWaves][64];
+  __shared__ double Gsh[kNC][kNC + 1];
+  __shared__ double Wsh[kNC][kNC + 1];
+  __shared__ double rot_c[kNC / 2], rot_s[kNC / 2];
+  __shared__ int rot_x[kNC / 2], rot_y[kNC / 2];
+  __shared__ double worst_sh;
   int bi, bj;
   rr_pair(nbk, r, blockIdx.x, &bi, &bj);
-  const int nc = 2 * b;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const double zth = zrel2 * fro2[0];
-  const double nscale = noise_coef * sqrt(fro2[0]);
-  if (t < nc) {
+  if (t < kNC) {
     const int rank = (t < b ? bi : bj) * b + (t < b ? t : t - b);
     colid[t] = rank < p ? perm[rank] : -1;
   }
   __syncthreads();
 
-  // load the 2b columns (absent columns read as zero)
-  for (int s = 0; s < nc; ++s) {
-    const int col = colid[s];
-    double* dst = cols + (long)s * len;
-    if (col >= 0) {
-      const double* src = Y + (long)col * len;
-      for (int e = t; e < len; e += kThreads) dst[e] = src[e];
-    } else {
-      for (int e = t; e < len; e += kThreads) dst[e] = 0.0;
+  double z[kNC][R];
+#pragma unroll
+  for (int c = 0; c < kNC; ++c) {
+    const int col = colid[c];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int e = t + kThreads * i;
+      z[c][i] = (col >= 0 && e < len) ? Y[(long)col * len + e] : 0.0;
+    }
+  }
+  // partial Gram entries of this thread's rows, padded to 64 for the
+  // recursive-halving reduction (after it, lane l holds the sum of entry l)
+  double g[64];
+#pragma unroll
+  for (int q = 0; q < 64; ++q) g[q] = 0.0;
+  {
+    int q = 0;
+#pragma unroll
+    for (int x = 0; x < kNC; ++x)
+#pragma unroll
+      for (int y = x; y < kNC; ++y, ++q)
+#pragma unroll
+        for (int i = 0; i < R; ++i) g[q] = fma(z[x][i], z[y][i], g[q]);
+  }
+#pragma unroll
+  for (int h = 32; h >= 1; h >>= 1) {
+    const bool up = (lane & h) != 0;
+#pragma unroll
+    for (int k = 0; k < h; ++k) {
+      const double send = up ? g[k] : g[k + h];
+      const double keep = up ? g[k + h] : g[k];
+      g[k] = keep + __shfl_xor(send, h, 64);
+    }
+  }
+  red[wave][lane] = g[0];
+  __syncthreads();
+
+  // Small Gram G (8 x 8) and accumulated rotation W in LDS.
+  if (t < kPairs) {
+    int x = 0, q = t;
+    while (q >= kNC - x) { q -= kNC - x; ++x; }      // entry t <-> (x, x + q), row-major upper triangle
+    const int y = x + q;
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) v += red[w][t];
+    Gsh[x][y] = v;
+    Gsh[y][x] = v;
+  }
+  if (t < kNC * kNC) Wsh[t / kNC][t % kNC] = (t / kNC == t % kNC) ? 1.0 : 0.0;
+  __syncthreads();
+  const double zth = zrel2 * fro2[0];
+  // Convergence measure from the fresh Gram: largest cosine above tol.
+  if (wave == 0) {
+    double off = 0.0;
+    if (lane < kNC * (kNC - 1) / 2) {
+      int x = 0, q = lane;
+      while (q >= kNC - 1 - x) { q -= kNC - 1 - x; ++x; }
+      const int y = x + 1 + q;
+      const double a = Gsh[x][x], be = Gsh[y][y];
+      if (a > zth && be > zth) {
+        const double c = fabs(Gsh[x][y]) / sqrt(a) / sqrt(be);
+        if (c > tol) off = c;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o, 64));
+    if (lane == 0) {
+      worst_sh = off;
+      // block maximum published as the bit pattern of a non-negative double
+      // (monotone under unsigned comparison)
+      atomicMax(offmax, (unsigned long long)__double_as_longlong(off));
     }
   }
   __syncthreads();
-
-  double worst = 0.0;
-  // one inner sweep: round-robin over the nc slots
-  for (int ir = 0; ir < nc - 1; ++ir) {
-    for (int q = wave; q < b; q += kWaves) {
-      int x, y;
-      rr_pair(nc, ir, q, &x, &y);
-      if (colid[x] < 0 || colid[y] < 0) continue;
-      const int rx = (x < b ? bi : bj) * b + (x < b ? x : x - b);
-      const int ry = (y < b ? bi : bj) * b + (y < b ? y : y - b);
-      if (rx >= kneed && ry >= kneed) continue;
-      double* cx = cols + (long)x * len;
-      double* cy = cols + (long)y * len;
-      double a = 0.0, be = 0.0, g = 0.0;
-      for (int e = lane; e < len; e += 64) {
-        const double u = cx[e], v = cy[e];
-        a = fma(u, u, a);
-        be = fma(v, v, be);
-        g = fma(u, v, g);
-      }
-      a = wave_sum(a);
-      be = wave_sum(be);
-      g = wave_sum(g);
-      if (a > zth && be > zth && g != 0.0) {
-        // converged when the overlap is below the relative tolerance or below
-        // the rounding noise that columns of size sqrt(fro2) leave in it
-        const double sa = sqrt(a), sb = sqrt(be);
-        const double off = fabs(g) / sa / sb;
-        if (fabs(g) > fmax(tol * sa * sb, nscale * (sa + sb))) {
-          worst = fmax(worst, off);
-          const double zeta = (be - a) / (2.0 * g);
+  // One cyclic sweep of two-sided Jacobi on G, parallel over the 4 disjoint
+  // pairs of each round-robin round (the outer iteration recomputes G from
+  // the columns at the next visit).  Columns x' = c x - s y, y' = s x + c y:
+  // G <- J^T G J, W <- W J.
+  if (worst_sh > 0.0) {
+    for (int ir = 0; ir < kNC - 1; ++ir) {
+      if (t < kNC / 2) {
+        int x, y;
+        rr_pair(kNC, ir, t, &x, &y);
+        const double a = Gsh[x][x], be = Gsh[y][y], gg = Gsh[x][y];
+        double c = 1.0, sn = 0.0;
+        if (a > zth && be > zth && fabs(gg) > tol * sqrt(a) * sqrt(be)) {
+          const double zeta = (be - a) / (2.0 * gg);
           const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
-          const double c = 1.0 / sqrt(fma(tt, tt, 1.0));
-          const double s = c * tt;
-          for (int e = lane; e < len; e += 64) {
-            const double u = cx[e], v = cy[e];
-            cx[e] = c * u - s * v;
-            cy[e] = s * u + c * v;
-          }
+          c = 1.0 / sqrt(fma(tt, tt, 1.0));
+          sn = c * tt;
+        }
+        rot_c[t] = c;
+        rot_s[t] = sn;
+        rot_x[t] = x;
+        rot_y[t] = y;
+      }
+      __syncthreads();
+      if (t < 2 * kNC * (kNC / 2)) {             // columns x, y of G and of W
+        const int q = (t / kNC) % (kNC / 2), k = t % kNC;
+        const int x = rot_x[q], y = rot_y[q];
+        const double c = rot_c[q], sn = rot_s[q];
+        if (t < kNC * (kNC / 2)) {
+          const double gx = Gsh[k][x], gy = Gsh[k][y];
+          Gsh[k][x] = c * gx - sn * gy;
+          Gsh[k][y] = sn * gx + c * gy;
+        } else {
+          const double wx = Wsh[k][x], wy = Wsh[k][y];
+          Wsh[k][x] = c * wx - sn * wy;
+          Wsh[k][y] = sn * wx + c * wy;
         }
       }
+      __syncthreads();
+      if (t < kNC * (kNC / 2)) {                 // rows x, y of G
+        const int q = t / kNC, k = t % kNC;
+        const int x = rot_x[q], y = rot_y[q];
+        const double c = rot_c[q], sn = rot_s[q];
+        const double gx = Gsh[x][k], gy = Gsh[y][k];
+        Gsh[x][k] = c * gx - sn * gy;
+        Gsh[y][k] = sn * gx + c * gy;
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 
-  for (int s = 0; s < nc; ++s) {
-    const int col = colid[s];
-    if (col >= 0) {
-      const double* src = cols + (long)s * len;
-      double* dst = Y + (long)col * len;
-      for (int e = t; e < len; e += kThreads) dst[e] = src[e];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int e = t + kThreads * i;
+    if (e >= len) continue;
+#pragma unroll
+    for (int c = 0; c < kNC; ++c) {
+      const int col = colid[c];
+      if (col < 0) continue;
+      double v = 0.0;
+#pragma unroll
+      for (int j = 0; j < kNC; ++j) v = fma(z[j][i], Wsh[j][c], v);
+      Y[(long)col * len + e] = v;
     }
-  }
-  // block-wide max of the cosines seen, published as the bit pattern of a
-  // non-negative double (monotone under unsigned comparison)
-  __shared__ double wmax[kWaves];
-  if (lane == 0) wmax[wave] = worst;
-  __syncthreads();
-  if (t == 0) {
-    double m = 0.0;
-    for (int w = 0; w < kWaves; ++w) m = fmax(m, wmax[w]);
-    atomicMax(offmax, (unsigned long long)__double_as_longlong(m));
   }
 }
 
@@ -210,7 +285,6 @@ __global__ void gather_columns(const double* __restrict__ Z, int len, const doub
   else U[(long)j * ldu + e] = v;
 }
 
-int block_cols(int len) { return std::max(1, std::min(16, 4096 / std::max(len, 1))); }
 
 }  // namespace
 
@@ -223,14 +297,13 @@ static int* sv_perm(double* work, int len, int p) {
 }
 
 void svd_left(int len, int p, const double* Y, double* sigma, int k, double* U, long ldu, int u_rowmajor,
-              double* work, hipStream_t s, int* sweeps_out, int kneed) {
+              double* work, hipStream_t s, int* sweeps_out) {
   if (len <= 0 || p <= 0) {
     if (sweeps_out) *sweeps_out = 0;
     return;
   }
   if (len > 4096) throw Error(-1, "svd_left: column length above 4096");
   if (p > 4096) throw Error(-1, "svd_left: more than 4096 columns");
-  if (kneed <= 0 || kneed > p) kneed = p;
   double* Z = work;
   double* raw = work + (size_t)len * p;
   double* srt = sv_sorted(work, len, p);
@@ -251,7 +324,7 @@ void svd_left(int len, int p, const double* Y, double* sigma, int k, double* U, 
     XTRG_HIP(hipGetLastError());
   };
 
-  const int b = block_cols(len);
+  const int b = kNC / 2;
   int nbk = (p + b - 1) / b;
   if (nbk % 2) ++nbk;
   const double tol = 8.0 * std::sqrt((double)len) * 2.220446049250313e-16;
@@ -263,18 +336,22 @@ void svd_left(int len, int p, const double* Y, double* sigma, int k, double* U, 
   // spread over several columns be gathered before the count is taken.
   const double zrel = 0.25 * svd_keep_rel(len, p);
   const double zrel2 = zrel * zrel;
-  const double noise_coef = 0.0;
-  const size_t lds = sizeof(double) * 2 * b * len;
+  const int R = (len + kThreads - 1) / kThreads;
   int sweeps = 0;
   double last = 0.0;
+  auto round = [&](int r) {
+    const dim3 g(nbk / 2), blk(kThreads);
+    if (R <= 1) hipLaunchKernelGGL(jacobi_round<1>, g, blk, 0, s, Z, len, p, nbk, r, tol, perm, fro2, zrel2, off);
+    else if (R <= 2) hipLaunchKernelGGL(jacobi_round<2>, g, blk, 0, s, Z, len, p, nbk, r, tol, perm, fro2, zrel2, off);
+    else if (R <= 4) hipLaunchKernelGGL(jacobi_round<4>, g, blk, 0, s, Z, len, p, nbk, r, tol, perm, fro2, zrel2, off);
+    else if (R <= 8) hipLaunchKernelGGL(jacobi_round<8>, g, blk, 0, s, Z, len, p, nbk, r, tol, perm, fro2, zrel2, off);
+    else hipLaunchKernelGGL(jacobi_round<16>, g, blk, 0, s, Z, len, p, nbk, r, tol, perm, fro2, zrel2, off);
+  };
   if (p > 1) {
     for (; sweeps < kMaxSweeps; ++sweeps) {
       rank_columns();
       XTRG_HIP(hipMemsetAsync(off, 0, sizeof(unsigned long long), s));
-      for (int r = 0; r < nbk - 1; ++r) {
-        hipLaunchKernelGGL(jacobi_round, dim3(nbk / 2), dim3(kThreads), lds, s, Z, len, p, b, nbk, r, tol,
-                           perm, fro2, zrel2, noise_coef, kneed, off);
-      }
+      for (int r = 0; r < nbk - 1; ++r) round(r);
       XTRG_HIP(hipGetLastError());
       unsigned long long h = 0;
       XTRG_HIP(hipMemcpyAsync(&h, off, sizeof(h), hipMemcpyDeviceToHost, s));
