@@ -103,6 +103,7 @@ def main():
         n_done += 1
         if saturated_at is None and info["D_kept_max"] >= args.D:
             saturated_at = n_done
+        print(f"warm-up doubling {n_done}: max bond {info['D_kept_max']}", file=sys.stderr, flush=True)
         if saturated_at is not None and n_done >= saturated_at + args.warmup:
             break
         if n_done >= wl.n_doublings:
@@ -121,6 +122,7 @@ def main():
         rho = new
         flops += info["flops"]
         steps_2site += info["steps"]
+        print(f"timed doubling done: {info['steps']} two-site steps", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = ctx.profile_report()

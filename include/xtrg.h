@@ -120,6 +120,23 @@ typedef struct {
 int xtrg_square_compress(xtrg_ctx ctx, xtrg_mpo rho_in, const xtrg_compress_opts* opts,
                          xtrg_mpo* rho_out, xtrg_compress_info* info);
 
+/* The same doubling for n independent chains at once, e.g. the interleaved
+ * temperature grids tau0 = 2^(z-1) tau0' of the z-shift average (Sec. II.C),
+ * other couplings, lengths or bond budgets.  Chain q runs with opts[q]; the
+ * chains advance one two-site step each per batch step (each on its own bond
+ * schedule, so lengths and sweep counts may differ), and the latency-bound
+ * SVD rounds of all chains run as one grouped launch.  Each result equals
+ * what xtrg_square_compress returns for that chain alone: the same kernels
+ * on the same data in the same order.
+ * rho_in, opts, rho_out: n entries each.  rho_out entries are set to NULL on
+ * entry; on success all n are new handles, on failure none is left to release.
+ * info: NULL or n entries (each with its own optional sv buffer).
+ * Device memory grows with n: one set of per-site environment blocks per
+ * chain (about 4 D^3 (L-1) doubles at bond D). */
+int xtrg_square_compress_batched(xtrg_ctx ctx, int n, const xtrg_mpo* rho_in,
+                                 const xtrg_compress_opts* opts, xtrg_mpo* rho_out,
+                                 xtrg_compress_info* info);
+
 /* Thermodynamics of a normalised MPO rho (rho_true = exp(log_norm) rho),
  * Eq. (ThermalQuan): f = -ln Z/(N beta), u = <H>/N, c = beta^2 (<H^2> - <H>^2)/N.
  * at_tau : beta = tau_n, Z = Tr rho.

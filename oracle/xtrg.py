@@ -68,9 +68,15 @@ def keep_count(S: np.ndarray, D: int, deg_rtol: float, sv_floor: float, abs_floo
     r = max(r, 1)
     if r <= D:
         return r
+    # a gap separates two multiplets only if it exceeds deg_rtol * S[k-1]
+    # plus the absolute rounding noise abs_floor of the values themselves:
+    # a split decided by noise would not be reproducible (deg_rtol = 0
+    # switches the multiplet protection off: cut at exactly D)
+    if deg_rtol <= 0:
+        return D
     lo = max(1, (D + 1) // 2)
     for k in range(D, lo - 1, -1):
-        if S[k - 1] - S[k] > deg_rtol * S[k - 1]:
+        if S[k - 1] - S[k] > deg_rtol * S[k - 1] + abs_floor:
             return k
     return D
 

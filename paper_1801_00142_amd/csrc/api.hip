@@ -172,6 +172,9 @@ double read_scalar(xtrg_ctx c, const double* d) {
   return h;
 }
 
+// Device descriptors of a grouped SVD launch over n problems.
+void* svd_desc(xtrg_ctx c, int n) { return c->need("svd_desc", xtrg::svd_desc_bytes(n) / sizeof(double) + 1); }
+
 void gemm(xtrg_ctx c, const Gemm& g) {
   const size_t w = xtrg::gemm_splitk_work(g);
   double* work = w ? c->need("splitk", w) : nullptr;
@@ -307,9 +310,13 @@ int keep_count(const std::vector<double>& S, int D, double deg_rtol, double floo
     if (v > f) ++r;
   r = std::max(r, 1);
   if (r <= D) return r;
+  // a gap separates two multiplets only if it exceeds deg_rtol * S[k-1]
+  // plus the absolute rounding noise abs_floor of the values themselves
+  // (deg_rtol = 0 switches the multiplet protection off: cut at exactly D)
+  if (!(deg_rtol > 0)) return D;
   const int lo = std::max(1, (D + 1) / 2);
   for (int k = D; k >= lo; --k)
-    if (S[k - 1] - S[k] > deg_rtol * S[k - 1]) return k;
+    if (S[k - 1] - S[k] > deg_rtol * S[k - 1] + abs_floor) return k;
   return D;
 }
 
@@ -374,7 +381,7 @@ void left_sweep(xtrg_mpo m, double floor, std::vector<std::vector<double>>* sv) 
     // note: transpose(dst, ldd, src, lds, R, C) reads src column-major (C cols of R);
     // the site matrix [rows][Dr] row-major is (Dr x rows) column-major.
     double* work = c->need("cs_work", xtrg::svd_work(rows, Dr));
-    xtrg::svd_left(rows, Dr, Y, nullptr, 0, nullptr, 0, 0, work, s, nullptr);
+    xtrg::svd_left(rows, Dr, Y, nullptr, 0, nullptr, 0, 0, work, svd_desc(c, 1), s, nullptr);
     std::vector<double> S = read_vec(c, xtrg::svd_sorted_values(work, rows, Dr), Dr);
     const int lim = std::min(rows, Dr);
     S.resize(lim);
@@ -408,7 +415,7 @@ void right_sweep(xtrg_mpo m, double floor, int Dmax, std::vector<std::vector<dou
     const int Dl = m->dims[i], Dr = m->dims[i + 1], Dp = m->dims[i - 1];
     const int len = 4 * Dr;
     double* work = c->need("cs_work", xtrg::svd_work(len, Dl));
-    xtrg::svd_left(len, Dl, m->site[i].p, nullptr, 0, nullptr, 0, 0, work, s, nullptr);
+    xtrg::svd_left(len, Dl, m->site[i].p, nullptr, 0, nullptr, 0, 0, work, svd_desc(c, 1), s, nullptr);
     std::vector<double> S = read_vec(c, xtrg::svd_sorted_values(work, len, Dl), Dl);
     S.resize(std::min(len, Dl));
     const double nf = noise_floor(c, work, len, Dl);
@@ -475,17 +482,14 @@ struct Doubler {
   std::vector<int> cap;                 // largest possible bond of C
   std::vector<const double*> A;         // rho sites
   std::vector<double*> Bp;              // rho sites with the physical indices swapped
-  std::vector<DevBuf> slot;             // Lb_i or Rb_i
+  std::string tag;                      // suffix of the chain's workspace names
   std::vector<Site> C;                  // output sites (capacity at cap)
+  std::map<int, double*> slot;          // Lb_i or Rb_i: one named workspace per site
 
-  double* slot_need(int i, size_t n) {
-    DevBuf& d = slot[i];
-    if (d.cap < n) {
-      c->release(d.p, d.cap);
-      d.p = c->alloc(n);
-      d.cap = n;
-    }
-    return d.p;
+  // Slot i holds Lb_i (4 cap_i Da_{i+1}^2) or Rb_i (Da_i^2 4 cap_{i+1}).
+  double* slot_need(int i) {
+    const size_t n = std::max((size_t)4 * cap[i] * Da[i + 1] * Da[i + 1], (size_t)Da[i] * Da[i] * 4 * cap[i + 1]);
+    return slot[i] = c->need("slot" + std::to_string(i) + tag, n);
   }
 
   // Lb[(c,s,s'')][(a',b')] = sum_{a,b,s'} E[c][a][b] A_i[a][s][s'][a'] A_i[b][s'][s''][b']
@@ -540,170 +544,260 @@ struct Doubler {
   }
 };
 
-void square_compress_impl(xtrg_ctx c, xtrg_mpo in, const xtrg_compress_opts& o, xtrg_mpo* out,
-                          xtrg_compress_info* info) {
-  const int L = in->L;
-  if (L < 2) throw Error(XTRG_EINVAL, "square_compress needs at least two sites");
+// State of one chain of a (possibly batched) doubling.
+struct Chain {
+  Doubler d;
+  xtrg_compress_opts o;
+  std::vector<Step> sched;
+  std::string tag;                        // suffix of this chain's workspace names
+  double* E = nullptr;                    // left environment of the current bond
+  double* F = nullptr;                    // right environment
+  double* th = nullptr;                   // two-site overlap C_E
+  double* work = nullptr;                 // SVD workspace
+  std::vector<std::vector<double>> sv;
+  std::vector<int> kept;
+  std::vector<double> disc;
+  double flops = 0.0, last_norm = 0.0;
+  // current step
+  int i = 0;
+  bool gauge_right = false;
+  double* Lb = nullptr;
+  double* Rb = nullptr;
+  int mL = 0, mR = 0, Kt = 0, len = 0, p = 0;
+};
+
+void check_opts(const xtrg_compress_opts& o) {
   if (o.D_max < 1 || o.n_sweeps < 1) throw Error(XTRG_EINVAL, "D_max and n_sweeps must be >= 1");
   if (o.precision != XTRG_FP64) throw Error(XTRG_EINVAL, "only XTRG_FP64 is available");
+}
+
+// Set up chain q: initial guess C = rho, swapped copies of rho's sites, and
+// the static right blocks Rb_j, j = L-1 .. 1 (the first left-to-right
+// half-sweep reads Rb_{i+1} for every bond i).
+void chain_setup(xtrg_ctx c, Chain& C, xtrg_mpo in, int q) {
   hipStream_t s = c->stream;
-  Doubler d;
+  const int L = in->L;
+  Doubler& d = C.d;
+  C.tag = q == 0 ? "" : "#" + std::to_string(q);
+  C.sched = schedule(L, C.o.n_sweeps);
   d.c = c;
   d.L = L;
+  d.tag = C.tag;
   d.Da = in->dims;
   d.Dc = in->dims;                         // initial guess C = rho (right-canonical)
   d.cap.resize(L + 1);
   for (int i = 0; i <= L; ++i) {
     double cp = 1.0;
-    for (int q = 0; q < std::min(i, L - i) && cp < 1e9; ++q) cp *= 4.0;
-    d.cap[i] = (int)std::min<double>(cp, (double)std::max(o.D_max, in->dims[i]));
+    for (int k = 0; k < std::min(i, L - i) && cp < 1e9; ++k) cp *= 4.0;
+    d.cap[i] = (int)std::min<double>(cp, (double)std::max(C.o.D_max, in->dims[i]));
   }
   d.A.resize(L);
   d.Bp.resize(L);
   d.C.resize(L);
-  d.slot.resize(L);
   for (int i = 0; i < L; ++i) {
     d.A[i] = in->site[i].p;
-    d.Bp[i] = c->need("Bp" + std::to_string(i), in->elems(i));
+    d.Bp[i] = c->need("Bp" + std::to_string(i) + C.tag, in->elems(i));
     xtrg::swap_phys(d.Bp[i], in->site[i].p, in->dims[i], in->dims[i + 1], s);
     d.C[i].n = (size_t)d.cap[i] * 4 * d.cap[i + 1];
-    d.C[i].p = c->need("C" + std::to_string(i), d.C[i].n);
+    d.C[i].p = c->need("C" + std::to_string(i) + C.tag, d.C[i].n);
     xtrg::copy(d.C[i].p, in->site[i].p, in->elems(i), s);
   }
   size_t env_max = 1;
   for (int i = 0; i <= L; ++i) env_max = std::max(env_max, (size_t)d.cap[i] * d.Da[i] * d.Da[i]);
-  double* E = c->need("E", env_max);
-  double* F = c->need("F", env_max);
-  xtrg::fill(E, 1.0, 1, s);
-  xtrg::fill(F, 1.0, 1, s);
-  auto lb_size = [&](int i) { return (size_t)4 * d.cap[i] * d.Da[i + 1] * d.Da[i + 1]; };
-  auto rb_size = [&](int j) { return (size_t)d.Da[j] * d.Da[j] * 4 * d.cap[j + 1]; };
-
-  // static right blocks Rb_j, j = L-1 .. 1, from C = rho (the first
-  // left-to-right half-sweep reads Rb_{i+1} for every bond i)
+  C.E = c->need("E" + C.tag, env_max);
+  C.F = c->need("F" + C.tag, env_max);
+  xtrg::fill(C.E, 1.0, 1, s);
+  xtrg::fill(C.F, 1.0, 1, s);
+  C.sv.resize(L - 1);
+  C.kept.assign(L - 1, 1);
+  C.disc.assign(L - 1, 0.0);
   for (int j = L - 1; j >= 1; --j) {
-    double* Rb = d.slot_need(j, std::max(lb_size(j), rb_size(j)));
-    d.right_block(j, F, Rb);
+    double* Rb = d.slot_need(j);
+    d.right_block(j, C.F, Rb);
     if (j == 1) break;
     const int mR = 4 * d.Dc[j + 1];
     const int k = d.Dc[j];
-    gemm(c, plain(d.Da[j] * d.Da[j], k, mR, Rb, mR, false, d.C[j].p, mR, true, F, k));
+    gemm(c, plain(d.Da[j] * d.Da[j], k, mR, Rb, mR, false, d.C[j].p, mR, true, C.F, k));
+  }
+}
+
+// After the SVD of the chain's two-site overlap: choose k, split into C_i and
+// C_{i+1} (the side the sweep moves away from takes the isometry), and
+// advance the environment on that side.
+void chain_truncate_split(xtrg_ctx c, Chain& C) {
+  hipStream_t s = c->stream;
+  auto& d = C.d;
+  const int i = C.i;
+  const int mL = C.mL, mR = C.mR, Kt = C.Kt, len = C.len, p = C.p;
+  std::vector<double> S = read_vec(c, xtrg::svd_sorted_values(C.work, len, p), p);
+  S.resize(std::min(mL, mR));
+  for (double v : S)
+    if (!std::isfinite(v)) throw Error(XTRG_ENUMERIC, "non-finite singular value");
+  const int k = keep_count(S, C.o.D_max, C.o.degen_rtol, C.o.sv_floor, noise_floor(c, C.work, len, p));
+  double tot = 0.0, kw = 0.0;
+  for (size_t q = 0; q < S.size(); ++q) {
+    tot += S[q] * S[q];
+    if ((int)q < k) kw += S[q] * S[q];
+  }
+  if (!(tot > 0)) throw Error(XTRG_ENUMERIC, "zero two-site tensor");
+  C.sv[i] = S;
+  C.kept[i] = k;
+  C.disc[i] = (tot - kw) / tot;
+  C.last_norm = std::sqrt(kw);
+  double* Ci = d.C[i].p;
+  double* Cn = d.C[i + 1].p;
+  if (C.gauge_right) {
+    {
+      Timed tm(c, P_SPLIT, 2.0 * k * (double)mL * mR, 0.0);
+      xtrg::svd_gather(len, p, C.work, k, Ci, k, 1, s);                               // C_i = U [mL][k]
+      orthonormalize(c, Ci, mL, k, true);
+      gemm(c, plain(k, mR, mL, Ci, k, true, C.th, mL, true, Cn, mR));                 // C_{i+1} = U^T theta
+    }
+    Timed tm(c, P_ENV, 2.0 * k * (double)Kt * mL, 8.0 * ((double)mL * Kt + (double)k * Kt));
+    gemm(c, plain(k, Kt, mL, Ci, k, true, C.Lb, Kt, false, C.E, Kt));                  // E_{i+1} = C_i^T Lb
+  } else {
+    {
+      Timed tm(c, P_SPLIT, 2.0 * k * (double)mL * mR, 0.0);
+      xtrg::svd_gather(len, p, C.work, k, Cn, len, 0, s);                             // C_{i+1} = V^T [k][mR]
+      orthonormalize(c, Cn, mR, k, false);
+      gemm(c, plain(mL, k, mR, C.th, mR, false, Cn, mR, true, Ci, k));                // C_i = theta V
+    }
+    Timed tm(c, P_ENV, 2.0 * k * (double)Kt * mR, 8.0 * ((double)mR * Kt + (double)k * Kt));
+    gemm(c, plain(d.Da[i + 1] * d.Da[i + 1], k, mR, C.Rb, mR, false, Cn, mR, true, C.F, k));  // F_{i+1}
+  }
+  d.Dc[i + 1] = k;
+}
+
+// One XTRG doubling of n independent chains at once.  Every chain follows
+// its own bond schedule (lengths and sweep counts may differ); step st of
+// all chains that still have one is issued together: the GEMMs per chain on
+// the one stream, and the Jacobi rounds of all their SVDs as one grouped
+// launch per round.  n = 1 is the plain single-chain doubling.
+void square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_compress_opts* opts,
+                          xtrg_mpo* outs, xtrg_compress_info* infos) {
+  if (n < 1) throw Error(XTRG_EINVAL, "need at least one chain");
+  for (int q = 0; q < n; ++q) {
+    if (!ins[q]) throw Error(XTRG_EINVAL, "null input MPO");
+    if (ins[q]->ctx != c) throw Error(XTRG_EINVAL, "input MPO belongs to another context");
+    if (ins[q]->L < 2) throw Error(XTRG_EINVAL, "square_compress needs at least two sites");
+    check_opts(opts[q]);
+  }
+  hipStream_t s = c->stream;
+  std::vector<Chain> ch(n);
+  size_t n_steps = 0;
+  for (int q = 0; q < n; ++q) {
+    ch[q].o = opts[q];
+    chain_setup(c, ch[q], ins[q], q);
+    n_steps = std::max(n_steps, ch[q].sched.size());
   }
 
-  const auto sched = schedule(L, o.n_sweeps);
-  std::vector<std::vector<double>> sv(L - 1);
-  std::vector<int> kept(L - 1, 1);
-  std::vector<double> disc(L - 1, 0.0);
-  double flops = 0.0;
-  double last_norm = 0.0;
-  for (size_t st = 0; st < sched.size(); ++st) {
-    const int i = sched[st].bond;
-    const bool final_step = st + 1 == sched.size();
-    bool gauge_right = (sched[st].dir > 0) != (sched[st].last && !final_step);
-    if (final_step) gauge_right = false;
-    double* Lb;
-    double* Rb;
-    const int mL = 4 * d.Dc[i], mR = 4 * d.Dc[i + 2];
-    const int Kt = d.Da[i + 1] * d.Da[i + 1];
-    const double sflops = Doubler::step_flops(d.Dc[i], d.Da[i], d.Da[i], d.Da[i + 1], d.Da[i + 1], d.Dc[i + 2]);
-    flops += sflops;
+  std::vector<Chain*> act;
+  std::vector<xtrg::SvdJob> jobs;
+  for (size_t st = 0; st < n_steps; ++st) {
+    act.clear();
+    for (auto& C : ch) {
+      if (st >= C.sched.size()) continue;
+      const Step& sp = C.sched[st];
+      const bool final_step = st + 1 == C.sched.size();
+      C.i = sp.bond;
+      C.gauge_right = final_step ? false : (sp.dir > 0) != sp.last;
+      act.push_back(&C);
+    }
     {
       // left block: 8 Dc Da Db Da' + 16 Dc Da' Db Db' (two substeps of Fig. VMPO(c));
       // the right block mirrors it with the right bond of C
-      double fb;
-      if (sched[st].dir > 0)
-        fb = 8.0 * d.Dc[i] * d.Da[i] * (double)d.Da[i] * d.Da[i + 1] +
-             16.0 * d.Dc[i] * d.Da[i + 1] * (double)d.Da[i] * d.Da[i + 1];
-      else
-        fb = 8.0 * d.Dc[i + 2] * d.Da[i + 2] * (double)d.Da[i + 2] * d.Da[i + 1] +
-             16.0 * d.Dc[i + 2] * d.Da[i + 1] * (double)d.Da[i + 2] * d.Da[i + 1];
+      double fb = 0.0;
+      for (Chain* C : act) {
+        const auto& d = C->d;
+        const int i = C->i;
+        if (C->sched[st].dir > 0)
+          fb += 8.0 * d.Dc[i] * d.Da[i] * (double)d.Da[i] * d.Da[i + 1] +
+                16.0 * d.Dc[i] * d.Da[i + 1] * (double)d.Da[i] * d.Da[i + 1];
+        else
+          fb += 8.0 * d.Dc[i + 2] * d.Da[i + 2] * (double)d.Da[i + 2] * d.Da[i + 1] +
+                16.0 * d.Dc[i + 2] * d.Da[i + 1] * (double)d.Da[i + 2] * d.Da[i + 1];
+      }
       Timed tm(c, P_BLOCK, fb, 0.0);
-      if (sched[st].dir > 0) {
-        Lb = d.slot_need(i, std::max(lb_size(i), rb_size(i)));
-        d.left_block(i, E, Lb);
-        Rb = d.slot[i + 1].p;
-      } else {
-        Rb = d.slot_need(i + 1, std::max(lb_size(i + 1), rb_size(i + 1)));
-        d.right_block(i + 1, F, Rb);
-        Lb = d.slot[i].p;
+      for (Chain* C : act) {
+        auto& d = C->d;
+        const int i = C->i;
+        if (C->sched[st].dir > 0) {
+          C->Lb = d.slot_need(i);
+          d.left_block(i, C->E, C->Lb);
+          C->Rb = d.slot.at(i + 1);
+        } else {
+          C->Rb = d.slot_need(i + 1);
+          d.right_block(i + 1, C->F, C->Rb);
+          C->Lb = d.slot.at(i);
+        }
       }
     }
-    double* th = c->need("theta", (size_t)mL * mR);
-    const int len = gauge_right ? mL : mR, p = gauge_right ? mR : mL;
     {
-      Timed tm(c, P_THETA, 2.0 * mL * (double)mR * Kt, 8.0 * ((double)mL * Kt + (double)Kt * mR + (double)mL * mR));
-      Gemm g = gauge_right ? plain(mR, mL, Kt, Rb, mR, true, Lb, Kt, true, th, mL)    // theta column-major
-                           : plain(mL, mR, Kt, Lb, Kt, false, Rb, mR, false, th, mR);  // theta row-major
-      g.tag = 1;
-      gemm(c, g);
+      double fth = 0.0, bth = 0.0;
+      for (Chain* C : act) {
+        const auto& d = C->d;
+        const int i = C->i;
+        C->mL = 4 * d.Dc[i];
+        C->mR = 4 * d.Dc[i + 2];
+        C->Kt = d.Da[i + 1] * d.Da[i + 1];
+        C->len = C->gauge_right ? C->mL : C->mR;
+        C->p = C->gauge_right ? C->mR : C->mL;
+        C->flops += Doubler::step_flops(d.Dc[i], d.Da[i], d.Da[i], d.Da[i + 1], d.Da[i + 1], d.Dc[i + 2]);
+        C->th = c->need("theta" + C->tag, (size_t)C->mL * C->mR);
+        C->work = c->need("svd" + C->tag, xtrg::svd_work(C->len, C->p));
+        fth += 2.0 * C->mL * (double)C->mR * C->Kt;
+        bth += 8.0 * ((double)C->mL * C->Kt + (double)C->Kt * C->mR + (double)C->mL * C->mR);
+      }
+      Timed tm(c, P_THETA, fth, bth);
+      for (Chain* C : act) {
+        Gemm g = C->gauge_right
+                     ? plain(C->mR, C->mL, C->Kt, C->Rb, C->mR, true, C->Lb, C->Kt, true, C->th, C->mL)  // column-major
+                     : plain(C->mL, C->mR, C->Kt, C->Lb, C->Kt, false, C->Rb, C->mR, false, C->th, C->mR);
+        g.tag = 1;
+        gemm(c, g);
+      }
     }
-    double* work = c->need("svd", xtrg::svd_work(len, p));
     {
-      Timed tm(c, P_SVD, 0.0, 8.0 * len * (double)p);
-      int sw = 0;
-      xtrg::svd_left(len, p, th, nullptr, 0, nullptr, 0, 0, work, s, &sw);
-      c->svd_calls += 1;
-      c->svd_sweeps += sw;
-    }
-    std::vector<double> S = read_vec(c, xtrg::svd_sorted_values(work, len, p), p);
-    S.resize(std::min(mL, mR));
-    for (double v : S)
-      if (!std::isfinite(v)) throw Error(XTRG_ENUMERIC, "non-finite singular value");
-    const int k = keep_count(S, o.D_max, o.degen_rtol, o.sv_floor, noise_floor(c, work, len, p));
-    double tot = 0.0, kw = 0.0;
-    for (size_t q = 0; q < S.size(); ++q) {
-      tot += S[q] * S[q];
-      if ((int)q < k) kw += S[q] * S[q];
-    }
-    if (!(tot > 0)) throw Error(XTRG_ENUMERIC, "zero two-site tensor");
-    sv[i] = S;
-    kept[i] = k;
-    disc[i] = (tot - kw) / tot;
-    last_norm = std::sqrt(kw);
-    double* Ci = d.C[i].p;
-    double* Cn = d.C[i + 1].p;
-    if (gauge_right) {
-      {
-        Timed tm(c, P_SPLIT, 2.0 * k * (double)mL * mR, 0.0);
-        xtrg::svd_gather(len, p, work, k, Ci, k, 1, s);                                 // C_i = U [mL][k]
-        orthonormalize(c, Ci, mL, k, true);
-        gemm(c, plain(k, mR, mL, Ci, k, true, th, mL, true, Cn, mR));                  // C_{i+1} = U^T theta
+      double bs = 0.0;
+      jobs.clear();
+      for (Chain* C : act) {
+        jobs.push_back(xtrg::SvdJob{C->len, C->p, C->th, C->work, 0});
+        bs += 8.0 * C->len * (double)C->p;
       }
-      Timed tm(c, P_ENV, 2.0 * k * (double)Kt * mL, 8.0 * ((double)mL * Kt + (double)k * Kt));
-      gemm(c, plain(k, Kt, mL, Ci, k, true, Lb, Kt, false, E, Kt));                    // E_{i+1} = C_i^T Lb
-    } else {
-      {
-        Timed tm(c, P_SPLIT, 2.0 * k * (double)mL * mR, 0.0);
-        xtrg::svd_gather(len, p, work, k, Cn, len, 0, s);                              // C_{i+1} = V^T [k][mR]
-        orthonormalize(c, Cn, mR, k, false);
-        gemm(c, plain(mL, k, mR, th, mR, false, Cn, mR, true, Ci, k));                 // C_i = theta V
+      Timed tm(c, P_SVD, 0.0, bs);
+      xtrg::svd_batched(jobs, svd_desc(c, (int)jobs.size()), s);
+      for (auto& J : jobs) {
+        c->svd_calls += 1;
+        c->svd_sweeps += J.sweeps;
       }
-      Timed tm(c, P_ENV, 2.0 * k * (double)Kt * mR, 8.0 * ((double)mR * Kt + (double)k * Kt));
-      gemm(c, plain(d.Da[i + 1] * d.Da[i + 1], k, mR, Rb, mR, false, Cn, mR, true, F, k));  // F_{i+1}
     }
-    d.Dc[i + 1] = k;
+    for (Chain* C : act) chain_truncate_split(c, *C);
   }
   // normalise: the centre is site 0 after the final right-to-left step
-  const double cnorm = last_norm;
-  xtrg::scale(d.C[0].p, 1.0 / cnorm, (size_t)4 * d.Dc[1], s);
-  auto m = new_mpo(c, d.Dc);
-  for (int i = 0; i < L; ++i) xtrg::copy(m->site[i].p, d.C[i].p, m->elems(i), s);
-  XTRG_HIP(hipStreamSynchronize(s));
-  // free the per-site caches of this call (slots); keep the named workspaces
-  for (auto& b : d.slot) c->release(b.p, b.cap);
-  if (info) {
-    info->dlog_norm = std::log(cnorm);
-    info->trunc_err_max = *std::max_element(disc.begin(), disc.end());
-    info->sweeps_done = o.n_sweeps;
-    info->D_kept_max = *std::max_element(d.Dc.begin(), d.Dc.end());
-    info->steps = (int)sched.size();
-    info->flops = flops;
-    if (info->sv && info->sv_stride > 0)
-      for (int b = 0; b < L - 1; ++b)
-        for (int q = 0; q < info->sv_stride; ++q)
-          info->sv[(size_t)b * info->sv_stride + q] = q < (int)sv[b].size() ? sv[b][q] : 0.0;
+  std::vector<std::unique_ptr<xtrg_mpo_s>> res(n);
+  for (int q = 0; q < n; ++q) {
+    auto& d = ch[q].d;
+    xtrg::scale(d.C[0].p, 1.0 / ch[q].last_norm, (size_t)4 * d.Dc[1], s);
+    res[q] = new_mpo(c, d.Dc);
+    for (int i = 0; i < d.L; ++i) xtrg::copy(res[q]->site[i].p, d.C[i].p, res[q]->elems(i), s);
   }
-  *out = m.release();
+  XTRG_HIP(hipStreamSynchronize(s));
+  for (int q = 0; q < n; ++q) {
+    const Chain& C = ch[q];
+    if (xtrg_compress_info* info = infos ? infos + q : nullptr) {
+      info->dlog_norm = std::log(C.last_norm);
+      info->trunc_err_max = *std::max_element(C.disc.begin(), C.disc.end());
+      info->sweeps_done = C.o.n_sweeps;
+      info->D_kept_max = *std::max_element(C.d.Dc.begin(), C.d.Dc.end());
+      info->steps = (int)C.sched.size();
+      info->flops = C.flops;
+      if (info->sv && info->sv_stride > 0)
+        for (int b = 0; b < C.d.L - 1; ++b)
+          for (int k = 0; k < info->sv_stride; ++k)
+            info->sv[(size_t)b * info->sv_stride + k] = k < (int)C.sv[b].size() ? C.sv[b][k] : 0.0;
+    }
+  }
+  for (int q = 0; q < n; ++q) outs[q] = res[q].release();
 }
 
 // ---------------------------------------------------------------------------
@@ -1044,7 +1138,17 @@ int xtrg_square_compress(xtrg_ctx c, xtrg_mpo rho_in, const xtrg_compress_opts* 
   if (!c || !rho_in || !opts || !rho_out) return XTRG_EINVAL;
   return guarded(c, [&] {
     set_device(c);
-    square_compress_impl(c, rho_in, *opts, rho_out, info);
+    square_compress_impl(c, 1, &rho_in, opts, rho_out, info);
+  });
+}
+
+int xtrg_square_compress_batched(xtrg_ctx c, int n, const xtrg_mpo* rho_in, const xtrg_compress_opts* opts,
+                                 xtrg_mpo* rho_out, xtrg_compress_info* info) {
+  if (!c || n < 1 || !rho_in || !opts || !rho_out) return XTRG_EINVAL;
+  for (int q = 0; q < n; ++q) rho_out[q] = nullptr;
+  return guarded(c, [&] {
+    set_device(c);
+    square_compress_impl(c, n, rho_in, opts, rho_out, info);
   });
 }
 
@@ -1113,7 +1217,7 @@ int xtrg_dsvd_left(xtrg_ctx c, int len, int p, const double* Y, double* sigma, i
     set_device(c);
     double* work = c->need("svd", xtrg::svd_work(len, p));
     int sw = 0;
-    xtrg::svd_left(len, p, Y, sigma, k, U, len, 0, work, c->stream, &sw);
+    xtrg::svd_left(len, p, Y, sigma, k, U, len, 0, work, svd_desc(c, 1), c->stream, &sw);
     c->svd_calls += 1;
     c->svd_sweeps += sw;
     if (k > 0 && U) orthonormalize(c, U, len, k, false);

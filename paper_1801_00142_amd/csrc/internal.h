@@ -52,8 +52,19 @@ size_t gemm_splitk_work(const Gemm& g);
 // if k > 0, U (device, column-major len x k, leading dim ldu) the leading
 // left singular vectors.  `work` must hold svd_work(len, p) doubles.
 size_t svd_work(int len, int p);
+// desc_dev: device scratch of svd_desc_bytes(n) bytes (n problems).
+size_t svd_desc_bytes(int n);
 void svd_left(int len, int p, const double* Y, double* sigma, int k, double* U, long ldu,
-              int u_rowmajor, double* work, hipStream_t s, int* sweeps_out);
+              int u_rowmajor, double* work, void* desc_dev, hipStream_t s, int* sweeps_out);
+// Several independent SVDs at once: every Jacobi round of all problems is one
+// grouped launch, so latency-bound rounds of independent chains overlap.
+struct SvdJob {
+  int len, p;
+  const double* Y;   // len x p column-major (device)
+  double* work;      // svd_work(len, p) doubles
+  int sweeps;        // out
+};
+void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s);
 
 // Two-stage use: svd_left with k = 0, read the sorted values, then gather.
 void svd_gather(int len, int p, double* work, int k, double* U, long ldu, int u_rowmajor, hipStream_t s);

@@ -3,12 +3,13 @@
 // The columns of Y (len x p, column-major) are made mutually orthogonal by
 // plane rotations from the right, Y V = Z.  The column norms of Z are the
 // singular values and the normalised columns the left singular vectors.
-// Columns are grouped into blocks of 4 by norm rank; each outer round pairs
+// Columns are grouped into blocks of 16 by norm rank; each outer round pairs
 // every block with one other block (round-robin tournament, all pairs met
-// once per sweep) and one workgroup per block pair orthogonalises its 8
-// columns (8 x 8 Gram from the columns, one sweep of small Jacobi on it,
-// one rotation pass).  Sweeps repeat until no pair in a sweep needs a
-// rotation.
+// once per sweep) and one workgroup per block pair orthogonalises its 32
+// columns (32 x 32 Gram from the columns on the matrix cores, one sweep of
+// small Jacobi on it, one rotation pass).  Sweeps repeat until no pair in a
+// sweep needs a rotation.  Several independent problems run in one grouped
+// launch per round (blockIdx.y = problem).
 //
 // Accuracy: the Gram entries are recomputed from the rotated columns at
 // every visit and the stopping test is on those fresh cosines, so singular
@@ -52,175 +53,250 @@ __host__ __device__ inline void rr_pair(int n, int r, int q, int* i, int* j) {
 // One outer round of one-sided block Jacobi.  Block pairing works on
 // ranks: rank q is the column with the q-th largest norm at the start of the
 // sweep (perm[q]), so each block holds columns of similar norm.  A
-// workgroup owns one block pair (kNC = 8 columns): every thread keeps its R
-// rows of the 8 columns in registers, the 8 x 8 Gram matrix of the pair is
-// formed from the columns themselves (fresh dot products every visit),
-// one cyclic two-sided Jacobi sweep is run on that small matrix, and the
-// accumulated 8 x 8 rotation W is applied to the columns in one pass
-// (Z <- Z W).  The convergence measure is the largest cosine
-// |z_i . z_j| / (|z_i| |z_j|) of the fresh Gram that exceeds tol; columns
-// with |z|^2 <= zth are numerically zero and take no part.
-constexpr int kNC = 8;
-constexpr int kPairs = kNC * (kNC + 1) / 2;   // 36 Gram entries
+// workgroup owns one block pair (kNC = 32 columns):
+//  1. the 32 x 32 Gram matrix of the pair is formed from the columns
+//     themselves (fresh dot products every visit): 128-row chunks are staged
+//     in LDS and every wave accumulates its 16 rows of each chunk on the FP64
+//     matrix cores; the wave partials are summed in a fixed order;
+//  2. the convergence measure is the largest cosine |z_i . z_j| / (|z_i| |z_j|)
+//     of that Gram which exceeds tol; columns with |z|^2 <= zth are
+//     numerically zero and take no part.  A pair with nothing to rotate is
+//     left untouched;
+//  3. one cyclic two-sided Jacobi sweep runs on the small Gram in LDS: 31
+//     rounds of 16 disjoint rotations (round r pairs k with k ^ r), each
+//     round one step for all threads (thread (q, k) rotates entries k of
+//     pair q with its row partner), G ping-ponging between two buffers;
+//  4. the accumulated rotation W is applied to the columns in one pass
+//     (Z <- Z W).
+constexpr int kWT = 512;                  // threads of a round workgroup
+constexpr int kWW = kWT / 64;             // its waves
+constexpr int kBlk = 16;                  // columns per block
+constexpr int kNC = 2 * kBlk;             // columns per block pair
+constexpr int kChunk = 128;               // rows per LDS chunk (16 per wave)
+constexpr int kZP = kChunk + 1;           // padded chunk column
+typedef double d4 __attribute__((ext_vector_type(4)));
 
-template <int R>
-__global__ __launch_bounds__(kThreads) void jacobi_round(double* __restrict__ Y, int len, int p, int nbk, int r,
-                                                          double tol, const int* __restrict__ perm,
-                                                          const double* __restrict__ fro2, double zrel2,
-                                                          unsigned long long* __restrict__ offmax) {
-  constexpr int b = kNC / 2;
+// One Jacobi problem of a grouped launch (blockIdx.y selects the problem).
+struct JacobiDesc {
+  double* Z;
+  const int* perm;
+  const double* fro2;
+  unsigned long long* off;
+  double tol, zrel2;
+  int len, p, nbk, active;
+};
+
+// 1/x and 1/sqrt(x) from the hardware estimates refined by two Newton
+// steps (each squares the relative error), to about one unit in the last place.
+__device__ inline double rcp_refined(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ inline double rsq_refined(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  r = fma(0.5 * r, fma(-x * r, r, 1.0), r);
+  return fma(0.5 * r, fma(-x * r, r, 1.0), r);
+}
+
+// Whether the pair with Gram entries [[a, g], [g, b]] needs a rotation:
+// both columns above the numerical-zero threshold zth and the cosine
+// |g| / sqrt(a b) above tol (tested as g^2 > tol^2 a b).  The convergence
+// measure and the rotations use this one test.
+__device__ inline bool needs_rot(double a, double b, double g, double tol2, double zth) {
+  return a > zth && b > zth && g * g > tol2 * (a * b);
+}
+
+// Rotation (c, s) that zeroes the off-diagonal of [[a, g], [g, b]] under
+// columns x' = c x - s y, y' = s x + c y (the smaller of the two angles:
+// t = tan = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (b - a) / 2g);
+// identity if the pair needs none.
+__device__ inline void jacobi_rot(double a, double b, double g, double tol2, double zth, double* c, double* s) {
+  *c = 1.0;
+  *s = 0.0;
+  if (needs_rot(a, b, g, tol2, zth)) {
+    const double zeta = (b - a) * rcp_refined(2.0 * g);
+    const double w = fma(zeta, zeta, 1.0);
+    const double tt = copysign(1.0, zeta) * rcp_refined(fabs(zeta) + w * rsq_refined(w));
+    *c = rsq_refined(fma(tt, tt, 1.0));
+    *s = *c * tt;
+  }
+}
+
+__global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict__ descs, int r) {
+  const JacobiDesc d = descs[blockIdx.y];
+  if (!d.active || r >= d.nbk - 1 || (int)blockIdx.x >= d.nbk / 2) return;
+  double* __restrict__ Y = d.Z;
+  const int len = d.len, p = d.p, nbk = d.nbk;
+  const double tol = d.tol;
   __shared__ int colid[kNC];
-  __shared__ double red[kWaves][64];
-  __shared__ double Gsh[kNC][kNC + 1];
-  __shared__ double Wsh[kNC][kNC + 1];
-  __shared__ double rot_c[kNC / 2], rot_s[kNC / 2];
-  __shared__ int rot_x[kNC / 2], rot_y[kNC / 2];
-  __shared__ double worst_sh;
+  __shared__ double buf[kWW * 3 * 4 * 64];   // chunk [kNC][kZP], then the wave partials
+  __shared__ double G[2][kNC][kNC + 1];
+  __shared__ double Wt[kNC][kNC + 2];         // W transposed: Wt[c][j] = W[j][c]
+  __shared__ double wmax[kWW];
   int bi, bj;
   rr_pair(nbk, r, blockIdx.x, &bi, &bj);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   if (t < kNC) {
-    const int rank = (t < b ? bi : bj) * b + (t < b ? t : t - b);
-    colid[t] = rank < p ? perm[rank] : -1;
+    const int rank = (t < kBlk ? bi : bj) * kBlk + (t % kBlk);
+    colid[t] = rank < p ? d.perm[rank] : -1;
   }
   __syncthreads();
 
-  double z[kNC][R];
+  // 1. Gram tiles (0,0), (0,1), (1,1) of the pair on the matrix cores.
+  d4 acc[3];
 #pragma unroll
-  for (int c = 0; c < kNC; ++c) {
-    const int col = colid[c];
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const int e = t + kThreads * i;
-      z[c][i] = (col >= 0 && e < len) ? Y[(long)col * len + e] : 0.0;
-    }
-  }
-  // partial Gram entries of this thread's rows, padded to 64 for the
-  // recursive-halving reduction (after it, lane l holds the sum of entry l)
-  double g[64];
-#pragma unroll
-  for (int q = 0; q < 64; ++q) g[q] = 0.0;
+  for (int q = 0; q < 3; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
   {
-    int q = 0;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int erow = t & (kChunk - 1), cb = t >> 7;
+    double pre[kNC / 4];                       // this thread's part of the next chunk
+    auto fetch = [&](int e0) {
+      const int e = e0 + erow;
 #pragma unroll
-    for (int x = 0; x < kNC; ++x)
+      for (int j = 0; j < kNC / 4; ++j) {
+        const int col = colid[cb + 4 * j];
+        pre[j] = (col >= 0 && e < len) ? Y[(long)col * len + e] : 0.0;
+      }
+    };
+    fetch(0);
+    for (int e0 = 0; e0 < len; e0 += kChunk) {
 #pragma unroll
-      for (int y = x; y < kNC; ++y, ++q)
+      for (int j = 0; j < kNC / 4; ++j) buf[(cb + 4 * j) * kZP + erow] = pre[j];
+      __syncthreads();
+      if (e0 + kChunk < len) fetch(e0 + kChunk);
 #pragma unroll
-        for (int i = 0; i < R; ++i) g[q] = fma(z[x][i], z[y][i], g[q]);
-  }
-#pragma unroll
-  for (int h = 32; h >= 1; h >>= 1) {
-    const bool up = (lane & h) != 0;
-#pragma unroll
-    for (int k = 0; k < h; ++k) {
-      const double send = up ? g[k] : g[k + h];
-      const double keep = up ? g[k + h] : g[k];
-      g[k] = keep + __shfl_xor(send, h, 64);
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int row = wave * 16 + s4 * 4 + lk;
+        const double a0 = buf[lr * kZP + row], a1 = buf[(kBlk + lr) * kZP + row];
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a0, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a1, acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a1, acc[2], 0, 0, 0);
+      }
+      __syncthreads();
     }
   }
-  red[wave][lane] = g[0];
+  // register q of lane l holds tile row l/16 + 4q, column l%16
+#pragma unroll
+  for (int tt = 0; tt < 3; ++tt)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) buf[((wave * 3 + tt) * 4 + q) * 64 + lane] = acc[tt][q];
+  for (int idx = t; idx < kNC * kNC; idx += kWT) Wt[idx / kNC][idx % kNC] = (idx / kNC == idx % kNC) ? 1.0 : 0.0;
   __syncthreads();
-
-  // Small Gram G (8 x 8) and accumulated rotation W in LDS.
-  if (t < kPairs) {
-    int x = 0, q = t;
-    while (q >= kNC - x) { q -= kNC - x; ++x; }      // entry t <-> (x, x + q), row-major upper triangle
-    const int y = x + q;
+  for (int idx = t; idx < 3 * 256; idx += kWT) {
+    const int tt = idx >> 8, q = (idx >> 6) & 3, l = idx & 63;
     double v = 0.0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) v += red[w][t];
-    Gsh[x][y] = v;
-    Gsh[y][x] = v;
-  }
-  if (t < kNC * kNC) Wsh[t / kNC][t % kNC] = (t / kNC == t % kNC) ? 1.0 : 0.0;
-  __syncthreads();
-  const double zth = zrel2 * fro2[0];
-  // Convergence measure from the fresh Gram: largest cosine above tol.
-  if (wave == 0) {
-    double off = 0.0;
-    if (lane < kNC * (kNC - 1) / 2) {
-      int x = 0, q = lane;
-      while (q >= kNC - 1 - x) { q -= kNC - 1 - x; ++x; }
-      const int y = x + 1 + q;
-      const double a = Gsh[x][x], be = Gsh[y][y];
-      if (a > zth && be > zth) {
-        const double c = fabs(Gsh[x][y]) / sqrt(a) / sqrt(be);
-        if (c > tol) off = c;
-      }
+    for (int w = 0; w < kWW; ++w) v += buf[((w * 3 + tt) * 4 + q) * 64 + l];
+    const int i = (l >> 4) + 4 * q, j = l & 15;
+    const int I = tt == 2 ? kBlk : 0, J = tt == 0 ? 0 : kBlk;
+    if (tt == 1) {
+      G[0][I + i][J + j] = v;
+      G[0][J + j][I + i] = v;
+    } else if (i <= j) {            // diagonal tiles: one triangle, mirrored
+      G[0][I + i][J + j] = v;
+      G[0][J + j][I + i] = v;
     }
+  }
+  __syncthreads();
+
+  // 2. Convergence measure.
+  const double zth = d.zrel2 * d.fro2[0];
+  const double tol2 = tol * tol;
+  double off = 0.0;
+  for (int idx = t; idx < kNC * (kNC - 1) / 2; idx += kWT) {
+    int x = 0, q = idx;
+    while (q >= kNC - 1 - x) {
+      q -= kNC - 1 - x;
+      ++x;
+    }
+    const int y = x + 1 + q;
+    const double a = G[0][x][x], b = G[0][y][y], g = G[0][x][y];
+    if (needs_rot(a, b, g, tol2, zth)) off = fmax(off, fabs(g) / sqrt(a * b));
+  }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o, 64));
-    if (lane == 0) {
-      worst_sh = off;
-      // block maximum published as the bit pattern of a non-negative double
-      // (monotone under unsigned comparison)
-      atomicMax(offmax, (unsigned long long)__double_as_longlong(off));
-    }
-  }
+  for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o, 64));
+  if (lane == 0) wmax[wave] = off;
   __syncthreads();
-  // One cyclic sweep of two-sided Jacobi on G, parallel over the 4 disjoint
-  // pairs of each round-robin round (the outer iteration recomputes G from
-  // the columns at the next visit).  Columns x' = c x - s y, y' = s x + c y:
-  // G <- J^T G J, W <- W J.
-  if (worst_sh > 0.0) {
-    for (int ir = 0; ir < kNC - 1; ++ir) {
-      if (t < kNC / 2) {
-        int x, y;
-        rr_pair(kNC, ir, t, &x, &y);
-        const double a = Gsh[x][x], be = Gsh[y][y], gg = Gsh[x][y];
-        double c = 1.0, sn = 0.0;
-        if (a > zth && be > zth && fabs(gg) > tol * sqrt(a) * sqrt(be)) {
-          const double zeta = (be - a) / (2.0 * gg);
-          const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
-          c = 1.0 / sqrt(fma(tt, tt, 1.0));
-          sn = c * tt;
-        }
-        rot_c[t] = c;
-        rot_s[t] = sn;
-        rot_x[t] = x;
-        rot_y[t] = y;
+  double worst = 0.0;
+#pragma unroll
+  for (int w = 0; w < kWW; ++w) worst = fmax(worst, wmax[w]);
+  // block maximum published as the bit pattern of a non-negative double
+  // (monotone under unsigned comparison)
+  if (t == 0 && worst > 0.0) atomicMax(d.off, (unsigned long long)__double_as_longlong(worst));
+  if (worst == 0.0) return;          // uniform: every thread read the same wmax
+
+  // 3. One sweep of parallel two-sided Jacobi on G; W <- W J per rotation.
+  {
+    const int q = t >> 5, k = t & 31;
+    int src = 0;
+    for (int rr = 1; rr < kNC; ++rr) {
+      const int h = 31 - __clz(rr);                                   // highest bit of rr
+      const int x = ((q >> h) << (h + 1)) | (q & ((1 << h) - 1));    // q-th k with k < (k ^ rr)
+      const int y = x ^ rr;
+      const int kb = k ^ rr;
+      const int kx = min(k, kb), ky = max(k, kb);
+      double c, s, c2, s2;
+      jacobi_rot(G[src][x][x], G[src][y][y], G[src][x][y], tol2, zth, &c, &s);
+      jacobi_rot(G[src][kx][kx], G[src][ky][ky], G[src][kx][ky], tol2, zth, &c2, &s2);
+      const double gkx = G[src][k][x], gky = G[src][k][y];
+      const double gbx = G[src][kb][x], gby = G[src][kb][y];
+      const double hkx = c * gkx - s * gky, hky = s * gkx + c * gky;   // columns rotated
+      const double hbx = c * gbx - s * gby, hby = s * gbx + c * gby;
+      if (k == kx) {                                                     // then rows
+        G[src ^ 1][k][x] = c2 * hkx - s2 * hbx;
+        G[src ^ 1][k][y] = c2 * hky - s2 * hby;
+      } else {
+        G[src ^ 1][k][x] = s2 * hbx + c2 * hkx;
+        G[src ^ 1][k][y] = s2 * hby + c2 * hky;
       }
-      __syncthreads();
-      if (t < 2 * kNC * (kNC / 2)) {             // columns x, y of G and of W
-        const int q = (t / kNC) % (kNC / 2), k = t % kNC;
-        const int x = rot_x[q], y = rot_y[q];
-        const double c = rot_c[q], sn = rot_s[q];
-        if (t < kNC * (kNC / 2)) {
-          const double gx = Gsh[k][x], gy = Gsh[k][y];
-          Gsh[k][x] = c * gx - sn * gy;
-          Gsh[k][y] = sn * gx + c * gy;
-        } else {
-          const double wx = Wsh[k][x], wy = Wsh[k][y];
-          Wsh[k][x] = c * wx - sn * wy;
-          Wsh[k][y] = sn * wx + c * wy;
-        }
-      }
-      __syncthreads();
-      if (t < kNC * (kNC / 2)) {                 // rows x, y of G
-        const int q = t / kNC, k = t % kNC;
-        const int x = rot_x[q], y = rot_y[q];
-        const double c = rot_c[q], sn = rot_s[q];
-        const double gx = Gsh[x][k], gy = Gsh[y][k];
-        Gsh[x][k] = c * gx - sn * gy;
-        Gsh[y][k] = sn * gx + c * gy;
-      }
+      const double wx = Wt[x][k], wy = Wt[y][k];
+      Wt[x][k] = c * wx - s * wy;
+      Wt[y][k] = s * wx + c * wy;
+      src ^= 1;
       __syncthreads();
     }
   }
 
+  // 4. Z <- Z W on this pair's columns, as (Z W)^T = W^T Z^T on the matrix
+  // cores: W^T (the A operand) stays in registers, each wave takes 16-row
+  // tiles of Z (the B operand, 16 consecutive rows of a column per 16 lanes)
+  // and writes the rotated rows back in place (no other wave touches them).
+  {
+    const int lr = lane & 15, lk = lane >> 4;
+    double wa[2][kNC / 4];
 #pragma unroll
-  for (int i = 0; i < R; ++i) {
-    const int e = t + kThreads * i;
-    if (e >= len) continue;
+    for (int I = 0; I < 2; ++I)
 #pragma unroll
-    for (int c = 0; c < kNC; ++c) {
-      const int col = colid[c];
-      if (col < 0) continue;
-      double v = 0.0;
+      for (int kk = 0; kk < kNC / 4; ++kk) wa[I][kk] = Wt[I * 16 + lr][kk * 4 + lk];
+    int cin[kNC / 4];
 #pragma unroll
-      for (int j = 0; j < kNC; ++j) v = fma(z[j][i], Wsh[j][c], v);
-      Y[(long)col * len + e] = v;
+    for (int kk = 0; kk < kNC / 4; ++kk) cin[kk] = colid[kk * 4 + lk];
+    int cout[2][4];
+#pragma unroll
+    for (int I = 0; I < 2; ++I)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cout[I][q] = colid[I * 16 + lk + 4 * q];
+    for (int e0 = wave * 16; e0 < len; e0 += kWW * 16) {
+      const int e = e0 + lr;
+      double zb[kNC / 4];
+#pragma unroll
+      for (int kk = 0; kk < kNC / 4; ++kk)
+        zb[kk] = (cin[kk] >= 0 && e < len) ? Y[(long)cin[kk] * len + e] : 0.0;
+      d4 o[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+      for (int kk = 0; kk < kNC / 4; ++kk) {
+        o[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[0][kk], zb[kk], o[0], 0, 0, 0);
+        o[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[1][kk], zb[kk], o[1], 0, 0, 0);
+      }
+      // register q of lane l: column I*16 + l/16 + 4q of Z W, row e0 + l%16
+      if (e < len) {
+#pragma unroll
+        for (int I = 0; I < 2; ++I)
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (cout[I][q] >= 0) Y[(long)cout[I][q] * len + e] = o[I][q];
+      }
     }
   }
 }
@@ -296,85 +372,114 @@ static int* sv_perm(double* work, int len, int p) {
   return reinterpret_cast<int*>(work + (size_t)len * p + 2 * (size_t)p);
 }
 
-void svd_left(int len, int p, const double* Y, double* sigma, int k, double* U, long ldu, int u_rowmajor,
-              double* work, hipStream_t s, int* sweeps_out) {
-  if (len <= 0 || p <= 0) {
-    if (sweeps_out) *sweeps_out = 0;
-    return;
-  }
-  if (len > 4096) throw Error(-1, "svd_left: column length above 4096");
-  if (p > 4096) throw Error(-1, "svd_left: more than 4096 columns");
-  double* Z = work;
-  double* raw = work + (size_t)len * p;
-  double* srt = sv_sorted(work, len, p);
-  int* perm = sv_perm(work, len, p);
-  double* tail = work + (size_t)len * p + 3 * (size_t)p;
-  unsigned long long* off = reinterpret_cast<unsigned long long*>(tail);
-  double* fro2 = tail + 1;
-  double* part = tail + 2;
-  XTRG_HIP(hipMemcpyAsync(Z, Y, sizeof(double) * len * p, hipMemcpyDeviceToDevice, s));
-  sumsq(Z, (size_t)len * p, fro2, part, s);
+size_t svd_desc_bytes(int n) { return sizeof(JacobiDesc) * (size_t)n + sizeof(unsigned long long) * (size_t)n; }
 
-  int n2 = 1;
-  while (n2 < p) n2 <<= 1;
-  const size_t sort_lds = (sizeof(double) + sizeof(int)) * n2;
-  auto rank_columns = [&]() {
-    hipLaunchKernelGGL(column_norms, dim3((p + 3) / 4), dim3(256), 0, s, Z, len, p, raw);
-    hipLaunchKernelGGL(sort_desc, dim3(1), dim3(1024), sort_lds, s, raw, p, srt, perm);
+void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s) {
+  const int n = (int)jobs.size();
+  if (n == 0) return;
+  JacobiDesc* d_desc = reinterpret_cast<JacobiDesc*>(desc_dev);
+  unsigned long long* d_off = reinterpret_cast<unsigned long long*>(d_desc + n);
+  std::vector<JacobiDesc> h(n);
+  std::vector<int> n2(n);
+  int max_nbk = 0, max_half = 0;
+  for (int j = 0; j < n; ++j) {
+    SvdJob& J = jobs[j];
+    J.sweeps = 0;
+    JacobiDesc& D = h[j];
+    D = JacobiDesc{};
+    D.len = J.len;
+    D.p = J.p;
+    if (J.len <= 0 || J.p <= 0) continue;
+    if (J.len > 4096) throw Error(-1, "svd: column length above 4096");
+    if (J.p > 4096) throw Error(-1, "svd: more than 4096 columns");
+    double* w = J.work;
+    D.Z = w;
+    D.perm = sv_perm(w, J.len, J.p);
+    D.fro2 = w + (size_t)J.len * J.p + 3 * (size_t)J.p + 1;
+    D.off = d_off + j;
+    D.tol = 8.0 * std::sqrt((double)J.len) * 2.220446049250313e-16;
+    // Columns below a quarter of the keep floor are numerically zero: they
+    // are neither rotated nor counted for convergence.  Columns of pure
+    // rounding noise (the null space of a rank-deficient Y) otherwise never
+    // settle, since every rotation leaves them a fresh O(1) relative error.
+    // The margin to the keep floor lets content near the floor that is still
+    // spread over several columns be gathered before the count is taken.
+    const double zrel = 0.25 * svd_keep_rel(J.len, J.p);
+    D.zrel2 = zrel * zrel;
+    D.nbk = (J.p + kBlk - 1) / kBlk;
+    if (D.nbk % 2) ++D.nbk;
+    D.active = J.p > 1;
+    XTRG_HIP(hipMemcpyAsync(w, J.Y, sizeof(double) * J.len * J.p, hipMemcpyDeviceToDevice, s));
+    sumsq(w, (size_t)J.len * J.p, w + (size_t)J.len * J.p + 3 * (size_t)J.p + 1,
+          w + (size_t)J.len * J.p + 3 * (size_t)J.p + 2, s);
+    n2[j] = 1;
+    while (n2[j] < J.p) n2[j] <<= 1;
+    max_nbk = std::max(max_nbk, D.nbk);
+    max_half = std::max(max_half, D.nbk / 2);
+  }
+  auto rank_columns = [&](int j) {
+    const SvdJob& J = jobs[j];
+    double* w = J.work;
+    double* raw = w + (size_t)J.len * J.p;
+    hipLaunchKernelGGL(column_norms, dim3((J.p + 3) / 4), dim3(256), 0, s, w, J.len, J.p, raw);
+    hipLaunchKernelGGL(sort_desc, dim3(1), dim3(1024), (sizeof(double) + sizeof(int)) * n2[j], s, raw, J.p,
+                       sv_sorted(w, J.len, J.p), sv_perm(w, J.len, J.p));
     XTRG_HIP(hipGetLastError());
   };
-
-  const int b = kNC / 2;
-  int nbk = (p + b - 1) / b;
-  if (nbk % 2) ++nbk;
-  const double tol = 8.0 * std::sqrt((double)len) * 2.220446049250313e-16;
-  // Columns below a quarter of the keep floor are numerically zero: they
-  // are neither rotated nor counted for convergence.  Columns of pure
-  // rounding noise (the null space of a rank-deficient Y) otherwise never
-  // settle, since every rotation leaves them a fresh O(1) relative error.
-  // The margin to the keep floor lets content near the floor that is still
-  // spread over several columns be gathered before the count is taken.
-  const double zrel = 0.25 * svd_keep_rel(len, p);
-  const double zrel2 = zrel * zrel;
-  const int R = (len + kThreads - 1) / kThreads;
-  int sweeps = 0;
-  double last = 0.0;
   auto round = [&](int r) {
-    const dim3 g(nbk / 2), blk(kThreads);
-    if (R <= 1) hipLaunchKernelGGL(jacobi_round<1>, g, blk, 0, s, Z, len, p, nbk, r, tol, perm, fro2, zrel2, off);
-    else if (R <= 2) hipLaunchKernelGGL(jacobi_round<2>, g, blk, 0, s, Z, len, p, nbk, r, tol, perm, fro2, zrel2, off);
-    else if (R <= 4) hipLaunchKernelGGL(jacobi_round<4>, g, blk, 0, s, Z, len, p, nbk, r, tol, perm, fro2, zrel2, off);
-    else if (R <= 8) hipLaunchKernelGGL(jacobi_round<8>, g, blk, 0, s, Z, len, p, nbk, r, tol, perm, fro2, zrel2, off);
-    else hipLaunchKernelGGL(jacobi_round<16>, g, blk, 0, s, Z, len, p, nbk, r, tol, perm, fro2, zrel2, off);
+    hipLaunchKernelGGL(jacobi_round, dim3(max_half, n), dim3(kWT), 0, s, d_desc, r);
   };
-  if (p > 1) {
-    for (; sweeps < kMaxSweeps; ++sweeps) {
-      rank_columns();
-      XTRG_HIP(hipMemsetAsync(off, 0, sizeof(unsigned long long), s));
-      for (int r = 0; r < nbk - 1; ++r) round(r);
-      XTRG_HIP(hipGetLastError());
-      unsigned long long h = 0;
-      XTRG_HIP(hipMemcpyAsync(&h, off, sizeof(h), hipMemcpyDeviceToHost, s));
-      XTRG_HIP(hipStreamSynchronize(s));
-      double m;
-      std::memcpy(&m, &h, sizeof(m));
-      if (!(m == m)) throw Error(-4, "svd_left: NaN in input");
-      last = m;
-      if (m == 0.0) { ++sweeps; break; }   // no pair needed a rotation
+  std::vector<unsigned long long> hoff(n);
+  std::vector<double> last(n, 0.0);
+  int n_active = 0;
+  for (auto& D : h) n_active += D.active;
+  bool dirty = true;
+  for (int sweep = 0; n_active > 0; ++sweep) {
+    if (sweep >= kMaxSweeps) {
+      for (int j = 0; j < n; ++j)
+        if (h[j].active)
+          throw Error(-4, "svd: Jacobi did not converge (len " + std::to_string(h[j].len) + ", p " +
+                              std::to_string(h[j].p) + ", largest cosine " + std::to_string(last[j]) + ")");
     }
-    if (sweeps >= kMaxSweeps)
-      throw Error(-4, "svd_left: Jacobi did not converge (len " + std::to_string(len) + ", p " +
-                          std::to_string(p) + ", largest cosine " + std::to_string(last) + ")");
-  }
-  rank_columns();
-  if (sigma) XTRG_HIP(hipMemcpyAsync(sigma, srt, sizeof(double) * p, hipMemcpyDeviceToDevice, s));
-  if (k > 0 && U) {
-    const long n = (long)len * k;
-    hipLaunchKernelGGL(gather_columns, dim3((n + 255) / 256), dim3(256), 0, s, Z, len, srt, perm, k, U, ldu,
-                       u_rowmajor);
+    for (int j = 0; j < n; ++j)
+      if (h[j].active) rank_columns(j);
+    if (dirty) {   // the active set changed: refresh the device descriptors
+      XTRG_HIP(hipMemcpyAsync(d_desc, h.data(), sizeof(JacobiDesc) * n, hipMemcpyHostToDevice, s));
+      dirty = false;
+    }
+    XTRG_HIP(hipMemsetAsync(d_off, 0, sizeof(unsigned long long) * n, s));
+    for (int r = 0; r < max_nbk - 1; ++r) round(r);
     XTRG_HIP(hipGetLastError());
+    XTRG_HIP(hipMemcpyAsync(hoff.data(), d_off, sizeof(unsigned long long) * n, hipMemcpyDeviceToHost, s));
+    XTRG_HIP(hipStreamSynchronize(s));
+    for (int j = 0; j < n; ++j) {
+      if (!h[j].active) continue;
+      double m;
+      std::memcpy(&m, &hoff[j], sizeof(m));
+      if (!(m == m)) throw Error(-4, "svd: NaN in input");
+      last[j] = m;
+      jobs[j].sweeps = sweep + 1;
+      if (m == 0.0) {            // no pair needed a rotation
+        h[j].active = 0;
+        --n_active;
+        dirty = true;
+      }
+    }
   }
-  if (sweeps_out) *sweeps_out = sweeps;
+  for (int j = 0; j < n; ++j)
+    if (jobs[j].len > 0 && jobs[j].p > 0) rank_columns(j);
+}
+
+void svd_left(int len, int p, const double* Y, double* sigma, int k, double* U, long ldu, int u_rowmajor,
+              double* work, void* desc_dev, hipStream_t s, int* sweeps_out) {
+  std::vector<SvdJob> jobs(1);
+  jobs[0] = SvdJob{len, p, Y, work, 0};
+  svd_batched(jobs, desc_dev, s);
+  if (len > 0 && p > 0) {
+    if (sigma) XTRG_HIP(hipMemcpyAsync(sigma, sv_sorted(work, len, p), sizeof(double) * p, hipMemcpyDeviceToDevice, s));
+    if (k > 0 && U) svd_gather(len, p, work, k, U, ldu, u_rowmajor, s);
+  }
+  if (sweeps_out) *sweeps_out = jobs[0].sweeps;
 }
 
 // Second stage after the caller has chosen k from the sorted values.

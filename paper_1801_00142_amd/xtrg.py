@@ -64,6 +64,8 @@ def load_library(path: Optional[str] = None):
         "xtrg_init_rho": (C.c_int, [vp, vp, C.c_double, C.c_int, C.c_int, C.POINTER(vp), dp]),
         "xtrg_square_compress": (C.c_int, [vp, vp, C.POINTER(CompressOpts), C.POINTER(vp),
                                            C.POINTER(CompressInfo)]),
+        "xtrg_square_compress_batched": (C.c_int, [vp, C.c_int, C.POINTER(vp), C.POINTER(CompressOpts),
+                                                   C.POINTER(vp), C.POINTER(CompressInfo)]),
         "xtrg_observables": (C.c_int, [vp, vp, C.c_double, C.c_double, vp, C.c_int, C.POINTER(Obs),
                                        C.POINTER(Obs), dp]),
         "xtrg_dgemm": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, vp, C.c_long, vp,
@@ -83,7 +85,7 @@ def load_library(path: Optional[str] = None):
 def exported_symbols() -> List[str]:
     return ["xtrg_ctx_create", "xtrg_ctx_destroy", "xtrg_last_error", "xtrg_ctx_bytes",
             "xtrg_hamiltonian_xxz", "xtrg_mpo_from_host", "xtrg_mpo_shape", "xtrg_mpo_to_host",
-            "xtrg_mpo_destroy", "xtrg_init_rho", "xtrg_square_compress", "xtrg_observables",
+            "xtrg_mpo_destroy", "xtrg_init_rho", "xtrg_square_compress", "xtrg_square_compress_batched", "xtrg_observables",
             "xtrg_dgemm", "xtrg_dsvd_left", "xtrg_profile_enable", "xtrg_profile_report"]
 
 
@@ -206,6 +208,39 @@ class Context:
         if buf is not None:
             out["sv"] = buf
         return MPO(self, h), out
+
+    def square_compress_batched(self, rhos: Sequence[MPO], D_max, n_sweeps=4,
+                                degen_rtol: float = 1e-6, sv_floor: float = 1e-14, sv_stride: int = 0):
+        """One doubling of every chain in `rhos` together.  D_max and n_sweeps
+        are one value for all chains or a sequence with one per chain.
+        Returns ([new MPO per chain], [info dict per chain])."""
+        n = len(rhos)
+        Ds = list(D_max) if isinstance(D_max, (list, tuple)) else [D_max] * n
+        Ss = list(n_sweeps) if isinstance(n_sweeps, (list, tuple)) else [n_sweeps] * n
+        if len(Ds) != n or len(Ss) != n:
+            raise ValueError("one D_max and n_sweeps per chain")
+        o = (CompressOpts * n)(*[CompressOpts(Ds[q], Ss[q], XTRG_FP64, degen_rtol, sv_floor) for q in range(n)])
+        infos = (CompressInfo * n)()
+        bufs = []
+        for q, r in enumerate(rhos):
+            if sv_stride > 0:
+                b = np.zeros((r.shape()[0] - 1, sv_stride))
+                infos[q].sv = b.ctypes.data_as(C.POINTER(C.c_double))
+                infos[q].sv_stride = sv_stride
+                bufs.append(b)
+        hin = (C.c_void_p * n)(*[r.h for r in rhos])
+        hout = (C.c_void_p * n)()
+        _check(self, _lib.xtrg_square_compress_batched(self.h, n, hin, o, hout, infos))
+        outs, dicts = [], []
+        for q in range(n):
+            outs.append(MPO(self, C.c_void_p(hout[q])))
+            d = dict(dlog_norm=infos[q].dlog_norm, trunc_err_max=infos[q].trunc_err_max,
+                     sweeps=infos[q].sweeps_done, D_kept_max=infos[q].D_kept_max, steps=infos[q].steps,
+                     flops=infos[q].flops)
+            if bufs:
+                d["sv"] = bufs[q]
+            dicts.append(d)
+        return outs, dicts
 
     def observables(self, rho: MPO, log_norm: float, tau: float, H: MPO, n_sites: int,
                     entropy: bool = True) -> Dict[str, Dict[str, float]]:

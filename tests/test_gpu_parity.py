@@ -235,3 +235,100 @@ def test_chain10_full_against_stored_oracle(ctx):
     E = ed.spectrum(lat.n_sites, lat.bonds, lat.jxy, lat.jz)
     o = gpu[-1]["obs"]["2tau"]
     assert abs(o["f"] - ed.thermo(E, o["beta"], lat.n_sites)[0]) < 5e-6
+
+
+# ---------------------------------------------------------------- batched chains
+
+def _single_vs_batched(ctx, lats, taus, D, n_doub, n_sweeps=2, skew=None):
+    """Advance each chain alone and all chains together; every doubling must
+    agree bit for bit (same kernels in the same order per chain).  D and
+    n_sweeps: one value, or one per chain."""
+    nq = len(lats)
+    Ds = D if isinstance(D, list) else [D] * nq
+    Ss = n_sweeps if isinstance(n_sweeps, list) else [n_sweeps] * nq
+    Hs = [ctx.hamiltonian_xxz(l.n_sites, l.bonds, l.jxy, l.jz) for l in lats]
+    solo = [ctx.init_rho(H, t, 1)[0] for H, t in zip(Hs, taus)]
+    both = [ctx.init_rho(H, t, 1)[0] for H, t in zip(Hs, taus)]
+    # optional head start: chain q first takes skew[q] doublings alone, so the
+    # batch mixes different bond dimensions (different SVD shapes per chain)
+    for q, extra in enumerate(skew or []):
+        for _ in range(extra):
+            for lst in (solo, both):
+                new, _ = ctx.square_compress(lst[q], Ds[q], Ss[q])
+                lst[q].close()
+                lst[q] = new
+    for _ in range(n_doub):
+        outs, infos = ctx.square_compress_batched(both, Ds, Ss, sv_stride=8)
+        for q in range(nq):
+            new, info = ctx.square_compress(solo[q], Ds[q], Ss[q], sv_stride=8)
+            assert new.bond_dims == outs[q].bond_dims
+            for a, b in zip(new.to_host(), outs[q].to_host()):
+                assert np.array_equal(a, b)
+            assert info["dlog_norm"] == infos[q]["dlog_norm"]
+            assert info["D_kept_max"] == infos[q]["D_kept_max"]
+            assert info["steps"] == infos[q]["steps"] and info["flops"] == infos[q]["flops"]
+            assert np.array_equal(info["sv"], infos[q]["sv"])
+            solo[q].close()
+            solo[q] = new
+        for r in both:
+            r.close()
+        both = outs
+    return both
+
+
+def test_batched_zshift_chains_equal_single(ctx):
+    """Three z-shifted temperature grids of the L = 10 chain (Sec. II.C) in one batch."""
+    lat = W.chain(10)
+    taus = W.zshift_tau0(2.0 ** -8, 3)
+    _single_vs_batched(ctx, [lat] * 3, taus, 24, 6)
+
+
+def test_batched_mixed_shapes_and_couplings(ctx):
+    """Chains at different stages (different bond dimensions, so different
+    SVD shapes in one grouped launch) and different couplings."""
+    lats = [W.chain(8), W.with_couplings(W.chain(8), 1.0, 0.5), W.random_couplings(W.chain(8), 5)]
+    _single_vs_batched(ctx, lats, [2.0 ** -6] * 3, 20, 3, skew=[0, 2, 4])
+
+
+def test_batched_ragged_lengths_budgets_sweeps(ctx):
+    """A ragged batch: different lengths (so different schedule lengths),
+    bond budgets and sweep counts, plus the shortest chain (L = 2)."""
+    lats = [W.chain(2), W.chain(6), W.square_cylinder(2, 4), W.random_couplings(W.chain(9), 2)]
+    _single_vs_batched(ctx, lats, [0.05, 2.0 ** -5, 2.0 ** -6, 2.0 ** -7], [4, 12, 24, 16], 4,
+                       n_sweeps=[1, 2, 3, 1])
+
+
+def test_batched_matches_oracle(ctx):
+    """Batched doublings against the oracle's single-chain run (free energy
+    to 1e-9 relative at every beta)."""
+    lat = W.square_cylinder(3, 3)
+    taus = W.zshift_tau0(2.0 ** -8, 2)
+    Hs = [ctx.hamiltonian_xxz(lat.n_sites, lat.bonds, lat.jxy, lat.jz) for _ in taus]
+    st = [ctx.init_rho(H, t, 1) for H, t in zip(Hs, taus)]
+    rhos, lams = [s[0] for s in st], [s[1] for s in st]
+    ora = [OX.run(lat.n_sites, lat.bonds, lat.jxy, lat.jz, t, 6, 32, order=1, n_sweeps=2) for t in taus]
+    for n in range(1, 7):
+        outs, infos = ctx.square_compress_batched(rhos, 32, 2)
+        for q in range(len(taus)):
+            lams[q] = 2 * lams[q] + infos[q]["dlog_norm"]
+            tau = taus[q] * 2 ** n
+            ob = ctx.observables(outs[q], lams[q], tau, Hs[q], lat.n_sites, entropy=False)
+            fo = ora[q][n]["obs"]["2tau"]["f"]
+            assert abs(ob["2tau"]["f"] - fo) <= 1e-9 * abs(fo), (q, n)
+        for r in rhos:
+            r.close()
+        rhos = outs
+
+
+def test_batched_error_paths(ctx):
+    from paper_1801_00142_amd import XtrgError
+    a = ctx.init_rho(ctx.hamiltonian_xxz(4, W.chain(4).bonds, [1.0] * 3, [1.0] * 3), 0.1, 1)[0]
+    b = ctx.init_rho(ctx.hamiltonian_xxz(5, W.chain(5).bonds, [1.0] * 4, [1.0] * 4), 0.1, 1)[0]
+    with pytest.raises(XtrgError):
+        ctx.square_compress_batched([a, b], [8, 0], 1)     # D_max = 0 for one chain
+    with pytest.raises(XtrgError):
+        ctx.square_compress_batched([a, b], 8, [1, 0])     # n_sweeps = 0 for one chain
+    outs, infos = ctx.square_compress_batched([a], 8, 1)   # n = 1 is the single-chain call
+    new, info = ctx.square_compress(a, 8, 1)
+    for x, y in zip(outs[0].to_host(), new.to_host()):
+        assert np.array_equal(x, y)
