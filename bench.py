@@ -10,7 +10,11 @@ runs at the saturated bond dimension.  The metric counts the algorithmic
 flops of the contractions (64 D^4 per uniform two-site step, counted with
 the actual bond dimensions) divided by the wall time of the timed steps.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--D 256] [--sweeps 2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--D 256] [--sweeps 2] [--batch N]
+
+--batch N runs N independent chains with interleaved temperature grids
+(tau0 * 2^(i/N), the z-shifts of Sec. II.C) through the batched doubling;
+the value is then the whole batch's flops over its wall time.
 
 Prints one JSON line.  Only one GPU is used: --gpus above 1 exits.
 """
@@ -28,6 +32,11 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 PEAK_HBM_GBS = 8000.0
+# HBM bytes per jacobi_round launch over a 1024 x 1024 matrix (32 block
+# pairs of 32 columns), from rocprofv3 FETCH_SIZE + WRITE_SIZE scaled by a
+# plain 1 GiB copy (FETCH x2.0, WRITE x1.0); see the counters summary in
+# profiles/.  Valid for the kernel as measured: reset to None when it changes.
+JACOBI_ROUND_TRAFFIC_1024 = 15.60e6
 
 
 def parse():
@@ -40,6 +49,7 @@ def parse():
     ap.add_argument("--sweeps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=1)
     return ap.parse_args()
 
 
@@ -78,7 +88,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); independent chains would shard "
-              "across GPUs without communication, see DESIGN.md", file=sys.stderr)
+              "across GPUs without communication", file=sys.stderr)
         sys.exit(2)
     import torch
     import workloads as W
@@ -86,29 +96,38 @@ def main():
 
     wl = W.workload(args.workload, args.D)
     lat = wl.lattice
+    nb = max(args.batch, 1)
+    taus = W.zshift_tau0(wl.tau0, nb)
     ctx = Context(0)
     H = ctx.hamiltonian_xxz(lat.n_sites, lat.bonds, lat.jxy, lat.jz)
-    rho, lam = ctx.init_rho(H, wl.tau0, wl.init_order)
-    tau = wl.tau0
-    n_done = 0
+    rhos = [ctx.init_rho(H, t, wl.init_order)[0] for t in taus]
+
+    def doubling():
+        nonlocal rhos
+        if nb == 1:
+            new, info = ctx.square_compress(rhos[0], args.D, args.sweeps)
+            news, infos = [new], [info]
+        else:
+            news, infos = ctx.square_compress_batched(rhos, args.D, args.sweeps)
+        for r in rhos:
+            r.close()
+        rhos = news
+        return infos
+
     # warm-up: grow the bonds to D, then --warmup more doublings
-    t_w = time.perf_counter()
+    n_done = 0
     saturated_at = None
     while True:
-        new, info = ctx.square_compress(rho, args.D, args.sweeps)
-        rho.close()
-        rho = new
-        lam = 2 * lam + info["dlog_norm"]      # lambda_{n+1} = 2 lambda_n + ln c
-        tau *= 2
+        infos = doubling()
         n_done += 1
-        if saturated_at is None and info["D_kept_max"] >= args.D:
+        dmax = min(i["D_kept_max"] for i in infos)
+        if saturated_at is None and dmax >= args.D:
             saturated_at = n_done
-        print(f"warm-up doubling {n_done}: max bond {info['D_kept_max']}", file=sys.stderr, flush=True)
+        print(f"warm-up doubling {n_done}: max bond {dmax}", file=sys.stderr, flush=True)
         if saturated_at is not None and n_done >= saturated_at + args.warmup:
             break
         if n_done >= wl.n_doublings:
             break
-    warm_s = time.perf_counter() - t_w
 
     torch.cuda.synchronize()
     ctx.profile(True)
@@ -117,12 +136,10 @@ def main():
     steps_2site = 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        new, info = ctx.square_compress(rho, args.D, args.sweeps)
-        rho.close()
-        rho = new
-        flops += info["flops"]
-        steps_2site += info["steps"]
-        print(f"timed doubling done: {info['steps']} two-site steps", file=sys.stderr, flush=True)
+        infos = doubling()
+        flops += sum(i["flops"] for i in infos)
+        steps_2site += sum(i["steps"] for i in infos)
+        print(f"timed doubling done: {steps_2site} two-site steps", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = ctx.profile_report()
@@ -131,13 +148,21 @@ def main():
     value = flops / dt / 1e12
     svd_calls = prof.pop("svd_calls", 0)
     svd_sweeps = prof.pop("svd_sweeps", 0)
+    rounds = prof.pop("svd_rounds")
     th = prof["theta_gemm"]
     th_avg_s = th["ms"] / max(th["calls"], 1) / 1e3
     th_flops = th["flops"] / max(th["calls"], 1)
-    achieved = th_flops / th_avg_s / 1e12 if th_avg_s > 0 else 0.0
+    th_achieved = th_flops / th_avg_s / 1e12 if th_avg_s > 0 else 0.0
+    rd_avg_s = rounds["ms"] / max(rounds["calls"], 1) / 1e3
+    rd_bytes = rounds["bytes"] / max(rounds["calls"], 1)
+    rd_gbs = rd_bytes / rd_avg_s / 1e9 if rd_avg_s > 0 else 0.0
     total_ms = sum(v["ms"] for v in prof.values())
     shares = {k: round(v["ms"] / total_ms, 4) if total_ms else 0.0 for k, v in prof.items()}
+    shares["svd_rounds_of_svd"] = round(rounds["ms"] / prof["svd"]["ms"], 4) if prof["svd"]["ms"] else 0.0
 
+    wl_name = f"{lat.name} Heisenberg, tau0=2^-12, D={args.D}, {args.sweeps} sweeps/doubling"
+    if nb > 1:
+        wl_name += f", {nb} z-shifted chains batched"
     out = {
         "metric": "TFLOP/s in MPO product-compression sweeps at D=256",
         "value": round(value, 4),
@@ -151,21 +176,29 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{lat.name} Heisenberg, tau0=2^-12, D={args.D}, {args.sweeps} sweeps/doubling",
-                   "L": lat.n_sites, "D": args.D, "n_sweeps": args.sweeps,
-                   "two_site_steps_per_doubling": steps_2site // max(args.steps, 1),
+        "config": {"workload": wl_name, "L": lat.n_sites, "D": args.D, "n_sweeps": args.sweeps,
+                   "chains": nb, "two_site_steps_per_doubling": steps_2site // max(args.steps, 1),
                    "warmup_doublings": n_done, "saturated_after": saturated_at},
-        "sweeps_per_s": round(args.steps * args.sweeps / dt, 4),
+        "sweeps_per_s": round(nb * args.steps * args.sweeps / dt, 4),
         "phase_share": shares,
         "svd_sweeps_avg": round(svd_sweeps / max(svd_calls, 1), 2),
-        "roofline": {"bound": "mfma", "kernel": "two-site overlap C_E (dgemm_kernel<...,1>)",
-                     "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
-                     "launches": th["calls"], "avg_launch_ms": round(th_avg_s * 1e3, 4),
-                     "flops_per_launch": th_flops},
+        # the dominant kernel: the Jacobi rounds of the SVD (bytes = each
+        # column of the visited pairs read and written once per round)
+        "roofline": {"bound": "hbm", "kernel": "jacobi_round (one-sided block Jacobi SVD round)",
+                     "achieved": round(rd_gbs, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(rd_gbs / PEAK_HBM_GBS, 4), "traffic": JACOBI_ROUND_TRAFFIC_1024,
+                     "traffic_note": "HBM bytes per 1024-column launch (rocprofv3 counters, copy-scaled)",
+                     "launches": rounds["calls"], "avg_launch_us": round(rd_avg_s * 1e6, 3),
+                     "bytes_per_launch": rd_bytes,
+                     "flops_per_launch": rounds["flops"] / max(rounds["calls"], 1)},
+        "roofline_theta": {"bound": "mfma", "kernel": "two-site overlap C_E (gemm_kernel<128,128,...,1,double,double>)",
+                           "achieved": round(th_achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                           "frac": round(th_achieved / PEAK_FP64_TFLOPS, 4),
+                           "launches": th["calls"], "avg_launch_ms": round(th_avg_s * 1e3, 4),
+                           "flops_per_launch": th_flops},
     }
     if not args.no_cpu_baseline:
-        sites = rho.to_host()
+        sites = rhos[0].to_host()
         tf, cdt, cfl, threads = cpu_baseline(sites, args.D, args.cpu_steps)
         out["cpu_baseline"] = {"value": round(tf, 5), "unit": "TFLOP/s",
                                "cores": len(os.sched_getaffinity(0)), "blas_threads": threads,
@@ -173,7 +206,8 @@ def main():
                                "sample": f"{args.cpu_steps} two-site steps (left/right block, C_E, LAPACK SVD, "
                                          f"environment) at the centre bond of the saturated D={args.D} MPO, "
                                          "seeded environments"}
-    rho.close()
+    for r in rhos:
+        r.close()
     H.close()
     ctx.close()
     print(json.dumps(out), flush=True)

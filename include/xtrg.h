@@ -44,7 +44,15 @@ enum {
   XTRG_EBUSY = -5
 };
 
-enum { XTRG_FP64 = 0 };
+/* Precision of the contractions of a doubling (xtrg_compress_opts.precision).
+ * XTRG_FP64: everything FP64.
+ * XTRG_FP32: the contractions (environment blocks, two-site overlap C_E,
+ *   environment advance) take FP32 copies of rho, C and the environments and
+ *   run on the FP32 matrix cores with FP32 accumulation (split-K partials are
+ *   summed in FP64); C_E is handed to the SVD in FP64, and the SVD, the
+ *   truncation, the split, the output sites and the normalisation stay FP64.
+ *   Free energies agree with the FP64 path to about 1e-6 relative (tested). */
+enum { XTRG_FP64 = 0, XTRG_FP32 = 1 };
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
  * (e.g. torch.cuda.current_stream().cuda_stream) or NULL for the null
@@ -92,7 +100,7 @@ int xtrg_init_rho(xtrg_ctx ctx, xtrg_mpo H, double tau0, int order, int D0_max,
 typedef struct {
   int D_max;         /* bond dimension budget D (> 0) */
   int n_sweeps;      /* full sweeps (left-to-right then right-to-left), >= 1 */
-  int precision;     /* XTRG_FP64 */
+  int precision;     /* XTRG_FP64 or XTRG_FP32 */
   double degen_rtol; /* multiplet-safe cut: back off to a gap > degen_rtol*sigma_k (1e-6) */
   double sv_floor;   /* singular values <= sv_floor*sigma_1 count as zero (1e-14) */
 } xtrg_compress_opts;
@@ -116,7 +124,9 @@ typedef struct {
  * is normalised and right-canonical; lambda_{n+1} = 2 lambda_n + info->dlog_norm.
  * Initial guess: rho_in.  Truncation: at most D_max states per bond, backed
  * off to the largest k >= D_max/2 with sigma_k - sigma_{k+1} > degen_rtol*sigma_k
- * (never split a degenerate multiplet); sigma <= sv_floor*sigma_1 dropped. */
+ * (never split a degenerate multiplet; a gap must also exceed the rounding
+ * noise of the values, and degen_rtol = 0 cuts at exactly D_max);
+ * sigma <= sv_floor*sigma_1 dropped. */
 int xtrg_square_compress(xtrg_ctx ctx, xtrg_mpo rho_in, const xtrg_compress_opts* opts,
                          xtrg_mpo* rho_out, xtrg_compress_info* info);
 
@@ -168,6 +178,11 @@ int xtrg_profile_report(xtrg_ctx ctx, char* buf, size_t cap);
  * C (M x N) row-major (ldc).  Inputs and output must not alias. */
 int xtrg_dgemm(xtrg_ctx ctx, int M, int N, int K, int transA, int transB,
                const double* A, long lda, const double* B, long ldb, double* C, long ldc);
+/* xtrg_sgemm: the same product in the XTRG_FP32 contraction precision:
+ * A, B float (device), FP32 matrix cores with FP32 accumulation (split-K
+ * partials summed in FP64); C is double if c_double, else float. */
+int xtrg_sgemm(xtrg_ctx ctx, int M, int N, int K, int transA, int transB,
+               const float* A, long lda, const float* B, long ldb, void* C, long ldc, int c_double);
 /* xtrg_dsvd_left: singular values of the len x p matrix Y stored
  * column-major (column j at Y + j*len, device), descending, into sigma
  * (device, p entries), and the left singular vectors of the first k of them

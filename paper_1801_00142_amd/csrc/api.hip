@@ -42,6 +42,7 @@ struct xtrg_ctx_s {
     int cat;
     hipEvent_t a, b;
     double flops, bytes;
+    long launches;
   };
   bool prof = false;
   std::vector<Prof> prof_recs;
@@ -105,8 +106,10 @@ struct xtrg_mpo_s {
 namespace {
 
 // Phases of the doubling step timed by the profiler.
-enum { P_THETA = 0, P_BLOCK, P_ENV, P_SVD, P_SPLIT, P_NCAT };
-const char* const kPhase[P_NCAT] = {"theta_gemm", "block_gemm", "env_gemm", "svd", "split"};
+// svd_rounds is the part of svd spent in the Jacobi round kernels; its
+// "calls" count kernel launches.
+enum { P_THETA = 0, P_BLOCK, P_ENV, P_SVD, P_SPLIT, P_ROUNDS, P_NCAT };
+const char* const kPhase[P_NCAT] = {"theta_gemm", "block_gemm", "env_gemm", "svd", "split", "svd_rounds"};
 
 // RAII event pair around the work enqueued in its scope.
 struct Timed {
@@ -117,6 +120,7 @@ struct Timed {
     r.cat = cat;
     r.flops = flops;
     r.bytes = bytes;
+    r.launches = 1;
     XTRG_HIP(hipEventCreate(&r.a));
     XTRG_HIP(hipEventCreate(&r.b));
     XTRG_HIP(hipEventRecord(r.a, c->stream));
@@ -172,6 +176,28 @@ double read_scalar(xtrg_ctx c, const double* d) {
   return h;
 }
 
+// Event pairs around the Jacobi round launches of each sweep.
+struct RoundProf : xtrg::RoundTimer {
+  xtrg_ctx c;
+  xtrg_ctx_s::Prof r{};
+  explicit RoundProf(xtrg_ctx ctx) : c(ctx) {}
+  void begin(hipStream_t s) override {
+    if (!c->prof) return;
+    XTRG_HIP(hipEventCreate(&r.a));
+    XTRG_HIP(hipEventCreate(&r.b));
+    XTRG_HIP(hipEventRecord(r.a, s));
+  }
+  void end(hipStream_t s, long launches, double flops, double bytes) override {
+    if (!c->prof) return;
+    XTRG_HIP(hipEventRecord(r.b, s));
+    r.cat = P_ROUNDS;
+    r.flops = flops;
+    r.bytes = bytes;
+    r.launches = launches;
+    c->prof_recs.push_back(r);
+  }
+};
+
 // Device descriptors of a grouped SVD launch over n problems.
 void* svd_desc(xtrg_ctx c, int n) { return c->need("svd_desc", xtrg::svd_desc_bytes(n) / sizeof(double) + 1); }
 
@@ -182,10 +208,11 @@ void gemm(xtrg_ctx c, const Gemm& g) {
 }
 
 // Plain row-major C[MxN] = op(A) op(B).
-Gemm plain(int M, int N, int K, const double* A, long lda, bool tA, const double* B, long ldb, bool tB,
-           double* C, long ldc) {
+Gemm plain(int M, int N, int K, const void* A, long lda, bool tA, const void* B, long ldb, bool tB,
+           void* C, long ldc, int prec = xtrg::GEMM_F64, int out64 = 1) {
   Gemm g;
   g.M = M; g.N = N; g.K = K;
+  g.prec = prec; g.out64 = out64;
   g.A = A; g.lda = lda; g.transA = tA;
   g.B = B; g.ldb = ldb; g.transB = tB;
   g.C = C; g.ldc = ldc;
@@ -480,23 +507,43 @@ struct Doubler {
   std::vector<int> Da;                  // bonds of A = B = rho
   std::vector<int> Dc;                  // bonds of C
   std::vector<int> cap;                 // largest possible bond of C
-  std::vector<const double*> A;         // rho sites
-  std::vector<double*> Bp;              // rho sites with the physical indices swapped
+  // Working precision of the contractions: GEMM_F64, or GEMM_F32 with FP32
+  // copies of rho, the environments, the blocks and C (the SVD, the split
+  // and the output sites stay FP64).
+  int prec = xtrg::GEMM_F64;
+  std::vector<const void*> A;           // rho sites (working precision)
+  std::vector<void*> Bp;                // rho sites with the physical indices swapped
   std::string tag;                      // suffix of the chain's workspace names
-  std::vector<Site> C;                  // output sites (capacity at cap)
-  std::map<int, double*> slot;          // Lb_i or Rb_i: one named workspace per site
+  std::vector<Site> C;                  // output sites, FP64 (capacity at cap)
+  std::vector<void*> Cw;                // working-precision copies of C (C itself in FP64)
+  std::map<int, void*> slot;            // Lb_i or Rb_i: one named workspace per site
+
+  // Named workspace of n elements of the working precision.
+  void* needw(const std::string& name, size_t n) {
+    if (prec == xtrg::GEMM_F64) return c->need(name, n);
+    return c->need(name + "/f32", (n + 1) / 2);
+  }
+  // Refresh the working copy of C_i (n leading elements) after C_i changed.
+  void sync_cw(int i, size_t n) {
+    if (prec != xtrg::GEMM_F64) xtrg::to_f32(static_cast<float*>(Cw[i]), C[i].p, n, c->stream);
+  }
+  Gemm wplain(int M, int N, int K, const void* A_, long lda, bool tA, const void* B_, long ldb, bool tB,
+              void* C_, long ldc) const {
+    return plain(M, N, K, A_, lda, tA, B_, ldb, tB, C_, ldc, prec, 0);
+  }
 
   // Slot i holds Lb_i (4 cap_i Da_{i+1}^2) or Rb_i (Da_i^2 4 cap_{i+1}).
-  double* slot_need(int i) {
+  void* slot_need(int i) {
     const size_t n = std::max((size_t)4 * cap[i] * Da[i + 1] * Da[i + 1], (size_t)Da[i] * Da[i] * 4 * cap[i + 1]);
-    return slot[i] = c->need("slot" + std::to_string(i) + tag, n);
+    return slot[i] = needw("slot" + std::to_string(i) + tag, n);
   }
 
   // Lb[(c,s,s'')][(a',b')] = sum_{a,b,s'} E[c][a][b] A_i[a][s][s'][a'] A_i[b][s'][s''][b']
-  void left_block(int i, const double* E, double* out) {
+  void left_block(int i, const void* E, void* out) {
     const int dc = Dc[i], da = Da[i], db = Da[i], da2 = Da[i + 1], db2 = Da[i + 1];
-    double* X = c->need("X", (size_t)dc * 4 * db * da2);
-    Gemm g1;   // X[c][s][b][(s',a')] = sum_a E[c][a][b] A[a][s][(s',a')]   batch (c, s)
+    void* X = needw("X", (size_t)dc * 4 * db * da2);
+    Gemm g1;
+    g1.prec = prec; g1.out64 = 0;   // X[c][s][b][(s',a')] = sum_a E[c][a][b] A[a][s][(s',a')]   batch (c, s)
     g1.M = db; g1.N = 2 * da2; g1.K = da;
     g1.transA = 1; g1.A = E; g1.lda = db;
     g1.B = A[i]; g1.ldb = 4 * da2;
@@ -506,7 +553,9 @@ struct Doubler {
     g1.sB[1] = 2L * da2;
     g1.sC[0] = 4L * db * da2; g1.sC[1] = 2L * db * da2;
     gemm(c, g1);
-    Gemm g2;   // Lb[c][s][s''][a'][b'] = sum_{(b,s')} X[c][s][(b,s')][a'] B[(b,s')][s''][b']  batch (c,s,s'')
+    Gemm g2;
+    g2.prec = prec; g2.out64 = 0;
+    //         Lb[c][s][s''][a'][b'] = sum_{(b,s')} X[c][s][(b,s')][a'] B[(b,s')][s''][b']  batch (c,s,s'')
     g2.M = da2; g2.N = db2; g2.K = 2 * db;
     g2.transA = 1; g2.A = X; g2.lda = da2;
     g2.B = A[i]; g2.ldb = 2 * db2;
@@ -519,11 +568,13 @@ struct Doubler {
   }
 
   // Rb[(a,b)][(t,t'',c'')] = sum_{a'',b'',t'} A_j[a][t][t'][a''] A_j[b][t'][t''][b''] F[a''][b''][c'']
-  void right_block(int j, const double* F, double* out) {
+  void right_block(int j, const void* F, void* out) {
     const int da = Da[j], db = Da[j], da2 = Da[j + 1], db2 = Da[j + 1], dc2 = Dc[j + 1];
-    double* Z = c->need("X", (size_t)4 * da * db2 * dc2);
-    gemm(c, plain(4 * da, db2 * dc2, da2, A[j], da2, false, F, (long)db2 * dc2, false, Z, (long)db2 * dc2));
-    Gemm g;    // batch (a, t, t''): Rb[a][b][t][t''][c''] = sum_{(t',b'')} Bp[b][t''][(t',b'')] Z[a][t][(t',b'')][c'']
+    void* Z = needw("X", (size_t)4 * da * db2 * dc2);
+    gemm(c, wplain(4 * da, db2 * dc2, da2, A[j], da2, false, F, (long)db2 * dc2, false, Z, (long)db2 * dc2));
+    Gemm g;
+    g.prec = prec; g.out64 = 0;
+    //         batch (a, t, t''): Rb[a][b][t][t''][c''] = sum_{(t',b'')} Bp[b][t''][(t',b'')] Z[a][t][(t',b'')][c'']
     g.M = db; g.N = dc2; g.K = 2 * db2;
     g.A = Bp[j]; g.lda = 4 * db2;
     g.B = Z; g.ldb = dc2;
@@ -550,8 +601,8 @@ struct Chain {
   xtrg_compress_opts o;
   std::vector<Step> sched;
   std::string tag;                        // suffix of this chain's workspace names
-  double* E = nullptr;                    // left environment of the current bond
-  double* F = nullptr;                    // right environment
+  void* E = nullptr;                      // left environment of the current bond (working precision)
+  void* F = nullptr;                      // right environment
   double* th = nullptr;                   // two-site overlap C_E
   double* work = nullptr;                 // SVD workspace
   std::vector<std::vector<double>> sv;
@@ -561,14 +612,15 @@ struct Chain {
   // current step
   int i = 0;
   bool gauge_right = false;
-  double* Lb = nullptr;
-  double* Rb = nullptr;
+  void* Lb = nullptr;
+  void* Rb = nullptr;
   int mL = 0, mR = 0, Kt = 0, len = 0, p = 0;
 };
 
 void check_opts(const xtrg_compress_opts& o) {
   if (o.D_max < 1 || o.n_sweeps < 1) throw Error(XTRG_EINVAL, "D_max and n_sweeps must be >= 1");
-  if (o.precision != XTRG_FP64) throw Error(XTRG_EINVAL, "only XTRG_FP64 is available");
+  if (o.precision != XTRG_FP64 && o.precision != XTRG_FP32)
+    throw Error(XTRG_EINVAL, "precision must be XTRG_FP64 or XTRG_FP32");
 }
 
 // Set up chain q: initial guess C = rho, swapped copies of rho's sites, and
@@ -583,6 +635,7 @@ void chain_setup(xtrg_ctx c, Chain& C, xtrg_mpo in, int q) {
   d.c = c;
   d.L = L;
   d.tag = C.tag;
+  d.prec = C.o.precision == XTRG_FP32 ? xtrg::GEMM_F32 : xtrg::GEMM_F64;
   d.Da = in->dims;
   d.Dc = in->dims;                         // initial guess C = rho (right-canonical)
   d.cap.resize(L + 1);
@@ -594,30 +647,54 @@ void chain_setup(xtrg_ctx c, Chain& C, xtrg_mpo in, int q) {
   d.A.resize(L);
   d.Bp.resize(L);
   d.C.resize(L);
+  d.Cw.resize(L);
+  const bool f32 = d.prec != xtrg::GEMM_F64;
   for (int i = 0; i < L; ++i) {
-    d.A[i] = in->site[i].p;
-    d.Bp[i] = c->need("Bp" + std::to_string(i) + C.tag, in->elems(i));
-    xtrg::swap_phys(d.Bp[i], in->site[i].p, in->dims[i], in->dims[i + 1], s);
+    const std::string si = std::to_string(i) + C.tag;
+    const size_t ne = in->elems(i);
     d.C[i].n = (size_t)d.cap[i] * 4 * d.cap[i + 1];
-    d.C[i].p = c->need("C" + std::to_string(i) + C.tag, d.C[i].n);
-    xtrg::copy(d.C[i].p, in->site[i].p, in->elems(i), s);
+    d.C[i].p = c->need("C" + si, d.C[i].n);
+    xtrg::copy(d.C[i].p, in->site[i].p, ne, s);
+    if (!f32) {
+      d.A[i] = in->site[i].p;
+      double* bp = c->need("Bp" + si, ne);
+      xtrg::swap_phys(bp, in->site[i].p, in->dims[i], in->dims[i + 1], s);
+      d.Bp[i] = bp;
+      d.Cw[i] = d.C[i].p;
+    } else {
+      float* a32 = static_cast<float*>(d.needw("A" + si, ne));
+      xtrg::to_f32(a32, in->site[i].p, ne, s);
+      d.A[i] = a32;
+      double* tmp = c->need("Bp_swap", ne);
+      xtrg::swap_phys(tmp, in->site[i].p, in->dims[i], in->dims[i + 1], s);
+      float* b32 = static_cast<float*>(d.needw("Bp" + si, ne));
+      xtrg::to_f32(b32, tmp, ne, s);
+      d.Bp[i] = b32;
+      d.Cw[i] = d.needw("Cw" + si, d.C[i].n);
+      d.sync_cw(i, ne);
+    }
   }
   size_t env_max = 1;
   for (int i = 0; i <= L; ++i) env_max = std::max(env_max, (size_t)d.cap[i] * d.Da[i] * d.Da[i]);
-  C.E = c->need("E" + C.tag, env_max);
-  C.F = c->need("F" + C.tag, env_max);
-  xtrg::fill(C.E, 1.0, 1, s);
-  xtrg::fill(C.F, 1.0, 1, s);
+  C.E = d.needw("E" + C.tag, env_max);
+  C.F = d.needw("F" + C.tag, env_max);
+  if (!f32) {
+    xtrg::fill(static_cast<double*>(C.E), 1.0, 1, s);
+    xtrg::fill(static_cast<double*>(C.F), 1.0, 1, s);
+  } else {
+    xtrg::fill_f32(static_cast<float*>(C.E), 1.0f, 1, s);
+    xtrg::fill_f32(static_cast<float*>(C.F), 1.0f, 1, s);
+  }
   C.sv.resize(L - 1);
   C.kept.assign(L - 1, 1);
   C.disc.assign(L - 1, 0.0);
   for (int j = L - 1; j >= 1; --j) {
-    double* Rb = d.slot_need(j);
+    void* Rb = d.slot_need(j);
     d.right_block(j, C.F, Rb);
     if (j == 1) break;
     const int mR = 4 * d.Dc[j + 1];
     const int k = d.Dc[j];
-    gemm(c, plain(d.Da[j] * d.Da[j], k, mR, Rb, mR, false, d.C[j].p, mR, true, C.F, k));
+    gemm(c, d.wplain(d.Da[j] * d.Da[j], k, mR, Rb, mR, false, d.Cw[j], mR, true, C.F, k));
   }
 }
 
@@ -654,7 +731,8 @@ void chain_truncate_split(xtrg_ctx c, Chain& C) {
       gemm(c, plain(k, mR, mL, Ci, k, true, C.th, mL, true, Cn, mR));                 // C_{i+1} = U^T theta
     }
     Timed tm(c, P_ENV, 2.0 * k * (double)Kt * mL, 8.0 * ((double)mL * Kt + (double)k * Kt));
-    gemm(c, plain(k, Kt, mL, Ci, k, true, C.Lb, Kt, false, C.E, Kt));                  // E_{i+1} = C_i^T Lb
+    d.sync_cw(i, (size_t)mL * k);
+    gemm(c, d.wplain(k, Kt, mL, d.Cw[i], k, true, C.Lb, Kt, false, C.E, Kt));          // E_{i+1} = C_i^T Lb
   } else {
     {
       Timed tm(c, P_SPLIT, 2.0 * k * (double)mL * mR, 0.0);
@@ -663,7 +741,8 @@ void chain_truncate_split(xtrg_ctx c, Chain& C) {
       gemm(c, plain(mL, k, mR, C.th, mR, false, Cn, mR, true, Ci, k));                // C_i = theta V
     }
     Timed tm(c, P_ENV, 2.0 * k * (double)Kt * mR, 8.0 * ((double)mR * Kt + (double)k * Kt));
-    gemm(c, plain(d.Da[i + 1] * d.Da[i + 1], k, mR, C.Rb, mR, false, Cn, mR, true, C.F, k));  // F_{i+1}
+    d.sync_cw(i + 1, (size_t)k * mR);
+    gemm(c, d.wplain(d.Da[i + 1] * d.Da[i + 1], k, mR, C.Rb, mR, false, d.Cw[i + 1], mR, true, C.F, k));  // F_{i+1}
   }
   d.Dc[i + 1] = k;
 }
@@ -750,9 +829,10 @@ void square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_com
       }
       Timed tm(c, P_THETA, fth, bth);
       for (Chain* C : act) {
+        const int pr = C->d.prec;   // FP64 output in every precision: the SVD is FP64
         Gemm g = C->gauge_right
-                     ? plain(C->mR, C->mL, C->Kt, C->Rb, C->mR, true, C->Lb, C->Kt, true, C->th, C->mL)  // column-major
-                     : plain(C->mL, C->mR, C->Kt, C->Lb, C->Kt, false, C->Rb, C->mR, false, C->th, C->mR);
+                     ? plain(C->mR, C->mL, C->Kt, C->Rb, C->mR, true, C->Lb, C->Kt, true, C->th, C->mL, pr, 1)  // column-major
+                     : plain(C->mL, C->mR, C->Kt, C->Lb, C->Kt, false, C->Rb, C->mR, false, C->th, C->mR, pr, 1);
         g.tag = 1;
         gemm(c, g);
       }
@@ -765,7 +845,8 @@ void square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_com
         bs += 8.0 * C->len * (double)C->p;
       }
       Timed tm(c, P_SVD, 0.0, bs);
-      xtrg::svd_batched(jobs, svd_desc(c, (int)jobs.size()), s);
+      RoundProf rp(c);
+      xtrg::svd_batched(jobs, svd_desc(c, (int)jobs.size()), s, &rp);
       for (auto& J : jobs) {
         c->svd_calls += 1;
         c->svd_sweeps += J.sweeps;
@@ -1180,7 +1261,7 @@ int xtrg_profile_report(xtrg_ctx c, char* buf, size_t cap) {
       ms[r.cat] += t;
       fl[r.cat] += r.flops;
       by[r.cat] += r.bytes;
-      n[r.cat] += 1;
+      n[r.cat] += r.launches;
       (void)hipEventDestroy(r.a);
       (void)hipEventDestroy(r.b);
     }
@@ -1207,6 +1288,16 @@ int xtrg_dgemm(xtrg_ctx c, int M, int N, int K, int transA, int transB, const do
   return guarded(c, [&] {
     set_device(c);
     gemm(c, plain(M, N, K, A, lda, transA != 0, B, ldb, transB != 0, C, ldc));
+    XTRG_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+int xtrg_sgemm(xtrg_ctx c, int M, int N, int K, int transA, int transB, const float* A, long lda,
+               const float* B, long ldb, void* C, long ldc, int c_double) {
+  if (!c || M < 0 || N < 0 || K < 0 || (M * (long)N > 0 && (!A || !B || !C))) return XTRG_EINVAL;
+  return guarded(c, [&] {
+    set_device(c);
+    gemm(c, plain(M, N, K, A, lda, transA != 0, B, ldb, transB != 0, C, ldc, xtrg::GEMM_F32, c_double != 0));
     XTRG_HIP(hipStreamSynchronize(c->stream));
   });
 }

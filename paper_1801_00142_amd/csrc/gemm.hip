@@ -1,29 +1,53 @@
-// Batched strided FP64 GEMM on CDNA4 matrix cores (v_mfma_f64_16x16x4f64).
+// Batched strided GEMM on CDNA4 matrix cores: FP64 (v_mfma_f64_16x16x4f64)
+// or FP32 (v_mfma_f32_16x16x4f32, FP32 accumulation).
 //
 // Workgroup = 4 waves (256 threads) in a 2 x 2 arrangement; each wave owns a
 // (BM/2) x (BN/2) block of C made of 16 x 16 MFMA tiles.  K is consumed in
 // steps of 16: the A and B tiles are staged through LDS with k as the slow
-// index so that every MFMA operand read is 16 consecutive doubles per lane
+// index so that every MFMA operand read is 16 consecutive elements per lane
 // group.  The next K tile is fetched into registers while the current one
-// is multiplied.
+// is multiplied.  Split-K partials are kept in double and reduced in a fixed
+// order.
 #include "internal.h"
 
 namespace xtrg {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int BK = 16;
 
+// One 16x16x4 MFMA step per element type.  Operand lane l holds A(i = l%16,
+// k = l/16) and B(k = l/16, j = l%16).
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  using acc = d4;
+  static __device__ inline acc step(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // register r of lane l holds row l/16 + 4r, column l%16
+  static __device__ inline int row(int lk, int r) { return lk + 4 * r; }
+};
+template <> struct Mfma<float> {
+  using acc = f4;
+  static __device__ inline acc step(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // register r of lane l holds row 4(l/16) + r, column l%16
+  static __device__ inline int row(int lk, int r) { return 4 * lk + r; }
+};
+
 // TAG only separates kernel symbols (1 = two-site overlap C_E) for profilers.
-template <int BM, int BN, bool TA, bool TB, int TAG>
-__global__ __launch_bounds__(256) void dgemm_kernel(Gemm g, int splitk, int kchunk, double* work) {
+template <int BM, int BN, bool TA, bool TB, int TAG, typename TI, typename TO>
+__global__ __launch_bounds__(256) void gemm_kernel(Gemm g, int splitk, int kchunk, double* work) {
+  using MF = Mfma<TI>;
   constexpr int WM = BM / 2, WN = BN / 2;     // wave tile
   constexpr int TM = WM / 16, TN = WN / 16;   // MFMA tiles per wave
-  constexpr int LA = BM * BK / 256;           // doubles of A per thread per K tile
+  constexpr int LA = BM * BK / 256;           // elements of A per thread per K tile
   constexpr int LB = BN * BK / 256;
   constexpr int PAD = 4;
-  __shared__ double As[BK][BM + PAD];
-  __shared__ double Bs[BK][BN + PAD];
+  __shared__ TI As[BK][BM + PAD];
+  __shared__ TI Bs[BK][BN + PAD];
 
   const int t = threadIdx.x;
   const int lane = t & 63;
@@ -36,8 +60,8 @@ __global__ __launch_bounds__(256) void dgemm_kernel(Gemm g, int splitk, int kchu
   const int b2 = z % g.nb[2];
   const int b1 = (z / g.nb[2]) % g.nb[1];
   const int b0 = z / (g.nb[2] * g.nb[1]);
-  const double* __restrict__ A = g.A + b0 * g.sA[0] + b1 * g.sA[1] + b2 * g.sA[2];
-  const double* __restrict__ B = g.B + b0 * g.sB[0] + b1 * g.sB[1] + b2 * g.sB[2];
+  const TI* __restrict__ A = static_cast<const TI*>(g.A) + b0 * g.sA[0] + b1 * g.sA[1] + b2 * g.sA[2];
+  const TI* __restrict__ B = static_cast<const TI*>(g.B) + b0 * g.sB[0] + b1 * g.sB[1] + b2 * g.sB[2];
 
   const int m0 = blockIdx.y * BM;
   const int n0 = blockIdx.x * BN;
@@ -45,7 +69,7 @@ __global__ __launch_bounds__(256) void dgemm_kernel(Gemm g, int splitk, int kchu
   const int kend = min(g.K, kbeg + kchunk);
   const int M = g.M, N = g.N;
 
-  double ra[LA], rb[LB];
+  TI ra[LA], rb[LB];
 
   auto load = [&](int k0) {
 #pragma unroll
@@ -55,13 +79,13 @@ __global__ __launch_bounds__(256) void dgemm_kernel(Gemm g, int splitk, int kchu
         const int k = k0 + (t & 3) * 4;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          ra[4 * c + j] = (m < M && k + j < kend) ? A[(long)m * g.lda + k + j] : 0.0;
+          ra[4 * c + j] = (m < M && k + j < kend) ? A[(long)m * g.lda + k + j] : TI(0);
       } else {              // A[k*lda + m]: thread -> (k row, 4 consecutive m)
         const int k = k0 + (t >> 4);
         const int m = m0 + (t & 15) * 4 + 64 * c;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          ra[4 * c + j] = (k < kend && m + j < M) ? A[(long)k * g.lda + m + j] : 0.0;
+          ra[4 * c + j] = (k < kend && m + j < M) ? A[(long)k * g.lda + m + j] : TI(0);
       }
     }
 #pragma unroll
@@ -71,13 +95,13 @@ __global__ __launch_bounds__(256) void dgemm_kernel(Gemm g, int splitk, int kchu
         const int n = n0 + (t & 15) * 4 + 64 * c;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          rb[4 * c + j] = (k < kend && n + j < N) ? B[(long)k * g.ldb + n + j] : 0.0;
+          rb[4 * c + j] = (k < kend && n + j < N) ? B[(long)k * g.ldb + n + j] : TI(0);
       } else {              // B[n*ldb + k]
         const int n = n0 + (t >> 2) + 64 * c;
         const int k = k0 + (t & 3) * 4;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          rb[4 * c + j] = (n < N && k + j < kend) ? B[(long)n * g.ldb + k + j] : 0.0;
+          rb[4 * c + j] = (n < N && k + j < kend) ? B[(long)n * g.ldb + k + j] : TI(0);
       }
     }
   };
@@ -100,11 +124,11 @@ __global__ __launch_bounds__(256) void dgemm_kernel(Gemm g, int splitk, int kchu
     }
   };
 
-  d4 acc[TM][TN];
+  typename MF::acc acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < TN; ++j) acc[i][j] = typename MF::acc{TI(0), TI(0), TI(0), TI(0)};
 
   const int lr = lane & 15, lk = lane >> 4;
   if (kbeg < kend) {
@@ -116,7 +140,7 @@ __global__ __launch_bounds__(256) void dgemm_kernel(Gemm g, int splitk, int kchu
       if (k0 + BK < kend) load(k0 + BK);
 #pragma unroll
       for (int kk = 0; kk < BK / 4; ++kk) {
-        double a[TM], b[TN];
+        TI a[TM], b[TN];
 #pragma unroll
         for (int i = 0; i < TM; ++i) a[i] = As[kk * 4 + lk][wm * WM + i * 16 + lr];
 #pragma unroll
@@ -125,62 +149,79 @@ __global__ __launch_bounds__(256) void dgemm_kernel(Gemm g, int splitk, int kchu
         for (int i = 0; i < TM; ++i)
 #pragma unroll
           for (int j = 0; j < TN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = MF::step(a[i], b[j], acc[i][j]);
       }
     }
   }
 
-  // Output of v_mfma_f64_16x16x4f64: register r of lane l holds row l/16 + 4r,
-  // column l%16 of the 16x16 tile.
-  double* __restrict__ C;
-  long ldc;
   if (splitk > 1) {
-    C = work + (long)ks * M * N;
-    ldc = N;
-  } else {
-    C = g.C + b0 * g.sC[0] + b1 * g.sC[1] + b2 * g.sC[2];
-    ldc = g.ldc;
-  }
+    double* __restrict__ W = work + (long)ks * M * N;
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int col = n0 + wn * WN + j * 16 + lr;
+      for (int j = 0; j < TN; ++j) {
+        const int col = n0 + wn * WN + j * 16 + lr;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * WM + i * 16 + lk + 4 * r;
-        if (row < M && col < N) C[(long)row * ldc + col] = acc[i][j][r];
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm * WM + i * 16 + MF::row(lk, r);
+          if (row < M && col < N) W[(long)row * N + col] = (double)acc[i][j][r];
+        }
       }
-    }
+  } else {
+    TO* __restrict__ C = static_cast<TO*>(g.C) + b0 * g.sC[0] + b1 * g.sC[1] + b2 * g.sC[2];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int col = n0 + wn * WN + j * 16 + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm * WM + i * 16 + MF::row(lk, r);
+          if (row < M && col < N) C[(long)row * g.ldc + col] = (TO)acc[i][j][r];
+        }
+      }
+  }
 }
 
 // Deterministic split-K reduction: C[row*ldc + col] = sum_ks work[ks][row][col].
+template <typename TO>
 __global__ void splitk_reduce(const double* __restrict__ work, int splitk, int M, int N,
-                              double* __restrict__ C, long ldc) {
+                              TO* __restrict__ C, long ldc) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long MN = (long)M * N;
   if (idx >= MN) return;
   double s = 0.0;
   for (int k = 0; k < splitk; ++k) s += work[k * MN + idx];
   const int row = (int)(idx / N), col = (int)(idx % N);
-  C[(long)row * ldc + col] = s;
+  C[(long)row * ldc + col] = (TO)s;
 }
 
 namespace {
 
-template <int BM, int BN, int TAG>
+template <int BM, int BN, int TAG, typename TI, typename TO>
 void launch(const Gemm& g, int splitk, int kchunk, double* work, hipStream_t s) {
   dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.nb[0] * g.nb[1] * g.nb[2] * splitk);
   dim3 block(256);
   if (!g.transA && !g.transB)
-    hipLaunchKernelGGL((dgemm_kernel<BM, BN, false, false, TAG>), grid, block, 0, s, g, splitk, kchunk, work);
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, false, false, TAG, TI, TO>), grid, block, 0, s, g, splitk, kchunk, work);
   else if (g.transA && !g.transB)
-    hipLaunchKernelGGL((dgemm_kernel<BM, BN, true, false, TAG>), grid, block, 0, s, g, splitk, kchunk, work);
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, true, false, TAG, TI, TO>), grid, block, 0, s, g, splitk, kchunk, work);
   else if (!g.transA && g.transB)
-    hipLaunchKernelGGL((dgemm_kernel<BM, BN, false, true, TAG>), grid, block, 0, s, g, splitk, kchunk, work);
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, false, true, TAG, TI, TO>), grid, block, 0, s, g, splitk, kchunk, work);
   else
-    hipLaunchKernelGGL((dgemm_kernel<BM, BN, true, true, TAG>), grid, block, 0, s, g, splitk, kchunk, work);
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, true, true, TAG, TI, TO>), grid, block, 0, s, g, splitk, kchunk, work);
   XTRG_HIP(hipGetLastError());
+}
+
+template <typename TI, typename TO>
+void launch_sized(const Gemm& g, bool big, int sk, int kchunk, double* work, hipStream_t s) {
+  if (g.tag == 1) {
+    if (big) launch<128, 128, 1, TI, TO>(g, sk, kchunk, work, s);
+    else launch<64, 64, 1, TI, TO>(g, sk, kchunk, work, s);
+  } else {
+    if (big) launch<128, 128, 0, TI, TO>(g, sk, kchunk, work, s);
+    else launch<64, 64, 0, TI, TO>(g, sk, kchunk, work, s);
+  }
 }
 
 int choose_splitk(const Gemm& g, bool big) {
@@ -216,17 +257,19 @@ void gemm(const Gemm& g, hipStream_t s, double* work, size_t work_cap) {
     kchunk = ((g.K + sk - 1) / sk + BK - 1) / BK * BK;
     sk = (g.K + kchunk - 1) / kchunk;
   }
-  if (g.tag == 1) {
-    if (big) launch<128, 128, 1>(g, sk, kchunk, work, s);
-    else launch<64, 64, 1>(g, sk, kchunk, work, s);
-  } else {
-    if (big) launch<128, 128, 0>(g, sk, kchunk, work, s);
-    else launch<64, 64, 0>(g, sk, kchunk, work, s);
-  }
+  const bool c64 = g.prec == GEMM_F64 || g.out64;
+  if (g.prec == GEMM_F64) launch_sized<double, double>(g, big, sk, kchunk, work, s);
+  else if (g.prec == GEMM_F32 && c64) launch_sized<float, double>(g, big, sk, kchunk, work, s);
+  else if (g.prec == GEMM_F32) launch_sized<float, float>(g, big, sk, kchunk, work, s);
+  else throw Error(-1, "gemm: unknown precision");
   if (sk > 1) {
     const long MN = (long)g.M * g.N;
-    hipLaunchKernelGGL(splitk_reduce, dim3((MN + 255) / 256), dim3(256), 0, s, work, sk, g.M, g.N,
-                       g.C, g.ldc);
+    if (c64)
+      hipLaunchKernelGGL(splitk_reduce<double>, dim3((MN + 255) / 256), dim3(256), 0, s, work, sk, g.M, g.N,
+                         static_cast<double*>(g.C), g.ldc);
+    else
+      hipLaunchKernelGGL(splitk_reduce<float>, dim3((MN + 255) / 256), dim3(256), 0, s, work, sk, g.M, g.N,
+                         static_cast<float*>(g.C), g.ldc);
     XTRG_HIP(hipGetLastError());
   }
 }

@@ -24,22 +24,28 @@ struct Error : std::runtime_error {
       throw ::xtrg::Error(-3, std::string(#call) + ": " + hipGetErrorString(e_));   \
   } while (0)
 
-// Batched, strided GEMM on FP64 MFMA:  C[b] = A[b] * B[b]
+// Batched, strided GEMM on the matrix cores:  C[b] = A[b] * B[b]
 //   A element (m, k): transA ? A[k*lda + m] : A[m*lda + k]
 //   B element (k, n): transB ? B[n*ldb + k] : B[k*ldb + n]
 //   C element (m, n): C[m*ldc + n]
 // The batch index is split into up to three levels b = (b0*nb1 + b1)*nb2 + b2,
-// each with its own offset stride for A, B and C.
+// each with its own offset stride (in elements) for A, B and C.
+// Precision: GEMM_F64 (double in, double out, FP64 MFMA) or GEMM_F32
+// (float in, FP32 MFMA with FP32 accumulation; out64 selects a double or a
+// float C).
+enum { GEMM_F64 = 0, GEMM_F32 = 1 };
 struct Gemm {
   int M = 0, N = 0, K = 0;
   int transA = 0, transB = 0;
   long lda = 0, ldb = 0, ldc = 0;
   int nb[3] = {1, 1, 1};
   long sA[3] = {0, 0, 0}, sB[3] = {0, 0, 0}, sC[3] = {0, 0, 0};
-  const double* A = nullptr;
-  const double* B = nullptr;
-  double* C = nullptr;
-  int tag = 0;   // 1: the two-site overlap C_E (its own kernel symbol for profiling)
+  const void* A = nullptr;
+  const void* B = nullptr;
+  void* C = nullptr;
+  int tag = 0;    // 1: the two-site overlap C_E (its own kernel symbol for profiling)
+  int prec = GEMM_F64;
+  int out64 = 1;  // GEMM_F32 only: C is double (1) or float (0)
 };
 
 // Launch; split-K (for small M*N and large K, unbatched only) uses `work`
@@ -64,7 +70,16 @@ struct SvdJob {
   double* work;      // svd_work(len, p) doubles
   int sweeps;        // out
 };
-void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s);
+// Optional timing of the Jacobi rounds (event pair around each sweep's
+// back-to-back round launches on the stream).
+struct RoundTimer {
+  virtual ~RoundTimer() = default;
+  virtual void begin(hipStream_t s) = 0;
+  // launches: round kernels in the bracket; flops: Gram (symmetric) plus
+  // rotation of every visited pair; bytes: each column read and written once
+  virtual void end(hipStream_t s, long launches, double flops, double bytes) = 0;
+};
+void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, RoundTimer* timer = nullptr);
 
 // Two-stage use: svd_left with k = 0, read the sorted values, then gather.
 void svd_gather(int len, int p, double* work, int k, double* U, long ldu, int u_rowmajor, hipStream_t s);
@@ -83,6 +98,8 @@ double svd_keep_rel(int len, int p);
 // Small elementwise / reduction kernels (misc.hip).
 void copy(double* dst, const double* src, size_t n, hipStream_t s);
 void fill(double* dst, double v, size_t n, hipStream_t s);
+void to_f32(float* dst, const double* src, size_t n, hipStream_t s);   // round to nearest
+void fill_f32(float* dst, float v, size_t n, hipStream_t s);
 void scale(double* x, double a, size_t n, hipStream_t s);
 // y = a*y + b*x
 void axpby(double* y, double a, const double* x, double b, size_t n, hipStream_t s);

@@ -134,7 +134,29 @@ __global__ void k_contract(Contract c, long n_out_total) {
   }
 }
 
+__global__ void k_to_f32(float* __restrict__ dst, const double* __restrict__ src, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
+__global__ void k_fill_f32(float* __restrict__ dst, float v, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = v;
+}
+
 }  // namespace
+
+void to_f32(float* dst, const double* src, size_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_to_f32, grid_for(n), dim3(kT), 0, s, dst, src, n);
+  XTRG_HIP(hipGetLastError());
+}
+
+void fill_f32(float* dst, float v, size_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_fill_f32, grid_for(n), dim3(kT), 0, s, dst, v, n);
+  XTRG_HIP(hipGetLastError());
+}
 
 void copy(double* dst, const double* src, size_t n, hipStream_t s) {
   if (n) XTRG_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, s));

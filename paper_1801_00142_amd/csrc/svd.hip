@@ -72,8 +72,6 @@ constexpr int kWT = 512;                  // threads of a round workgroup
 constexpr int kWW = kWT / 64;             // its waves
 constexpr int kBlk = 16;                  // columns per block
 constexpr int kNC = 2 * kBlk;             // columns per block pair
-constexpr int kChunk = 128;               // rows per LDS chunk (16 per wave)
-constexpr int kZP = kChunk + 1;           // padded chunk column
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // One Jacobi problem of a grouped launch (blockIdx.y selects the problem).
@@ -111,16 +109,17 @@ __device__ inline bool needs_rot(double a, double b, double g, double tol2, doub
 // columns x' = c x - s y, y' = s x + c y (the smaller of the two angles:
 // t = tan = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (b - a) / 2g);
 // identity if the pair needs none.
+// Branch-free (the value is selected at the end), so that two rotations in
+// one thread interleave their dependent chains.
 __device__ inline void jacobi_rot(double a, double b, double g, double tol2, double zth, double* c, double* s) {
-  *c = 1.0;
-  *s = 0.0;
-  if (needs_rot(a, b, g, tol2, zth)) {
-    const double zeta = (b - a) * rcp_refined(2.0 * g);
-    const double w = fma(zeta, zeta, 1.0);
-    const double tt = copysign(1.0, zeta) * rcp_refined(fabs(zeta) + w * rsq_refined(w));
-    *c = rsq_refined(fma(tt, tt, 1.0));
-    *s = *c * tt;
-  }
+  const bool need = needs_rot(a, b, g, tol2, zth);
+  const double gg = need ? g : 1.0;
+  const double zeta = (b - a) * rcp_refined(2.0 * gg);
+  const double w = fma(zeta, zeta, 1.0);
+  const double tt = copysign(1.0, zeta) * rcp_refined(fabs(zeta) + w * rsq_refined(w));
+  const double cc = rsq_refined(fma(tt, tt, 1.0));
+  *c = need ? cc : 1.0;
+  *s = need ? cc * tt : 0.0;
 }
 
 __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict__ descs, int r) {
@@ -130,10 +129,11 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   const int len = d.len, p = d.p, nbk = d.nbk;
   const double tol = d.tol;
   __shared__ int colid[kNC];
-  __shared__ double buf[kWW * 3 * 4 * 64];   // chunk [kNC][kZP], then the wave partials
+  __shared__ double buf[kWW * 3 * 4 * 64];   // wave partials of the Gram tiles
   __shared__ double G[2][kNC][kNC + 1];
   __shared__ double Wt[kNC][kNC + 2];         // W transposed: Wt[c][j] = W[j][c]
   __shared__ double wmax[kWW];
+  __shared__ unsigned wmask[kWW];
   int bi, bj;
   rr_pair(nbk, r, blockIdx.x, &bi, &bj);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -143,37 +143,33 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   }
   __syncthreads();
 
-  // 1. Gram tiles (0,0), (0,1), (1,1) of the pair on the matrix cores.
+  // 1. Gram tiles (0,0), (0,1), (1,1) of the pair on the matrix cores,
+  // operands straight from memory: per MFMA step a wave takes 4 rows, lane l
+  // row l/16 of column l%16 of each block (4 consecutive rows of a column
+  // per 4 lanes, 32-byte sectors fully used).  Waves interleave 4-row groups.
   d4 acc[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
   {
     const int lr = lane & 15, lk = lane >> 4;
-    const int erow = t & (kChunk - 1), cb = t >> 7;
-    double pre[kNC / 4];                       // this thread's part of the next chunk
-    auto fetch = [&](int e0) {
-      const int e = e0 + erow;
+    const int c0 = colid[lr], c1 = colid[kBlk + lr];
+    const double* __restrict__ y0 = Y + (long)(c0 >= 0 ? c0 : 0) * len;
+    const double* __restrict__ y1 = Y + (long)(c1 >= 0 ? c1 : 0) * len;
+    constexpr int U = 16;                      // row groups in flight per wave
+    for (int g0 = wave * 4; g0 < len; g0 += kWW * 4 * U) {
+      double a0[U], a1[U];
 #pragma unroll
-      for (int j = 0; j < kNC / 4; ++j) {
-        const int col = colid[cb + 4 * j];
-        pre[j] = (col >= 0 && e < len) ? Y[(long)col * len + e] : 0.0;
+      for (int u = 0; u < U; ++u) {
+        const int e = g0 + u * kWW * 4 + lk;
+        a0[u] = (c0 >= 0 && e < len) ? y0[e] : 0.0;
+        a1[u] = (c1 >= 0 && e < len) ? y1[e] : 0.0;
       }
-    };
-    fetch(0);
-    for (int e0 = 0; e0 < len; e0 += kChunk) {
 #pragma unroll
-      for (int j = 0; j < kNC / 4; ++j) buf[(cb + 4 * j) * kZP + erow] = pre[j];
-      __syncthreads();
-      if (e0 + kChunk < len) fetch(e0 + kChunk);
-#pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) {
-        const int row = wave * 16 + s4 * 4 + lk;
-        const double a0 = buf[lr * kZP + row], a1 = buf[(kBlk + lr) * kZP + row];
-        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a0, acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a1, acc[1], 0, 0, 0);
-        acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a1, acc[2], 0, 0, 0);
+      for (int u = 0; u < U; ++u) {
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], a0[u], acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], a1[u], acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], a1[u], acc[2], 0, 0, 0);
       }
-      __syncthreads();
     }
   }
   // register q of lane l holds tile row l/16 + 4q, column l%16
@@ -204,6 +200,7 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   const double zth = d.zrel2 * d.fro2[0];
   const double tol2 = tol * tol;
   double off = 0.0;
+  unsigned mask = 0;                 // bit r: some pair (k, k ^ r) needs a rotation
   for (int idx = t; idx < kNC * (kNC - 1) / 2; idx += kWT) {
     int x = 0, q = idx;
     while (q >= kNC - 1 - x) {
@@ -212,15 +209,28 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
     }
     const int y = x + 1 + q;
     const double a = G[0][x][x], b = G[0][y][y], g = G[0][x][y];
-    if (needs_rot(a, b, g, tol2, zth)) off = fmax(off, fabs(g) / sqrt(a * b));
+    if (needs_rot(a, b, g, tol2, zth)) {
+      off = fmax(off, fabs(g) / sqrt(a * b));
+      mask |= 1u << (x ^ y);
+    }
   }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o, 64));
-  if (lane == 0) wmax[wave] = off;
+  for (int o = 32; o > 0; o >>= 1) {
+    off = fmax(off, __shfl_xor(off, o, 64));
+    mask |= __shfl_xor(mask, o, 64);
+  }
+  if (lane == 0) {
+    wmax[wave] = off;
+    wmask[wave] = mask;
+  }
   __syncthreads();
   double worst = 0.0;
+  mask = 0;
 #pragma unroll
-  for (int w = 0; w < kWW; ++w) worst = fmax(worst, wmax[w]);
+  for (int w = 0; w < kWW; ++w) {
+    worst = fmax(worst, wmax[w]);
+    mask |= wmask[w];
+  }
   // block maximum published as the bit pattern of a non-negative double
   // (monotone under unsigned comparison)
   if (t == 0 && worst > 0.0) atomicMax(d.off, (unsigned long long)__double_as_longlong(worst));
@@ -231,6 +241,10 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
     const int q = t >> 5, k = t & 31;
     int src = 0;
     for (int rr = 1; rr < kNC; ++rr) {
+      // rounds with no flagged pair are skipped (uniform: mask is shared);
+      // rotations in earlier rounds may push a pair of a skipped round over
+      // tol, which the next visit's fresh Gram flags again
+      if (!((mask >> rr) & 1u)) continue;
       const int h = 31 - __clz(rr);                                   // highest bit of rr
       const int x = ((q >> h) << (h + 1)) | (q & ((1 << h) - 1));    // q-th k with k < (k ^ rr)
       const int y = x ^ rr;
@@ -277,25 +291,33 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
     for (int I = 0; I < 2; ++I)
 #pragma unroll
       for (int q = 0; q < 4; ++q) cout[I][q] = colid[I * 16 + lk + 4 * q];
-    for (int e0 = wave * 16; e0 < len; e0 += kWW * 16) {
-      const int e = e0 + lr;
-      double zb[kNC / 4];
+    constexpr int T = 4;                       // 16-row tiles in flight per wave
+    for (int e0 = wave * 16; e0 < len; e0 += kWW * 16 * T) {
+      double zb[T][kNC / 4];
 #pragma unroll
-      for (int kk = 0; kk < kNC / 4; ++kk)
-        zb[kk] = (cin[kk] >= 0 && e < len) ? Y[(long)cin[kk] * len + e] : 0.0;
-      d4 o[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
+      for (int u = 0; u < T; ++u) {
+        const int e = e0 + u * kWW * 16 + lr;
 #pragma unroll
-      for (int kk = 0; kk < kNC / 4; ++kk) {
-        o[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[0][kk], zb[kk], o[0], 0, 0, 0);
-        o[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[1][kk], zb[kk], o[1], 0, 0, 0);
+        for (int kk = 0; kk < kNC / 4; ++kk)
+          zb[u][kk] = (cin[kk] >= 0 && e < len) ? Y[(long)cin[kk] * len + e] : 0.0;
       }
-      // register q of lane l: column I*16 + l/16 + 4q of Z W, row e0 + l%16
-      if (e < len) {
 #pragma unroll
-        for (int I = 0; I < 2; ++I)
+      for (int u = 0; u < T; ++u) {
+        const int e = e0 + u * kWW * 16 + lr;
+        d4 o[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
 #pragma unroll
-          for (int q = 0; q < 4; ++q)
-            if (cout[I][q] >= 0) Y[(long)cout[I][q] * len + e] = o[I][q];
+        for (int kk = 0; kk < kNC / 4; ++kk) {
+          o[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[0][kk], zb[u][kk], o[0], 0, 0, 0);
+          o[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[1][kk], zb[u][kk], o[1], 0, 0, 0);
+        }
+        // register q of lane l: column I*16 + l/16 + 4q of Z W, row e
+        if (e < len) {
+#pragma unroll
+          for (int I = 0; I < 2; ++I)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              if (cout[I][q] >= 0) Y[(long)cout[I][q] * len + e] = o[I][q];
+        }
       }
     }
   }
@@ -374,7 +396,7 @@ static int* sv_perm(double* work, int len, int p) {
 
 size_t svd_desc_bytes(int n) { return sizeof(JacobiDesc) * (size_t)n + sizeof(unsigned long long) * (size_t)n; }
 
-void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s) {
+void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, RoundTimer* timer) {
   const int n = (int)jobs.size();
   if (n == 0) return;
   JacobiDesc* d_desc = reinterpret_cast<JacobiDesc*>(desc_dev);
@@ -448,8 +470,19 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s) {
       dirty = false;
     }
     XTRG_HIP(hipMemsetAsync(d_off, 0, sizeof(unsigned long long) * n, s));
+    if (timer) timer->begin(s);
     for (int r = 0; r < max_nbk - 1; ++r) round(r);
     XTRG_HIP(hipGetLastError());
+    if (timer) {
+      double fl = 0.0, by = 0.0;
+      for (const auto& D : h)
+        if (D.active) {
+          const double pairs = 0.5 * D.nbk * (D.nbk - 1);          // over the whole sweep
+          fl += pairs * (kNC * (kNC + 1) / 2 * 2.0 + 2.0 * kNC * kNC) * D.len;
+          by += (D.nbk - 1) * 16.0 * D.len * D.p;
+        }
+      timer->end(s, max_nbk - 1, fl, by);
+    }
     XTRG_HIP(hipMemcpyAsync(hoff.data(), d_off, sizeof(unsigned long long) * n, hipMemcpyDeviceToHost, s));
     XTRG_HIP(hipStreamSynchronize(s));
     for (int j = 0; j < n; ++j) {

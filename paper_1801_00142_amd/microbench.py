@@ -1,0 +1,60 @@
+"""Kernel micro-benchmarks of the library (for profiling runs).
+
+    python -m paper_1801_00142_amd.microbench svd N DECADES [REPS]
+        one-sided Jacobi SVD (xtrg_dsvd_left) of an N x N matrix with a
+        graded spectrum sigma_k = 10^(-DECADES k/(N-1)) and random orthogonal
+        factors (seeded); prints the time and Jacobi sweeps per call.
+    python -m paper_1801_00142_amd.microbench copy GIB
+        one device-to-device copy of GIB GiB: the reference for scaling the
+        HBM byte counters (FETCH_SIZE, WRITE_SIZE) of other kernels.
+"""
+import sys
+import time
+
+import numpy as np
+
+
+def svd(n: int, decades: float, reps: int = 2) -> None:
+    import torch
+    from . import Context
+    rng = np.random.default_rng(0)
+    U0, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    V0, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    s0 = 10.0 ** -np.linspace(0, decades, n)
+    Y = (U0 * s0) @ V0.T
+    ctx = Context(0)
+    dY = torch.from_numpy(Y.T.copy()).cuda()
+    sig = torch.zeros(n, dtype=torch.float64, device="cuda")
+    ctx.profile(True)
+    ctx.profile_report()
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ctx.dsvd_left(n, n, dY.data_ptr(), sig.data_ptr(), 0, None)
+        torch.cuda.synchronize()
+        print(f"svd {n}x{n}, {decades} decades: {time.perf_counter() - t:.4f} s", flush=True)
+    r = ctx.profile_report()
+    print(f"sweeps per call {r['svd_sweeps'] / max(r['svd_calls'], 1):.1f}; "
+          f"max |sigma - sigma_exact| / sigma_1 = {np.abs(sig.cpu().numpy() - s0).max():.2e}", flush=True)
+    ctx.close()
+
+
+def copy(gib: float) -> None:
+    import torch
+    n = int(gib * 2 ** 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"copied {n * 8} bytes", flush=True)
+
+
+if __name__ == "__main__":
+    if len(sys.argv) >= 4 and sys.argv[1] == "svd":
+        svd(int(sys.argv[2]), float(sys.argv[3]), int(sys.argv[4]) if len(sys.argv) > 4 else 2)
+    elif len(sys.argv) == 3 and sys.argv[1] == "copy":
+        copy(float(sys.argv[2]))
+    else:
+        print(__doc__)
+        sys.exit(2)

@@ -19,6 +19,7 @@ _LIB_PATH = os.path.join(_HERE, "libxtrg.so")
 _lib = None
 
 XTRG_FP64 = 0
+XTRG_FP32 = 1
 
 
 class XtrgError(RuntimeError):
@@ -70,6 +71,8 @@ def load_library(path: Optional[str] = None):
                                        C.POINTER(Obs), dp]),
         "xtrg_dgemm": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, vp, C.c_long, vp,
                                  C.c_long, vp, C.c_long]),
+        "xtrg_sgemm": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, vp, C.c_long, vp,
+                                 C.c_long, vp, C.c_long, C.c_int]),
         "xtrg_dsvd_left": (C.c_int, [vp, C.c_int, C.c_int, vp, vp, C.c_int, vp]),
         "xtrg_profile_enable": (C.c_int, [vp, C.c_int]),
         "xtrg_profile_report": (C.c_int, [vp, C.c_char_p, C.c_size_t]),
@@ -86,7 +89,7 @@ def exported_symbols() -> List[str]:
     return ["xtrg_ctx_create", "xtrg_ctx_destroy", "xtrg_last_error", "xtrg_ctx_bytes",
             "xtrg_hamiltonian_xxz", "xtrg_mpo_from_host", "xtrg_mpo_shape", "xtrg_mpo_to_host",
             "xtrg_mpo_destroy", "xtrg_init_rho", "xtrg_square_compress", "xtrg_square_compress_batched", "xtrg_observables",
-            "xtrg_dgemm", "xtrg_dsvd_left", "xtrg_profile_enable", "xtrg_profile_report"]
+            "xtrg_dgemm", "xtrg_sgemm", "xtrg_dsvd_left", "xtrg_profile_enable", "xtrg_profile_report"]
 
 
 class MPO:
@@ -192,8 +195,8 @@ class Context:
         return MPO(self, h), lam.value
 
     def square_compress(self, rho: MPO, D_max: int, n_sweeps: int = 4, degen_rtol: float = 1e-6,
-                        sv_floor: float = 1e-14, sv_stride: int = 0):
-        o = CompressOpts(D_max, n_sweeps, XTRG_FP64, degen_rtol, sv_floor)
+                        sv_floor: float = 1e-14, sv_stride: int = 0, precision: int = XTRG_FP64):
+        o = CompressOpts(D_max, n_sweeps, precision, degen_rtol, sv_floor)
         info = CompressInfo()
         L = rho.shape()[0]
         buf = None
@@ -210,7 +213,8 @@ class Context:
         return MPO(self, h), out
 
     def square_compress_batched(self, rhos: Sequence[MPO], D_max, n_sweeps=4,
-                                degen_rtol: float = 1e-6, sv_floor: float = 1e-14, sv_stride: int = 0):
+                                degen_rtol: float = 1e-6, sv_floor: float = 1e-14, sv_stride: int = 0,
+                                precision: int = XTRG_FP64):
         """One doubling of every chain in `rhos` together.  D_max and n_sweeps
         are one value for all chains or a sequence with one per chain.
         Returns ([new MPO per chain], [info dict per chain])."""
@@ -219,7 +223,7 @@ class Context:
         Ss = list(n_sweeps) if isinstance(n_sweeps, (list, tuple)) else [n_sweeps] * n
         if len(Ds) != n or len(Ss) != n:
             raise ValueError("one D_max and n_sweeps per chain")
-        o = (CompressOpts * n)(*[CompressOpts(Ds[q], Ss[q], XTRG_FP64, degen_rtol, sv_floor) for q in range(n)])
+        o = (CompressOpts * n)(*[CompressOpts(Ds[q], Ss[q], precision, degen_rtol, sv_floor) for q in range(n)])
         infos = (CompressInfo * n)()
         bufs = []
         for q, r in enumerate(rhos):
@@ -272,6 +276,10 @@ class Context:
         _check(self, _lib.xtrg_dgemm(self.h, M, N, K, int(transA), int(transB), C.c_void_p(A), lda,
                                      C.c_void_p(B), ldb, C.c_void_p(Cp), ldc))
 
+    def sgemm(self, M, N, K, transA, transB, A, lda, B, ldb, Cp, ldc, c_double=True):
+        _check(self, _lib.xtrg_sgemm(self.h, M, N, K, int(transA), int(transB), C.c_void_p(A), lda,
+                                     C.c_void_p(B), ldb, C.c_void_p(Cp), ldc, int(c_double)))
+
     def dsvd_left(self, length, p, Y, sigma, k=0, U=None):
         _check(self, _lib.xtrg_dsvd_left(self.h, length, p, C.c_void_p(Y), C.c_void_p(sigma), k,
                                          C.c_void_p(U) if U else None))
@@ -279,9 +287,14 @@ class Context:
 
 def run(ctx: Context, n_sites: int, bonds, jxy, jz, tau0: float, n_doublings: int, D: int, order: int = 1,
         n_sweeps: int = 4, degen_rtol: float = 1e-6, sv_floor: float = 1e-14, observe: bool = True,
-        entropy: bool = False):
+        entropy: bool = False, precision: int = XTRG_FP64, beta_mix: float = 1.0):
     """Full XTRG run through the library: rho(tau0), then n_doublings doublings;
-    returns per-doubling records (observables at beta = tau_n and 2 tau_n)."""
+    returns per-doubling records (observables at beta = tau_n and 2 tau_n).
+
+    precision != XTRG_FP64 applies from the doubling whose result reaches
+    beta = 2 tau_{n+1} >= beta_mix; earlier doublings run in FP64.  The
+    relative error a doubling leaves in ln Z enters f = -ln Z/(N beta) divided
+    by beta, so the high-temperature doublings need the most precision."""
     H = ctx.hamiltonian_xxz(n_sites, bonds, jxy, jz)
     rho, lam = ctx.init_rho(H, tau0, order)
     tau = tau0
@@ -297,7 +310,8 @@ def run(ctx: Context, n_sites: int, bonds, jxy, jz, tau0: float, n_doublings: in
 
     recs.append(rec(0))
     for n in range(1, n_doublings + 1):
-        new, info = ctx.square_compress(rho, D, n_sweeps, degen_rtol, sv_floor)
+        prec = precision if 4 * tau >= beta_mix else XTRG_FP64
+        new, info = ctx.square_compress(rho, D, n_sweeps, degen_rtol, sv_floor, precision=prec)
         rho.close()
         rho = new
         lam = 2 * lam + info["dlog_norm"]

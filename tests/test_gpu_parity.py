@@ -56,6 +56,31 @@ def test_dgemm_matches_fp64_matmul(ctx, M_, N_, K_, tA, tB):
     assert np.abs(got - want).max() <= 4 * bound
 
 
+@pytest.mark.parametrize("M_,N_,K_", [(1, 1, 1), (17, 33, 5), (130, 257, 70), (300, 129, 1000), (128, 128, 8192)])
+@pytest.mark.parametrize("tA,tB", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("c_double", [True, False])
+def test_sgemm_matches_fp64_matmul(ctx, M_, N_, K_, tA, tB, c_double):
+    """The FP32 contraction precision: float operands, FP32 accumulation.
+    Bound: K FP32 roundings of the largest product (split-K partials are
+    summed in FP64), plus the final rounding of a float output."""
+    import torch
+    rng = np.random.default_rng(M_ * 5 + N_ * 7 + K_ + 3 * tA + 17 * tB)
+    A = rng.standard_normal((K_, M_) if tA else (M_, K_)).astype(np.float32)
+    B = rng.standard_normal((N_, K_) if tB else (K_, N_)).astype(np.float32)
+    want = (A.T if tA else A).astype(np.float64) @ (B.T if tB else B).astype(np.float64)
+    dA, dB = _dev(A), _dev(B)
+    dt = torch.float64 if c_double else torch.float32
+    dC = torch.full((M_, N_), float("nan"), dtype=dt, device="cuda")
+    ctx.sgemm(M_, N_, K_, tA, tB, dA.data_ptr(), A.shape[1], dB.data_ptr(), B.shape[1], dC.data_ptr(), N_,
+              c_double)
+    torch.cuda.synchronize()
+    got = dC.cpu().numpy().astype(np.float64)
+    eps32 = 2.0 ** -24
+    bound = 2 * eps32 * K_ * np.abs(A).max() * np.abs(B).max() + eps32 * np.abs(want).max()
+    assert np.all(np.isfinite(got))
+    assert np.abs(got - want).max() <= bound
+
+
 @pytest.mark.parametrize("length,p", [(1, 1), (5, 3), (3, 5), (64, 64), (100, 37), (37, 100), (300, 256),
                                       (1024, 64)])
 def test_svd_graded_spectrum(ctx, length, p):
@@ -332,3 +357,43 @@ def test_batched_error_paths(ctx):
     new, info = ctx.square_compress(a, 8, 1)
     for x, y in zip(outs[0].to_host(), new.to_host()):
         assert np.array_equal(x, y)
+
+
+# ---------------------------------------------------------------- FP32 contractions
+
+@pytest.mark.parametrize("case", [
+    dict(lat=W.chain(10), tau0=2.0 ** -10, n=10, D=32, order=2, beta_mix=1.0, rtol=1e-6),
+    dict(lat=W.square_cylinder(3, 3), tau0=2.0 ** -8, n=8, D=40, order=1, beta_mix=1.0, rtol=1e-6),
+    dict(lat=W.chain(10), tau0=2.0 ** -10, n=10, D=32, order=2, beta_mix=0.0, rtol=3e-5),
+], ids=["chain10_D32_mix1", "sq3x3_D40_mix1", "chain10_D32_all_fp32"])
+def test_fp32_run_matches_oracle(ctx, case):
+    """XTRG_FP32 contractions with FP64 truncation against the FP64 oracle:
+    free energy and energy per site to 1e-6 relative at every beta (the
+    mixed-precision target) when the doublings below beta_mix = 1 run in
+    FP64.  Without that schedule the FP32 rounding of ln Z is divided by a
+    small beta and the high-temperature f is only good to ~1e-5 (measured
+    7e-6 at beta = 2^-9), which the last case bounds."""
+    from paper_1801_00142_amd import XTRG_FP32, run
+    lat = case["lat"]
+    args = (lat.n_sites, lat.bonds, lat.jxy, lat.jz, case["tau0"], case["n"], case["D"])
+    gpu = run(ctx, *args, order=case["order"], n_sweeps=2, precision=XTRG_FP32, beta_mix=case["beta_mix"])
+    ora = OX.run(*args, order=case["order"], n_sweeps=2)
+    _compare_runs(gpu, ora, lat.n_sites, case["rtol"])
+    for g in gpu:
+        assert max(g["bond_dims"]) <= case["D"]
+
+
+def test_fp32_batched_equals_single(ctx):
+    """The batched doubling in FP32 returns what the single-chain call does."""
+    from paper_1801_00142_amd import XTRG_FP32
+    lat = W.chain(8)
+    H = ctx.hamiltonian_xxz(lat.n_sites, lat.bonds, lat.jxy, lat.jz)
+    rhos = [ctx.init_rho(H, t, 1)[0] for t in W.zshift_tau0(2.0 ** -6, 2)]
+    for _ in range(3):
+        outs, infos = ctx.square_compress_batched(rhos, 16, 2, precision=XTRG_FP32)
+        for q, r in enumerate(rhos):
+            new, info = ctx.square_compress(r, 16, 2, precision=XTRG_FP32)
+            for x, y in zip(new.to_host(), outs[q].to_host()):
+                assert np.array_equal(x, y)
+            assert info["dlog_norm"] == infos[q]["dlog_norm"]
+        rhos = outs
