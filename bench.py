@@ -148,6 +148,7 @@ def main():
     value = flops / dt / 1e12
     svd_calls = prof.pop("svd_calls", 0)
     svd_sweeps = prof.pop("svd_sweeps", 0)
+    warm_stats = {k: prof.pop(k, 0) for k in ("warm_built", "warm_rejected", "warm_used", "warm_m")}
     rounds = prof.pop("svd_rounds")
     th = prof["theta_gemm"]
     th_avg_s = th["ms"] / max(th["calls"], 1) / 1e3
@@ -182,6 +183,10 @@ def main():
         "sweeps_per_s": round(nb * args.steps * args.sweeps / dt, 4),
         "phase_share": shares,
         "svd_sweeps_avg": round(svd_sweeps / max(svd_calls, 1), 2),
+        "svd_warm": {"calls": svd_calls, "warm_started": warm_stats["warm_used"],
+                     "bases_built": warm_stats["warm_built"], "bases_rejected": warm_stats["warm_rejected"],
+                     "mean_completion": round(warm_stats["warm_m"] /
+                                              max(warm_stats["warm_built"] + warm_stats["warm_rejected"], 1), 1)},
         # the dominant kernel: the Jacobi rounds of the SVD (bytes = each
         # column of the visited pairs read and written once per round)
         "roofline": {"bound": "hbm", "kernel": "jacobi_round (one-sided block Jacobi SVD round)",

@@ -103,6 +103,9 @@ typedef struct {
   int precision;     /* XTRG_FP64 or XTRG_FP32 */
   double degen_rtol; /* multiplet-safe cut: back off to a gap > degen_rtol*sigma_k (1e-6) */
   double sv_floor;   /* singular values <= sv_floor*sigma_1 count as zero (1e-14) */
+  int no_warm_start; /* 0: each SVD after the first visit of a bond starts from the
+                        previous visit's singular basis (same result, fewer Jacobi
+                        sweeps); 1: every SVD starts cold */
 } xtrg_compress_opts;
 
 /* Diagnostics of one doubling. */

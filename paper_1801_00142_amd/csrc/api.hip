@@ -47,6 +47,8 @@ struct xtrg_ctx_s {
   bool prof = false;
   std::vector<Prof> prof_recs;
   long svd_calls = 0, svd_sweeps = 0;
+  // warm-start statistics: bases built, rejected, used; sum of completion sizes m
+  long warm_built = 0, warm_rejected = 0, warm_used = 0, warm_m = 0;
 
   double* alloc(size_t n) {
     const size_t b = std::max<size_t>(n, 1) * sizeof(double);
@@ -108,8 +110,9 @@ namespace {
 // Phases of the doubling step timed by the profiler.
 // svd_rounds is the part of svd spent in the Jacobi round kernels; its
 // "calls" count kernel launches.
-enum { P_THETA = 0, P_BLOCK, P_ENV, P_SVD, P_SPLIT, P_ROUNDS, P_NCAT };
-const char* const kPhase[P_NCAT] = {"theta_gemm", "block_gemm", "env_gemm", "svd", "split", "svd_rounds"};
+// warm is the building of the warm-start bases and the rotation of the SVD input.
+enum { P_THETA = 0, P_BLOCK, P_ENV, P_SVD, P_SPLIT, P_ROUNDS, P_WARM, P_NCAT };
+const char* const kPhase[P_NCAT] = {"theta_gemm", "block_gemm", "env_gemm", "svd", "split", "svd_rounds", "warm"};
 
 // RAII event pair around the work enqueued in its scope.
 struct Timed {
@@ -357,10 +360,14 @@ std::vector<double> read_vec(xtrg_ctx c, const double* d, size_t n) {
 }
 
 // Absolute rounding-noise floor of the matrix last decomposed in `work`.
-double noise_floor(xtrg_ctx c, const double* work, int len, int p) {
-  const double f2 = read_vec(c, xtrg::svd_fro2(work, len, p), 1)[0];
+// work holds an SVD of len x p_work columns; p is the column count of the
+// matrix whose rounding noise is meant (C_E itself when the SVD ran on C_E
+// rotated into extra columns).
+double noise_floor(xtrg_ctx c, const double* work, int len, int p_work, int p) {
+  const double f2 = read_vec(c, xtrg::svd_fro2(work, len, p_work), 1)[0];
   return xtrg::svd_keep_rel(len, p) * std::sqrt(std::max(f2, 0.0));
 }
+double noise_floor(xtrg_ctx c, const double* work, int len, int p) { return noise_floor(c, work, len, p, p); }
 
 // Enforce orthonormal columns on the len x k isometry U by Newton-Schulz
 // polar iterations U <- U (3I - U^T U)/2: the column space is kept and the
@@ -609,12 +616,24 @@ struct Chain {
   std::vector<int> kept;
   std::vector<double> disc;
   double flops = 0.0, last_norm = 0.0;
+  // Warm start of the SVD at each bond: an orthogonal basis from the
+  // previous visit of the bond (side 0: left index of C_E, 1: right index).
+  struct WarmQ {
+    int side = -1;
+    int dim = 0;      // rows of the basis block Q (the index dimension)
+    int cols = 0;     // its columns: dim, plus the extra columns of the completion
+  };
+  std::vector<WarmQ> warm;
+  std::vector<char> revisit;              // step st: its bond is visited again later
+  size_t st = 0;                          // current step
   // current step
   int i = 0;
   bool gauge_right = false;
+  const double* Y = nullptr;              // SVD input: C_E, or C_E rotated by the warm basis
   void* Lb = nullptr;
   void* Rb = nullptr;
   int mL = 0, mR = 0, Kt = 0, len = 0, p = 0;
+  int psvd = 0;                           // columns of the SVD input (p, or p + extra with a warm start)
 };
 
 void check_opts(const xtrg_compress_opts& o) {
@@ -632,6 +651,14 @@ void chain_setup(xtrg_ctx c, Chain& C, xtrg_mpo in, int q) {
   Doubler& d = C.d;
   C.tag = q == 0 ? "" : "#" + std::to_string(q);
   C.sched = schedule(L, C.o.n_sweeps);
+  C.revisit.assign(C.sched.size(), 0);
+  {
+    std::vector<char> seen(L, 0);
+    for (size_t q = C.sched.size(); q-- > 0;) {
+      C.revisit[q] = seen[C.sched[q].bond];
+      seen[C.sched[q].bond] = 1;
+    }
+  }
   d.c = c;
   d.L = L;
   d.tag = C.tag;
@@ -686,6 +713,7 @@ void chain_setup(xtrg_ctx c, Chain& C, xtrg_mpo in, int q) {
     xtrg::fill_f32(static_cast<float*>(C.F), 1.0f, 1, s);
   }
   C.sv.resize(L - 1);
+  C.warm.assign(L - 1, Chain::WarmQ{});
   C.kept.assign(L - 1, 1);
   C.disc.assign(L - 1, 0.0);
   for (int j = L - 1; j >= 1; --j) {
@@ -698,6 +726,105 @@ void chain_setup(xtrg_ctx c, Chain& C, xtrg_mpo in, int q) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Warm start of the SVD.  Consecutive visits of bond i share one index basis
+// of C_E: a left-to-right step and the right-to-left step that follows it
+// at the same bond share the left index (C_{i-1} is unchanged in between),
+// that step and the next left-to-right one share the right index (C_{i+2}
+// is unchanged).  The singular vectors of the previous visit on the shared
+// side, completed to an orthogonal basis Q, rotate the next SVD input:
+// Y Q has the same left singular vectors and values as Y for any orthogonal
+// Q, and nearly orthogonal columns when Q is close to the new right
+// singular vectors, so the one-sided Jacobi needs far fewer sweeps.  Q only
+// steers the convergence; its orthogonality (to 1e-13) is what the result
+// relies on, and it is checked.
+// ---------------------------------------------------------------------------
+constexpr int kWarmMin = 128;   // smallest SVD column count worth a warm start
+
+// it Newton-Schulz steps X <- X (3I - X^T X)/2 on the columns of X
+// (column-major len x k, sigma_max(X) < sqrt(3)): singular values below 1
+// grow by up to 1.5 per step, then converge quadratically.
+void ns_steps(xtrg_ctx c, double* X, int len, int k, int it) {
+  double* G = c->need("wq_G", (size_t)k * k);
+  double* T = c->need("wq_T", (size_t)len * k);
+  for (int q = 0; q < it; ++q) {
+    gemm(c, plain(k, k, len, X, len, false, X, len, true, G, k));       // X^T X
+    gemm(c, plain(k, len, k, G, k, false, X, len, false, T, len));       // X (X^T X)
+    xtrg::axpby(X, 1.5, T, -0.5, (size_t)len * k, c->stream);
+  }
+}
+
+// max |X^T X - I| for X column-major len x k.
+double orth_dev(xtrg_ctx c, const double* X, int len, int k) {
+  double* G = c->need("wq_G", (size_t)k * k);
+  gemm(c, plain(k, k, len, X, len, false, X, len, true, G, k));
+  xtrg::eye_dev(G, k, c->scratch, c->scratch + 1024, c->stream);
+  return read_scalar(c, c->scratch);
+}
+
+// After the SVD of this visit: a basis block Q for the next visit of the
+// bond, with Q Q^T = I on the row space of Y.  The normalised Jacobi columns
+// above the noise level (r of them) are orthonormal to the Jacobi tolerance.
+// The complement (dimension m = len - r) is represented by m + o hashed
+// noise vectors projected off them (twice) and driven by Newton-Schulz to
+// their polar factor X, for which X X^T is the projector onto the complement
+// (the o surplus directions have singular values that stay at rounding
+// level and add ~1e-25 to X X^T).  The surplus keeps the noise block
+// rectangular and so well conditioned: a square random block has a smallest
+// singular value with a tail towards zero.  The next SVD runs on Y [Q0 X]
+// (len + o columns), whose left singular vectors and values are those of Y.
+constexpr int kWarmExtra = 32;
+
+void build_warm(xtrg_ctx c, Chain& C, const std::vector<double>& S, double keep_floor, unsigned long long seed) {
+  hipStream_t s = c->stream;
+  const int len = C.len, pw = C.psvd;
+  auto& w = C.warm[C.i];
+  w.side = -1;
+  if (len < kWarmMin || pw < 1) return;
+  int r = 0;
+  const int rmax = std::min(len, pw);
+  while (r < rmax && S[r] > 0.5 * keep_floor) ++r;
+  const int m = len - r;
+  if (4 * r < len) return;                  // mostly noise: the completion would dominate
+  const int o = m > 0 ? kWarmExtra : 0;
+  const int cols = len + o;
+  double* Q = c->need("wq" + std::to_string(C.i) + C.tag, (size_t)len * cols);
+  xtrg::svd_gather(len, pw, C.work, r, Q, len, 0, s);
+  if (m > 0) {
+    const int mo = m + o;
+    double* R = Q + (size_t)len * r;
+    xtrg::fill_hash(R, (size_t)len * mo, seed, s);
+    double* T1 = c->need("wq_T1", (size_t)r * mo);
+    double* P = c->need("wq_P", (size_t)len * mo);
+    for (int pass = 0; pass < 2; ++pass) {
+      gemm(c, plain(r, mo, len, Q, len, false, R, len, true, T1, mo));   // Q0^T R
+      gemm(c, plain(mo, len, r, T1, mo, true, Q, len, false, P, len));   // Q0 (Q0^T R)
+      xtrg::axpby(R, 1.0, P, -1.0, (size_t)len * mo, s);
+    }
+    // coordinates of R in the complement: an m x (m + o) block of variance
+    // 1/3, singular values within sqrt(1/3) (sqrt(m + o) -+ sqrt(m))
+    const double hi = 1.1 * std::sqrt(1.0 / 3.0) * (std::sqrt((double)mo) + std::sqrt((double)m));
+    const double lo = std::sqrt(1.0 / 3.0) * (std::sqrt((double)mo) - std::sqrt((double)m));
+    xtrg::scale(R, 1.0 / hi, (size_t)len * mo, s);
+    ns_steps(c, R, len, mo, (int)std::ceil(std::log(hi / lo) / std::log(1.5)) + 9);
+  }
+  // Q Q^T = I on R^len?
+  double* G = c->need("wq_G", (size_t)len * len);
+  gemm(c, plain(len, len, cols, Q, len, true, Q, len, false, G, len));  // Q Q^T
+  xtrg::eye_dev(G, len, c->scratch, c->scratch + 1024, s);
+  const double dev = read_scalar(c, c->scratch);
+  c->warm_m += m;
+  // the Jacobi leaves cosines <= 8 sqrt(len) eps between kept columns
+  if (!(dev <= 32.0 * std::sqrt((double)len) * 2.220446049250313e-16)) {
+    c->warm_rejected += 1;
+    return;
+  }
+  c->warm_built += 1;
+  w.side = C.gauge_right ? 0 : 1;   // Z lives in the row space of Y
+  w.dim = len;
+  w.cols = cols;
+}
+
 // After the SVD of the chain's two-site overlap: choose k, split into C_i and
 // C_{i+1} (the side the sweep moves away from takes the isometry), and
 // advance the environment on that side.
@@ -705,12 +832,14 @@ void chain_truncate_split(xtrg_ctx c, Chain& C) {
   hipStream_t s = c->stream;
   auto& d = C.d;
   const int i = C.i;
-  const int mL = C.mL, mR = C.mR, Kt = C.Kt, len = C.len, p = C.p;
-  std::vector<double> S = read_vec(c, xtrg::svd_sorted_values(C.work, len, p), p);
-  S.resize(std::min(mL, mR));
+  const int mL = C.mL, mR = C.mR, Kt = C.Kt, len = C.len, p = C.p, pw = C.psvd;
+  std::vector<double> S = read_vec(c, xtrg::svd_sorted_values(C.work, len, pw), pw);
   for (double v : S)
     if (!std::isfinite(v)) throw Error(XTRG_ENUMERIC, "non-finite singular value");
-  const int k = keep_count(S, C.o.D_max, C.o.degen_rtol, C.o.sv_floor, noise_floor(c, C.work, len, p));
+  const std::vector<double> S_all = S;
+  S.resize(std::min(mL, mR));
+  const double kf = noise_floor(c, C.work, len, pw, p);
+  const int k = keep_count(S, C.o.D_max, C.o.degen_rtol, C.o.sv_floor, kf);
   double tot = 0.0, kw = 0.0;
   for (size_t q = 0; q < S.size(); ++q) {
     tot += S[q] * S[q];
@@ -726,7 +855,7 @@ void chain_truncate_split(xtrg_ctx c, Chain& C) {
   if (C.gauge_right) {
     {
       Timed tm(c, P_SPLIT, 2.0 * k * (double)mL * mR, 0.0);
-      xtrg::svd_gather(len, p, C.work, k, Ci, k, 1, s);                               // C_i = U [mL][k]
+      xtrg::svd_gather(len, pw, C.work, k, Ci, k, 1, s);                              // C_i = U [mL][k]
       orthonormalize(c, Ci, mL, k, true);
       gemm(c, plain(k, mR, mL, Ci, k, true, C.th, mL, true, Cn, mR));                 // C_{i+1} = U^T theta
     }
@@ -736,7 +865,7 @@ void chain_truncate_split(xtrg_ctx c, Chain& C) {
   } else {
     {
       Timed tm(c, P_SPLIT, 2.0 * k * (double)mL * mR, 0.0);
-      xtrg::svd_gather(len, p, C.work, k, Cn, len, 0, s);                             // C_{i+1} = V^T [k][mR]
+      xtrg::svd_gather(len, pw, C.work, k, Cn, len, 0, s);                            // C_{i+1} = V^T [k][mR]
       orthonormalize(c, Cn, mR, k, false);
       gemm(c, plain(mL, k, mR, C.th, mR, false, Cn, mR, true, Ci, k));                // C_i = theta V
     }
@@ -745,6 +874,10 @@ void chain_truncate_split(xtrg_ctx c, Chain& C) {
     gemm(c, d.wplain(d.Da[i + 1] * d.Da[i + 1], k, mR, C.Rb, mR, false, d.Cw[i + 1], mR, true, C.F, k));  // F_{i+1}
   }
   d.Dc[i + 1] = k;
+  if (!C.o.no_warm_start && C.revisit[C.st]) {
+    Timed tm(c, P_WARM, 0.0, 0.0);
+    build_warm(c, C, S_all, kf, 0x5EEDull + 7919ull * (unsigned long long)i);
+  }
 }
 
 // One XTRG doubling of n independent chains at once.  Every chain follows
@@ -779,6 +912,7 @@ void square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_com
       const Step& sp = C.sched[st];
       const bool final_step = st + 1 == C.sched.size();
       C.i = sp.bond;
+      C.st = st;
       C.gauge_right = final_step ? false : (sp.dir > 0) != sp.last;
       act.push_back(&C);
     }
@@ -823,7 +957,6 @@ void square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_com
         C->p = C->gauge_right ? C->mR : C->mL;
         C->flops += Doubler::step_flops(d.Dc[i], d.Da[i], d.Da[i], d.Da[i + 1], d.Da[i + 1], d.Dc[i + 2]);
         C->th = c->need("theta" + C->tag, (size_t)C->mL * C->mR);
-        C->work = c->need("svd" + C->tag, xtrg::svd_work(C->len, C->p));
         fth += 2.0 * C->mL * (double)C->mR * C->Kt;
         bth += 8.0 * ((double)C->mL * C->Kt + (double)C->Kt * C->mR + (double)C->mL * C->mR);
       }
@@ -837,12 +970,28 @@ void square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_com
         gemm(c, g);
       }
     }
+    for (Chain* C : act) {
+      C->Y = C->th;
+      C->psvd = C->p;
+      const auto& w = C->warm[C->i];
+      const int need_side = C->gauge_right ? 1 : 0;   // the column index of Y
+      if (!C->o.no_warm_start && C->p >= kWarmMin && w.side == need_side && w.dim == C->p) {
+        Timed tm(c, P_WARM, 2.0 * C->len * (double)C->p * w.cols, 0.0);
+        const double* Q = c->need("wq" + std::to_string(C->i) + C->tag, (size_t)C->p * w.cols);
+        double* Yw = c->need("svd_in" + C->tag, (size_t)C->len * w.cols);
+        gemm(c, plain(w.cols, C->len, C->p, Q, C->p, false, C->th, C->len, false, Yw, C->len));   // Y [Q0 X]
+        C->Y = Yw;
+        C->psvd = w.cols;
+        c->warm_used += 1;
+      }
+      C->work = c->need("svd" + C->tag, xtrg::svd_work(C->len, C->psvd));
+    }
     {
       double bs = 0.0;
       jobs.clear();
       for (Chain* C : act) {
-        jobs.push_back(xtrg::SvdJob{C->len, C->p, C->th, C->work, 0});
-        bs += 8.0 * C->len * (double)C->p;
+        jobs.push_back(xtrg::SvdJob{C->len, C->psvd, C->Y, C->work, 0});
+        bs += 8.0 * C->len * (double)C->psvd;
       }
       Timed tm(c, P_SVD, 0.0, bs);
       RoundProf rp(c);
@@ -1273,10 +1422,14 @@ int xtrg_profile_report(xtrg_ctx c, char* buf, size_t cap) {
                     q ? ", " : "", kPhase[q], ms[q], n[q], fl[q], by[q]);
       out += tmp;
     }
-    char tail[128];
-    std::snprintf(tail, sizeof tail, ", \"svd_calls\": %ld, \"svd_sweeps\": %ld}", c->svd_calls, c->svd_sweeps);
+    char tail[320];
+    std::snprintf(tail, sizeof tail,
+                  ", \"svd_calls\": %ld, \"svd_sweeps\": %ld, \"warm_built\": %ld, \"warm_rejected\": %ld, "
+                  "\"warm_used\": %ld, \"warm_m\": %ld}",
+                  c->svd_calls, c->svd_sweeps, c->warm_built, c->warm_rejected, c->warm_used, c->warm_m);
     out += tail;
     c->svd_calls = c->svd_sweeps = 0;
+    c->warm_built = c->warm_rejected = c->warm_used = c->warm_m = 0;
     if (out.size() + 1 > cap) throw Error(XTRG_EINVAL, "profile report buffer too small");
     std::memcpy(buf, out.c_str(), out.size() + 1);
   });

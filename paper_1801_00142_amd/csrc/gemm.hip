@@ -230,9 +230,9 @@ int choose_splitk(const Gemm& g, bool big) {
   const int bm = big ? 128 : 64, bn = big ? 128 : 64;
   const long tiles = (long)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);
   const long target = 1024;   // workgroups to fill 256 CUs several times over
-  if (tiles >= target || g.K < 1024) return 1;
+  if (tiles >= target || g.K < 256) return 1;
   long sk = (target + tiles - 1) / tiles;
-  sk = std::min<long>(sk, g.K / 512);
+  sk = std::min<long>(sk, g.K / 128);
   sk = std::min<long>(sk, 64);
   return (int)std::max<long>(sk, 1);
 }

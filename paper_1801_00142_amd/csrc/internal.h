@@ -99,6 +99,10 @@ double svd_keep_rel(int len, int p);
 void copy(double* dst, const double* src, size_t n, hipStream_t s);
 void fill(double* dst, double v, size_t n, hipStream_t s);
 void to_f32(float* dst, const double* src, size_t n, hipStream_t s);   // round to nearest
+// n values uniform in (-1, 1) from a counter-based hash of (seed, index).
+void fill_hash(double* dst, size_t n, unsigned long long seed, hipStream_t s);
+// *out = max |G - I| of the k x k matrix G (device); part: >= 1024 doubles.
+void eye_dev(const double* G, int k, double* out, double* part, hipStream_t s);
 void fill_f32(float* dst, float v, size_t n, hipStream_t s);
 void scale(double* x, double a, size_t n, hipStream_t s);
 // y = a*y + b*x

@@ -144,7 +144,65 @@ __global__ void k_fill_f32(float* __restrict__ dst, float v, size_t n) {
     dst[i] = v;
 }
 
+// Uniform values in (-1, 1) from a counter-based hash (splitmix64 of the
+// element index plus seed): reproducible, independent of the launch shape.
+__global__ void k_fill_hash(double* __restrict__ d, size_t n, unsigned long long seed) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    unsigned long long z = seed + 0x9E3779B97F4A7C15ull * (i + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    d[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  }
+}
+
+// Partial maxima of |G[i][j] - delta_ij| over a k x k row-major matrix.
+__global__ void k_eye_dev_partial(const double* __restrict__ G, int k, double* __restrict__ part) {
+  __shared__ double sm[kT];
+  double m = 0.0;
+  const size_t n = (size_t)k * k;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const double v = G[i] - ((i / k == i % k) ? 1.0 : 0.0);
+    m = fmax(m, fabs(v));
+  }
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = kT / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+__global__ void k_max_final(const double* __restrict__ part, int n, double* __restrict__ out) {
+  __shared__ double sm[kT];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += kT) m = fmax(m, part[i]);
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = kT / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sm[0];
+}
+
 }  // namespace
+
+void fill_hash(double* dst, size_t n, unsigned long long seed, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_fill_hash, grid_for(n), dim3(kT), 0, s, dst, n, seed);
+  XTRG_HIP(hipGetLastError());
+}
+
+void eye_dev(const double* G, int k, double* out, double* part, hipStream_t s) {
+  const size_t n = (size_t)k * k;
+  unsigned nb = (unsigned)std::min<size_t>(1024, (n + kT - 1) / kT);
+  if (nb == 0) nb = 1;
+  hipLaunchKernelGGL(k_eye_dev_partial, dim3(nb), dim3(kT), 0, s, G, k, part);
+  hipLaunchKernelGGL(k_max_final, dim3(1), dim3(kT), 0, s, part, (int)nb, out);
+  XTRG_HIP(hipGetLastError());
+}
 
 void to_f32(float* dst, const double* src, size_t n, hipStream_t s) {
   if (!n) return;

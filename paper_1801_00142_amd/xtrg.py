@@ -28,7 +28,7 @@ class XtrgError(RuntimeError):
 
 class CompressOpts(C.Structure):
     _fields_ = [("D_max", C.c_int), ("n_sweeps", C.c_int), ("precision", C.c_int),
-                ("degen_rtol", C.c_double), ("sv_floor", C.c_double)]
+                ("degen_rtol", C.c_double), ("sv_floor", C.c_double), ("no_warm_start", C.c_int)]
 
 
 class CompressInfo(C.Structure):
@@ -195,8 +195,9 @@ class Context:
         return MPO(self, h), lam.value
 
     def square_compress(self, rho: MPO, D_max: int, n_sweeps: int = 4, degen_rtol: float = 1e-6,
-                        sv_floor: float = 1e-14, sv_stride: int = 0, precision: int = XTRG_FP64):
-        o = CompressOpts(D_max, n_sweeps, precision, degen_rtol, sv_floor)
+                        sv_floor: float = 1e-14, sv_stride: int = 0, precision: int = XTRG_FP64,
+                        warm_start: bool = True):
+        o = CompressOpts(D_max, n_sweeps, precision, degen_rtol, sv_floor, int(not warm_start))
         info = CompressInfo()
         L = rho.shape()[0]
         buf = None
@@ -214,7 +215,7 @@ class Context:
 
     def square_compress_batched(self, rhos: Sequence[MPO], D_max, n_sweeps=4,
                                 degen_rtol: float = 1e-6, sv_floor: float = 1e-14, sv_stride: int = 0,
-                                precision: int = XTRG_FP64):
+                                precision: int = XTRG_FP64, warm_start: bool = True):
         """One doubling of every chain in `rhos` together.  D_max and n_sweeps
         are one value for all chains or a sequence with one per chain.
         Returns ([new MPO per chain], [info dict per chain])."""
@@ -223,7 +224,8 @@ class Context:
         Ss = list(n_sweeps) if isinstance(n_sweeps, (list, tuple)) else [n_sweeps] * n
         if len(Ds) != n or len(Ss) != n:
             raise ValueError("one D_max and n_sweeps per chain")
-        o = (CompressOpts * n)(*[CompressOpts(Ds[q], Ss[q], precision, degen_rtol, sv_floor) for q in range(n)])
+        o = (CompressOpts * n)(*[CompressOpts(Ds[q], Ss[q], precision, degen_rtol, sv_floor, int(not warm_start))
+                               for q in range(n)])
         infos = (CompressInfo * n)()
         bufs = []
         for q, r in enumerate(rhos):
