@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--batch", type=int, default=1)
+    ap.add_argument("--serve", type=int, default=0,
+                    help="serve N requests of the scaled-down mixed workload instead (p50/p99 latency)")
+    ap.add_argument("--serve-rate", type=float, default=2.0)
     return ap.parse_args()
 
 
@@ -84,6 +87,43 @@ def cpu_baseline(sites, D, n_steps):
     return flops / dt / 1e12, dt, flops, threads
 
 
+def serve_main(args):
+    """Continuous batching of a mixed request stream: square XXZ cylinders
+    W in {2,3}, L in [4,8], Delta in [1,2], D in {16,32,64}, tau0 = 2^-10
+    2^(k/4), 10 doublings, Poisson arrivals (the serving workload's
+    distributions at a scale that finishes in about a minute)."""
+    import workloads as W
+    from paper_1801_00142_amd import Context
+    from paper_1801_00142_amd.serve import Server, Solve, percentile
+    reqs = W.serve_requests(args.serve, seed=0, rate_hz=args.serve_rate, widths=(2, 3), lengths=(4, 8),
+                            Ds=(16, 32, 64), n_doublings=10)
+    solves = [Solve(r.rid, r.lattice.n_sites, r.lattice.bonds, r.lattice.jxy, r.lattice.jz, r.tau0,
+                    r.n_doublings, r.D, arrival_s=r.arrival_s) for r in reqs]
+    ctx = Context(0)
+    ctx.profile(True)
+    ctx.profile_report()
+    t0 = time.perf_counter()
+    res = Server(ctx).run(solves, log=lambda m: print(m, file=sys.stderr, flush=True))
+    dt = time.perf_counter() - t0
+    prof = ctx.profile_report()
+    ctx.profile(False)
+    lat = [v["latency_s"] for v in res.values()]
+    flops = sum(v["flops"] for k, v in prof.items() if isinstance(v, dict) and k in
+                ("theta_gemm", "block_gemm", "env_gemm"))
+    out = {
+        "metric": "TFLOP/s in MPO product-compression sweeps at D=256; p50/p99 serve latency",
+        "value": round(flops / dt / 1e12, 4), "unit": "TFLOP/s", "n_gpus": 1, "steps": len(solves),
+        "warmup": 0, "ms_per_step": round(dt / len(solves) * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{len(solves)} mixed requests: square XXZ cylinders W 2-3, L 4-8, "
+                               f"D 16/32/64, 10 doublings, Poisson arrivals {args.serve_rate}/s"},
+        "serve": {"p50_latency_s": round(percentile(lat, 50), 3), "p99_latency_s": round(percentile(lat, 99), 3),
+                  "solves_per_s": round(len(solves) / dt, 4), "wall_s": round(dt, 2)},
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -93,6 +133,8 @@ def main():
     import torch
     import workloads as W
     from paper_1801_00142_amd import Context
+    if args.serve > 0:
+        return serve_main(args)
 
     wl = W.workload(args.workload, args.D)
     lat = wl.lattice

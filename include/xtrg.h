@@ -64,6 +64,10 @@ int xtrg_ctx_destroy(xtrg_ctx ctx);
 const char* xtrg_last_error(xtrg_ctx ctx);
 /* Device bytes currently held by ctx (MPOs + workspaces). */
 size_t xtrg_ctx_bytes(xtrg_ctx ctx);
+/* Release the context's workspaces (environment blocks, SVD and GEMM
+ * scratch), which otherwise stay allocated at their largest size for reuse;
+ * MPO handles are untouched.  Waits for the context stream. */
+int xtrg_ctx_trim(xtrg_ctx ctx);
 
 /* Hamiltonian MPO of the spin-1/2 XXZ model on an arbitrary bond list,
  * H = sum_b jxy_b (Sx Sx + Sy Sy) + jz_b Sz Sz

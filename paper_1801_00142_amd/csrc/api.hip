@@ -1241,6 +1241,16 @@ const char* xtrg_last_error(xtrg_ctx c) { return c ? c->err.c_str() : "null cont
 
 size_t xtrg_ctx_bytes(xtrg_ctx c) { return c ? c->bytes : 0; }
 
+int xtrg_ctx_trim(xtrg_ctx c) {
+  if (!c) return XTRG_EINVAL;
+  return guarded(c, [&] {
+    set_device(c);
+    XTRG_HIP(hipStreamSynchronize(c->stream));
+    for (auto& kv : c->ws) c->release(kv.second.p, kv.second.cap);
+    c->ws.clear();
+  });
+}
+
 int xtrg_hamiltonian_xxz(xtrg_ctx c, int n_sites, int n_bonds, const int* bonds, const double* jxy,
                          const double* jz, xtrg_mpo* H_out) {
   if (!c || !H_out || n_sites < 2 || n_bonds < 0 || (n_bonds > 0 && (!bonds || !jxy || !jz)))

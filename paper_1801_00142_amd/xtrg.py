@@ -57,6 +57,7 @@ def load_library(path: Optional[str] = None):
         "xtrg_ctx_destroy": (C.c_int, [vp]),
         "xtrg_last_error": (C.c_char_p, [vp]),
         "xtrg_ctx_bytes": (C.c_size_t, [vp]),
+        "xtrg_ctx_trim": (C.c_int, [vp]),
         "xtrg_hamiltonian_xxz": (C.c_int, [vp, C.c_int, C.c_int, ip, dp, dp, C.POINTER(vp)]),
         "xtrg_mpo_from_host": (C.c_int, [vp, C.c_int, C.c_int, ip, C.POINTER(dp), C.POINTER(vp)]),
         "xtrg_mpo_shape": (C.c_int, [vp, ip, ip]),
@@ -86,7 +87,7 @@ def load_library(path: Optional[str] = None):
 
 
 def exported_symbols() -> List[str]:
-    return ["xtrg_ctx_create", "xtrg_ctx_destroy", "xtrg_last_error", "xtrg_ctx_bytes",
+    return ["xtrg_ctx_create", "xtrg_ctx_destroy", "xtrg_last_error", "xtrg_ctx_bytes", "xtrg_ctx_trim",
             "xtrg_hamiltonian_xxz", "xtrg_mpo_from_host", "xtrg_mpo_shape", "xtrg_mpo_to_host",
             "xtrg_mpo_destroy", "xtrg_init_rho", "xtrg_square_compress", "xtrg_square_compress_batched", "xtrg_observables",
             "xtrg_dgemm", "xtrg_sgemm", "xtrg_dsvd_left", "xtrg_profile_enable", "xtrg_profile_report"]
@@ -168,6 +169,10 @@ class Context:
     @property
     def bytes(self) -> int:
         return int(_lib.xtrg_ctx_bytes(self.h))
+
+    def trim(self):
+        """Release the workspaces (kept at their largest size between calls)."""
+        _check(self, _lib.xtrg_ctx_trim(self.h))
 
     def hamiltonian_xxz(self, n_sites: int, bonds: Sequence, jxy: Sequence[float], jz: Sequence[float]) -> MPO:
         b = np.ascontiguousarray(np.array(bonds, dtype=np.int32).reshape(-1))

@@ -431,3 +431,51 @@ def test_warm_start_same_result_fewer_sweeps(ctx):
     Ma, Mb = M.to_dense(Da), M.to_dense(Db)
     assert np.linalg.norm(Ma - Mb) < 1e-10 * np.linalg.norm(Ma)
     assert sweeps[True] < 0.8 * sweeps[False], sweeps
+
+
+# ---------------------------------------------------------------- serving
+
+def _solves():
+    from paper_1801_00142_amd.serve import Solve
+    out = []
+    lats = [W.chain(6), W.square_cylinder(2, 3), W.with_couplings(W.chain(7), 1.0, 1.5),
+            W.random_couplings(W.chain(5), 3), W.chain(8)]
+    for q, (lat, D, arr) in enumerate(zip(lats, [8, 12, 16, 6, 10], [0.0, 0.0, 3.0, 5.0, 9.0])):
+        out.append(Solve(q, lat.n_sites, lat.bonds, lat.jxy, lat.jz, 2.0 ** -6 * 2 ** (q / 4), 5, D,
+                         arrival_s=arr))
+    return out
+
+
+def test_serve_results_equal_alone(ctx):
+    """Continuous batching: requests admitted at different steps (a step
+    clock), under a memory budget that forces some to wait, give the same
+    records (bond dimensions, lambda, f, u, c at every doubling) as each
+    request served alone."""
+    from paper_1801_00142_amd.serve import Server, footprint_bytes
+
+    class StepClock:
+        def __init__(self):
+            self.t = 0.0
+
+        def __call__(self):
+            self.t += 1.0
+            return self.t
+
+    solves = _solves()
+    budget = 2 * max(footprint_bytes(s.n_sites, s.D) for s in solves)
+    mixed = Server(ctx, hbm_budget=budget).run(solves, clock=StepClock())
+    assert sorted(mixed) == [s.rid for s in solves]
+    admitted = sorted(mixed[r]["admitted_s"] for r in mixed)
+    assert len(set(admitted)) > 1                          # not all admitted at once
+    for s in solves:
+        alone = Server(ctx, hbm_budget=budget).run([dataclasses_replace(s)], clock=StepClock())[s.rid]
+        for a, b in zip(alone["records"], mixed[s.rid]["records"]):
+            assert a["bond_dims"] == b["bond_dims"]
+            for key in ("lam", "f_tau", "f_2tau", "u_2tau", "c_2tau"):
+                assert a[key] == b[key], (s.rid, a["n"], key)
+        assert len(mixed[s.rid]["records"]) == s.n_doublings + 1
+
+
+def dataclasses_replace(s):
+    import dataclasses
+    return dataclasses.replace(s, arrival_s=0.0)

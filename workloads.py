@@ -179,22 +179,25 @@ class Request:
     arrival_s: float
 
 
-def serve_requests(n: int = 64, seed: int = 0, rate_hz: float = 1.0) -> List[Request]:
+def serve_requests(n: int = 64, seed: int = 0, rate_hz: float = 1.0, widths=(4, 6), lengths=(8, 16),
+                   Ds=(64, 128, 256), n_doublings: int = 15) -> List[Request]:
     """Seeded request mix: XXZ square cylinders W in {4,6}, L ~ U{8..16},
     Delta = Jz/Jxy ~ U[1,2], D in {64,128,256}, tau0 = 2^-10 * 2^(k/4)
-    (k = 0..3, interleaved z-shift grids), 15 doublings, Poisson arrivals."""
+    (k = 0..3, interleaved z-shift grids), 15 doublings, Poisson arrivals.
+    The widths, length range, bond budgets and doublings can be scaled down
+    (same distributions otherwise)."""
     rng = random.Random(seed)
     out = []
     t = 0.0
     for r in range(n):
-        W = rng.choice([4, 6])
-        L = rng.randint(8, 16)
+        W = rng.choice(list(widths))
+        L = rng.randint(lengths[0], lengths[1])
         delta = rng.uniform(1.0, 2.0)
-        D = rng.choice([64, 128, 256])
+        D = rng.choice(list(Ds))
         k = rng.randint(0, 3)
         t += rng.expovariate(rate_hz)
         lat = with_couplings(square_cylinder(W, L), 1.0, delta)
-        out.append(Request(r, lat, 2.0 ** -10 * 2.0 ** (k / 4.0), 15, D, t))
+        out.append(Request(r, lat, 2.0 ** -10 * 2.0 ** (k / 4.0), n_doublings, D, t))
     return out
 
 
