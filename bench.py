@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--batch", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16x3"], default="fp64",
+                    help="contraction precision of the doublings that reach beta >= --beta-mix")
+    ap.add_argument("--beta-mix", type=float, default=1.0)
     ap.add_argument("--serve", type=int, default=0,
                     help="serve N requests of the scaled-down mixed workload instead (p50/p99 latency)")
     ap.add_argument("--serve-rate", type=float, default=2.0)
@@ -144,13 +147,20 @@ def main():
     H = ctx.hamiltonian_xxz(lat.n_sites, lat.bonds, lat.jxy, lat.jz)
     rhos = [ctx.init_rho(H, t, wl.init_order)[0] for t in taus]
 
+    from paper_1801_00142_amd import XTRG_BF16X3, XTRG_FP32, XTRG_FP64
+    mixed = {"fp64": XTRG_FP64, "fp32": XTRG_FP32, "bf16x3": XTRG_BF16X3}[args.precision]
+    tau = [wl.tau0]
+
     def doubling():
         nonlocal rhos
+        # the result reaches beta = 2 tau_{n+1} = 4 tau_n (the schedule of run())
+        prec = mixed if 4 * tau[0] >= args.beta_mix else XTRG_FP64
+        tau[0] *= 2
         if nb == 1:
-            new, info = ctx.square_compress(rhos[0], args.D, args.sweeps)
+            new, info = ctx.square_compress(rhos[0], args.D, args.sweeps, precision=prec)
             news, infos = [new], [info]
         else:
-            news, infos = ctx.square_compress_batched(rhos, args.D, args.sweeps)
+            news, infos = ctx.square_compress_batched(rhos, args.D, args.sweeps, precision=prec)
         for r in rhos:
             r.close()
         rhos = news
@@ -217,7 +227,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"fp64": "f64", "fp32": "f32 contractions, f64 svd", "bf16x3": "bf16x3 contractions, f64 svd"}[
+            args.precision],
         "data": "synthetic",
         "config": {"workload": wl_name, "L": lat.n_sites, "D": args.D, "n_sweeps": args.sweeps,
                    "chains": nb, "two_site_steps_per_doubling": steps_2site // max(args.steps, 1),

@@ -51,8 +51,12 @@ enum {
  *   run on the FP32 matrix cores with FP32 accumulation (split-K partials are
  *   summed in FP64); C_E is handed to the SVD in FP64, and the SVD, the
  *   truncation, the split, the output sites and the normalisation stay FP64.
- *   Free energies agree with the FP64 path to about 1e-6 relative (tested). */
-enum { XTRG_FP64 = 0, XTRG_FP32 = 1 };
+ *   Free energies agree with the FP64 path to about 1e-6 relative (tested).
+ * XTRG_BF16X3: as XTRG_FP32, but the contractions split every FP32 operand
+ *   into two bf16 terms (hi = bf16(x), lo = bf16(x - hi)) and accumulate
+ *   hi*hi + hi*lo + lo*hi in FP32 on the bf16 matrix cores (about 16
+ *   significant bits per product). */
+enum { XTRG_FP64 = 0, XTRG_FP32 = 1, XTRG_BF16X3 = 2 };
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
  * (e.g. torch.cuda.current_stream().cuda_stream) or NULL for the null
@@ -104,7 +108,7 @@ int xtrg_init_rho(xtrg_ctx ctx, xtrg_mpo H, double tau0, int order, int D0_max,
 typedef struct {
   int D_max;         /* bond dimension budget D (> 0) */
   int n_sweeps;      /* full sweeps (left-to-right then right-to-left), >= 1 */
-  int precision;     /* XTRG_FP64 or XTRG_FP32 */
+  int precision;     /* XTRG_FP64, XTRG_FP32 or XTRG_BF16X3 */
   double degen_rtol; /* multiplet-safe cut: back off to a gap > degen_rtol*sigma_k (1e-6) */
   double sv_floor;   /* singular values <= sv_floor*sigma_1 count as zero (1e-14) */
   int no_warm_start; /* 0: each SVD after the first visit of a bond starts from the
@@ -190,6 +194,11 @@ int xtrg_dgemm(xtrg_ctx ctx, int M, int N, int K, int transA, int transB,
  * partials summed in FP64); C is double if c_double, else float. */
 int xtrg_sgemm(xtrg_ctx ctx, int M, int N, int K, int transA, int transB,
                const float* A, long lda, const float* B, long ldb, void* C, long ldc, int c_double);
+/* xtrg_gemm_bf16x3: the same product in the XTRG_BF16X3 contraction
+ * precision (float operands split into bf16 hi + lo, three bf16 products,
+ * FP32 accumulation, split-K partials summed in FP64). */
+int xtrg_gemm_bf16x3(xtrg_ctx ctx, int M, int N, int K, int transA, int transB,
+                     const float* A, long lda, const float* B, long ldb, void* C, long ldc, int c_double);
 /* xtrg_dsvd_left: singular values of the len x p matrix Y stored
  * column-major (column j at Y + j*len, device), descending, into sigma
  * (device, p entries), and the left singular vectors of the first k of them

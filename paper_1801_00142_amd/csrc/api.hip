@@ -638,8 +638,8 @@ struct Chain {
 
 void check_opts(const xtrg_compress_opts& o) {
   if (o.D_max < 1 || o.n_sweeps < 1) throw Error(XTRG_EINVAL, "D_max and n_sweeps must be >= 1");
-  if (o.precision != XTRG_FP64 && o.precision != XTRG_FP32)
-    throw Error(XTRG_EINVAL, "precision must be XTRG_FP64 or XTRG_FP32");
+  if (o.precision != XTRG_FP64 && o.precision != XTRG_FP32 && o.precision != XTRG_BF16X3)
+    throw Error(XTRG_EINVAL, "precision must be XTRG_FP64, XTRG_FP32 or XTRG_BF16X3");
 }
 
 // Set up chain q: initial guess C = rho, swapped copies of rho's sites, and
@@ -662,7 +662,9 @@ void chain_setup(xtrg_ctx c, Chain& C, xtrg_mpo in, int q) {
   d.c = c;
   d.L = L;
   d.tag = C.tag;
-  d.prec = C.o.precision == XTRG_FP32 ? xtrg::GEMM_F32 : xtrg::GEMM_F64;
+  d.prec = C.o.precision == XTRG_FP32     ? xtrg::GEMM_F32
+           : C.o.precision == XTRG_BF16X3 ? xtrg::GEMM_BF16X3
+                                          : xtrg::GEMM_F64;
   d.Da = in->dims;
   d.Dc = in->dims;                         // initial guess C = rho (right-canonical)
   d.cap.resize(L + 1);
@@ -1461,6 +1463,16 @@ int xtrg_sgemm(xtrg_ctx c, int M, int N, int K, int transA, int transB, const fl
   return guarded(c, [&] {
     set_device(c);
     gemm(c, plain(M, N, K, A, lda, transA != 0, B, ldb, transB != 0, C, ldc, xtrg::GEMM_F32, c_double != 0));
+    XTRG_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+int xtrg_gemm_bf16x3(xtrg_ctx c, int M, int N, int K, int transA, int transB, const float* A, long lda,
+                     const float* B, long ldb, void* C, long ldc, int c_double) {
+  if (!c || M < 0 || N < 0 || K < 0 || (M * (long)N > 0 && (!A || !B || !C))) return XTRG_EINVAL;
+  return guarded(c, [&] {
+    set_device(c);
+    gemm(c, plain(M, N, K, A, lda, transA != 0, B, ldb, transB != 0, C, ldc, xtrg::GEMM_BF16X3, c_double != 0));
     XTRG_HIP(hipStreamSynchronize(c->stream));
   });
 }

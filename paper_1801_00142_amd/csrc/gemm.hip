@@ -183,6 +183,170 @@ __global__ __launch_bounds__(256) void gemm_kernel(Gemm g, int splitk, int kchun
   }
 }
 
+// Split-BF16 (bf16x3) variant for float operands: every element x is split
+// at staging into hi = bf16(x) and lo = bf16(x - hi) (round to nearest
+// even), and the product is accumulated in FP32 on the bf16 matrix cores
+// (v_mfma_f32_16x16x16_bf16) as hi*hi + hi*lo + lo*hi.  The tiles are kept
+// in LDS as [m][k] and [n][k] so that each lane's 4 consecutive k are one
+// 8-byte read.
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+__device__ inline unsigned short bf16_rne(float x) {
+  const unsigned u = __float_as_uint(x);
+  return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ inline void split_bf16(float x, unsigned short* hi, unsigned short* lo) {
+  *hi = bf16_rne(x);
+  *lo = bf16_rne(x - __uint_as_float((unsigned)*hi << 16));
+}
+
+template <int BM, int BN, bool TA, bool TB, int TAG, typename TO>
+__global__ __launch_bounds__(256) void gemm_bf3_kernel(Gemm g, int splitk, int kchunk, double* work) {
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int LA = BM * BK / 256;
+  constexpr int LB = BN * BK / 256;
+  constexpr int KP = BK + 8;                  // padded k extent (shorts), 8-byte aligned rows
+  __shared__ unsigned short Ah[BM][KP], Al[BM][KP];
+  __shared__ unsigned short Bh[BN][KP], Bl[BN][KP];
+
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  int z = blockIdx.z;
+  const int ks = z % splitk;
+  z /= splitk;
+  const int b2 = z % g.nb[2];
+  const int b1 = (z / g.nb[2]) % g.nb[1];
+  const int b0 = z / (g.nb[2] * g.nb[1]);
+  const float* __restrict__ A = static_cast<const float*>(g.A) + b0 * g.sA[0] + b1 * g.sA[1] + b2 * g.sA[2];
+  const float* __restrict__ B = static_cast<const float*>(g.B) + b0 * g.sB[0] + b1 * g.sB[1] + b2 * g.sB[2];
+
+  const int m0 = blockIdx.y * BM;
+  const int n0 = blockIdx.x * BN;
+  const int kbeg = ks * kchunk;
+  const int kend = min(g.K, kbeg + kchunk);
+  const int M = g.M, N = g.N;
+
+  float ra[LA], rb[LB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int c = 0; c < LA / 4; ++c) {
+      if (!TA) {
+        const int m = m0 + (t >> 2) + 64 * c;
+        const int k = k0 + (t & 3) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ra[4 * c + j] = (m < M && k + j < kend) ? A[(long)m * g.lda + k + j] : 0.f;
+      } else {
+        const int k = k0 + (t >> 4);
+        const int m = m0 + (t & 15) * 4 + 64 * c;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ra[4 * c + j] = (k < kend && m + j < M) ? A[(long)k * g.lda + m + j] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < LB / 4; ++c) {
+      if (!TB) {
+        const int k = k0 + (t >> 4);
+        const int n = n0 + (t & 15) * 4 + 64 * c;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) rb[4 * c + j] = (k < kend && n + j < N) ? B[(long)k * g.ldb + n + j] : 0.f;
+      } else {
+        const int n = n0 + (t >> 2) + 64 * c;
+        const int k = k0 + (t & 3) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) rb[4 * c + j] = (n < N && k + j < kend) ? B[(long)n * g.ldb + k + j] : 0.f;
+      }
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int c = 0; c < LA / 4; ++c)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int mm = !TA ? (t >> 2) + 64 * c : (t & 15) * 4 + 64 * c + j;
+        const int kk = !TA ? (t & 3) * 4 + j : (t >> 4);
+        split_bf16(ra[4 * c + j], &Ah[mm][kk], &Al[mm][kk]);
+      }
+#pragma unroll
+    for (int c = 0; c < LB / 4; ++c)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int nn = !TB ? (t & 15) * 4 + 64 * c + j : (t >> 2) + 64 * c;
+        const int kk = !TB ? (t >> 4) : (t & 3) * 4 + j;
+        split_bf16(rb[4 * c + j], &Bh[nn][kk], &Bl[nn][kk]);
+      }
+  };
+
+  f4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  const int lr = lane & 15, lk = lane >> 4;
+  if (kbeg < kend) {
+    load(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+      __syncthreads();
+      stash();
+      __syncthreads();
+      if (k0 + BK < kend) load(k0 + BK);
+      // operand lane l: A(i = l%16, k = 4 (l/16) + v), B(k = 4 (l/16) + v, j = l%16), v = 0..3
+      s4 ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        ah[i] = *reinterpret_cast<const s4*>(&Ah[wm * WM + i * 16 + lr][4 * lk]);
+        al[i] = *reinterpret_cast<const s4*>(&Al[wm * WM + i * 16 + lr][4 * lk]);
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        bh[j] = *reinterpret_cast<const s4*>(&Bh[wn * WN + j * 16 + lr][4 * lk]);
+        bl[j] = *reinterpret_cast<const s4*>(&Bl[wn * WN + j * 16 + lr][4 * lk]);
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+    }
+  }
+
+  // register r of lane l holds row 4 (l/16) + r, column l%16 of the tile
+  if (splitk > 1) {
+    double* __restrict__ W = work + (long)ks * M * N;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int col = n0 + wn * WN + j * 16 + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm * WM + i * 16 + 4 * lk + r;
+          if (row < M && col < N) W[(long)row * N + col] = (double)acc[i][j][r];
+        }
+      }
+  } else {
+    TO* __restrict__ C = static_cast<TO*>(g.C) + b0 * g.sC[0] + b1 * g.sC[1] + b2 * g.sC[2];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int col = n0 + wn * WN + j * 16 + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm * WM + i * 16 + 4 * lk + r;
+          if (row < M && col < N) C[(long)row * g.ldc + col] = (TO)acc[i][j][r];
+        }
+      }
+  }
+}
+
 // Deterministic split-K reduction: C[row*ldc + col] = sum_ks work[ks][row][col].
 template <typename TO>
 __global__ void splitk_reduce(const double* __restrict__ work, int splitk, int M, int N,
@@ -211,6 +375,32 @@ void launch(const Gemm& g, int splitk, int kchunk, double* work, hipStream_t s) 
   else
     hipLaunchKernelGGL((gemm_kernel<BM, BN, true, true, TAG, TI, TO>), grid, block, 0, s, g, splitk, kchunk, work);
   XTRG_HIP(hipGetLastError());
+}
+
+template <int BM, int BN, int TAG, typename TO>
+void launch_bf3(const Gemm& g, int splitk, int kchunk, double* work, hipStream_t s) {
+  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.nb[0] * g.nb[1] * g.nb[2] * splitk);
+  dim3 block(256);
+  if (!g.transA && !g.transB)
+    hipLaunchKernelGGL((gemm_bf3_kernel<BM, BN, false, false, TAG, TO>), grid, block, 0, s, g, splitk, kchunk, work);
+  else if (g.transA && !g.transB)
+    hipLaunchKernelGGL((gemm_bf3_kernel<BM, BN, true, false, TAG, TO>), grid, block, 0, s, g, splitk, kchunk, work);
+  else if (!g.transA && g.transB)
+    hipLaunchKernelGGL((gemm_bf3_kernel<BM, BN, false, true, TAG, TO>), grid, block, 0, s, g, splitk, kchunk, work);
+  else
+    hipLaunchKernelGGL((gemm_bf3_kernel<BM, BN, true, true, TAG, TO>), grid, block, 0, s, g, splitk, kchunk, work);
+  XTRG_HIP(hipGetLastError());
+}
+
+template <typename TO>
+void launch_bf3_sized(const Gemm& g, bool big, int sk, int kchunk, double* work, hipStream_t s) {
+  if (g.tag == 1) {
+    if (big) launch_bf3<128, 128, 1, TO>(g, sk, kchunk, work, s);
+    else launch_bf3<64, 64, 1, TO>(g, sk, kchunk, work, s);
+  } else {
+    if (big) launch_bf3<128, 128, 0, TO>(g, sk, kchunk, work, s);
+    else launch_bf3<64, 64, 0, TO>(g, sk, kchunk, work, s);
+  }
 }
 
 template <typename TI, typename TO>
@@ -257,10 +447,12 @@ void gemm(const Gemm& g, hipStream_t s, double* work, size_t work_cap) {
     kchunk = ((g.K + sk - 1) / sk + BK - 1) / BK * BK;
     sk = (g.K + kchunk - 1) / kchunk;
   }
-  const bool c64 = g.prec == GEMM_F64 || g.out64;
+  const bool c64 = g.prec == GEMM_F64 || g.out64;   // FP32 and BF16X3 take float operands
   if (g.prec == GEMM_F64) launch_sized<double, double>(g, big, sk, kchunk, work, s);
   else if (g.prec == GEMM_F32 && c64) launch_sized<float, double>(g, big, sk, kchunk, work, s);
   else if (g.prec == GEMM_F32) launch_sized<float, float>(g, big, sk, kchunk, work, s);
+  else if (g.prec == GEMM_BF16X3 && c64) launch_bf3_sized<double>(g, big, sk, kchunk, work, s);
+  else if (g.prec == GEMM_BF16X3) launch_bf3_sized<float>(g, big, sk, kchunk, work, s);
   else throw Error(-1, "gemm: unknown precision");
   if (sk > 1) {
     const long MN = (long)g.M * g.N;

@@ -30,10 +30,11 @@ struct Error : std::runtime_error {
 //   C element (m, n): C[m*ldc + n]
 // The batch index is split into up to three levels b = (b0*nb1 + b1)*nb2 + b2,
 // each with its own offset stride (in elements) for A, B and C.
-// Precision: GEMM_F64 (double in, double out, FP64 MFMA) or GEMM_F32
-// (float in, FP32 MFMA with FP32 accumulation; out64 selects a double or a
-// float C).
-enum { GEMM_F64 = 0, GEMM_F32 = 1 };
+// Precision: GEMM_F64 (double in, double out, FP64 MFMA), GEMM_F32 (float
+// in, FP32 MFMA with FP32 accumulation) or GEMM_BF16X3 (float in, each
+// operand split into two bf16 terms, three bf16 MFMA products with FP32
+// accumulation); for the float modes out64 selects a double or a float C.
+enum { GEMM_F64 = 0, GEMM_F32 = 1, GEMM_BF16X3 = 2 };   // BF16X3: float operands split hi + lo
 struct Gemm {
   int M = 0, N = 0, K = 0;
   int transA = 0, transB = 0;

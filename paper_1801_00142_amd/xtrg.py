@@ -20,6 +20,7 @@ _lib = None
 
 XTRG_FP64 = 0
 XTRG_FP32 = 1
+XTRG_BF16X3 = 2
 
 
 class XtrgError(RuntimeError):
@@ -74,6 +75,8 @@ def load_library(path: Optional[str] = None):
                                  C.c_long, vp, C.c_long]),
         "xtrg_sgemm": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, vp, C.c_long, vp,
                                  C.c_long, vp, C.c_long, C.c_int]),
+        "xtrg_gemm_bf16x3": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, vp, C.c_long, vp,
+                                       C.c_long, vp, C.c_long, C.c_int]),
         "xtrg_dsvd_left": (C.c_int, [vp, C.c_int, C.c_int, vp, vp, C.c_int, vp]),
         "xtrg_profile_enable": (C.c_int, [vp, C.c_int]),
         "xtrg_profile_report": (C.c_int, [vp, C.c_char_p, C.c_size_t]),
@@ -90,7 +93,7 @@ def exported_symbols() -> List[str]:
     return ["xtrg_ctx_create", "xtrg_ctx_destroy", "xtrg_last_error", "xtrg_ctx_bytes", "xtrg_ctx_trim",
             "xtrg_hamiltonian_xxz", "xtrg_mpo_from_host", "xtrg_mpo_shape", "xtrg_mpo_to_host",
             "xtrg_mpo_destroy", "xtrg_init_rho", "xtrg_square_compress", "xtrg_square_compress_batched", "xtrg_observables",
-            "xtrg_dgemm", "xtrg_sgemm", "xtrg_dsvd_left", "xtrg_profile_enable", "xtrg_profile_report"]
+            "xtrg_dgemm", "xtrg_sgemm", "xtrg_gemm_bf16x3", "xtrg_dsvd_left", "xtrg_profile_enable", "xtrg_profile_report"]
 
 
 class MPO:
@@ -286,6 +289,10 @@ class Context:
     def sgemm(self, M, N, K, transA, transB, A, lda, B, ldb, Cp, ldc, c_double=True):
         _check(self, _lib.xtrg_sgemm(self.h, M, N, K, int(transA), int(transB), C.c_void_p(A), lda,
                                      C.c_void_p(B), ldb, C.c_void_p(Cp), ldc, int(c_double)))
+
+    def gemm_bf16x3(self, M, N, K, transA, transB, A, lda, B, ldb, Cp, ldc, c_double=True):
+        _check(self, _lib.xtrg_gemm_bf16x3(self.h, M, N, K, int(transA), int(transB), C.c_void_p(A), lda,
+                                           C.c_void_p(B), ldb, C.c_void_p(Cp), ldc, int(c_double)))
 
     def dsvd_left(self, length, p, Y, sigma, k=0, U=None):
         _check(self, _lib.xtrg_dsvd_left(self.h, length, p, C.c_void_p(Y), C.c_void_p(sigma), k,
