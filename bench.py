@@ -36,7 +36,7 @@ PEAK_HBM_GBS = 8000.0
 # pairs of 32 columns), from rocprofv3 FETCH_SIZE + WRITE_SIZE scaled by a
 # plain 1 GiB copy (FETCH x2.0, WRITE x1.0); see the counters summary in
 # profiles/.  Valid for the kernel as measured: reset to None when it changes.
-JACOBI_ROUND_TRAFFIC_1024 = 15.60e6
+JACOBI_ROUND_TRAFFIC_1024 = None
 
 
 def parse():
@@ -242,13 +242,13 @@ def main():
                                               max(warm_stats["warm_built"] + warm_stats["warm_rejected"], 1), 1)},
         # the dominant kernel: the Jacobi rounds of the SVD (bytes = each
         # column of the visited pairs read and written once per round)
-        "roofline": {"bound": "hbm", "kernel": "jacobi_round (one-sided block Jacobi SVD round)",
+        "roofline": {"bound": "hbm", "kernel": "jacobi_round (one block-Jacobi SVD round: Gram + rotate launches over row slices)",
                      "achieved": round(rd_gbs, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(rd_gbs / PEAK_HBM_GBS, 4), "traffic": JACOBI_ROUND_TRAFFIC_1024,
                      "traffic_note": "HBM bytes per 1024-column launch (rocprofv3 counters, copy-scaled)",
-                     "launches": rounds["calls"], "avg_launch_us": round(rd_avg_s * 1e6, 3),
-                     "bytes_per_launch": rd_bytes,
-                     "flops_per_launch": rounds["flops"] / max(rounds["calls"], 1)},
+                     "rounds": rounds["calls"], "avg_round_us": round(rd_avg_s * 1e6, 3),
+                     "bytes_per_round": rd_bytes,
+                     "flops_per_round": rounds["flops"] / max(rounds["calls"], 1)},
         "roofline_theta": {"bound": "mfma", "kernel": "two-site overlap C_E (gemm_kernel<128,128,...,1,double,double>)",
                            "achieved": round(th_achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                            "frac": round(th_achieved / PEAK_FP64_TFLOPS, 4),

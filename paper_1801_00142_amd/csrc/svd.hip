@@ -82,7 +82,26 @@ struct JacobiDesc {
   unsigned long long* off;
   double tol, zrel2;
   int len, p, nbk, active;
+  int split;        // row slices per block pair (workgroups sharing one pair's round)
 };
+
+// Rows [a, b) of slice s of `split` (slices start at multiples of 128 rows).
+__device__ inline void slice_rows(int len, int split, int s, int* a, int* b) {
+  const int per = (((len + split - 1) / split) + 127) / 128 * 128;
+  *a = min(len, s * per);
+  *b = min(len, *a + per);
+}
+
+// Kernel modes: one workgroup per block pair doing the whole round, or the
+// round split over `split` workgroups per pair in two launches: partial
+// Gram matrices of row slices, then (every slice alike) the sum of the
+// partials in slice order, the small Jacobi sweep, and the rotation of the
+// slice's rows.  A chain's split depends only on its own shape, so a chain
+// gets the same result alone and in a batch.
+enum { ROUND_FUSED = 0, ROUND_GRAM = 1, ROUND_ROTATE = 2 };
+constexpr int kMaxSplit = 4;
+constexpr int kMaxPairs = 128;            // p <= 4096 columns in blocks of 16
+constexpr int kGramVals = 3 * 256;        // three 16 x 16 tiles
 
 // 1/x and 1/sqrt(x) from the hardware estimates refined by two Newton
 // steps (each squares the relative error), to about one unit in the last place.
@@ -122,9 +141,16 @@ __device__ inline void jacobi_rot(double a, double b, double g, double tol2, dou
   *s = need ? cc * tt : 0.0;
 }
 
-__global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict__ descs, int r) {
+template <int MODE>
+__global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict__ descs, int r, int smax,
+                                                    double* __restrict__ parts) {
   const JacobiDesc d = descs[blockIdx.y];
-  if (!d.active || r >= d.nbk - 1 || (int)blockIdx.x >= d.nbk / 2) return;
+  const int pair = (int)blockIdx.x / smax, sl = (int)blockIdx.x % smax;
+  const int split = MODE == ROUND_FUSED ? 1 : d.split;
+  if (!d.active || r >= d.nbk - 1 || pair >= d.nbk / 2 || sl >= split) return;
+  int ra, rb;
+  slice_rows(d.len, split, sl, &ra, &rb);
+  double* __restrict__ part = parts + ((size_t)blockIdx.y * kMaxPairs + pair) * kMaxSplit * kGramVals;
   double* __restrict__ Y = d.Z;
   const int len = d.len, p = d.p, nbk = d.nbk;
   const double tol = d.tol;
@@ -135,7 +161,7 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   __shared__ double wmax[kWW];
   __shared__ unsigned wmask[kWW];
   int bi, bj;
-  rr_pair(nbk, r, blockIdx.x, &bi, &bj);
+  rr_pair(nbk, r, pair, &bi, &bj);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   if (t < kNC) {
     const int rank = (t < kBlk ? bi : bj) * kBlk + (t % kBlk);
@@ -150,19 +176,19 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   d4 acc[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
-  {
+  if (MODE != ROUND_ROTATE) {
     const int lr = lane & 15, lk = lane >> 4;
     const int c0 = colid[lr], c1 = colid[kBlk + lr];
     const double* __restrict__ y0 = Y + (long)(c0 >= 0 ? c0 : 0) * len;
     const double* __restrict__ y1 = Y + (long)(c1 >= 0 ? c1 : 0) * len;
     constexpr int U = 16;                      // row groups in flight per wave
-    for (int g0 = wave * 4; g0 < len; g0 += kWW * 4 * U) {
+    for (int g0 = ra + wave * 4; g0 < rb; g0 += kWW * 4 * U) {
       double a0[U], a1[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int e = g0 + u * kWW * 4 + lk;
-        a0[u] = (c0 >= 0 && e < len) ? y0[e] : 0.0;
-        a1[u] = (c1 >= 0 && e < len) ? y1[e] : 0.0;
+        a0[u] = (c0 >= 0 && e < rb) ? y0[e] : 0.0;
+        a1[u] = (c1 >= 0 && e < rb) ? y1[e] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -173,17 +199,29 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
     }
   }
   // register q of lane l holds tile row l/16 + 4q, column l%16
+  if (MODE != ROUND_ROTATE) {
 #pragma unroll
-  for (int tt = 0; tt < 3; ++tt)
+    for (int tt = 0; tt < 3; ++tt)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) buf[((wave * 3 + tt) * 4 + q) * 64 + lane] = acc[tt][q];
+      for (int q = 0; q < 4; ++q) buf[((wave * 3 + tt) * 4 + q) * 64 + lane] = acc[tt][q];
+  }
   for (int idx = t; idx < kNC * kNC; idx += kWT) Wt[idx / kNC][idx % kNC] = (idx / kNC == idx % kNC) ? 1.0 : 0.0;
   __syncthreads();
-  for (int idx = t; idx < 3 * 256; idx += kWT) {
+  for (int idx = t; idx < kGramVals; idx += kWT) {
     const int tt = idx >> 8, q = (idx >> 6) & 3, l = idx & 63;
-    double v = 0.0;
+    double v;
+    if (MODE == ROUND_ROTATE) {                 // partials of the slices, in slice order
+      v = part[idx];
+      for (int s2 = 1; s2 < split; ++s2) v += part[s2 * kGramVals + idx];
+    } else {
+      v = 0.0;
 #pragma unroll
-    for (int w = 0; w < kWW; ++w) v += buf[((w * 3 + tt) * 4 + q) * 64 + l];
+      for (int w = 0; w < kWW; ++w) v += buf[((w * 3 + tt) * 4 + q) * 64 + l];
+      if (MODE == ROUND_GRAM) {
+        part[sl * kGramVals + idx] = v;
+        continue;
+      }
+    }
     const int i = (l >> 4) + 4 * q, j = l & 15;
     const int I = tt == 2 ? kBlk : 0, J = tt == 0 ? 0 : kBlk;
     if (tt == 1) {
@@ -194,6 +232,7 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
       G[0][J + j][I + i] = v;
     }
   }
+  if (MODE == ROUND_GRAM) return;
   __syncthreads();
 
   // 2. Convergence measure.
@@ -233,7 +272,7 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   }
   // block maximum published as the bit pattern of a non-negative double
   // (monotone under unsigned comparison)
-  if (t == 0 && worst > 0.0) atomicMax(d.off, (unsigned long long)__double_as_longlong(worst));
+  if (t == 0 && sl == 0 && worst > 0.0) atomicMax(d.off, (unsigned long long)__double_as_longlong(worst));
   if (worst == 0.0) return;          // uniform: every thread read the same wmax
 
   // 3. One sweep of parallel two-sided Jacobi on G; W <- W J per rotation.
@@ -292,14 +331,14 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
 #pragma unroll
       for (int q = 0; q < 4; ++q) cout[I][q] = colid[I * 16 + lk + 4 * q];
     constexpr int T = 4;                       // 16-row tiles in flight per wave
-    for (int e0 = wave * 16; e0 < len; e0 += kWW * 16 * T) {
+    for (int e0 = ra + wave * 16; e0 < rb; e0 += kWW * 16 * T) {
       double zb[T][kNC / 4];
 #pragma unroll
       for (int u = 0; u < T; ++u) {
         const int e = e0 + u * kWW * 16 + lr;
 #pragma unroll
         for (int kk = 0; kk < kNC / 4; ++kk)
-          zb[u][kk] = (cin[kk] >= 0 && e < len) ? Y[(long)cin[kk] * len + e] : 0.0;
+          zb[u][kk] = (cin[kk] >= 0 && e < rb) ? Y[(long)cin[kk] * len + e] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < T; ++u) {
@@ -311,7 +350,7 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
           o[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[1][kk], zb[u][kk], o[1], 0, 0, 0);
         }
         // register q of lane l: column I*16 + l/16 + 4q of Z W, row e
-        if (e < len) {
+        if (e < rb) {
 #pragma unroll
           for (int I = 0; I < 2; ++I)
 #pragma unroll
@@ -394,13 +433,24 @@ static int* sv_perm(double* work, int len, int p) {
   return reinterpret_cast<int*>(work + (size_t)len * p + 2 * (size_t)p);
 }
 
-size_t svd_desc_bytes(int n) { return sizeof(JacobiDesc) * (size_t)n + sizeof(unsigned long long) * (size_t)n; }
+// [descs: n][off: n][pad to 256 B][Gram partials: n x kMaxPairs x kMaxSplit x kGramVals doubles]
+static size_t parts_offset(int n) {
+  return (sizeof(JacobiDesc) * (size_t)n + sizeof(unsigned long long) * (size_t)n + 255) / 256 * 256;
+}
+size_t svd_desc_bytes(int n) {
+  return parts_offset(n) + sizeof(double) * (size_t)n * kMaxPairs * kMaxSplit * kGramVals;
+}
+
+// Row slices per block pair: long columns are split so that one round of a
+// single chain spreads over more compute units.
+static int split_for(int len) { return len >= 1024 ? 4 : len >= 512 ? 2 : 1; }
 
 void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, RoundTimer* timer) {
   const int n = (int)jobs.size();
   if (n == 0) return;
   JacobiDesc* d_desc = reinterpret_cast<JacobiDesc*>(desc_dev);
   unsigned long long* d_off = reinterpret_cast<unsigned long long*>(d_desc + n);
+  double* d_parts = reinterpret_cast<double*>(static_cast<char*>(desc_dev) + parts_offset(n));
   std::vector<JacobiDesc> h(n);
   std::vector<int> n2(n);
   int max_nbk = 0, max_half = 0;
@@ -431,6 +481,7 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
     D.nbk = (J.p + kBlk - 1) / kBlk;
     if (D.nbk % 2) ++D.nbk;
     D.active = J.p > 1;
+    D.split = split_for(J.len);
     XTRG_HIP(hipMemcpyAsync(w, J.Y, sizeof(double) * J.len * J.p, hipMemcpyDeviceToDevice, s));
     sumsq(w, (size_t)J.len * J.p, w + (size_t)J.len * J.p + 3 * (size_t)J.p + 1,
           w + (size_t)J.len * J.p + 3 * (size_t)J.p + 2, s);
@@ -448,8 +499,18 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
                        sv_sorted(w, J.len, J.p), sv_perm(w, J.len, J.p));
     XTRG_HIP(hipGetLastError());
   };
+  int smax = 1;
+  for (const auto& D : h)
+    if (D.active) smax = std::max(smax, D.split);
   auto round = [&](int r) {
-    hipLaunchKernelGGL(jacobi_round, dim3(max_half, n), dim3(kWT), 0, s, d_desc, r);
+    if (smax == 1) {
+      hipLaunchKernelGGL(jacobi_round<ROUND_FUSED>, dim3(max_half, n), dim3(kWT), 0, s, d_desc, r, 1, d_parts);
+    } else {
+      hipLaunchKernelGGL(jacobi_round<ROUND_GRAM>, dim3(max_half * smax, n), dim3(kWT), 0, s, d_desc, r, smax,
+                         d_parts);
+      hipLaunchKernelGGL(jacobi_round<ROUND_ROTATE>, dim3(max_half * smax, n), dim3(kWT), 0, s, d_desc, r, smax,
+                         d_parts);
+    }
   };
   std::vector<unsigned long long> hoff(n);
   std::vector<double> last(n, 0.0);
