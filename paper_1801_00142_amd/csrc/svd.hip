@@ -96,8 +96,10 @@ __device__ inline void slice_rows(int len, int split, int s, int* a, int* b) {
 // round split over `split` workgroups per pair in two launches: partial
 // Gram matrices of row slices, then (every slice alike) the sum of the
 // partials in slice order, the small Jacobi sweep, and the rotation of the
-// slice's rows.  A chain's split depends only on its own shape, so a chain
-// gets the same result alone and in a batch.
+// slice's rows.  The slices depend only on the column length and the fused
+// workgroup sums the same slice partials in the same order, so both modes
+// give identical results and a chain gets the same result alone and in a
+// batch.
 enum { ROUND_FUSED = 0, ROUND_GRAM = 1, ROUND_ROTATE = 2 };
 constexpr int kMaxSplit = 4;
 constexpr int kMaxPairs = 128;            // p <= 4096 columns in blocks of 16
@@ -146,16 +148,17 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
                                                     double* __restrict__ parts) {
   const JacobiDesc d = descs[blockIdx.y];
   const int pair = (int)blockIdx.x / smax, sl = (int)blockIdx.x % smax;
-  const int split = MODE == ROUND_FUSED ? 1 : d.split;
-  if (!d.active || r >= d.nbk - 1 || pair >= d.nbk / 2 || sl >= split) return;
-  int ra, rb;
-  slice_rows(d.len, split, sl, &ra, &rb);
+  const int split = d.split;
+  if (!d.active || r >= d.nbk - 1 || pair >= d.nbk / 2 || sl >= (MODE == ROUND_FUSED ? 1 : split)) return;
+  int ra = 0, rb = d.len;                       // rows this workgroup rotates
+  if (MODE != ROUND_FUSED) slice_rows(d.len, split, sl, &ra, &rb);
   double* __restrict__ part = parts + ((size_t)blockIdx.y * kMaxPairs + pair) * kMaxSplit * kGramVals;
   double* __restrict__ Y = d.Z;
   const int len = d.len, p = d.p, nbk = d.nbk;
   const double tol = d.tol;
   __shared__ int colid[kNC];
   __shared__ double buf[kWW * 3 * 4 * 64];   // wave partials of the Gram tiles
+  __shared__ double gsum[kGramVals];          // fused round: running sum over the slices
   __shared__ double G[2][kNC][kNC + 1];
   __shared__ double Wt[kNC][kNC + 2];         // W transposed: Wt[c][j] = W[j][c]
   __shared__ double wmax[kWW];
@@ -173,22 +176,23 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   // operands straight from memory: per MFMA step a wave takes 4 rows, lane l
   // row l/16 of column l%16 of each block (4 consecutive rows of a column
   // per 4 lanes, 32-byte sectors fully used).  Waves interleave 4-row groups.
-  d4 acc[3];
+  // Partial Gram of rows [a, b): per-wave tiles left in buf.
+  auto gram_rows = [&](int a, int b) {
+    d4 acc[3];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
-  if (MODE != ROUND_ROTATE) {
+    for (int q = 0; q < 3; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
     const int lr = lane & 15, lk = lane >> 4;
     const int c0 = colid[lr], c1 = colid[kBlk + lr];
     const double* __restrict__ y0 = Y + (long)(c0 >= 0 ? c0 : 0) * len;
     const double* __restrict__ y1 = Y + (long)(c1 >= 0 ? c1 : 0) * len;
     constexpr int U = 16;                      // row groups in flight per wave
-    for (int g0 = ra + wave * 4; g0 < rb; g0 += kWW * 4 * U) {
+    for (int g0 = a + wave * 4; g0 < b; g0 += kWW * 4 * U) {
       double a0[U], a1[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int e = g0 + u * kWW * 4 + lk;
-        a0[u] = (c0 >= 0 && e < rb) ? y0[e] : 0.0;
-        a1[u] = (c1 >= 0 && e < rb) ? y1[e] : 0.0;
+        a0[u] = (c0 >= 0 && e < b) ? y0[e] : 0.0;
+        a1[u] = (c1 >= 0 && e < b) ? y1[e] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -197,30 +201,51 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
         acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], a1[u], acc[2], 0, 0, 0);
       }
     }
-  }
-  // register q of lane l holds tile row l/16 + 4q, column l%16
-  if (MODE != ROUND_ROTATE) {
+    // register q of lane l holds tile row l/16 + 4q, column l%16
 #pragma unroll
     for (int tt = 0; tt < 3; ++tt)
 #pragma unroll
       for (int q = 0; q < 4; ++q) buf[((wave * 3 + tt) * 4 + q) * 64 + lane] = acc[tt][q];
+  };
+  auto wave_sum = [&](int idx) {
+    const int tt = idx >> 8, q = (idx >> 6) & 3, l = idx & 63;
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWW; ++w) v += buf[((w * 3 + tt) * 4 + q) * 64 + l];
+    return v;
+  };
+
+  // The Gram matrix is the sum, in slice order, of the slices' partials
+  // (each the sum over waves in wave order), whichever way the round runs:
+  // the fused workgroup walks the slices itself.
+  if (MODE == ROUND_GRAM) {
+    gram_rows(ra, rb);
+    __syncthreads();
+    for (int idx = t; idx < kGramVals; idx += kWT) part[sl * kGramVals + idx] = wave_sum(idx);
+    return;
+  }
+  if (MODE == ROUND_FUSED) {
+    for (int s2 = 0; s2 < split; ++s2) {
+      int a2, b2;
+      slice_rows(len, split, s2, &a2, &b2);
+      gram_rows(a2, b2);
+      __syncthreads();
+      for (int idx = t; idx < kGramVals; idx += kWT) {
+        const double v = wave_sum(idx);
+        gsum[idx] = s2 == 0 ? v : gsum[idx] + v;
+      }
+      __syncthreads();
+    }
   }
   for (int idx = t; idx < kNC * kNC; idx += kWT) Wt[idx / kNC][idx % kNC] = (idx / kNC == idx % kNC) ? 1.0 : 0.0;
-  __syncthreads();
   for (int idx = t; idx < kGramVals; idx += kWT) {
     const int tt = idx >> 8, q = (idx >> 6) & 3, l = idx & 63;
     double v;
-    if (MODE == ROUND_ROTATE) {                 // partials of the slices, in slice order
+    if (MODE == ROUND_ROTATE) {
       v = part[idx];
       for (int s2 = 1; s2 < split; ++s2) v += part[s2 * kGramVals + idx];
     } else {
-      v = 0.0;
-#pragma unroll
-      for (int w = 0; w < kWW; ++w) v += buf[((w * 3 + tt) * 4 + q) * 64 + l];
-      if (MODE == ROUND_GRAM) {
-        part[sl * kGramVals + idx] = v;
-        continue;
-      }
+      v = gsum[idx];
     }
     const int i = (l >> 4) + 4 * q, j = l & 15;
     const int I = tt == 2 ? kBlk : 0, J = tt == 0 ? 0 : kBlk;
@@ -232,7 +257,6 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
       G[0][J + j][I + i] = v;
     }
   }
-  if (MODE == ROUND_GRAM) return;
   __syncthreads();
 
   // 2. Convergence measure.
@@ -499,9 +523,16 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
                        sv_sorted(w, J.len, J.p), sv_perm(w, J.len, J.p));
     XTRG_HIP(hipGetLastError());
   };
+  // Sliced launches pay off while the fused rounds would leave most compute
+  // units idle; the results are the same either way.
   int smax = 1;
+  long wgs = 0;
   for (const auto& D : h)
-    if (D.active) smax = std::max(smax, D.split);
+    if (D.active) {
+      smax = std::max(smax, D.split);
+      wgs += (long)(D.nbk / 2) * D.split;
+    }
+  if (wgs > 256) smax = 1;
   auto round = [&](int r) {
     if (smax == 1) {
       hipLaunchKernelGGL(jacobi_round<ROUND_FUSED>, dim3(max_half, n), dim3(kWT), 0, s, d_desc, r, 1, d_parts);
