@@ -32,11 +32,12 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 PEAK_HBM_GBS = 8000.0
-# HBM bytes per jacobi_round launch over a 1024 x 1024 matrix (32 block
-# pairs of 32 columns), from rocprofv3 FETCH_SIZE + WRITE_SIZE scaled by a
-# plain 1 GiB copy (FETCH x2.0, WRITE x1.0); see the counters summary in
-# profiles/.  Valid for the kernel as measured: reset to None when it changes.
-JACOBI_ROUND_TRAFFIC_1024 = None
+# HBM bytes per Jacobi round of a 1024 x 1024 SVD in the row-sliced form
+# (Gram + rotate launches, 32 block pairs x 4 slices), from rocprofv3
+# FETCH_SIZE + WRITE_SIZE scaled by a plain 1 GiB copy (FETCH x2.0, WRITE
+# x1.0); see the counters summary in profiles/.  Valid for the kernels as
+# measured: reset to None when they change.
+JACOBI_ROUND_TRAFFIC_1024 = 26.77e6
 
 
 def parse():
@@ -245,7 +246,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "jacobi_round (one block-Jacobi SVD round: Gram + rotate launches over row slices)",
                      "achieved": round(rd_gbs, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(rd_gbs / PEAK_HBM_GBS, 4), "traffic": JACOBI_ROUND_TRAFFIC_1024,
-                     "traffic_note": "HBM bytes per 1024-column launch (rocprofv3 counters, copy-scaled)",
+                     "traffic_note": "HBM bytes per round of a 1024 x 1024 SVD, sliced form (rocprofv3 counters, copy-scaled)",
                      "rounds": rounds["calls"], "avg_round_us": round(rd_avg_s * 1e6, 3),
                      "bytes_per_round": rd_bytes,
                      "flops_per_round": rounds["flops"] / max(rounds["calls"], 1)},
