@@ -68,7 +68,7 @@ __host__ __device__ inline void rr_pair(int n, int r, int q, int* i, int* j) {
 //     pair q with its row partner), G ping-ponging between two buffers;
 //  4. the accumulated rotation W is applied to the columns in one pass
 //     (Z <- Z W).
-constexpr int kWT = 512;                  // threads of a round workgroup
+constexpr int kWT = 576;                  // threads of a round workgroup: 8 update waves + 1 rotation wave
 constexpr int kWW = kWT / 64;             // its waves
 constexpr int kBlk = 16;                  // columns per block
 constexpr int kNC = 2 * kBlk;             // columns per block pair
@@ -161,6 +161,7 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   __shared__ double gsum[kGramVals];          // fused round: running sum over the slices
   __shared__ double G[2][kNC][kNC + 1];
   __shared__ double Wt[kNC][kNC + 2];         // W transposed: Wt[c][j] = W[j][c]
+  __shared__ double rotc[2][kNC / 2], rots[2][kNC / 2];   // rotations of a round (double-buffered)
   __shared__ double wmax[kWW];
   __shared__ unsigned wmask[kWW];
   int bi, bj;
@@ -300,37 +301,86 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   if (worst == 0.0) return;          // uniform: every thread read the same wmax
 
   // 3. One sweep of parallel two-sided Jacobi on G; W <- W J per rotation.
+  // The 16 rotations of a round are computed once (one thread per pair) and
+  // read by all; the threads that compute them work one round ahead: from
+  // G before round r and round r's rotations they form the three entries of
+  // G after round r that fix their pair's rotation in the next round, so the
+  // rotation chains overlap the updates and a round costs one barrier.
+  // Waves 0-7 update G and W (thread (q, k): entries k of pair q), lanes
+  // 0-15 of wave 8 compute the rotations.
   {
-    const int q = t >> 5, k = t & 31;
-    int src = 0;
-    for (int rr = 1; rr < kNC; ++rr) {
-      // rounds with no flagged pair are skipped (uniform: mask is shared);
-      // rotations in earlier rounds may push a pair of a skipped round over
-      // tol, which the next visit's fresh Gram flags again
-      if (!((mask >> rr) & 1u)) continue;
-      const int h = 31 - __clz(rr);                                   // highest bit of rr
-      const int x = ((q >> h) << (h + 1)) | (q & ((1 << h) - 1));    // q-th k with k < (k ^ rr)
-      const int y = x ^ rr;
-      const int kb = k ^ rr;
-      const int kx = min(k, kb), ky = max(k, kb);
-      double c, s, c2, s2;
-      jacobi_rot(G[src][x][x], G[src][y][y], G[src][x][y], tol2, zth, &c, &s);
-      jacobi_rot(G[src][kx][kx], G[src][ky][ky], G[src][kx][ky], tol2, zth, &c2, &s2);
-      const double gkx = G[src][k][x], gky = G[src][k][y];
-      const double gbx = G[src][kb][x], gby = G[src][kb][y];
-      const double hkx = c * gkx - s * gky, hky = s * gkx + c * gky;   // columns rotated
-      const double hbx = c * gbx - s * gby, hby = s * gbx + c * gby;
-      if (k == kx) {                                                     // then rows
-        G[src ^ 1][k][x] = c2 * hkx - s2 * hbx;
-        G[src ^ 1][k][y] = c2 * hky - s2 * hby;
-      } else {
-        G[src ^ 1][k][x] = s2 * hbx + c2 * hkx;
-        G[src ^ 1][k][y] = s2 * hby + c2 * hky;
+    const bool upd = t < 16 * kNC;
+    const int q = (t >> 5) & 15, k = t & 31;
+    const int qr = t - 16 * kNC;              // rotation lane: pair index
+    auto next_round = [&](int r0) {
+      for (int r2 = r0 + 1; r2 < kNC; ++r2)
+        if ((mask >> r2) & 1u) return r2;
+      return 0;
+    };
+    // members of pair qq in round rr: x = qq with a zero bit inserted at the
+    // highest bit h of rr, y = x ^ rr; and back: pair index of a member
+    auto pair_x = [](int rr, int qq) {
+      const int h = 31 - __clz(rr);
+      return ((qq >> h) << (h + 1)) | (qq & ((1 << h) - 1));
+    };
+    auto pair_of = [](int rr, int a) {
+      const int h = 31 - __clz(rr);
+      const int am = min(a, a ^ rr);
+      return ((am >> (h + 1)) << h) | (am & ((1 << h) - 1));
+    };
+    int rc = next_round(0);
+    if (qr >= 0 && qr < kNC / 2 && rc) {
+      const int x = pair_x(rc, qr), y = x ^ rc;
+      jacobi_rot(G[0][x][x], G[0][y][y], G[0][x][y], tol2, zth, &rotc[0][qr], &rots[0][qr]);
+    }
+    __syncthreads();
+    int src = 0, rb = 0;
+    while (rc) {
+      const int rn = next_round(rc);
+      if (upd) {
+        const int x = pair_x(rc, q), y = x ^ rc;
+        const int kb = k ^ rc;
+        const int kx = min(k, kb);
+        const int qk = pair_of(rc, k);
+        const double c = rotc[rb][q], sn = rots[rb][q];
+        const double c2 = rotc[rb][qk], s2 = rots[rb][qk];
+        const double gkx = G[src][k][x], gky = G[src][k][y];
+        const double gbx = G[src][kb][x], gby = G[src][kb][y];
+        const double hkx = c * gkx - sn * gky, hky = sn * gkx + c * gky;   // columns rotated
+        const double hbx = c * gbx - sn * gby, hby = sn * gbx + c * gby;
+        if (k == kx) {                                                      // then rows
+          G[src ^ 1][k][x] = c2 * hkx - s2 * hbx;
+          G[src ^ 1][k][y] = c2 * hky - s2 * hby;
+        } else {
+          G[src ^ 1][k][x] = s2 * hbx + c2 * hkx;
+          G[src ^ 1][k][y] = s2 * hby + c2 * hky;
+        }
+        const double wx = Wt[x][k], wy = Wt[y][k];
+        Wt[x][k] = c * wx - sn * wy;
+        Wt[y][k] = sn * wx + c * wy;
+      } else if (qr < kNC / 2 && rn) {
+        // entry (a, b) of G after round rc: sum over i in {a, a^rc}, j in
+        // {b, b^rc} of J[i][a] G[i][j] J[j][b]; column a of J holds
+        // (u, v) = (c, -s) on rows (a, a^rc) if a is the smaller member of
+        // its pair, (c, s) if it is the larger
+        auto coef = [&](int a2, double* u, double* v) {
+          const int qa = pair_of(rc, a2);
+          *u = rotc[rb][qa];
+          *v = (a2 < (a2 ^ rc)) ? -rots[rb][qa] : rots[rb][qa];
+        };
+        auto gnew = [&](int a2, int b2) {
+          double ua, va, ub, vb;
+          coef(a2, &ua, &va);
+          coef(b2, &ub, &vb);
+          const int ar = a2 ^ rc, br = b2 ^ rc;
+          return ua * (ub * G[src][a2][b2] + vb * G[src][a2][br]) + va * (ub * G[src][ar][b2] + vb * G[src][ar][br]);
+        };
+        const int xn = pair_x(rn, qr), yn = xn ^ rn;
+        jacobi_rot(gnew(xn, xn), gnew(yn, yn), gnew(xn, yn), tol2, zth, &rotc[rb ^ 1][qr], &rots[rb ^ 1][qr]);
       }
-      const double wx = Wt[x][k], wy = Wt[y][k];
-      Wt[x][k] = c * wx - s * wy;
-      Wt[y][k] = s * wx + c * wy;
       src ^= 1;
+      rb ^= 1;
+      rc = rn;
       __syncthreads();
     }
   }
