@@ -113,7 +113,12 @@ typedef struct {
   double sv_floor;   /* singular values <= sv_floor*sigma_1 count as zero (1e-14) */
   int no_warm_start; /* 0: each SVD after the first visit of a bond starts from the
                         previous visit's singular basis (same result, fewer Jacobi
-                        sweeps); 1: every SVD starts cold */
+                        sweeps); 1: every SVD starts cold (and no_qr_start is implied) */
+  int no_qr_start;   /* 0: a first visit (no basis from an earlier visit) with at least
+                        256 rows and columns (and at most 2048 rows) starts from the right
+                        singular vectors of the triangular factor of a column-pivoted QR
+                        of its two-site tensor (same result, fewer Jacobi sweeps);
+                        1: such SVDs start cold */
 } xtrg_compress_opts;
 
 /* Diagnostics of one doubling. */
@@ -205,6 +210,21 @@ int xtrg_gemm_bf16x3(xtrg_ctx ctx, int M, int N, int K, int transA, int transB,
  * into U (device, column-major len x k).  Y is not modified.  One-sided
  * (Hestenes) Jacobi with column blocks. */
 int xtrg_dsvd_left(xtrg_ctx ctx, int len, int p, const double* Y, double* sigma, int k, double* U);
+/* xtrg_dqrcp: Householder QR with column pivoting of Y (len x p stored
+ * column-major, device, not modified), triangular factor only: the start of
+ * the truncated SVD of App. D.1 on a first visit (a preconditioner; the
+ * result of the SVD does not depend on it).  Step r pivots the remaining
+ * column of largest norm below row r, so that Y[:, piv] = Q R with R upper
+ * triangular and |R_rr| non-increasing.  The factorisation stops when every
+ * remaining column has norm^2 <= stop_rel^2 ||Y||_F^2 (stop_rel = 0: after
+ * min(len, p) steps, or at exactly zero remaining columns); *keff (host)
+ * receives the number of steps.  piv (device, min(len, p) ints): the pivot
+ * column of each step (first keff written).  RT (device, p x min(len, p)
+ * doubles, column-major, leading dimension p; first keff columns written):
+ * R^T in the input's column order, RT[r*p + c] = R's entry at row r for
+ * input column c (zero for columns pivoted before step r).  Requires
+ * len <= 2048, p <= 4096; XTRG_EINVAL otherwise. */
+int xtrg_dqrcp(xtrg_ctx ctx, int len, int p, const double* Y, double stop_rel, int* piv, double* RT, int* keff);
 
 #ifdef __cplusplus
 }

@@ -49,6 +49,9 @@ struct xtrg_ctx_s {
   long svd_calls = 0, svd_sweeps = 0;
   // warm-start statistics: bases built, rejected, used; sum of completion sizes m
   long warm_built = 0, warm_rejected = 0, warm_used = 0, warm_m = 0;
+  // QR-preconditioned first visits: factorisations, their rows, Jacobi
+  // sweeps on R^T, starts used, bases rejected by the orthogonality check
+  long qr_calls = 0, qr_rows = 0, qr_sweeps = 0, qr_used = 0, qr_rejected = 0;
 
   double* alloc(size_t n) {
     const size_t b = std::max<size_t>(n, 1) * sizeof(double);
@@ -111,8 +114,9 @@ namespace {
 // svd_rounds is the part of svd spent in the Jacobi round kernels; its
 // "calls" count kernel launches.
 // warm is the building of the warm-start bases and the rotation of the SVD input.
-enum { P_THETA = 0, P_BLOCK, P_ENV, P_SVD, P_SPLIT, P_ROUNDS, P_WARM, P_NCAT };
-const char* const kPhase[P_NCAT] = {"theta_gemm", "block_gemm", "env_gemm", "svd", "split", "svd_rounds", "warm"};
+enum { P_THETA = 0, P_BLOCK, P_ENV, P_SVD, P_SPLIT, P_ROUNDS, P_WARM, P_QR, P_NCAT };
+const char* const kPhase[P_NCAT] = {"theta_gemm", "block_gemm", "env_gemm", "svd",
+                                    "split", "svd_rounds", "warm", "qr_start"};
 
 // RAII event pair around the work enqueued in its scope.
 struct Timed {
@@ -203,6 +207,7 @@ struct RoundProf : xtrg::RoundTimer {
 
 // Device descriptors of a grouped SVD launch over n problems.
 void* svd_desc(xtrg_ctx c, int n) { return c->need("svd_desc", xtrg::svd_desc_bytes(n) / sizeof(double) + 1); }
+void* qr_desc(xtrg_ctx c, int n) { return c->need("qr_desc", xtrg::qr_desc_bytes(n) / sizeof(double) + 1); }
 
 void gemm(xtrg_ctx c, const Gemm& g) {
   const size_t w = xtrg::gemm_splitk_work(g);
@@ -777,21 +782,24 @@ double orth_dev(xtrg_ctx c, const double* X, int len, int k) {
 // (len + o columns), whose left singular vectors and values are those of Y.
 constexpr int kWarmExtra = 32;
 
-void build_warm(xtrg_ctx c, Chain& C, const std::vector<double>& S, double keep_floor, unsigned long long seed) {
+// The block from the Jacobi workspace `work` of a dim x pw problem (sorted
+// values S) into Q (dim x (dim + kWarmExtra) doubles, column-major).
+// Returns its column count, 0 if none is built (small, or mostly noise), or
+// -1 if it fails the orthogonality check; *m_out: the completion size.
+int build_basis(xtrg_ctx c, double* work, int dim, int pw, const std::vector<double>& S, double keep_floor,
+                unsigned long long seed, double* Q, int* m_out) {
   hipStream_t s = c->stream;
-  const int len = C.len, pw = C.psvd;
-  auto& w = C.warm[C.i];
-  w.side = -1;
-  if (len < kWarmMin || pw < 1) return;
+  const int len = dim;
+  *m_out = 0;
+  if (len < kWarmMin || pw < 1) return 0;
   int r = 0;
   const int rmax = std::min(len, pw);
   while (r < rmax && S[r] > 0.5 * keep_floor) ++r;
   const int m = len - r;
-  if (4 * r < len) return;                  // mostly noise: the completion would dominate
+  if (4 * r < len) return 0;                // mostly noise: the completion would dominate
   const int o = m > 0 ? kWarmExtra : 0;
   const int cols = len + o;
-  double* Q = c->need("wq" + std::to_string(C.i) + C.tag, (size_t)len * cols);
-  xtrg::svd_gather(len, pw, C.work, r, Q, len, 0, s);
+  xtrg::svd_gather(len, pw, work, r, Q, len, 0, s);
   if (m > 0) {
     const int mo = m + o;
     double* R = Q + (size_t)len * r;
@@ -815,16 +823,82 @@ void build_warm(xtrg_ctx c, Chain& C, const std::vector<double>& S, double keep_
   gemm(c, plain(len, len, cols, Q, len, true, Q, len, false, G, len));  // Q Q^T
   xtrg::eye_dev(G, len, c->scratch, c->scratch + 1024, s);
   const double dev = read_scalar(c, c->scratch);
-  c->warm_m += m;
+  *m_out = m;
   // the Jacobi leaves cosines <= 8 sqrt(len) eps between kept columns
-  if (!(dev <= 32.0 * std::sqrt((double)len) * 2.220446049250313e-16)) {
-    c->warm_rejected += 1;
-    return;
-  }
+  if (!(dev <= 32.0 * std::sqrt((double)len) * 2.220446049250313e-16)) return -1;
+  return cols;
+}
+
+void build_warm(xtrg_ctx c, Chain& C, const std::vector<double>& S, double keep_floor, unsigned long long seed) {
+  auto& w = C.warm[C.i];
+  w.side = -1;
+  const int len = C.len;
+  if (len < kWarmMin || C.psvd < 1) return;
+  double* Q = c->need("wq" + std::to_string(C.i) + C.tag, (size_t)len * (len + kWarmExtra));
+  int m = 0;
+  const int cols = build_basis(c, C.work, len, C.psvd, S, keep_floor, seed, Q, &m);
+  c->warm_m += m;
+  if (cols < 0) c->warm_rejected += 1;
+  if (cols <= 0) return;
   c->warm_built += 1;
   w.side = C.gauge_right ? 0 : 1;   // Z lives in the row space of Y
   w.dim = len;
   w.cols = cols;
+}
+
+// First visits of a bond (no basis from an earlier visit): a start for the
+// Jacobi from a column-pivoted QR of Y.  With Y P = Q R, the right singular
+// vectors of Y are those of R; the one-sided Jacobi on R^T (p x keff) finds
+// them in a fraction of the sweeps that it needs on Y (the pivoted factor is
+// graded), and they make a basis block as after a visit; the SVD then runs
+// on Y [Q0 X].  The QR stops at the Jacobi's numerical zero (a quarter of
+// the keep floor), since directions below it are never rotated.  All
+// chains at once: one grouped QR and one grouped Jacobi.
+constexpr int kQrMin = 256;   // smallest SVD (rows and columns) that gets the QR start
+
+void qr_start(xtrg_ctx c, const std::vector<Chain*>& pre, xtrg::RoundTimer* rt) {
+  hipStream_t s = c->stream;
+  const int n = (int)pre.size();
+  std::vector<xtrg::QrJob> qj;
+  for (Chain* C : pre)
+    qj.push_back(xtrg::QrJob{C->len, C->p, C->th, c->need("qr" + C->tag, xtrg::qr_work(C->len, C->p)),
+                             0.25 * xtrg::svd_keep_rel(C->len, C->p), 0});
+  xtrg::qrcp_batched(qj, qr_desc(c, n), s);
+  std::vector<xtrg::SvdJob> sj;
+  std::vector<int> at;
+  for (int q = 0; q < n; ++q) {
+    Chain* C = pre[q];
+    const auto& J = qj[q];
+    c->qr_calls += 1;
+    c->qr_rows += J.keff;
+    if (4 * J.keff < C->p) continue;         // mostly noise: no block would be built
+    double* RT = c->need("qr_rt" + C->tag, (size_t)C->p * J.keff);
+    xtrg::qr_rt(J, RT, s);
+    sj.push_back(xtrg::SvdJob{C->p, J.keff, RT, c->need("qr_svd" + C->tag, xtrg::svd_work(C->p, J.keff)), 0});
+    at.push_back(q);
+  }
+  if (sj.empty()) return;
+  xtrg::svd_batched(sj, svd_desc(c, (int)sj.size()), s, rt);
+  for (size_t t = 0; t < sj.size(); ++t) {
+    Chain* C = pre[at[t]];
+    const int keff = sj[t].p;
+    c->qr_sweeps += sj[t].sweeps;
+    const std::vector<double> S = read_vec(c, xtrg::svd_sorted_values(sj[t].work, C->p, keff), keff);
+    // keep floor of Y (||R^T||_F = ||Y||_F up to the columns below the stop)
+    const double f2 = read_vec(c, xtrg::svd_fro2(sj[t].work, C->p, keff), 1)[0];
+    const double kf = xtrg::svd_keep_rel(C->len, C->p) * std::sqrt(std::max(f2, 0.0));
+    double* Q = c->need("pq" + C->tag, (size_t)C->p * (C->p + kWarmExtra));
+    int m = 0;
+    const int cols = build_basis(c, sj[t].work, C->p, keff, S, kf, 0xC01Dull + 7919ull * (unsigned long long)C->i, Q, &m);
+    if (cols < 0) c->qr_rejected += 1;
+    if (cols <= 0) continue;
+    double* Yw = c->need("svd_in" + C->tag, (size_t)C->len * cols);
+    gemm(c, plain(cols, C->len, C->p, Q, C->p, false, C->th, C->len, false, Yw, C->len));   // Y [Q0 X]
+    C->Y = Yw;
+    C->psvd = cols;
+    C->work = c->need("svd" + C->tag, xtrg::svd_work(C->len, cols));
+    c->qr_used += 1;
+  }
 }
 
 // After the SVD of the chain's two-site overlap: choose k, split into C_i and
@@ -987,6 +1061,18 @@ void square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_com
         c->warm_used += 1;
       }
       C->work = c->need("svd" + C->tag, xtrg::svd_work(C->len, C->psvd));
+    }
+    {
+      std::vector<Chain*> pre;
+      for (Chain* C : act)
+        if (C->psvd == C->p && !C->o.no_warm_start && !C->o.no_qr_start && C->p >= kQrMin && C->len >= kQrMin &&
+            C->len <= xtrg::kQrMaxLen)
+          pre.push_back(C);
+      if (!pre.empty()) {
+        Timed tm(c, P_QR, 0.0, 0.0);
+        RoundProf rp(c);
+        qr_start(c, pre, &rp);
+      }
     }
     {
       double bs = 0.0;
@@ -1434,14 +1520,17 @@ int xtrg_profile_report(xtrg_ctx c, char* buf, size_t cap) {
                     q ? ", " : "", kPhase[q], ms[q], n[q], fl[q], by[q]);
       out += tmp;
     }
-    char tail[320];
+    char tail[512];
     std::snprintf(tail, sizeof tail,
                   ", \"svd_calls\": %ld, \"svd_sweeps\": %ld, \"warm_built\": %ld, \"warm_rejected\": %ld, "
-                  "\"warm_used\": %ld, \"warm_m\": %ld}",
-                  c->svd_calls, c->svd_sweeps, c->warm_built, c->warm_rejected, c->warm_used, c->warm_m);
+                  "\"warm_used\": %ld, \"warm_m\": %ld, \"qr_calls\": %ld, \"qr_rows\": %ld, "
+                  "\"qr_sweeps\": %ld, \"qr_used\": %ld, \"qr_rejected\": %ld}",
+                  c->svd_calls, c->svd_sweeps, c->warm_built, c->warm_rejected, c->warm_used, c->warm_m,
+                  c->qr_calls, c->qr_rows, c->qr_sweeps, c->qr_used, c->qr_rejected);
     out += tail;
     c->svd_calls = c->svd_sweeps = 0;
     c->warm_built = c->warm_rejected = c->warm_used = c->warm_m = 0;
+    c->qr_calls = c->qr_rows = c->qr_sweeps = c->qr_used = c->qr_rejected = 0;
     if (out.size() + 1 > cap) throw Error(XTRG_EINVAL, "profile report buffer too small");
     std::memcpy(buf, out.c_str(), out.size() + 1);
   });
@@ -1488,6 +1577,24 @@ int xtrg_dsvd_left(xtrg_ctx c, int len, int p, const double* Y, double* sigma, i
     c->svd_sweeps += sw;
     if (k > 0 && U) orthonormalize(c, U, len, k, false);
     XTRG_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+int xtrg_dqrcp(xtrg_ctx c, int len, int p, const double* Y, double stop_rel, int* piv, double* RT, int* keff) {
+  if (!c || len < 0 || p < 0 || !keff || !(stop_rel >= 0.0) || len > xtrg::kQrMaxLen || p > 4096 ||
+      (len * (long)p > 0 && (!Y || !piv || !RT)))
+    return XTRG_EINVAL;
+  return guarded(c, [&] {
+    set_device(c);
+    std::vector<xtrg::QrJob> jobs{xtrg::QrJob{len, p, Y, c->need("qr", xtrg::qr_work(len, p)), stop_rel, 0}};
+    xtrg::qrcp_batched(jobs, qr_desc(c, 1), c->stream);
+    const int k = jobs[0].keff;
+    if (k > 0) {
+      xtrg::qr_rt(jobs[0], RT, c->stream);
+      XTRG_HIP(hipMemcpyAsync(piv, xtrg::qr_pivots(jobs[0]), sizeof(int) * k, hipMemcpyDeviceToDevice, c->stream));
+    }
+    XTRG_HIP(hipStreamSynchronize(c->stream));
+    *keff = k;
   });
 }
 

@@ -82,6 +82,26 @@ struct RoundTimer {
 };
 void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, RoundTimer* timer = nullptr);
 
+// Householder QR with column pivoting of Y (len x p, column-major), the
+// triangular factor only, stopped once every remaining column has norm^2
+// <= stop_rel^2 ||Y||_F^2 (keff rows; each job its own stop_rel).  Columns stay in place: R's entry
+// at row r for column c is read with qr_rt.  Several problems per launch.
+constexpr int kQrMaxLen = 2048;
+struct QrJob {
+  int len, p;
+  const double* Y;   // len x p column-major (device), not modified
+  double* work;      // qr_work(len, p) doubles
+  double stop_rel;
+  int keff;          // out: rows of R
+};
+size_t qr_work(int len, int p);
+size_t qr_desc_bytes(int n);
+void qrcp_batched(std::vector<QrJob>& jobs, void* desc_dev, hipStream_t s);
+// R^T into RT (p x keff, column-major, leading dimension p).
+void qr_rt(const QrJob& J, double* RT, hipStream_t s);
+// Pivot column of each step (device, keff ints).
+const int* qr_pivots(const QrJob& J);
+
 // Two-stage use: svd_left with k = 0, read the sorted values, then gather.
 void svd_gather(int len, int p, double* work, int k, double* U, long ldu, int u_rowmajor, hipStream_t s);
 const double* svd_sorted_values(const double* work, int len, int p);

@@ -1,0 +1,274 @@
+// Householder QR with column pivoting (triangular factor only), FP64.
+//
+// Used to precondition the one-sided Jacobi SVD of a two-site overlap that
+// has no singular basis from an earlier visit: with Y P = Q R, the right
+// singular vectors of Y are those of R, and the one-sided Jacobi on R^T
+// converges in a fraction of the sweeps it needs on Y itself (the pivoted
+// factor is graded: its rows fall off in norm, and the column scaling that
+// remains after the grading is well conditioned).  Those vectors then start
+// the Jacobi on Y.  The factorisation only steers the convergence; the
+// singular values and vectors still come from the Jacobi on Y.
+//
+// Layout: the columns are never moved.  Step i takes the remaining column
+// of largest norm below row i (its index is the pivot piv[i]), forms the
+// reflector H_i = I - tau v v^T that maps that column to beta e_i, and
+// applies it to rows i.. of every column not yet pivoted.  Row i of a
+// column not pivoted before step i is then final: it is R's entry at row i.
+// The factorisation stops once every remaining column is below a threshold
+// (the numerical zero of the Jacobi), so R has keff <= min(len, p) rows.
+//
+// One launch per step, one wave per column.  Every workgroup forms the
+// reflector itself from the pivot column (the same arithmetic in every
+// workgroup, so all agree); the next pivot is the maximum of the packed
+// (norm^2, column) keys that the waves post with one atomic each.
+#include "internal.h"
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+
+namespace xtrg {
+
+namespace {
+
+constexpr int kQT = 256;                      // threads of a step workgroup (4 waves, one column each)
+constexpr int kIdxBits = 12;                  // column index in the low bits of a pivot key
+constexpr unsigned long long kIdxMask = (1ull << kIdxBits) - 1;
+constexpr int kChunk = 64;                    // steps launched between checks for the stop
+
+struct QrDesc {
+  double* A;                                  // len x p column-major, overwritten
+  unsigned long long* best;                   // kmax + 1 pivot keys (zeroed)
+  int* piv;                                   // kmax: pivot column of each step
+  int* stepof;                                // p: step at which a column was pivoted (INT_MAX: never)
+  double* rdiag;                              // kmax: diagonal of R (beta of each step)
+  int* keff;                                  // rows of R (starts at kmax, lowered at the stop)
+  const double* fro2;                         // ||Y||_F^2
+  double stop_rel2;
+  int len, p, kmax;
+};
+
+// Pivot key: the bit pattern of a non-negative double is monotone under
+// unsigned comparison; its low 12 mantissa bits carry the column index
+// (a relative change of 2^-40 in the compared norm, which only decides
+// between columns of equal norm to that precision).
+__device__ inline unsigned long long qr_key(double n2, int c) {
+  return ((unsigned long long)__double_as_longlong(n2) & ~kIdxMask) | (unsigned long long)c;
+}
+__device__ inline double qr_key_norm2(unsigned long long k) {
+  return __longlong_as_double((long long)(k & ~kIdxMask));
+}
+
+__device__ inline double qr_wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Column norms of Y: the first pivot; marks every column not pivoted.
+__global__ __launch_bounds__(kQT) void qr_init(const QrDesc* __restrict__ descs) {
+  const QrDesc d = descs[blockIdx.y];
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int gt = blockIdx.x * kQT + t;
+  if (gt < d.p) d.stepof[gt] = INT_MAX;
+  const int c = blockIdx.x * (kQT / 64) + wave;
+  if (c >= d.p || d.kmax <= 0) return;
+  const double* __restrict__ y = d.A + (size_t)c * d.len;
+  double ss = 0.0;
+  for (int r = lane; r < d.len; r += 64) ss = fma(y[r], y[r], ss);
+  ss = qr_wave_sum(ss);
+  if (lane == 0) atomicMax(d.best, qr_key(ss, c));
+}
+
+// Step i.  R: rows per lane (len - i <= 64 R).
+template <int R>
+__global__ __launch_bounds__(kQT) void qr_step(const QrDesc* __restrict__ descs, int i) {
+  const QrDesc d = descs[blockIdx.y];
+  if (i >= d.kmax) return;
+  const unsigned long long key = d.best[i];
+  if (!(qr_key_norm2(key) > d.stop_rel2 * d.fro2[0])) {     // every remaining column is numerically zero
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicMin(d.keff, i);
+    return;
+  }
+  const int ci = (int)(key & kIdxMask);
+  const int m = d.len - i;                    // rows i .. len-1
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int c = blockIdx.x * (kQT / 64) + wave;
+  // this wave's column (not the pivot, not pivoted before): loads issued first
+  const bool mine = c < d.p && c != ci && d.stepof[c] > i;
+  double* __restrict__ yc = d.A + (size_t)(mine ? c : 0) * d.len + i;
+  double y[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int r = lane + 64 * u;
+    y[u] = (mine && r < m) ? yc[r] : 0.0;
+  }
+  // the reflector, from the pivot column (read only in this step)
+  __shared__ double v[64 * R];
+  __shared__ double red[kQT / 64];
+  const double* __restrict__ xc = d.A + (size_t)ci * d.len + i;
+  double ss = 0.0;
+  for (int r = t; r < m; r += kQT) {
+    const double x = xc[r];
+    v[r] = x;
+    ss = fma(x, x, ss);
+  }
+  ss = qr_wave_sum(ss);
+  if (lane == 0) red[wave] = ss;
+  __syncthreads();
+  const double sig2 = (red[0] + red[1]) + (red[2] + red[3]);
+  const double alpha = v[0];
+  const double beta = -copysign(sqrt(sig2), alpha);   // |alpha - beta| = |alpha| + sigma > 0
+  const double tau = (beta - alpha) / beta;
+  const double sc = 1.0 / (alpha - beta);
+  __syncthreads();                            // v[0] read by all before it is overwritten
+  for (int r = t; r < m; r += kQT) v[r] = r == 0 ? 1.0 : v[r] * sc;
+  __syncthreads();
+  if (blockIdx.x == 0 && t == 0) {
+    d.piv[i] = ci;
+    d.rdiag[i] = beta;
+    d.stepof[ci] = i;
+  }
+  if (!mine) return;
+  // y <- (I - tau v v^T) y; norm^2 of rows i+1.. for the next pivot
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int r = lane + 64 * u;
+    if (r < m) s = fma(v[r], y[u], s);
+  }
+  s = qr_wave_sum(s) * tau;
+  double n2 = 0.0;
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int r = lane + 64 * u;
+    if (r < m) {
+      const double z = fma(-s, v[r], y[u]);
+      yc[r] = z;
+      if (r > 0) n2 = fma(z, z, n2);
+    }
+  }
+  n2 = qr_wave_sum(n2);
+  if (lane == 0) atomicMax(d.best + i + 1, qr_key(n2, c));
+}
+
+// R^T (p x keff, column-major, leading dimension p): entry (c, r) is R's
+// entry at row r for column c: beta_r for the pivot of step r, row r of the
+// updated column if c was pivoted after step r (or never), else zero.
+// 32 x 32 tiles through LDS (reads along A's columns, writes along R^T's).
+__global__ __launch_bounds__(256) void qr_rt(const double* __restrict__ A, int len, int p, int keff,
+                                             const int* __restrict__ piv, const int* __restrict__ stepof,
+                                             const double* __restrict__ rdiag, double* __restrict__ RT) {
+  __shared__ double tile[32][33];
+  const int r0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;    // 32 x 8
+  for (int q = ty; q < 32; q += 8) {
+    const int c = c0 + q, r = r0 + tx;
+    double v = 0.0;
+    if (c < p && r < keff) {
+      if (piv[r] == c) v = rdiag[r];
+      else if (stepof[c] > r) v = A[(size_t)c * len + r];
+    }
+    tile[q][tx] = v;
+  }
+  __syncthreads();
+  for (int q = ty; q < 32; q += 8) {
+    const int r = r0 + q, c = c0 + tx;
+    if (r < keff && c < p) RT[(size_t)r * p + c] = tile[tx][q];
+  }
+}
+
+// Workspace layout (doubles): A (len p), fro2 (1), sumsq scratch (1024),
+// rdiag (kmax), best (kmax + 1), piv (kmax ints), stepof (p ints).
+struct QrLayout {
+  double* A;
+  double* fro2;
+  double* part;
+  double* rdiag;
+  unsigned long long* best;
+  int* piv;
+  int* stepof;
+};
+QrLayout qr_layout(double* w, int len, int p) {
+  const size_t kmax = (size_t)std::min(len, p);
+  QrLayout L;
+  L.A = w;
+  L.fro2 = w + (size_t)len * p;
+  L.part = L.fro2 + 1;
+  L.rdiag = L.part + 1024;
+  L.best = reinterpret_cast<unsigned long long*>(L.rdiag + kmax);
+  L.piv = reinterpret_cast<int*>(L.best + kmax + 1);
+  L.stepof = L.piv + kmax;
+  return L;
+}
+
+}  // namespace
+
+size_t qr_work(int len, int p) {
+  const size_t kmax = (size_t)std::min(len, p);
+  return (size_t)len * p + 1 + 1024 + kmax + (kmax + 1) + (kmax + 1) / 2 + ((size_t)p + 1) / 2 + 2;
+}
+
+size_t qr_desc_bytes(int n) { return (sizeof(QrDesc) + sizeof(int)) * (size_t)n + 256; }
+
+void qrcp_batched(std::vector<QrJob>& jobs, void* desc_dev, hipStream_t s) {
+  const int n = (int)jobs.size();
+  if (n == 0) return;
+  QrDesc* d_desc = reinterpret_cast<QrDesc*>(desc_dev);
+  int* d_keff = reinterpret_cast<int*>(d_desc + n);
+  std::vector<QrDesc> h(n);
+  std::vector<int> kmax(n);
+  int kmax_all = 0, pmax = 0, lenmax = 0;
+  for (int j = 0; j < n; ++j) {
+    QrJob& J = jobs[j];
+    if (J.len < 0 || J.p < 0) throw Error(-1, "qrcp: negative size");
+    if (J.len > kQrMaxLen) throw Error(-1, "qrcp: column length above 2048");
+    if (J.p > (int)kIdxMask + 1) throw Error(-1, "qrcp: more than 4096 columns");
+    kmax[j] = std::min(J.len, J.p);
+    J.keff = 0;
+    QrLayout L = qr_layout(J.work, J.len, J.p);
+    h[j] = QrDesc{L.A, L.best, L.piv, L.stepof, L.rdiag, d_keff + j, L.fro2, J.stop_rel * J.stop_rel, J.len, J.p, kmax[j]};
+    if (kmax[j] == 0) continue;
+    XTRG_HIP(hipMemcpyAsync(L.A, J.Y, sizeof(double) * J.len * J.p, hipMemcpyDeviceToDevice, s));
+    XTRG_HIP(hipMemsetAsync(L.best, 0, sizeof(unsigned long long) * (kmax[j] + 1), s));
+    sumsq(L.A, (size_t)J.len * J.p, L.fro2, L.part, s);
+    kmax_all = std::max(kmax_all, kmax[j]);
+    pmax = std::max(pmax, J.p);
+    lenmax = std::max(lenmax, J.len);
+  }
+  XTRG_HIP(hipMemcpyAsync(d_desc, h.data(), sizeof(QrDesc) * n, hipMemcpyHostToDevice, s));
+  XTRG_HIP(hipMemcpyAsync(d_keff, kmax.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+  std::vector<int> keff(kmax);
+  if (kmax_all > 0) {
+    const dim3 grid((pmax + kQT / 64 - 1) / (kQT / 64), n);
+    hipLaunchKernelGGL(qr_init, grid, dim3(kQT), 0, s, d_desc);
+    for (int i0 = 0; i0 < kmax_all; i0 += kChunk) {
+      const int i1 = std::min(kmax_all, i0 + kChunk);
+      for (int i = i0; i < i1; ++i) {
+        if (lenmax <= 256) hipLaunchKernelGGL(qr_step<4>, grid, dim3(kQT), 0, s, d_desc, i);
+        else if (lenmax <= 512) hipLaunchKernelGGL(qr_step<8>, grid, dim3(kQT), 0, s, d_desc, i);
+        else if (lenmax <= 1024) hipLaunchKernelGGL(qr_step<16>, grid, dim3(kQT), 0, s, d_desc, i);
+        else hipLaunchKernelGGL(qr_step<32>, grid, dim3(kQT), 0, s, d_desc, i);
+      }
+      XTRG_HIP(hipGetLastError());
+      XTRG_HIP(hipMemcpyAsync(keff.data(), d_keff, sizeof(int) * n, hipMemcpyDeviceToHost, s));
+      XTRG_HIP(hipStreamSynchronize(s));
+      bool more = false;
+      for (int j = 0; j < n; ++j) more = more || (keff[j] == kmax[j] && kmax[j] > i1);
+      if (!more) break;
+    }
+  }
+  for (int j = 0; j < n; ++j) jobs[j].keff = keff[j];
+}
+
+void qr_rt(const QrJob& J, double* RT, hipStream_t s) {
+  if (J.keff <= 0 || J.p <= 0) return;
+  QrLayout L = qr_layout(J.work, J.len, J.p);
+  hipLaunchKernelGGL(qr_rt, dim3((J.keff + 31) / 32, (J.p + 31) / 32), dim3(256), 0, s, L.A, J.len, J.p, J.keff,
+                     L.piv, L.stepof, L.rdiag, RT);
+  XTRG_HIP(hipGetLastError());
+}
+
+const int* qr_pivots(const QrJob& J) { return qr_layout(J.work, J.len, J.p).piv; }
+
+}  // namespace xtrg

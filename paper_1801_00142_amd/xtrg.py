@@ -29,7 +29,8 @@ class XtrgError(RuntimeError):
 
 class CompressOpts(C.Structure):
     _fields_ = [("D_max", C.c_int), ("n_sweeps", C.c_int), ("precision", C.c_int),
-                ("degen_rtol", C.c_double), ("sv_floor", C.c_double), ("no_warm_start", C.c_int)]
+                ("degen_rtol", C.c_double), ("sv_floor", C.c_double), ("no_warm_start", C.c_int),
+                ("no_qr_start", C.c_int)]
 
 
 class CompressInfo(C.Structure):
@@ -78,6 +79,7 @@ def load_library(path: Optional[str] = None):
         "xtrg_gemm_bf16x3": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, vp, C.c_long, vp,
                                        C.c_long, vp, C.c_long, C.c_int]),
         "xtrg_dsvd_left": (C.c_int, [vp, C.c_int, C.c_int, vp, vp, C.c_int, vp]),
+        "xtrg_dqrcp": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_double, vp, vp, ip]),
         "xtrg_profile_enable": (C.c_int, [vp, C.c_int]),
         "xtrg_profile_report": (C.c_int, [vp, C.c_char_p, C.c_size_t]),
     }
@@ -93,7 +95,7 @@ def exported_symbols() -> List[str]:
     return ["xtrg_ctx_create", "xtrg_ctx_destroy", "xtrg_last_error", "xtrg_ctx_bytes", "xtrg_ctx_trim",
             "xtrg_hamiltonian_xxz", "xtrg_mpo_from_host", "xtrg_mpo_shape", "xtrg_mpo_to_host",
             "xtrg_mpo_destroy", "xtrg_init_rho", "xtrg_square_compress", "xtrg_square_compress_batched", "xtrg_observables",
-            "xtrg_dgemm", "xtrg_sgemm", "xtrg_gemm_bf16x3", "xtrg_dsvd_left", "xtrg_profile_enable", "xtrg_profile_report"]
+            "xtrg_dgemm", "xtrg_sgemm", "xtrg_gemm_bf16x3", "xtrg_dsvd_left", "xtrg_dqrcp", "xtrg_profile_enable", "xtrg_profile_report"]
 
 
 class MPO:
@@ -204,8 +206,9 @@ class Context:
 
     def square_compress(self, rho: MPO, D_max: int, n_sweeps: int = 4, degen_rtol: float = 1e-6,
                         sv_floor: float = 1e-14, sv_stride: int = 0, precision: int = XTRG_FP64,
-                        warm_start: bool = True):
-        o = CompressOpts(D_max, n_sweeps, precision, degen_rtol, sv_floor, int(not warm_start))
+                        warm_start: bool = True, qr_start: bool = True):
+        o = CompressOpts(D_max, n_sweeps, precision, degen_rtol, sv_floor, int(not warm_start),
+                         int(not qr_start))
         info = CompressInfo()
         L = rho.shape()[0]
         buf = None
@@ -223,7 +226,7 @@ class Context:
 
     def square_compress_batched(self, rhos: Sequence[MPO], D_max, n_sweeps=4,
                                 degen_rtol: float = 1e-6, sv_floor: float = 1e-14, sv_stride: int = 0,
-                                precision: int = XTRG_FP64, warm_start: bool = True):
+                                precision: int = XTRG_FP64, warm_start: bool = True, qr_start: bool = True):
         """One doubling of every chain in `rhos` together.  D_max and n_sweeps
         are one value for all chains or a sequence with one per chain.
         Returns ([new MPO per chain], [info dict per chain])."""
@@ -232,7 +235,8 @@ class Context:
         Ss = list(n_sweeps) if isinstance(n_sweeps, (list, tuple)) else [n_sweeps] * n
         if len(Ds) != n or len(Ss) != n:
             raise ValueError("one D_max and n_sweeps per chain")
-        o = (CompressOpts * n)(*[CompressOpts(Ds[q], Ss[q], precision, degen_rtol, sv_floor, int(not warm_start))
+        o = (CompressOpts * n)(*[CompressOpts(Ds[q], Ss[q], precision, degen_rtol, sv_floor, int(not warm_start),
+                                              int(not qr_start))
                                for q in range(n)])
         infos = (CompressInfo * n)()
         bufs = []
@@ -297,6 +301,13 @@ class Context:
     def dsvd_left(self, length, p, Y, sigma, k=0, U=None):
         _check(self, _lib.xtrg_dsvd_left(self.h, length, p, C.c_void_p(Y), C.c_void_p(sigma), k,
                                          C.c_void_p(U) if U else None))
+
+    def dqrcp(self, length, p, Y, stop_rel, piv, RT):
+        """Column-pivoted QR (triangular factor) of the device matrix Y; returns keff."""
+        k = C.c_int()
+        _check(self, _lib.xtrg_dqrcp(self.h, length, p, C.c_void_p(Y), stop_rel, C.c_void_p(piv),
+                                     C.c_void_p(RT), C.byref(k)))
+        return k.value
 
 
 def run(ctx: Context, n_sites: int, bonds, jxy, jz, tau0: float, n_doublings: int, D: int, order: int = 1,

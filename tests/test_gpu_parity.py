@@ -155,6 +155,146 @@ def test_svd_rank_deficient(ctx):
     assert np.all(s[21:] < noise)
 
 
+# ---------------------------------------------------------------- column-pivoted QR (SVD start)
+
+def _qrcp_host(Y, stop_rel):
+    """Householder QR with column pivoting, textbook form (largest remaining
+    column norm below the current row, recomputed every step), columns kept
+    in place; returns (pivots, R in the input's column order)."""
+    A = np.array(Y, dtype=np.float64)
+    n, p = A.shape
+    stop2 = stop_rel ** 2 * float(np.sum(A * A))
+    piv, rows, act = [], [], np.ones(p, bool)
+    for i in range(min(n, p)):
+        n2 = np.where(act, np.sum(A[i:, :] ** 2, axis=0), -1.0)
+        c = int(np.argmax(n2))
+        if not n2[c] > stop2:
+            break
+        x = A[i:, c].copy()
+        beta = -math.copysign(math.sqrt(float(x @ x)), x[0])
+        v = x / (x[0] - beta)
+        v[0] = 1.0
+        tau = (beta - x[0]) / beta
+        act[c] = False
+        A[i:, act] -= tau * np.outer(v, v @ A[i:, act])
+        row = np.where(act, A[i, :], 0.0)
+        row[c] = beta
+        piv.append(c)
+        rows.append(row)
+    k = len(piv)
+    R = np.zeros((k, p))
+    for i in range(k):
+        R[i] = rows[i]
+        R[i, piv[:i]] = 0.0
+    return piv, R
+
+
+def _dqrcp(ctx, Y, stop_rel):
+    import torch
+    n, p = Y.shape
+    kmax = max(1, min(n, p))
+    dY = _dev(Y.T.copy())
+    piv = torch.full((kmax,), -1, dtype=torch.int32, device="cuda")
+    RT = torch.full((kmax * max(p, 1),), float("nan"), dtype=torch.float64, device="cuda")
+    k = ctx.dqrcp(n, p, dY.data_ptr(), stop_rel, piv.data_ptr(), RT.data_ptr())
+    torch.cuda.synchronize()
+    R = RT.cpu().numpy()[: k * p].reshape(k, p)
+    return k, piv.cpu().numpy()[:k], R
+
+
+@pytest.mark.parametrize("n,p", [(300, 200), (150, 260), (1, 7), (9, 1), (64, 64), (1000, 1030), (2048, 96)])
+def test_dqrcp_matches_pivoted_householder(ctx, n, p):
+    """Pivots and R of the GPU factorisation against the textbook one, on
+    Gaussian matrices (distinct column norms at every step); R^T R = Y^T Y,
+    R[:, piv] upper triangular with |diagonal| non-increasing; scipy's
+    pivoted QR gives the same |diagonal|."""
+    import scipy.linalg as sl
+    rng = np.random.default_rng(n * 31 + p)
+    Y = rng.standard_normal((n, p)) * rng.uniform(0.5, 2.0, p)
+    k, piv, R = _dqrcp(ctx, Y, 0.0)
+    assert k == min(n, p)
+    pw, Rw = _qrcp_host(Y, 0.0)
+    assert list(piv) == pw
+    scale = np.linalg.norm(Y)
+    assert np.abs(R - Rw).max() <= 1e-13 * scale * math.sqrt(n)
+    Rp = R[:, piv]
+    assert np.all(np.tril(Rp[:, :k], -1) == 0.0)
+    d = np.abs(np.diag(Rp[:, :k]))
+    assert np.all(d[1:] <= d[:-1] * (1 + 1e-12))
+    assert np.abs(R.T @ R - Y.T @ Y).max() <= 1e-13 * scale ** 2
+    _, Rs, _ = sl.qr(Y, mode="economic", pivoting=True)
+    assert np.abs(d - np.abs(np.diag(Rs))[:k]).max() <= 1e-12 * d[0]
+
+
+def test_dqrcp_stops_at_threshold_on_graded_matrix(ctx):
+    """A 1024 x 1024 matrix with singular values over 16 decades: the
+    factorisation stops where the textbook one does, at the first step whose
+    remaining columns all have norm^2 <= stop^2 ||Y||_F^2; R is the same."""
+    rng = np.random.default_rng(77)
+    n = 1024
+    U0, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    V0, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    Y = (U0 * 10.0 ** -np.linspace(0, 16, n)) @ V0.T
+    stop = 1e-7
+    k, piv, R = _dqrcp(ctx, Y, stop)
+    pw, Rw = _qrcp_host(Y, stop)
+    assert 0 < k < n and k == len(pw)
+    assert list(piv) == pw
+    assert np.abs(R - Rw).max() <= 1e-13 * np.linalg.norm(Y) * math.sqrt(n)
+
+
+def test_dqrcp_degenerate_inputs(ctx):
+    """All-zero input: no step.  A zero column is never pivoted while a
+    nonzero one remains; exact rank r stops after r steps at stop 0 only if
+    the rest is exactly zero, else at the rounding level with a tiny stop."""
+    k, piv, R = _dqrcp(ctx, np.zeros((40, 30)), 0.0)
+    assert k == 0
+    rng = np.random.default_rng(3)
+    Y = rng.standard_normal((40, 30))
+    Y[:, 7] = 0.0
+    k, piv, R = _dqrcp(ctx, Y, 0.0)
+    assert k == 29 and 7 not in list(piv)
+    assert np.all(R[:, 7] == 0.0)
+    Y = rng.standard_normal((60, 12)) @ rng.standard_normal((12, 50))
+    k, piv, R = _dqrcp(ctx, Y, 1e-12)
+    assert k == 12
+
+
+def test_dqrcp_rejects_out_of_range(ctx):
+    from paper_1801_00142_amd import XtrgError
+    import torch
+    buf = torch.zeros(8, dtype=torch.float64, device="cuda")
+    ip = torch.zeros(8, dtype=torch.int32, device="cuda")
+    for n, p, stop in [(2049, 4, 0.0), (4, 4097, 0.0), (4, 4, -1.0), (-1, 4, 0.0)]:
+        with pytest.raises(XtrgError):
+            ctx.dqrcp(n, p, buf.data_ptr(), stop, ip.data_ptr(), buf.data_ptr())
+
+
+def test_qr_start_same_result_fewer_rounds(ctx):
+    """Chain L=10 at D=128 (first-visit SVDs of 512 x 512): the QR start
+    changes neither the bonds nor the MPO beyond rounding, and is used."""
+    lat = W.chain(10)
+    H = ctx.hamiltonian_xxz(lat.n_sites, lat.bonds, lat.jxy, lat.jz)
+    rho, lam = ctx.init_rho(H, 2.0 ** -6, 1)
+    for _ in range(6):
+        rho, _i = ctx.square_compress(rho, 128, 2)
+    res = {}
+    for qr in (False, True):
+        ctx.profile(True)
+        ctx.profile_report()                 # counters start from zero
+        out, info = ctx.square_compress(rho, 128, 2, sv_stride=128, qr_start=qr)
+        rep = ctx.profile_report()
+        ctx.profile(False)
+        res[qr] = (out, info, rep)
+    a, b = res[False], res[True]
+    assert b[2]["qr_used"] > 0 and a[2]["qr_calls"] == 0
+    assert a[0].bond_dims == b[0].bond_dims
+    assert abs(a[1]["dlog_norm"] - b[1]["dlog_norm"]) < 1e-11
+    assert np.abs(a[1]["sv"] - b[1]["sv"]).max() <= 1e-11 * np.abs(a[1]["sv"]).max()
+    ta, tb = M.to_dense(a[0].to_host()), M.to_dense(b[0].to_host())
+    assert np.linalg.norm(ta - tb) <= 1e-9 * np.linalg.norm(ta)
+
+
 # ---------------------------------------------------------------- Hamiltonian, start
 
 @pytest.mark.parametrize("lat", [W.chain(6), W.random_couplings(W.chain(7), 3), W.square_cylinder(3, 3),
