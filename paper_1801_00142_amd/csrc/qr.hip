@@ -19,8 +19,10 @@
 //
 // One launch per step, one wave per column.  Every workgroup forms the
 // reflector itself from the pivot column (the same arithmetic in every
-// workgroup, so all agree); the next pivot is the maximum of the packed
-// (norm^2, column) keys that the waves post with one atomic each.
+// workgroup, so all agree).  The next pivot is the largest packed
+// (norm^2, column) key: each workgroup writes the largest of its waves'
+// keys to its own slot, and every workgroup of the next step reduces the
+// slots itself (no atomics on one address, which would serialise).
 #include "internal.h"
 
 #include <algorithm>
@@ -38,7 +40,7 @@ constexpr int kChunk = 64;                    // steps launched between checks f
 
 struct QrDesc {
   double* A;                                  // len x p column-major, overwritten
-  unsigned long long* best;                   // kmax + 1 pivot keys (zeroed)
+  unsigned long long* keys;                   // 2 x nslot: workgroup keys, by step parity
   int* piv;                                   // kmax: pivot column of each step
   int* stepof;                                // p: step at which a column was pivoted (INT_MAX: never)
   double* rdiag;                              // kmax: diagonal of R (beta of each step)
@@ -46,6 +48,7 @@ struct QrDesc {
   const double* fro2;                         // ||Y||_F^2
   double stop_rel2;
   int len, p, kmax;
+  int nslot;                                  // workgroups with columns: ceil(p / 4)
 };
 
 // Pivot key: the bit pattern of a non-negative double is monotone under
@@ -64,38 +67,74 @@ __device__ inline double qr_wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
+__device__ inline unsigned long long qr_wave_max(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long w = __shfl_xor(v, o, 64);
+    v = w > v ? w : v;
+  }
+  return v;
+}
 
-// Column norms of Y: the first pivot; marks every column not pivoted.
+// Largest of the waves' keys (lane 0 of each holds its wave's key) into
+// the workgroup's slot of the given step parity.  All threads call it.
+__device__ inline void qr_post(const QrDesc& d, int parity, unsigned long long key, unsigned long long* red) {
+  const int t = threadIdx.x;
+  if ((t & 63) == 0) red[t >> 6] = key;
+  __syncthreads();
+  if (t == 0 && (int)blockIdx.x < d.nslot) {
+    unsigned long long m = red[0];
+    for (int w = 1; w < kQT / 64; ++w) m = red[w] > m ? red[w] : m;
+    d.keys[(size_t)parity * d.nslot + blockIdx.x] = m;
+  }
+}
+
+// Largest key of all workgroups of the previous step (every thread gets it).
+__device__ inline unsigned long long qr_pivot_key(const QrDesc& d, int parity, unsigned long long* red) {
+  const int t = threadIdx.x;
+  unsigned long long m = 0;
+  for (int q = t; q < d.nslot; q += kQT) {
+    const unsigned long long k = d.keys[(size_t)parity * d.nslot + q];
+    m = k > m ? k : m;
+  }
+  m = qr_wave_max(m);
+  if ((t & 63) == 0) red[t >> 6] = m;
+  __syncthreads();
+  m = red[0];
+  for (int w = 1; w < kQT / 64; ++w) m = red[w] > m ? red[w] : m;
+  return m;
+}
+
+// Column norms of Y: the keys of the first pivot; marks every column not
+// pivoted.
 __global__ __launch_bounds__(kQT) void qr_init(const QrDesc* __restrict__ descs) {
   const QrDesc d = descs[blockIdx.y];
+  if (d.kmax <= 0 || (int)blockIdx.x >= d.nslot) return;   // (a workgroup past nslot has no column)
+  __shared__ unsigned long long red[kQT / 64];
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int gt = blockIdx.x * kQT + t;
   if (gt < d.p) d.stepof[gt] = INT_MAX;
   const int c = blockIdx.x * (kQT / 64) + wave;
-  if (c >= d.p || d.kmax <= 0) return;
-  const double* __restrict__ y = d.A + (size_t)c * d.len;
   double ss = 0.0;
-  for (int r = lane; r < d.len; r += 64) ss = fma(y[r], y[r], ss);
+  if (c < d.p) {
+    const double* __restrict__ y = d.A + (size_t)c * d.len;
+    for (int r = lane; r < d.len; r += 64) ss = fma(y[r], y[r], ss);
+  }
   ss = qr_wave_sum(ss);
-  if (lane == 0) atomicMax(d.best, qr_key(ss, c));
+  qr_post(d, 0, c < d.p ? qr_key(ss, c) : 0ull, red);
 }
 
 // Step i.  R: rows per lane (len - i <= 64 R).
 template <int R>
 __global__ __launch_bounds__(kQT) void qr_step(const QrDesc* __restrict__ descs, int i) {
   const QrDesc d = descs[blockIdx.y];
-  if (i >= d.kmax) return;
-  const unsigned long long key = d.best[i];
-  if (!(qr_key_norm2(key) > d.stop_rel2 * d.fro2[0])) {     // every remaining column is numerically zero
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicMin(d.keff, i);
-    return;
-  }
-  const int ci = (int)(key & kIdxMask);
+  if (i >= d.kmax || (int)blockIdx.x >= d.nslot) return;
   const int m = d.len - i;                    // rows i .. len-1
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int c = blockIdx.x * (kQT / 64) + wave;
-  // this wave's column (not the pivot, not pivoted before): loads issued first
-  const bool mine = c < d.p && c != ci && d.stepof[c] > i;
+  // this wave's column if not pivoted before: its loads are issued first,
+  // the pivot (which it may turn out to be) is known after the reduction
+  bool mine = c < d.p && d.stepof[c] > i;
   double* __restrict__ yc = d.A + (size_t)(mine ? c : 0) * d.len + i;
   double y[R];
 #pragma unroll
@@ -103,9 +142,20 @@ __global__ __launch_bounds__(kQT) void qr_step(const QrDesc* __restrict__ descs,
     const int r = lane + 64 * u;
     y[u] = (mine && r < m) ? yc[r] : 0.0;
   }
+  __shared__ unsigned long long red[kQT / 64];
+  const unsigned long long key = qr_pivot_key(d, i & 1, red);
+  if (!(qr_key_norm2(key) > d.stop_rel2 * d.fro2[0])) {     // every remaining column is numerically zero
+    if (t == 0) {
+      d.keys[(size_t)((i + 1) & 1) * d.nslot + blockIdx.x] = 0;   // so that every later step stops too
+      if (blockIdx.x == 0) atomicMin(d.keff, i);
+    }
+    return;
+  }
+  const int ci = (int)(key & kIdxMask);
+  mine = mine && c != ci;
   // the reflector, from the pivot column (read only in this step)
   __shared__ double v[64 * R];
-  __shared__ double red[kQT / 64];
+  __shared__ double rsum[kQT / 64];
   const double* __restrict__ xc = d.A + (size_t)ci * d.len + i;
   double ss = 0.0;
   for (int r = t; r < m; r += kQT) {
@@ -114,9 +164,9 @@ __global__ __launch_bounds__(kQT) void qr_step(const QrDesc* __restrict__ descs,
     ss = fma(x, x, ss);
   }
   ss = qr_wave_sum(ss);
-  if (lane == 0) red[wave] = ss;
+  if (lane == 0) rsum[wave] = ss;
   __syncthreads();
-  const double sig2 = (red[0] + red[1]) + (red[2] + red[3]);
+  const double sig2 = (rsum[0] + rsum[1]) + (rsum[2] + rsum[3]);
   const double alpha = v[0];
   const double beta = -copysign(sqrt(sig2), alpha);   // |alpha - beta| = |alpha| + sigma > 0
   const double tau = (beta - alpha) / beta;
@@ -129,27 +179,30 @@ __global__ __launch_bounds__(kQT) void qr_step(const QrDesc* __restrict__ descs,
     d.rdiag[i] = beta;
     d.stepof[ci] = i;
   }
-  if (!mine) return;
   // y <- (I - tau v v^T) y; norm^2 of rows i+1.. for the next pivot
-  double s = 0.0;
+  unsigned long long mykey = 0;
+  if (mine) {
+    double s = 0.0;
 #pragma unroll
-  for (int u = 0; u < R; ++u) {
-    const int r = lane + 64 * u;
-    if (r < m) s = fma(v[r], y[u], s);
-  }
-  s = qr_wave_sum(s) * tau;
-  double n2 = 0.0;
-#pragma unroll
-  for (int u = 0; u < R; ++u) {
-    const int r = lane + 64 * u;
-    if (r < m) {
-      const double z = fma(-s, v[r], y[u]);
-      yc[r] = z;
-      if (r > 0) n2 = fma(z, z, n2);
+    for (int u = 0; u < R; ++u) {
+      const int r = lane + 64 * u;
+      if (r < m) s = fma(v[r], y[u], s);
     }
+    s = qr_wave_sum(s) * tau;
+    double n2 = 0.0;
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int r = lane + 64 * u;
+      if (r < m) {
+        const double z = fma(-s, v[r], y[u]);
+        yc[r] = z;
+        if (r > 0) n2 = fma(z, z, n2);
+      }
+    }
+    n2 = qr_wave_sum(n2);
+    mykey = qr_key(n2, c);
   }
-  n2 = qr_wave_sum(n2);
-  if (lane == 0) atomicMax(d.best + i + 1, qr_key(n2, c));
+  qr_post(d, (i + 1) & 1, mykey, red);
 }
 
 // R^T (p x keff, column-major, leading dimension p): entry (c, r) is R's
@@ -179,13 +232,14 @@ __global__ __launch_bounds__(256) void qr_rt(const double* __restrict__ A, int l
 }
 
 // Workspace layout (doubles): A (len p), fro2 (1), sumsq scratch (1024),
-// rdiag (kmax), best (kmax + 1), piv (kmax ints), stepof (p ints).
+// rdiag (kmax), keys (2 nslot), piv (kmax ints), stepof (p ints).
+int qr_nslot(int p) { return (p + kQT / 64 - 1) / (kQT / 64); }
 struct QrLayout {
   double* A;
   double* fro2;
   double* part;
   double* rdiag;
-  unsigned long long* best;
+  unsigned long long* keys;
   int* piv;
   int* stepof;
 };
@@ -196,8 +250,8 @@ QrLayout qr_layout(double* w, int len, int p) {
   L.fro2 = w + (size_t)len * p;
   L.part = L.fro2 + 1;
   L.rdiag = L.part + 1024;
-  L.best = reinterpret_cast<unsigned long long*>(L.rdiag + kmax);
-  L.piv = reinterpret_cast<int*>(L.best + kmax + 1);
+  L.keys = reinterpret_cast<unsigned long long*>(L.rdiag + kmax);
+  L.piv = reinterpret_cast<int*>(L.keys + 2 * (size_t)qr_nslot(p));
   L.stepof = L.piv + kmax;
   return L;
 }
@@ -206,7 +260,7 @@ QrLayout qr_layout(double* w, int len, int p) {
 
 size_t qr_work(int len, int p) {
   const size_t kmax = (size_t)std::min(len, p);
-  return (size_t)len * p + 1 + 1024 + kmax + (kmax + 1) + (kmax + 1) / 2 + ((size_t)p + 1) / 2 + 2;
+  return (size_t)len * p + 1 + 1024 + kmax + 2 * (size_t)qr_nslot(p) + (kmax + 1) / 2 + ((size_t)p + 1) / 2 + 2;
 }
 
 size_t qr_desc_bytes(int n) { return (sizeof(QrDesc) + sizeof(int)) * (size_t)n + 256; }
@@ -227,10 +281,10 @@ void qrcp_batched(std::vector<QrJob>& jobs, void* desc_dev, hipStream_t s) {
     kmax[j] = std::min(J.len, J.p);
     J.keff = 0;
     QrLayout L = qr_layout(J.work, J.len, J.p);
-    h[j] = QrDesc{L.A, L.best, L.piv, L.stepof, L.rdiag, d_keff + j, L.fro2, J.stop_rel * J.stop_rel, J.len, J.p, kmax[j]};
+    h[j] = QrDesc{L.A,   L.keys,  L.piv,  L.stepof,  L.rdiag, d_keff + j, L.fro2, J.stop_rel * J.stop_rel,
+                  J.len, J.p, kmax[j], qr_nslot(J.p)};
     if (kmax[j] == 0) continue;
     XTRG_HIP(hipMemcpyAsync(L.A, J.Y, sizeof(double) * J.len * J.p, hipMemcpyDeviceToDevice, s));
-    XTRG_HIP(hipMemsetAsync(L.best, 0, sizeof(unsigned long long) * (kmax[j] + 1), s));
     sumsq(L.A, (size_t)J.len * J.p, L.fro2, L.part, s);
     kmax_all = std::max(kmax_all, kmax[j]);
     pmax = std::max(pmax, J.p);

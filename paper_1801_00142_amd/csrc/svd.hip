@@ -127,20 +127,26 @@ __device__ inline bool needs_rot(double a, double b, double g, double tol2, doub
 }
 
 // Rotation (c, s) that zeroes the off-diagonal of [[a, g], [g, b]] under
-// columns x' = c x - s y, y' = s x + c y (the smaller of the two angles:
-// t = tan = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (b - a) / 2g);
-// identity if the pair needs none.
-// Branch-free (the value is selected at the end), so that two rotations in
-// one thread interleave their dependent chains.
+// columns x' = c x - s y, y' = s x + c y (the smaller of the two angles,
+// tan = sign(d) h / (|d| + r) with d = b - a, h = 2g, r = |(d, h)|), in the
+// form c = sqrt(u / 2r), s = sign(d) h / sqrt(2 r u), u = |d| + r, which
+// needs one square root and one reciprocal square root in sequence (no
+// cancellation: u >= r); d and h are first scaled by a power of two so that
+// the squares cannot overflow or underflow.  c^2 + s^2 = 1 to a few ulp.
+// Identity if the pair needs none.  Branch-free (the value is selected at
+// the end), so that two rotations in one thread interleave their chains.
 __device__ inline void jacobi_rot(double a, double b, double g, double tol2, double zth, double* c, double* s) {
   const bool need = needs_rot(a, b, g, tol2, zth);
-  const double gg = need ? g : 1.0;
-  const double zeta = (b - a) * rcp_refined(2.0 * gg);
-  const double w = fma(zeta, zeta, 1.0);
-  const double tt = copysign(1.0, zeta) * rcp_refined(fabs(zeta) + w * rsq_refined(w));
-  const double cc = rsq_refined(fma(tt, tt, 1.0));
-  *c = need ? cc : 1.0;
-  *s = need ? cc * tt : 0.0;
+  const double d0 = b - a, h0 = need ? 2.0 * g : 1.0;
+  int e;
+  (void)frexp(fmax(fabs(d0), fabs(h0)), &e);
+  const double d = ldexp(d0, -e), h = ldexp(h0, -e);     // max(|d|, |h|) in [1/2, 1)
+  const double x = fma(d, d, h * h);
+  const double r = x * rsq_refined(x);
+  const double u = fabs(d) + r;
+  const double q = rsq_refined(2.0 * r * u);
+  *c = need ? u * q : 1.0;
+  *s = need ? copysign(1.0, d) * h * q : 0.0;
 }
 
 template <int MODE>
@@ -300,6 +306,24 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   if (t == 0 && sl == 0 && worst > 0.0) atomicMax(d.off, (unsigned long long)__double_as_longlong(worst));
   if (worst == 0.0) return;          // uniform: every thread read the same wmax
 
+  // The first tiles that step 4 rotates are loaded now: their latency
+  // passes during the small Jacobi sweep (no other workgroup writes them).
+  constexpr int T = 4;                         // 16-row tiles in flight per wave
+  const int lr = lane & 15, lk = lane >> 4;
+  int cin[kNC / 4];
+#pragma unroll
+  for (int kk = 0; kk < kNC / 4; ++kk) cin[kk] = colid[kk * 4 + lk];
+  double zb[T][kNC / 4];
+  {
+    const int e0 = ra + wave * 16;
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+      const int e = e0 + u * kWW * 16 + lr;
+#pragma unroll
+      for (int kk = 0; kk < kNC / 4; ++kk) zb[u][kk] = (cin[kk] >= 0 && e < rb) ? Y[(long)cin[kk] * len + e] : 0.0;
+    }
+  }
+
   // 3. One sweep of parallel two-sided Jacobi on G; W <- W J per rotation.
   // The 16 rotations of a round are computed once (one thread per pair) and
   // read by all; the threads that compute them work one round ahead: from
@@ -390,29 +414,25 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   // tiles of Z (the B operand, 16 consecutive rows of a column per 16 lanes)
   // and writes the rotated rows back in place (no other wave touches them).
   {
-    const int lr = lane & 15, lk = lane >> 4;
     double wa[2][kNC / 4];
 #pragma unroll
     for (int I = 0; I < 2; ++I)
 #pragma unroll
       for (int kk = 0; kk < kNC / 4; ++kk) wa[I][kk] = Wt[I * 16 + lr][kk * 4 + lk];
-    int cin[kNC / 4];
-#pragma unroll
-    for (int kk = 0; kk < kNC / 4; ++kk) cin[kk] = colid[kk * 4 + lk];
     int cout[2][4];
 #pragma unroll
     for (int I = 0; I < 2; ++I)
 #pragma unroll
       for (int q = 0; q < 4; ++q) cout[I][q] = colid[I * 16 + lk + 4 * q];
-    constexpr int T = 4;                       // 16-row tiles in flight per wave
     for (int e0 = ra + wave * 16; e0 < rb; e0 += kWW * 16 * T) {
-      double zb[T][kNC / 4];
+      if (e0 != ra + wave * 16) {              // later tiles (the first are loaded)
 #pragma unroll
-      for (int u = 0; u < T; ++u) {
-        const int e = e0 + u * kWW * 16 + lr;
+        for (int u = 0; u < T; ++u) {
+          const int e = e0 + u * kWW * 16 + lr;
 #pragma unroll
-        for (int kk = 0; kk < kNC / 4; ++kk)
-          zb[u][kk] = (cin[kk] >= 0 && e < rb) ? Y[(long)cin[kk] * len + e] : 0.0;
+          for (int kk = 0; kk < kNC / 4; ++kk)
+            zb[u][kk] = (cin[kk] >= 0 && e < rb) ? Y[(long)cin[kk] * len + e] : 0.0;
+        }
       }
 #pragma unroll
       for (int u = 0; u < T; ++u) {
