@@ -70,6 +70,7 @@ __host__ __device__ inline void rr_pair(int n, int r, int q, int* i, int* j) {
 //     (Z <- Z W).
 constexpr int kWT = 576;                  // threads of a round workgroup: 8 update waves + 1 rotation wave
 constexpr int kWW = kWT / 64;             // its waves
+constexpr int kUW = 8;                    // update waves: Gram, G and W updates, rotation of Z
 constexpr int kBlk = 16;                  // columns per block
 constexpr int kNC = 2 * kBlk;             // columns per block pair
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -163,7 +164,7 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   const int len = d.len, p = d.p, nbk = d.nbk;
   const double tol = d.tol;
   __shared__ int colid[kNC];
-  __shared__ double buf[kWW * 3 * 4 * 64];   // wave partials of the Gram tiles
+  __shared__ double buf[kUW * 3 * 4 * 64];   // wave partials of the Gram tiles
   __shared__ double gsum[kGramVals];          // fused round: running sum over the slices
   __shared__ double G[2][kNC][kNC + 1];
   __shared__ double Wt[kNC][kNC + 2];         // W transposed: Wt[c][j] = W[j][c]
@@ -182,9 +183,12 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   // 1. Gram tiles (0,0), (0,1), (1,1) of the pair on the matrix cores,
   // operands straight from memory: per MFMA step a wave takes 4 rows, lane l
   // row l/16 of column l%16 of each block (4 consecutive rows of a column
-  // per 4 lanes, 32-byte sectors fully used).  Waves interleave 4-row groups.
-  // Partial Gram of rows [a, b): per-wave tiles left in buf.
+  // per 4 lanes, 32-byte sectors fully used).  The update waves interleave
+  // 4-row groups (two waves per SIMD, equal shares); a group past the end
+  // issues no matrix-core work (an FP64 16x16x4 product occupies a SIMD for
+  // 64 cycles).  Partial Gram of rows [a, b): per-wave tiles left in buf.
   auto gram_rows = [&](int a, int b) {
+    if (wave >= kUW) return;
     d4 acc[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
@@ -193,16 +197,17 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
     const double* __restrict__ y0 = Y + (long)(c0 >= 0 ? c0 : 0) * len;
     const double* __restrict__ y1 = Y + (long)(c1 >= 0 ? c1 : 0) * len;
     constexpr int U = 16;                      // row groups in flight per wave
-    for (int g0 = a + wave * 4; g0 < b; g0 += kWW * 4 * U) {
+    for (int g0 = a + wave * 4; g0 < b; g0 += kUW * 4 * U) {
       double a0[U], a1[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int e = g0 + u * kWW * 4 + lk;
+        const int e = g0 + u * kUW * 4 + lk;
         a0[u] = (c0 >= 0 && e < b) ? y0[e] : 0.0;
         a1[u] = (c1 >= 0 && e < b) ? y1[e] : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
+        if (g0 + u * kUW * 4 >= b) break;      // uniform over the wave
         acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], a0[u], acc[0], 0, 0, 0);
         acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], a1[u], acc[1], 0, 0, 0);
         acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], a1[u], acc[2], 0, 0, 0);
@@ -218,7 +223,7 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
     const int tt = idx >> 8, q = (idx >> 6) & 3, l = idx & 63;
     double v = 0.0;
 #pragma unroll
-    for (int w = 0; w < kWW; ++w) v += buf[((w * 3 + tt) * 4 + q) * 64 + l];
+    for (int w = 0; w < kUW; ++w) v += buf[((w * 3 + tt) * 4 + q) * 64 + l];
     return v;
   };
 
@@ -308,17 +313,17 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
 
   // The first tiles that step 4 rotates are loaded now: their latency
   // passes during the small Jacobi sweep (no other workgroup writes them).
-  constexpr int T = 4;                         // 16-row tiles in flight per wave
+  constexpr int T = 2;                         // 16-row tiles in flight per update wave
   const int lr = lane & 15, lk = lane >> 4;
   int cin[kNC / 4];
 #pragma unroll
   for (int kk = 0; kk < kNC / 4; ++kk) cin[kk] = colid[kk * 4 + lk];
   double zb[T][kNC / 4];
-  {
+  if (wave < kUW) {
     const int e0 = ra + wave * 16;
 #pragma unroll
     for (int u = 0; u < T; ++u) {
-      const int e = e0 + u * kWW * 16 + lr;
+      const int e = e0 + u * kUW * 16 + lr;
 #pragma unroll
       for (int kk = 0; kk < kNC / 4; ++kk) zb[u][kk] = (cin[kk] >= 0 && e < rb) ? Y[(long)cin[kk] * len + e] : 0.0;
     }
@@ -410,10 +415,11 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   }
 
   // 4. Z <- Z W on this pair's columns, as (Z W)^T = W^T Z^T on the matrix
-  // cores: W^T (the A operand) stays in registers, each wave takes 16-row
-  // tiles of Z (the B operand, 16 consecutive rows of a column per 16 lanes)
-  // and writes the rotated rows back in place (no other wave touches them).
-  {
+  // cores: W^T (the A operand) stays in registers, each update wave takes
+  // 16-row tiles of Z (the B operand, 16 consecutive rows of a column per 16
+  // lanes; tile k to wave k mod 8, no products for tiles past the end) and
+  // writes the rotated rows back in place (no other wave touches them).
+  if (wave < kUW) {
     double wa[2][kNC / 4];
 #pragma unroll
     for (int I = 0; I < 2; ++I)
@@ -424,11 +430,11 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
     for (int I = 0; I < 2; ++I)
 #pragma unroll
       for (int q = 0; q < 4; ++q) cout[I][q] = colid[I * 16 + lk + 4 * q];
-    for (int e0 = ra + wave * 16; e0 < rb; e0 += kWW * 16 * T) {
+    for (int e0 = ra + wave * 16; e0 < rb; e0 += kUW * 16 * T) {
       if (e0 != ra + wave * 16) {              // later tiles (the first are loaded)
 #pragma unroll
         for (int u = 0; u < T; ++u) {
-          const int e = e0 + u * kWW * 16 + lr;
+          const int e = e0 + u * kUW * 16 + lr;
 #pragma unroll
           for (int kk = 0; kk < kNC / 4; ++kk)
             zb[u][kk] = (cin[kk] >= 0 && e < rb) ? Y[(long)cin[kk] * len + e] : 0.0;
@@ -436,7 +442,8 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
       }
 #pragma unroll
       for (int u = 0; u < T; ++u) {
-        const int e = e0 + u * kWW * 16 + lr;
+        if (e0 + u * kUW * 16 >= rb) break;    // uniform over the wave
+        const int e = e0 + u * kUW * 16 + lr;
         d4 o[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
 #pragma unroll
         for (int kk = 0; kk < kNC / 4; ++kk) {
