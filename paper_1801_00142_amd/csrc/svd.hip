@@ -163,6 +163,25 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   double* __restrict__ Y = d.Z;
   const int len = d.len, p = d.p, nbk = d.nbk;
   const double tol = d.tol;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  // loads whose latency overlaps the column lookup: ||Y||_F^2 for the zero
+  // threshold and, in a rotate launch, this thread's Gram values (the
+  // slices' partials summed in slice order)
+  const double fro2v = MODE == ROUND_GRAM ? 0.0 : d.fro2[0];
+  double pv[2] = {0.0, 0.0};
+  if (MODE == ROUND_ROTATE) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int idx = t + k * kWT;
+      if (idx < kGramVals) {
+        double v = part[idx];
+#pragma unroll
+        for (int s2 = 1; s2 < kMaxSplit; ++s2)
+          if (s2 < split) v += part[s2 * kGramVals + idx];
+        pv[k] = v;
+      }
+    }
+  }
   __shared__ int colid[kNC];
   __shared__ double buf[kUW * 3 * 4 * 64];   // wave partials of the Gram tiles
   __shared__ double gsum[kGramVals];          // fused round: running sum over the slices
@@ -173,7 +192,6 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   __shared__ unsigned wmask[kWW];
   int bi, bj;
   rr_pair(nbk, r, pair, &bi, &bj);
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   if (t < kNC) {
     const int rank = (t < kBlk ? bi : bj) * kBlk + (t % kBlk);
     colid[t] = rank < p ? d.perm[rank] : -1;
@@ -250,15 +268,12 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
     }
   }
   for (int idx = t; idx < kNC * kNC; idx += kWT) Wt[idx / kNC][idx % kNC] = (idx / kNC == idx % kNC) ? 1.0 : 0.0;
-  for (int idx = t; idx < kGramVals; idx += kWT) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int idx = t + k * kWT;
+    if (idx >= kGramVals) break;
     const int tt = idx >> 8, q = (idx >> 6) & 3, l = idx & 63;
-    double v;
-    if (MODE == ROUND_ROTATE) {
-      v = part[idx];
-      for (int s2 = 1; s2 < split; ++s2) v += part[s2 * kGramVals + idx];
-    } else {
-      v = gsum[idx];
-    }
+    const double v = MODE == ROUND_ROTATE ? pv[k] : gsum[idx];
     const int i = (l >> 4) + 4 * q, j = l & 15;
     const int I = tt == 2 ? kBlk : 0, J = tt == 0 ? 0 : kBlk;
     if (tt == 1) {
@@ -272,7 +287,7 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   __syncthreads();
 
   // 2. Convergence measure.
-  const double zth = d.zrel2 * d.fro2[0];
+  const double zth = d.zrel2 * fro2v;
   const double tol2 = tol * tol;
   double off = 0.0;
   unsigned mask = 0;                 // bit r: some pair (k, k ^ r) needs a rotation
