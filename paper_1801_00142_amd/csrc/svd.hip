@@ -106,17 +106,14 @@ constexpr int kMaxSplit = 4;
 constexpr int kMaxPairs = 128;            // p <= 4096 columns in blocks of 16
 constexpr int kGramVals = 3 * 256;        // three 16 x 16 tiles
 
-// 1/x and 1/sqrt(x) from the hardware estimates refined by two Newton
-// steps (each squares the relative error), to about one unit in the last place.
-__device__ inline double rcp_refined(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
-  return fma(r, fma(-x, r, 1.0), r);
-}
+// 1/sqrt(x) from the hardware estimate (relative error ~5e-8) refined by
+// one third-order step: with r = 1 - x y^2, x^(-1/2) = y (1 - r)^(-1/2)
+// = y (1 + r/2 + 3r^2/8 + O(r^3)); the truncation is ~1e-22, the result is
+// within a few ulp (r is formed by one fused multiply-add).
 __device__ inline double rsq_refined(double x) {
-  double r = __builtin_amdgcn_rsq(x);
-  r = fma(0.5 * r, fma(-x * r, r, 1.0), r);
-  return fma(0.5 * r, fma(-x * r, r, 1.0), r);
+  const double y = __builtin_amdgcn_rsq(x);
+  const double r = fma(-x * y, y, 1.0);
+  return fma(y * r, fma(0.375, r, 0.5), y);
 }
 
 // Whether the pair with Gram entries [[a, g], [g, b]] needs a rotation:
@@ -148,6 +145,14 @@ __device__ inline void jacobi_rot(double a, double b, double g, double tol2, dou
   const double q = rsq_refined(2.0 * r * u);
   *c = need ? u * q : 1.0;
   *s = need ? copysign(1.0, d) * h * q : 0.0;
+}
+
+// Members of pair qq in XOR round rr (rr = 1 .. kNC-1, qq = 0 .. kNC/2-1):
+// x = qq with a zero bit inserted at the highest set bit h of rr, y = x ^ rr.
+// The kNC - 1 rounds of kNC/2 disjoint pairs each cover every pair once.
+__device__ inline int xor_pair_x(int rr, int qq) {
+  const int h = 31 - __clz(rr);
+  return ((qq >> h) << (h + 1)) | (qq & ((1 << h) - 1));
 }
 
 template <int MODE>
@@ -187,7 +192,7 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   __shared__ double gsum[kGramVals];          // fused round: running sum over the slices
   __shared__ double G[2][kNC][kNC + 1];
   __shared__ double Wt[kNC][kNC + 2];         // W transposed: Wt[c][j] = W[j][c]
-  __shared__ double rotc[2][kNC / 2], rots[2][kNC / 2];   // rotations of a round (double-buffered)
+  __shared__ double2 rot[2][kNC / 2];          // (c, s) of each pair of a round (double-buffered)
   __shared__ double wmax[kWW];
   __shared__ unsigned wmask[kWW];
   int bi, bj;
@@ -289,19 +294,15 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   // 2. Convergence measure.
   const double zth = d.zrel2 * fro2v;
   const double tol2 = tol * tol;
-  double off = 0.0;
+  double off = 0.0;                  // largest squared cosine
   unsigned mask = 0;                 // bit r: some pair (k, k ^ r) needs a rotation
-  for (int idx = t; idx < kNC * (kNC - 1) / 2; idx += kWT) {
-    int x = 0, q = idx;
-    while (q >= kNC - 1 - x) {
-      q -= kNC - 1 - x;
-      ++x;
-    }
-    const int y = x + 1 + q;
+  for (int idx = t; idx < (kNC / 2) * (kNC - 1); idx += kWT) {   // pair qq of XOR round rr
+    const int rr = 1 + idx / (kNC / 2), qq = idx % (kNC / 2);
+    const int x = xor_pair_x(rr, qq), y = x ^ rr;
     const double a = G[0][x][x], b = G[0][y][y], g = G[0][x][y];
     if (needs_rot(a, b, g, tol2, zth)) {
-      off = fmax(off, fabs(g) / sqrt(a * b));
-      mask |= 1u << (x ^ y);
+      off = fmax(off, g * g / (a * b));
+      mask |= 1u << rr;
     }
   }
 #pragma unroll
@@ -321,6 +322,7 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
     worst = fmax(worst, wmax[w]);
     mask |= wmask[w];
   }
+  worst = sqrt(worst);
   // block maximum published as the bit pattern of a non-negative double
   // (monotone under unsigned comparison)
   if (t == 0 && sl == 0 && worst > 0.0) atomicMax(d.off, (unsigned long long)__double_as_longlong(worst));
@@ -350,23 +352,21 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   // G before round r and round r's rotations they form the three entries of
   // G after round r that fix their pair's rotation in the next round, so the
   // rotation chains overlap the updates and a round costs one barrier.
-  // Waves 0-7 update G and W (thread (q, k): entries k of pair q), lanes
-  // 0-15 of wave 8 compute the rotations.
+  // Waves 0-3 update G (thread (qc, lo): the 2 x 2 block of G on the rows
+  // of pair lo and the columns of pair qc), waves 4-7 update W (thread
+  // (qc, lo): rows lo and lo + 16 of W, columns of pair qc), lanes 0-15 of
+  // wave 8 compute the rotations.
   {
-    const bool upd = t < 16 * kNC;
-    const int q = (t >> 5) & 15, k = t & 31;
-    const int qr = t - 16 * kNC;              // rotation lane: pair index
+    const bool gupd = t < 256, wupd = t >= 256 && t < 512;
+    const int qc = (t >> 4) & 15, lo = t & 15;
+    const int qr = t - 512;                   // rotation lane: pair index
     auto next_round = [&](int r0) {
       for (int r2 = r0 + 1; r2 < kNC; ++r2)
         if ((mask >> r2) & 1u) return r2;
       return 0;
     };
-    // members of pair qq in round rr: x = qq with a zero bit inserted at the
-    // highest bit h of rr, y = x ^ rr; and back: pair index of a member
-    auto pair_x = [](int rr, int qq) {
-      const int h = 31 - __clz(rr);
-      return ((qq >> h) << (h + 1)) | (qq & ((1 << h) - 1));
-    };
+    auto pair_x = [](int rr, int qq) { return xor_pair_x(rr, qq); };
+    // pair index of member a in round rr
     auto pair_of = [](int rr, int a) {
       const int h = 31 - __clz(rr);
       const int am = min(a, a ^ rr);
@@ -375,52 +375,60 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
     int rc = next_round(0);
     if (qr >= 0 && qr < kNC / 2 && rc) {
       const int x = pair_x(rc, qr), y = x ^ rc;
-      jacobi_rot(G[0][x][x], G[0][y][y], G[0][x][y], tol2, zth, &rotc[0][qr], &rots[0][qr]);
+      double c, sn;
+      jacobi_rot(G[0][x][x], G[0][y][y], G[0][x][y], tol2, zth, &c, &sn);
+      rot[0][qr] = make_double2(c, sn);
     }
     __syncthreads();
     int src = 0, rb = 0;
     while (rc) {
       const int rn = next_round(rc);
-      if (upd) {
-        const int x = pair_x(rc, q), y = x ^ rc;
-        const int kb = k ^ rc;
-        const int kx = min(k, kb);
-        const int qk = pair_of(rc, k);
-        const double c = rotc[rb][q], sn = rots[rb][q];
-        const double c2 = rotc[rb][qk], s2 = rots[rb][qk];
+      if (gupd) {
+        const int x = pair_x(rc, qc), y = x ^ rc;     // columns
+        const int k = pair_x(rc, lo), kb = k ^ rc;    // rows, k < kb
+        const double2 cs = rot[rb][qc], cs2 = rot[rb][lo];
+        const double c = cs.x, sn = cs.y, c2 = cs2.x, s2 = cs2.y;
         const double gkx = G[src][k][x], gky = G[src][k][y];
         const double gbx = G[src][kb][x], gby = G[src][kb][y];
         const double hkx = c * gkx - sn * gky, hky = sn * gkx + c * gky;   // columns rotated
         const double hbx = c * gbx - sn * gby, hby = sn * gbx + c * gby;
-        if (k == kx) {                                                      // then rows
-          G[src ^ 1][k][x] = c2 * hkx - s2 * hbx;
-          G[src ^ 1][k][y] = c2 * hky - s2 * hby;
-        } else {
-          G[src ^ 1][k][x] = s2 * hbx + c2 * hkx;
-          G[src ^ 1][k][y] = s2 * hby + c2 * hky;
+        G[src ^ 1][k][x] = c2 * hkx - s2 * hbx;                              // then rows
+        G[src ^ 1][k][y] = c2 * hky - s2 * hby;
+        G[src ^ 1][kb][x] = s2 * hkx + c2 * hbx;
+        G[src ^ 1][kb][y] = s2 * hky + c2 * hby;
+      } else if (wupd) {
+        const int x = pair_x(rc, qc), y = x ^ rc;
+        const double2 cs = rot[rb][qc];
+        const double c = cs.x, sn = cs.y;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int k = lo + 16 * h;
+          const double wx = Wt[x][k], wy = Wt[y][k];
+          Wt[x][k] = c * wx - sn * wy;
+          Wt[y][k] = sn * wx + c * wy;
         }
-        const double wx = Wt[x][k], wy = Wt[y][k];
-        Wt[x][k] = c * wx - sn * wy;
-        Wt[y][k] = sn * wx + c * wy;
       } else if (qr < kNC / 2 && rn) {
         // entry (a, b) of G after round rc: sum over i in {a, a^rc}, j in
         // {b, b^rc} of J[i][a] G[i][j] J[j][b]; column a of J holds
         // (u, v) = (c, -s) on rows (a, a^rc) if a is the smaller member of
-        // its pair, (c, s) if it is the larger
-        auto coef = [&](int a2, double* u, double* v) {
-          const int qa = pair_of(rc, a2);
-          *u = rotc[rb][qa];
-          *v = (a2 < (a2 ^ rc)) ? -rots[rb][qa] : rots[rb][qa];
-        };
-        auto gnew = [&](int a2, int b2) {
-          double ua, va, ub, vb;
-          coef(a2, &ua, &va);
-          coef(b2, &ub, &vb);
-          const int ar = a2 ^ rc, br = b2 ^ rc;
-          return ua * (ub * G[src][a2][b2] + vb * G[src][a2][br]) + va * (ub * G[src][ar][b2] + vb * G[src][ar][br]);
-        };
+        // its pair, (c, s) if it is the larger.  Every LDS value is read
+        // first, in one batch (one LDS latency on the rotation chain).
         const int xn = pair_x(rn, qr), yn = xn ^ rn;
-        jacobi_rot(gnew(xn, xn), gnew(yn, yn), gnew(xn, yn), tol2, zth, &rotc[rb ^ 1][qr], &rots[rb ^ 1][qr]);
+        const int xr = xn ^ rc, yr = yn ^ rc;
+        const int qx = pair_of(rc, xn), qy = pair_of(rc, yn);
+        const double2 csx = rot[rb][qx], csy = rot[rb][qy];
+        const double cx = csx.x, sx = csx.y, cy = csy.x, sy = csy.y;
+        const double gxx = G[src][xn][xn], gxX = G[src][xn][xr], gXx = G[src][xr][xn], gXX = G[src][xr][xr];
+        const double gyy = G[src][yn][yn], gyY = G[src][yn][yr], gYy = G[src][yr][yn], gYY = G[src][yr][yr];
+        const double gxy = G[src][xn][yn], gxY = G[src][xn][yr], gXy = G[src][xr][yn], gXY = G[src][xr][yr];
+        const double ux = cx, vx = xn < xr ? -sx : sx;
+        const double uy = cy, vy = yn < yr ? -sy : sy;
+        const double na = ux * (ux * gxx + vx * gxX) + vx * (ux * gXx + vx * gXX);
+        const double nb = uy * (uy * gyy + vy * gyY) + vy * (uy * gYy + vy * gYY);
+        const double ng = ux * (uy * gxy + vy * gxY) + vx * (uy * gXy + vy * gXY);
+        double c, sn;
+        jacobi_rot(na, nb, ng, tol2, zth, &c, &sn);
+        rot[rb ^ 1][qr] = make_double2(c, sn);
       }
       src ^= 1;
       rb ^= 1;
