@@ -207,6 +207,10 @@ struct RoundProf : xtrg::RoundTimer {
 
 // Device descriptors of a grouped SVD launch over n problems.
 void* svd_desc(xtrg_ctx c, int n) { return c->need("svd_desc", xtrg::svd_desc_bytes(n) / sizeof(double) + 1); }
+// Workspace of the Jacobi's closing check (Z^T Z), for SVDs of up to 2048 columns.
+double* svd_gram(xtrg_ctx c, const std::string& tag, int p) {
+  return p <= 2048 ? c->need("svd_gram" + tag, (size_t)p * p) : nullptr;
+}
 void* qr_desc(xtrg_ctx c, int n) { return c->need("qr_desc", xtrg::qr_desc_bytes(n) / sizeof(double) + 1); }
 
 void gemm(xtrg_ctx c, const Gemm& g) {
@@ -874,7 +878,8 @@ void qr_start(xtrg_ctx c, const std::vector<Chain*>& pre, xtrg::RoundTimer* rt) 
     if (4 * J.keff < C->p) continue;         // mostly noise: no block would be built
     double* RT = c->need("qr_rt" + C->tag, (size_t)C->p * J.keff);
     xtrg::qr_rt(J, RT, s);
-    sj.push_back(xtrg::SvdJob{C->p, J.keff, RT, c->need("qr_svd" + C->tag, xtrg::svd_work(C->p, J.keff)), 0});
+    sj.push_back(xtrg::SvdJob{C->p, J.keff, RT, c->need("qr_svd" + C->tag, xtrg::svd_work(C->p, J.keff)), 0,
+                              svd_gram(c, C->tag, J.keff)});
     at.push_back(q);
   }
   if (sj.empty()) return;
@@ -1078,7 +1083,7 @@ void square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_com
       double bs = 0.0;
       jobs.clear();
       for (Chain* C : act) {
-        jobs.push_back(xtrg::SvdJob{C->len, C->psvd, C->Y, C->work, 0});
+        jobs.push_back(xtrg::SvdJob{C->len, C->psvd, C->Y, C->work, 0, svd_gram(c, C->tag, C->psvd)});
         bs += 8.0 * C->len * (double)C->psvd;
       }
       Timed tm(c, P_SVD, 0.0, bs);

@@ -432,13 +432,13 @@ bool use_big(const Gemm& g) { return g.M >= 128 && g.N >= 128; }
 }  // namespace
 
 size_t gemm_splitk_work(const Gemm& g) {
-  const int sk = choose_splitk(g, use_big(g));
+  const int sk = choose_splitk(g, use_big(g) && !g.tiles64);
   return sk > 1 ? (size_t)sk * g.M * g.N : 0;
 }
 
 void gemm(const Gemm& g, hipStream_t s, double* work, size_t work_cap) {
   if (g.M <= 0 || g.N <= 0) return;
-  const bool big = use_big(g);
+  const bool big = use_big(g) && !g.tiles64;
   int sk = choose_splitk(g, big);
   if (sk > 1 && (work == nullptr || work_cap < (size_t)sk * g.M * g.N)) sk = 1;
   if (g.K <= 0) sk = 1;

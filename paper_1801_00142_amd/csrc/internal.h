@@ -47,6 +47,7 @@ struct Gemm {
   int tag = 0;    // 1: the two-site overlap C_E (its own kernel symbol for profiling)
   int prec = GEMM_F64;
   int out64 = 1;  // GEMM_F32 only: C is double (1) or float (0)
+  int tiles64 = 0;  // 64 x 64 output tiles even for large M and N (more workgroups without split-K)
 };
 
 // Launch; split-K (for small M*N and large K, unbatched only) uses `work`
@@ -70,6 +71,10 @@ struct SvdJob {
   const double* Y;   // len x p column-major (device)
   double* work;      // svd_work(len, p) doubles
   int sweeps;        // out
+  // optional p x p doubles: once a sweep's largest cosine is below 1e-6,
+  // the closing sweep is replaced by one check of all pairs on Z^T Z (a
+  // GEMM); the Jacobi stops if no pair needs a rotation, as that sweep would
+  double* gram = nullptr;
 };
 // Optional timing of the Jacobi rounds (event pair around each sweep's
 // back-to-back round launches on the stream).

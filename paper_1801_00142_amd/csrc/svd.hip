@@ -31,6 +31,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kMaxSweeps = 60;
+constexpr double kCheckBelow = 1e-6;   // largest cosine of a sweep below which the closing check is a GEMM
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -486,6 +487,25 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   }
 }
 
+// Largest cosine over all column pairs x < y of Z from G = Z^T Z (p x p,
+// row-major), with the rotation test of the rounds, into *off (bit
+// pattern of a non-negative double; 0 if no pair needs a rotation).
+__global__ __launch_bounds__(256) void gram_check(const double* __restrict__ G, int p, double tol2, double zrel2,
+                                                  const double* __restrict__ fro2, unsigned long long* off) {
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  double worst = 0.0;
+  if (idx < (long)p * p) {
+    const int x = (int)(idx / p), y = (int)(idx % p);
+    if (y > x) {
+      const double a = G[(long)x * p + x], b = G[(long)y * p + y], g = G[(long)x * p + y];
+      if (needs_rot(a, b, g, tol2, zrel2 * fro2[0])) worst = g * g / (a * b);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) worst = fmax(worst, __shfl_xor(worst, o, 64));
+  if ((threadIdx.x & 63) == 0 && worst > 0.0) atomicMax(off, (unsigned long long)__double_as_longlong(sqrt(worst)));
+}
+
 __global__ void column_norms(const double* __restrict__ Y, int len, int p, double* __restrict__ out) {
   const int col = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -677,6 +697,7 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
     }
     XTRG_HIP(hipMemcpyAsync(hoff.data(), d_off, sizeof(unsigned long long) * n, hipMemcpyDeviceToHost, s));
     XTRG_HIP(hipStreamSynchronize(s));
+    std::vector<int> chk;
     for (int j = 0; j < n; ++j) {
       if (!h[j].active) continue;
       double m;
@@ -688,7 +709,44 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
         h[j].active = 0;
         --n_active;
         dirty = true;
+      } else if (m < kCheckBelow && jobs[j].gram) {
+        chk.push_back(j);
       }
+    }
+    // Nearly converged: the closing sweep would only confirm it.  One GEMM
+    // gives every pair's fresh Gram entries at once; the job stops here if
+    // none needs a rotation (what that sweep would find, with no rotation
+    // in it the columns do not change while it runs).
+    if (!chk.empty()) {
+      XTRG_HIP(hipMemsetAsync(d_off, 0, sizeof(unsigned long long) * n, s));
+      for (int j : chk) {
+        const SvdJob& J = jobs[j];
+        Gemm g;
+        g.M = J.p;
+        g.N = J.p;
+        g.K = J.len;
+        g.A = J.work;
+        g.lda = J.len;
+        g.B = J.work;
+        g.ldb = J.len;
+        g.transB = 1;
+        g.C = J.gram;
+        g.ldc = J.p;
+        g.tiles64 = 1;
+        gemm(g, s);
+        const long np = (long)J.p * J.p;
+        hipLaunchKernelGGL(gram_check, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, J.gram, J.p,
+                           h[j].tol * h[j].tol, h[j].zrel2, h[j].fro2, d_off + j);
+      }
+      XTRG_HIP(hipGetLastError());
+      XTRG_HIP(hipMemcpyAsync(hoff.data(), d_off, sizeof(unsigned long long) * n, hipMemcpyDeviceToHost, s));
+      XTRG_HIP(hipStreamSynchronize(s));
+      for (int j : chk)
+        if (hoff[j] == 0ull) {
+          h[j].active = 0;
+          --n_active;
+          dirty = true;
+        }
     }
   }
   for (int j = 0; j < n; ++j)

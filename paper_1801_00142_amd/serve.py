@@ -40,7 +40,8 @@ def footprint_bytes(n_sites: int, D: int) -> int:
     the per-site environment blocks 4 D^3 (L - 1), the warm-start bases
     (4D)(4D + 32) (L - 1), sites and their copies 4 x 4 D^2 L, environments,
     the two-site overlap, SVD workspaces and those of the QR start of
-    first visits (factor, R^T, its Jacobi, basis block)."""
+    first visits (factor, R^T, its Jacobi, basis block) and the Jacobi's
+    closing check (Z^T Z)."""
     L = n_sites
     blocks = 4.0 * D ** 3 * (L - 1)
     warm = (4.0 * D) * (4.0 * D + 32) * (L - 1)
@@ -48,7 +49,8 @@ def footprint_bytes(n_sites: int, D: int) -> int:
     envs = 2.0 * D ** 3 + 4.0 * D ** 3
     svd = 4 * (4.0 * D) * (4.0 * D + 32)
     qr = 4 * (4.0 * D) * (4.0 * D + 32)
-    return int(8 * (blocks + warm + sites + envs + svd + qr))
+    check = (4.0 * D + 32) ** 2
+    return int(8 * (blocks + warm + sites + envs + svd + qr + check))
 
 
 @dataclasses.dataclass
