@@ -4,6 +4,10 @@
         one-sided Jacobi SVD (xtrg_dsvd_left) of an N x N matrix with a
         graded spectrum sigma_k = 10^(-DECADES k/(N-1)) and random orthogonal
         factors (seeded); prints the time and Jacobi sweeps per call.
+    python -m paper_1801_00142_amd.microbench qr N [REPS]
+        column-pivoted QR (xtrg_dqrcp, triangular factor, no early stop) of a
+        seeded Gaussian N x N matrix: N Householder steps, one launch each;
+        prints the time per call and per step.
     python -m paper_1801_00142_amd.microbench copy GIB
         one device-to-device copy of GIB GiB: the reference for scaling the
         HBM byte counters (FETCH_SIZE, WRITE_SIZE) of other kernels.
@@ -39,6 +43,25 @@ def svd(n: int, decades: float, reps: int = 2) -> None:
     ctx.close()
 
 
+def qr(n: int, reps: int = 3) -> None:
+    import torch
+    from . import Context
+    rng = np.random.default_rng(1)
+    Y = rng.standard_normal((n, n))
+    ctx = Context(0)
+    dY = torch.from_numpy(Y.T.copy()).cuda()
+    piv = torch.zeros(n, dtype=torch.int32, device="cuda")
+    RT = torch.zeros(n * n, dtype=torch.float64, device="cuda")
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        k = ctx.dqrcp(n, n, dY.data_ptr(), 0.0, piv.data_ptr(), RT.data_ptr())
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        print(f"qr {n}x{n}: {dt:.4f} s, {k} steps, {dt / max(k, 1) * 1e6:.2f} us per step", flush=True)
+    ctx.close()
+
+
 def copy(gib: float) -> None:
     import torch
     n = int(gib * 2 ** 30) // 8
@@ -53,6 +76,8 @@ def copy(gib: float) -> None:
 if __name__ == "__main__":
     if len(sys.argv) >= 4 and sys.argv[1] == "svd":
         svd(int(sys.argv[2]), float(sys.argv[3]), int(sys.argv[4]) if len(sys.argv) > 4 else 2)
+    elif len(sys.argv) >= 3 and sys.argv[1] == "qr":
+        qr(int(sys.argv[2]), int(sys.argv[3]) if len(sys.argv) > 3 else 3)
     elif len(sys.argv) == 3 and sys.argv[1] == "copy":
         copy(float(sys.argv[2]))
     else:
