@@ -765,6 +765,29 @@ void ns_steps(xtrg_ctx c, double* X, int len, int k, int it) {
   }
 }
 
+// Polar factor of X (column-major len x k, singular values in [s0, 1]):
+// quintic steps X <- X (a I + b X^T X + c (X^T X)^2), which multiply small
+// singular values by a = 3.4445 and map [s, 1] with s >= 0.3 into
+// [0.70, 1.19], until the lower bound passes 0.3 (tracked on the host with
+// the same polynomial), then 7 cubic Newton-Schulz steps, which converge
+// quadratically from there (deviation 0.51 -> ~1e-26).
+void polar_ns(xtrg_ctx c, double* X, int len, int k, double s0) {
+  constexpr double a = 3.4445, b = -4.7750, cq = 2.0315;
+  double* G = c->need("wq_G", (size_t)k * k);
+  double* G2 = c->need("wq_G2", (size_t)k * k);
+  double* T = c->need("wq_T", (size_t)len * k);
+  double s = s0;
+  for (int q = 0; s < 0.3 && q < 8; ++q) {
+    gemm(c, plain(k, k, len, X, len, false, X, len, true, G, k));        // X^T X
+    gemm(c, plain(k, k, k, G, k, false, G, k, false, G2, k));            // (X^T X)^2
+    xtrg::axpby(G2, cq, G, b, (size_t)k * k, c->stream);                 // b G + c G^2
+    gemm(c, plain(k, len, k, G2, k, false, X, len, false, T, len));      // X (b G + c G^2)
+    xtrg::axpby(X, a, T, 1.0, (size_t)len * k, c->stream);
+    s = s * (a + s * s * (b + cq * s * s));
+  }
+  ns_steps(c, X, len, k, 7);
+}
+
 // max |X^T X - I| for X column-major len x k.
 double orth_dev(xtrg_ctx c, const double* X, int len, int k) {
   double* G = c->need("wq_G", (size_t)k * k);
@@ -820,16 +843,23 @@ int build_basis(xtrg_ctx c, double* work, int dim, int pw, const std::vector<dou
     const double hi = 1.1 * std::sqrt(1.0 / 3.0) * (std::sqrt((double)mo) + std::sqrt((double)m));
     const double lo = std::sqrt(1.0 / 3.0) * (std::sqrt((double)mo) - std::sqrt((double)m));
     xtrg::scale(R, 1.0 / hi, (size_t)len * mo, s);
-    ns_steps(c, R, len, mo, (int)std::ceil(std::log(hi / lo) / std::log(1.5)) + 9);
+    polar_ns(c, R, len, mo, 0.5 * lo / hi);
   }
-  // Q Q^T = I on R^len?
-  double* G = c->need("wq_G", (size_t)len * len);
-  gemm(c, plain(len, len, cols, Q, len, true, Q, len, false, G, len));  // Q Q^T
-  xtrg::eye_dev(G, len, c->scratch, c->scratch + 1024, s);
-  const double dev = read_scalar(c, c->scratch);
+  // Q Q^T = I on R^len?  The Jacobi leaves cosines <= 8 sqrt(len) eps
+  // between kept columns; a completion whose smallest singular value
+  // started below the estimate gets up to two rounds of further steps.
+  const double lim = 32.0 * std::sqrt((double)len) * 2.220446049250313e-16;
+  double dev = 0.0;
+  for (int attempt = 0;; ++attempt) {
+    double* G = c->need("wq_G", (size_t)len * len);
+    gemm(c, plain(len, len, cols, Q, len, true, Q, len, false, G, len));  // Q Q^T
+    xtrg::eye_dev(G, len, c->scratch, c->scratch + 1024, s);
+    dev = read_scalar(c, c->scratch);
+    if (dev <= lim || m == 0 || attempt == 2) break;
+    ns_steps(c, Q + (size_t)len * r, len, m + o, 3);
+  }
   *m_out = m;
-  // the Jacobi leaves cosines <= 8 sqrt(len) eps between kept columns
-  if (!(dev <= 32.0 * std::sqrt((double)len) * 2.220446049250313e-16)) return -1;
+  if (!(dev <= lim)) return -1;
   return cols;
 }
 
