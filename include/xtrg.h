@@ -115,10 +115,12 @@ typedef struct {
                         previous visit's singular basis (same result, fewer Jacobi
                         sweeps); 1: every SVD starts cold (and no_qr_start is implied) */
   int no_qr_start;   /* 0: a first visit (no basis from an earlier visit) with at least
-                        256 rows and columns (and at most 2048 rows) starts from the right
-                        singular vectors of the triangular factor of a column-pivoted QR
-                        of its two-site tensor (same result, fewer Jacobi sweeps);
-                        1: such SVDs start cold */
+                        256 rows and columns (at most 2048 of each) is factorised through
+                        a column-pivoted QR of its two-site tensor, Y P = Q R, and the
+                        one-sided Jacobi on R^T with its rotations W accumulated: the
+                        singular values are those of R, the left singular vectors Q W
+                        (same result to rounding, fewer Jacobi sweeps);
+                        1: such SVDs run the Jacobi on the two-site tensor itself */
 } xtrg_compress_opts;
 
 /* Diagnostics of one doubling. */

@@ -643,6 +643,7 @@ struct Chain {
   void* Rb = nullptr;
   int mL = 0, mR = 0, Kt = 0, len = 0, p = 0;
   int psvd = 0;                           // columns of the SVD input (p, or p + extra with a warm start)
+  bool svd_done = false;                  // the QR start produced this step's factorisation
 };
 
 void check_opts(const xtrg_compress_opts& o) {
@@ -898,6 +899,8 @@ void qr_start(xtrg_ctx c, const std::vector<Chain*>& pre, xtrg::RoundTimer* rt) 
     qj.push_back(xtrg::QrJob{C->len, C->p, C->th, c->need("qr" + C->tag, xtrg::qr_work(C->len, C->p)),
                              0.25 * xtrg::svd_keep_rel(C->len, C->p), 0});
   xtrg::qrcp_batched(qj, qr_desc(c, n), s);
+  // Jacobi on [R^T; I]: orthogonal columns on the first p rows, the
+  // accumulated rotation W below
   std::vector<xtrg::SvdJob> sj;
   std::vector<int> at;
   for (int q = 0; q < n; ++q) {
@@ -905,33 +908,39 @@ void qr_start(xtrg_ctx c, const std::vector<Chain*>& pre, xtrg::RoundTimer* rt) 
     const auto& J = qj[q];
     c->qr_calls += 1;
     c->qr_rows += J.keff;
-    if (4 * J.keff < C->p) continue;         // mostly noise: no block would be built
-    double* RT = c->need("qr_rt" + C->tag, (size_t)C->p * J.keff);
-    xtrg::qr_rt(J, RT, s);
-    sj.push_back(xtrg::SvdJob{C->p, J.keff, RT, c->need("qr_svd" + C->tag, xtrg::svd_work(C->p, J.keff)), 0,
-                              svd_gram(c, C->tag, J.keff)});
+    if (4 * J.keff < C->p) continue;         // mostly noise: the Jacobi on Y itself
+    const long ld = (long)C->p + J.keff;
+    double* RT = c->need("qr_rt" + C->tag, (size_t)ld * J.keff);
+    xtrg::qr_rt(J, RT, ld, true, s);
+    sj.push_back(xtrg::SvdJob{(int)ld, J.keff, RT, c->need("qr_svd" + C->tag, xtrg::svd_work((int)ld, J.keff)), 0,
+                              svd_gram(c, C->tag, J.keff), C->p});
     at.push_back(q);
   }
   if (sj.empty()) return;
   xtrg::svd_batched(sj, svd_desc(c, (int)sj.size()), s, rt);
+  // Y P = Q R and R^T W = U_R Sigma give R = W Sigma U_R^T, so Y's left
+  // singular vectors are Q W: the SVD workspace of Y takes Q [W Sigma; 0]
+  std::vector<xtrg::QrJob> aj;
+  std::vector<double*> Ms;
+  std::vector<int> nc;
   for (size_t t = 0; t < sj.size(); ++t) {
     Chain* C = pre[at[t]];
     const int keff = sj[t].p;
     c->qr_sweeps += sj[t].sweeps;
-    const std::vector<double> S = read_vec(c, xtrg::svd_sorted_values(sj[t].work, C->p, keff), keff);
-    // keep floor of Y (||R^T||_F = ||Y||_F up to the columns below the stop)
-    const double f2 = read_vec(c, xtrg::svd_fro2(sj[t].work, C->p, keff), 1)[0];
-    const double kf = xtrg::svd_keep_rel(C->len, C->p) * std::sqrt(std::max(f2, 0.0));
-    double* Q = c->need("pq" + C->tag, (size_t)C->p * (C->p + kWarmExtra));
-    int m = 0;
-    const int cols = build_basis(c, sj[t].work, C->p, keff, S, kf, 0xC01Dull + 7919ull * (unsigned long long)C->i, Q, &m);
-    if (cols < 0) c->qr_rejected += 1;
-    if (cols <= 0) continue;
-    double* Yw = c->need("svd_in" + C->tag, (size_t)C->len * cols);
-    gemm(c, plain(cols, C->len, C->p, Q, C->p, false, C->th, C->len, false, Yw, C->len));   // Y [Q0 X]
-    C->Y = Yw;
-    C->psvd = cols;
-    C->work = c->need("svd" + C->tag, xtrg::svd_work(C->len, cols));
+    double* M = c->need("qr_M" + C->tag, (size_t)C->len * keff);
+    xtrg::qr_lift(sj[t].work, sj[t].len, C->p, keff, xtrg::svd_column_norms(sj[t].work, sj[t].len, keff), M, C->len, s);
+    aj.push_back(qj[at[t]]);
+    Ms.push_back(M);
+    nc.push_back(keff);
+  }
+  xtrg::qr_apply_q(aj, Ms, nc, qr_desc(c, n), s);
+  for (size_t t = 0; t < sj.size(); ++t) {
+    Chain* C = pre[at[t]];
+    const int keff = sj[t].p;
+    C->work = c->need("svd" + C->tag, xtrg::svd_work(C->len, keff));
+    xtrg::svd_adopt(C->len, keff, Ms[t], C->work, s);
+    C->psvd = keff;
+    C->svd_done = true;
     c->qr_used += 1;
   }
 }
@@ -1084,6 +1093,7 @@ void square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_com
     for (Chain* C : act) {
       C->Y = C->th;
       C->psvd = C->p;
+      C->svd_done = false;
       const auto& w = C->warm[C->i];
       const int need_side = C->gauge_right ? 1 : 0;   // the column index of Y
       if (!C->o.no_warm_start && C->p >= kWarmMin && w.side == need_side && w.dim == C->p) {
@@ -1101,7 +1111,7 @@ void square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_com
       std::vector<Chain*> pre;
       for (Chain* C : act)
         if (C->psvd == C->p && !C->o.no_warm_start && !C->o.no_qr_start && C->p >= kQrMin && C->len >= kQrMin &&
-            C->len <= xtrg::kQrMaxLen)
+            C->len <= xtrg::kQrMaxLen && C->p <= 2048)
           pre.push_back(C);
       if (!pre.empty()) {
         Timed tm(c, P_QR, 0.0, 0.0);
@@ -1113,6 +1123,7 @@ void square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_com
       double bs = 0.0;
       jobs.clear();
       for (Chain* C : act) {
+        if (C->svd_done) continue;
         jobs.push_back(xtrg::SvdJob{C->len, C->psvd, C->Y, C->work, 0, svd_gram(c, C->tag, C->psvd)});
         bs += 8.0 * C->len * (double)C->psvd;
       }
@@ -1625,7 +1636,7 @@ int xtrg_dqrcp(xtrg_ctx c, int len, int p, const double* Y, double stop_rel, int
     xtrg::qrcp_batched(jobs, qr_desc(c, 1), c->stream);
     const int k = jobs[0].keff;
     if (k > 0) {
-      xtrg::qr_rt(jobs[0], RT, c->stream);
+      xtrg::qr_rt(jobs[0], RT, p, false, c->stream);
       XTRG_HIP(hipMemcpyAsync(piv, xtrg::qr_pivots(jobs[0]), sizeof(int) * k, hipMemcpyDeviceToDevice, c->stream));
     }
     XTRG_HIP(hipStreamSynchronize(c->stream));

@@ -75,6 +75,10 @@ struct SvdJob {
   // the closing sweep is replaced by one check of all pairs on Z^T Z (a
   // GEMM); the Jacobi stops if no pair needs a rotation, as that sweep would
   double* gram = nullptr;
+  // rows that define the Gram matrix (0: all len): the columns are
+  // orthogonalised on their first glen rows and the remaining rows are only
+  // rotated with them (rows of an identity appended below accumulate V)
+  int glen = 0;
 };
 // Optional timing of the Jacobi rounds (event pair around each sweep's
 // back-to-back round launches on the stream).
@@ -102,10 +106,26 @@ struct QrJob {
 size_t qr_work(int len, int p);
 size_t qr_desc_bytes(int n);
 void qrcp_batched(std::vector<QrJob>& jobs, void* desc_dev, hipStream_t s);
-// R^T into RT (p x keff, column-major, leading dimension p).
-void qr_rt(const QrJob& J, double* RT, hipStream_t s);
+// R^T into RT (p x keff, column-major, leading dimension ld >= p); with
+// identity, rows p .. p + keff - 1 of RT hold the keff x keff identity
+// (ld >= p + keff).
+void qr_rt(const QrJob& J, double* RT, long ld, bool identity, hipStream_t s);
+// M <- Q M for the orthogonal factor Q = H_0 H_1 ... H_{keff-1} of each job
+// (M: len x ncols, column-major, leading dimension len; jobs with keff = 0
+// are left alone).  One launch per reflector.
+void qr_apply_q(std::vector<QrJob>& jobs, const std::vector<double*>& M, const std::vector<int>& ncols,
+                void* desc_dev, hipStream_t s);
+// M = [W Sigma; 0] (len x keff) from the Jacobi columns Z of [R^T; I]
+// (leading dimension ldz): W = their rows p .., Sigma = norms (device, keff).
+void qr_lift(const double* Z, long ldz, int p, int keff, const double* norms, double* M, int len, hipStream_t s);
 // Pivot column of each step (device, keff ints).
 const int* qr_pivots(const QrJob& J);
+
+// Put Z (len x p, column-major, device) into an SVD workspace as if the
+// Jacobi had produced it: ||Z||_F^2, column norms, their descending order.
+void svd_adopt(int len, int p, const double* Z, double* work, hipStream_t s);
+// Column norms over the first glen rows, as the Jacobi left them (device, p).
+const double* svd_column_norms(const double* work, int len, int p);
 
 // Two-stage use: svd_left with k = 0, read the sorted values, then gather.
 void svd_gather(int len, int p, double* work, int k, double* U, long ldu, int u_rowmajor, hipStream_t s);

@@ -205,30 +205,97 @@ __global__ __launch_bounds__(kQT) void qr_step(const QrDesc* __restrict__ descs,
   qr_post(d, (i + 1) & 1, mykey, red);
 }
 
-// R^T (p x keff, column-major, leading dimension p): entry (c, r) is R's
+// R^T (p x keff, column-major, leading dimension ld): entry (c, r) is R's
 // entry at row r for column c: beta_r for the pivot of step r, row r of the
-// updated column if c was pivoted after step r (or never), else zero.
+// updated column if c was pivoted after step r (or never), else zero; rows
+// p .. p + rows_id - 1 hold the first rows_id rows of an identity.
 // 32 x 32 tiles through LDS (reads along A's columns, writes along R^T's).
-__global__ __launch_bounds__(256) void qr_rt(const double* __restrict__ A, int len, int p, int keff,
+__global__ __launch_bounds__(256) void qr_rt(const double* __restrict__ A, int len, int p, int keff, int rows_id,
                                              const int* __restrict__ piv, const int* __restrict__ stepof,
-                                             const double* __restrict__ rdiag, double* __restrict__ RT) {
+                                             const double* __restrict__ rdiag, double* __restrict__ RT, long ld) {
   __shared__ double tile[32][33];
   const int r0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;    // 32 x 8
+  const int rows = p + rows_id;
   for (int q = ty; q < 32; q += 8) {
     const int c = c0 + q, r = r0 + tx;
     double v = 0.0;
     if (c < p && r < keff) {
       if (piv[r] == c) v = rdiag[r];
       else if (stepof[c] > r) v = A[(size_t)c * len + r];
+    } else if (c >= p && c < rows && r < keff) {
+      v = c - p == r ? 1.0 : 0.0;
     }
     tile[q][tx] = v;
   }
   __syncthreads();
   for (int q = ty; q < 32; q += 8) {
     const int r = r0 + q, c = c0 + tx;
-    if (r < keff && c < p) RT[(size_t)r * p + c] = tile[tx][q];
+    if (r < keff && c < rows) RT[(size_t)r * ld + c] = tile[tx][q];
   }
+}
+
+// M <- H_i M for one Householder reflector of the factorisation (step i),
+// rebuilt from its pivot column, which no step after i has changed; every
+// workgroup forms it with the same arithmetic as the factorisation step.
+// One wave per column of M.
+struct QrApply {
+  const double* A;
+  const int* piv;
+  const double* rdiag;
+  double* M;
+  int len, keff, ncols;
+};
+
+template <int R>
+__global__ __launch_bounds__(kQT) void qr_reflect(const QrApply* __restrict__ descs, int i) {
+  const QrApply d = descs[blockIdx.y];
+  if (i >= d.keff || (int)blockIdx.x * (kQT / 64) >= d.ncols) return;
+  const int m = d.len - i;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int c = blockIdx.x * (kQT / 64) + wave;
+  const bool mine = c < d.ncols;
+  double* __restrict__ mc = d.M + (size_t)(mine ? c : 0) * d.len + i;
+  double y[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int r = lane + 64 * u;
+    y[u] = (mine && r < m) ? mc[r] : 0.0;
+  }
+  __shared__ double v[64 * R];
+  const double* __restrict__ xc = d.A + (size_t)d.piv[i] * d.len + i;
+  for (int r = t; r < m; r += kQT) v[r] = xc[r];
+  __syncthreads();
+  const double alpha = v[0], beta = d.rdiag[i];
+  const double tau = (beta - alpha) / beta;
+  const double sc = 1.0 / (alpha - beta);
+  __syncthreads();                            // v[0] read by all before it is overwritten
+  for (int r = t; r < m; r += kQT) v[r] = r == 0 ? 1.0 : v[r] * sc;
+  __syncthreads();
+  if (!mine) return;
+  double sdot = 0.0;
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int r = lane + 64 * u;
+    if (r < m) sdot = fma(v[r], y[u], sdot);
+  }
+  sdot = qr_wave_sum(sdot) * tau;
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int r = lane + 64 * u;
+    if (r < m) mc[r] = fma(-sdot, v[r], y[u]);
+  }
+}
+
+// M (len x keff, column-major) = [W Sigma; 0]: W = rows p .. p + keff - 1 of
+// the Jacobi columns Z (leading dimension ldz), Sigma = their norms over the
+// first p rows.
+__global__ void qr_lift_kernel(const double* __restrict__ Z, long ldz, int p, int keff,
+                               const double* __restrict__ norms, double* __restrict__ M, int len) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)len * keff) return;
+  const int c = (int)(idx / len), r = (int)(idx % len);
+  M[idx] = r < keff ? Z[(long)c * ldz + p + r] * norms[c] : 0.0;
 }
 
 // Workspace layout (doubles): A (len p), fro2 (1), sumsq scratch (1024),
@@ -315,11 +382,51 @@ void qrcp_batched(std::vector<QrJob>& jobs, void* desc_dev, hipStream_t s) {
   for (int j = 0; j < n; ++j) jobs[j].keff = keff[j];
 }
 
-void qr_rt(const QrJob& J, double* RT, hipStream_t s) {
+void qr_rt(const QrJob& J, double* RT, long ld, bool identity, hipStream_t s) {
   if (J.keff <= 0 || J.p <= 0) return;
+  const int rows_id = identity ? J.keff : 0;
+  if (ld < (long)J.p + rows_id) throw Error(-1, "qr_rt: leading dimension too small");
   QrLayout L = qr_layout(J.work, J.len, J.p);
-  hipLaunchKernelGGL(qr_rt, dim3((J.keff + 31) / 32, (J.p + 31) / 32), dim3(256), 0, s, L.A, J.len, J.p, J.keff,
-                     L.piv, L.stepof, L.rdiag, RT);
+  hipLaunchKernelGGL(qr_rt, dim3((J.keff + 31) / 32, (J.p + rows_id + 31) / 32), dim3(256), 0, s, L.A, J.len, J.p,
+                     J.keff, rows_id, L.piv, L.stepof, L.rdiag, RT, ld);
+  XTRG_HIP(hipGetLastError());
+}
+
+void qr_apply_q(std::vector<QrJob>& jobs, const std::vector<double*>& M, const std::vector<int>& ncols,
+                void* desc_dev, hipStream_t s) {
+  const int n = (int)jobs.size();
+  if (n == 0) return;
+  static_assert(sizeof(QrApply) <= sizeof(QrDesc), "descriptor space");
+  QrApply* d_desc = reinterpret_cast<QrApply*>(desc_dev);
+  std::vector<QrApply> h(n);
+  int kmax = 0, cmax = 0, lenmax = 0;
+  for (int j = 0; j < n; ++j) {
+    const QrJob& J = jobs[j];
+    QrLayout L = qr_layout(J.work, J.len, J.p);
+    h[j] = QrApply{L.A, L.piv, L.rdiag, M[j], J.len, J.keff, ncols[j]};
+    if (J.keff <= 0 || ncols[j] <= 0) continue;
+    if (J.len > kQrMaxLen) throw Error(-1, "qr_apply_q: column length above 2048");
+    kmax = std::max(kmax, J.keff);
+    cmax = std::max(cmax, ncols[j]);
+    lenmax = std::max(lenmax, J.len);
+  }
+  if (kmax == 0) return;
+  XTRG_HIP(hipMemcpyAsync(d_desc, h.data(), sizeof(QrApply) * n, hipMemcpyHostToDevice, s));
+  const dim3 grid((cmax + kQT / 64 - 1) / (kQT / 64), n);
+  for (int i = kmax - 1; i >= 0; --i) {       // Q M = H_0 (H_1 (... (H_{k-1} M)))
+    if (lenmax <= 256) hipLaunchKernelGGL(qr_reflect<4>, grid, dim3(kQT), 0, s, d_desc, i);
+    else if (lenmax <= 512) hipLaunchKernelGGL(qr_reflect<8>, grid, dim3(kQT), 0, s, d_desc, i);
+    else if (lenmax <= 1024) hipLaunchKernelGGL(qr_reflect<16>, grid, dim3(kQT), 0, s, d_desc, i);
+    else hipLaunchKernelGGL(qr_reflect<32>, grid, dim3(kQT), 0, s, d_desc, i);
+  }
+  XTRG_HIP(hipGetLastError());
+}
+
+void qr_lift(const double* Z, long ldz, int p, int keff, const double* norms, double* M, int len, hipStream_t s) {
+  if (keff <= 0 || len <= 0) return;
+  if (keff > len) throw Error(-1, "qr_lift: more columns than rows");
+  const long n = (long)len * keff;
+  hipLaunchKernelGGL(qr_lift_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, Z, ldz, p, keff, norms, M, len);
   XTRG_HIP(hipGetLastError());
 }
 

@@ -85,6 +85,7 @@ struct JacobiDesc {
   double tol, zrel2;
   int len, p, nbk, active;
   int split;        // row slices per block pair (workgroups sharing one pair's round)
+  int glen;         // leading rows that define the Gram matrix (<= len; the rest are only rotated)
 };
 
 // Rows [a, b) of slice s of `split` (slices start at multiples of 128 rows).
@@ -165,6 +166,8 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   if (!d.active || r >= d.nbk - 1 || pair >= d.nbk / 2 || sl >= (MODE == ROUND_FUSED ? 1 : split)) return;
   int ra = 0, rb = d.len;                       // rows this workgroup rotates
   if (MODE != ROUND_FUSED) slice_rows(d.len, split, sl, &ra, &rb);
+  int ga = 0, gb = d.glen;                      // rows of its Gram partial
+  if (MODE == ROUND_GRAM) slice_rows(d.glen, split, sl, &ga, &gb);
   double* __restrict__ part = parts + ((size_t)blockIdx.y * kMaxPairs + pair) * kMaxSplit * kGramVals;
   double* __restrict__ Y = d.Z;
   const int len = d.len, p = d.p, nbk = d.nbk;
@@ -255,7 +258,7 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   // (each the sum over waves in wave order), whichever way the round runs:
   // the fused workgroup walks the slices itself.
   if (MODE == ROUND_GRAM) {
-    gram_rows(ra, rb);
+    gram_rows(ga, gb);
     __syncthreads();
     for (int idx = t; idx < kGramVals; idx += kWT) part[sl * kGramVals + idx] = wave_sum(idx);
     return;
@@ -263,7 +266,7 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   if (MODE == ROUND_FUSED) {
     for (int s2 = 0; s2 < split; ++s2) {
       int a2, b2;
-      slice_rows(len, split, s2, &a2, &b2);
+      slice_rows(d.glen, split, s2, &a2, &b2);
       gram_rows(a2, b2);
       __syncthreads();
       for (int idx = t; idx < kGramVals; idx += kWT) {
@@ -506,15 +509,31 @@ __global__ __launch_bounds__(256) void gram_check(const double* __restrict__ G, 
   if ((threadIdx.x & 63) == 0 && worst > 0.0) atomicMax(off, (unsigned long long)__double_as_longlong(sqrt(worst)));
 }
 
-__global__ void column_norms(const double* __restrict__ Y, int len, int p, double* __restrict__ out) {
+// Norms of the columns of Y (stride len) over their first glen rows.
+__global__ void column_norms(const double* __restrict__ Y, int len, int glen, int p, double* __restrict__ out) {
   const int col = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (col >= p) return;
   const double* c = Y + (long)col * len;
   double s = 0.0;
-  for (int e = lane; e < len; e += 64) s = fma(c[e], c[e], s);
+  for (int e = lane; e < glen; e += 64) s = fma(c[e], c[e], s);
   s = wave_sum(s);
   if (lane == 0) out[col] = sqrt(s);
+}
+
+// *out = sum of x[i]^2 for i < n, one workgroup, a fixed summation order.
+__global__ __launch_bounds__(256) void sum_squares_ordered(const double* __restrict__ x, int n,
+                                                           double* __restrict__ out) {
+  __shared__ double part[256];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) v = fma(x[i], x[i], v);
+  part[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = part[0];
 }
 
 // Descending bitonic sort of (value, index) in one workgroup, n <= 4096.
@@ -585,6 +604,12 @@ size_t svd_desc_bytes(int n) {
   return parts_offset(n) + sizeof(double) * (size_t)n * kMaxPairs * kMaxSplit * kGramVals;
 }
 
+static int pow2_at_least(int p) {
+  int n = 1;
+  while (n < p) n <<= 1;
+  return n;
+}
+
 // Row slices per block pair: long columns are split so that one round of a
 // single chain spreads over more compute units.
 static int split_for(int len) { return len >= 1024 ? 4 : len >= 512 ? 2 : 1; }
@@ -605,6 +630,9 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
     D = JacobiDesc{};
     D.len = J.len;
     D.p = J.p;
+    const int glen = J.glen > 0 ? J.glen : J.len;
+    if (glen > J.len) throw Error(-1, "svd: Gram rows beyond the column length");
+    D.glen = glen;
     if (J.len <= 0 || J.p <= 0) continue;
     if (J.len > 4096) throw Error(-1, "svd: column length above 4096");
     if (J.p > 4096) throw Error(-1, "svd: more than 4096 columns");
@@ -613,22 +641,29 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
     D.perm = sv_perm(w, J.len, J.p);
     D.fro2 = w + (size_t)J.len * J.p + 3 * (size_t)J.p + 1;
     D.off = d_off + j;
-    D.tol = 8.0 * std::sqrt((double)J.len) * 2.220446049250313e-16;
+    D.tol = 8.0 * std::sqrt((double)glen) * 2.220446049250313e-16;
     // Columns below a quarter of the keep floor are numerically zero: they
     // are neither rotated nor counted for convergence.  Columns of pure
     // rounding noise (the null space of a rank-deficient Y) otherwise never
     // settle, since every rotation leaves them a fresh O(1) relative error.
     // The margin to the keep floor lets content near the floor that is still
     // spread over several columns be gathered before the count is taken.
-    const double zrel = 0.25 * svd_keep_rel(J.len, J.p);
+    const double zrel = 0.25 * svd_keep_rel(glen, J.p);
     D.zrel2 = zrel * zrel;
     D.nbk = (J.p + kBlk - 1) / kBlk;
     if (D.nbk % 2) ++D.nbk;
     D.active = J.p > 1;
-    D.split = split_for(J.len);
+    D.split = split_for(glen);
     XTRG_HIP(hipMemcpyAsync(w, J.Y, sizeof(double) * J.len * J.p, hipMemcpyDeviceToDevice, s));
-    sumsq(w, (size_t)J.len * J.p, w + (size_t)J.len * J.p + 3 * (size_t)J.p + 1,
-          w + (size_t)J.len * J.p + 3 * (size_t)J.p + 2, s);
+    if (glen == J.len) {
+      sumsq(w, (size_t)J.len * J.p, w + (size_t)J.len * J.p + 3 * (size_t)J.p + 1,
+            w + (size_t)J.len * J.p + 3 * (size_t)J.p + 2, s);
+    } else {   // ||Y||_F^2 of the leading rows, from the column norms in fixed order
+      double* raw = w + (size_t)J.len * J.p;
+      hipLaunchKernelGGL(column_norms, dim3((J.p + 3) / 4), dim3(256), 0, s, w, J.len, glen, J.p, raw);
+      hipLaunchKernelGGL(sum_squares_ordered, dim3(1), dim3(256), 0, s, raw, J.p,
+                         w + (size_t)J.len * J.p + 3 * (size_t)J.p + 1);
+    }
     n2[j] = 1;
     while (n2[j] < J.p) n2[j] <<= 1;
     max_nbk = std::max(max_nbk, D.nbk);
@@ -638,7 +673,7 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
     const SvdJob& J = jobs[j];
     double* w = J.work;
     double* raw = w + (size_t)J.len * J.p;
-    hipLaunchKernelGGL(column_norms, dim3((J.p + 3) / 4), dim3(256), 0, s, w, J.len, J.p, raw);
+    hipLaunchKernelGGL(column_norms, dim3((J.p + 3) / 4), dim3(256), 0, s, w, J.len, h[j].glen, J.p, raw);
     hipLaunchKernelGGL(sort_desc, dim3(1), dim3(1024), (sizeof(double) + sizeof(int)) * n2[j], s, raw, J.p,
                        sv_sorted(w, J.len, J.p), sv_perm(w, J.len, J.p));
     XTRG_HIP(hipGetLastError());
@@ -724,7 +759,7 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
         Gemm g;
         g.M = J.p;
         g.N = J.p;
-        g.K = J.len;
+        g.K = h[j].glen;
         g.A = J.work;
         g.lda = J.len;
         g.B = J.work;
@@ -773,6 +808,21 @@ void svd_gather(int len, int p, double* work, int k, double* U, long ldu, int u_
                      sv_perm(work, len, p), k, U, ldu, u_rowmajor);
   XTRG_HIP(hipGetLastError());
 }
+
+void svd_adopt(int len, int p, const double* Z, double* work, hipStream_t s) {
+  if (len <= 0 || p <= 0) return;
+  if (p > 4096) throw Error(-1, "svd: more than 4096 columns");
+  XTRG_HIP(hipMemcpyAsync(work, Z, sizeof(double) * len * p, hipMemcpyDeviceToDevice, s));
+  sumsq(work, (size_t)len * p, work + (size_t)len * p + 3 * (size_t)p + 1, work + (size_t)len * p + 3 * (size_t)p + 2,
+        s);
+  double* raw = work + (size_t)len * p;
+  hipLaunchKernelGGL(column_norms, dim3((p + 3) / 4), dim3(256), 0, s, work, len, len, p, raw);
+  hipLaunchKernelGGL(sort_desc, dim3(1), dim3(1024), (sizeof(double) + sizeof(int)) * (size_t)pow2_at_least(p), s,
+                     raw, p, sv_sorted(work, len, p), sv_perm(work, len, p));
+  XTRG_HIP(hipGetLastError());
+}
+
+const double* svd_column_norms(const double* work, int len, int p) { return work + (size_t)len * p; }
 
 const double* svd_sorted_values(const double* work, int len, int p) {
   return work + (size_t)len * p + p;
