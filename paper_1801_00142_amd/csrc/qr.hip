@@ -1,13 +1,12 @@
 // Householder QR with column pivoting (triangular factor only), FP64.
 //
-// Used to precondition the one-sided Jacobi SVD of a two-site overlap that
-// has no singular basis from an earlier visit: with Y P = Q R, the right
-// singular vectors of Y are those of R, and the one-sided Jacobi on R^T
-// converges in a fraction of the sweeps it needs on Y itself (the pivoted
-// factor is graded: its rows fall off in norm, and the column scaling that
-// remains after the grading is well conditioned).  Those vectors then start
-// the Jacobi on Y.  The factorisation only steers the convergence; the
-// singular values and vectors still come from the Jacobi on Y.
+// Used for the SVD of a two-site overlap that has no singular basis from an
+// earlier visit: with Y P = Q R, the one-sided Jacobi on R^T converges in a
+// fraction of the sweeps it needs on Y itself (the pivoted factor is graded:
+// its rows fall off in norm, and the column scaling that remains after the
+// grading is well conditioned).  Run on [R^T; I], it accumulates its
+// rotations W below: R^T W = U_R Sigma, R = W Sigma U_R^T, and Y's left
+// singular vectors are Q W, formed by applying the reflectors (qr_apply_q).
 //
 // Layout: the columns are never moved.  Step i takes the remaining column
 // of largest norm below row i (its index is the pivot piv[i]), forms the
