@@ -234,10 +234,12 @@ __global__ __launch_bounds__(256) void qr_rt(const double* __restrict__ A, int l
   }
 }
 
-// M <- H_i M for one Householder reflector of the factorisation (step i),
-// rebuilt from its pivot column, which no step after i has changed; every
-// workgroup forms it with the same arithmetic as the factorisation step.
-// One wave per column of M.
+// M <- Q M = H_0 (H_1 (... (H_{keff-1} M))).  Every column of M is
+// transformed on its own, so one launch does it all: a wave keeps its column
+// in registers and applies the reflectors from the last to the first; the
+// workgroup stages them through LDS, kQC at a time, each rebuilt from its
+// pivot column (which no later step of the factorisation changed) with the
+// arithmetic of the factorisation step.
 struct QrApply {
   const double* A;
   const int* piv;
@@ -245,44 +247,51 @@ struct QrApply {
   double* M;
   int len, keff, ncols;
 };
+constexpr int kQC = 4;                        // reflectors per LDS stage
 
 template <int R>
-__global__ __launch_bounds__(kQT) void qr_reflect(const QrApply* __restrict__ descs, int i) {
+__global__ __launch_bounds__(kQT) void qr_apply_kernel(const QrApply* __restrict__ descs) {
   const QrApply d = descs[blockIdx.y];
-  if (i >= d.keff || (int)blockIdx.x * (kQT / 64) >= d.ncols) return;
-  const int m = d.len - i;
+  if (d.keff <= 0 || (int)blockIdx.x * (kQT / 64) >= d.ncols) return;
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int c = blockIdx.x * (kQT / 64) + wave;
   const bool mine = c < d.ncols;
-  double* __restrict__ mc = d.M + (size_t)(mine ? c : 0) * d.len + i;
+  double* __restrict__ mc = d.M + (size_t)(mine ? c : 0) * d.len;
   double y[R];
 #pragma unroll
   for (int u = 0; u < R; ++u) {
     const int r = lane + 64 * u;
-    y[u] = (mine && r < m) ? mc[r] : 0.0;
+    y[u] = (mine && r < d.len) ? mc[r] : 0.0;
   }
-  __shared__ double v[64 * R];
-  const double* __restrict__ xc = d.A + (size_t)d.piv[i] * d.len + i;
-  for (int r = t; r < m; r += kQT) v[r] = xc[r];
-  __syncthreads();
-  const double alpha = v[0], beta = d.rdiag[i];
-  const double tau = (beta - alpha) / beta;
-  const double sc = 1.0 / (alpha - beta);
-  __syncthreads();                            // v[0] read by all before it is overwritten
-  for (int r = t; r < m; r += kQT) v[r] = r == 0 ? 1.0 : v[r] * sc;
-  __syncthreads();
+  __shared__ double v[kQC][64 * R];
+  __shared__ double tau[kQC];
+  for (int i1 = d.keff; i1 > 0; i1 -= kQC) {
+    const int i0 = max(0, i1 - kQC);           // reflectors i0 .. i1-1 of this stage
+    __syncthreads();                          // the previous stage's reflectors are used up
+    for (int q = 0; q < i1 - i0; ++q) {
+      const int i = i0 + q;
+      const double* __restrict__ xc = d.A + (size_t)d.piv[i] * d.len;
+      const double alpha = xc[i], beta = d.rdiag[i];
+      const double sc = 1.0 / (alpha - beta);
+      for (int r = t; r < 64 * R; r += kQT) v[q][r] = (r < i || r >= d.len) ? 0.0 : r == i ? 1.0 : xc[r] * sc;
+      if (t == 0) tau[q] = (beta - alpha) / beta;
+    }
+    __syncthreads();
+    if (!mine) continue;
+    for (int q = i1 - i0 - 1; q >= 0; --q) {
+      double s = 0.0;
+#pragma unroll
+      for (int u = 0; u < R; ++u) s = fma(v[q][lane + 64 * u], y[u], s);
+      s = qr_wave_sum(s) * tau[q];
+#pragma unroll
+      for (int u = 0; u < R; ++u) y[u] = fma(-s, v[q][lane + 64 * u], y[u]);
+    }
+  }
   if (!mine) return;
-  double sdot = 0.0;
 #pragma unroll
   for (int u = 0; u < R; ++u) {
     const int r = lane + 64 * u;
-    if (r < m) sdot = fma(v[r], y[u], sdot);
-  }
-  sdot = qr_wave_sum(sdot) * tau;
-#pragma unroll
-  for (int u = 0; u < R; ++u) {
-    const int r = lane + 64 * u;
-    if (r < m) mc[r] = fma(-sdot, v[r], y[u]);
+    if (r < d.len) mc[r] = y[u];
   }
 }
 
@@ -412,12 +421,10 @@ void qr_apply_q(std::vector<QrJob>& jobs, const std::vector<double*>& M, const s
   if (kmax == 0) return;
   XTRG_HIP(hipMemcpyAsync(d_desc, h.data(), sizeof(QrApply) * n, hipMemcpyHostToDevice, s));
   const dim3 grid((cmax + kQT / 64 - 1) / (kQT / 64), n);
-  for (int i = kmax - 1; i >= 0; --i) {       // Q M = H_0 (H_1 (... (H_{k-1} M)))
-    if (lenmax <= 256) hipLaunchKernelGGL(qr_reflect<4>, grid, dim3(kQT), 0, s, d_desc, i);
-    else if (lenmax <= 512) hipLaunchKernelGGL(qr_reflect<8>, grid, dim3(kQT), 0, s, d_desc, i);
-    else if (lenmax <= 1024) hipLaunchKernelGGL(qr_reflect<16>, grid, dim3(kQT), 0, s, d_desc, i);
-    else hipLaunchKernelGGL(qr_reflect<32>, grid, dim3(kQT), 0, s, d_desc, i);
-  }
+  if (lenmax <= 256) hipLaunchKernelGGL(qr_apply_kernel<4>, grid, dim3(kQT), 0, s, d_desc);
+  else if (lenmax <= 512) hipLaunchKernelGGL(qr_apply_kernel<8>, grid, dim3(kQT), 0, s, d_desc);
+  else if (lenmax <= 1024) hipLaunchKernelGGL(qr_apply_kernel<16>, grid, dim3(kQT), 0, s, d_desc);
+  else hipLaunchKernelGGL(qr_apply_kernel<32>, grid, dim3(kQT), 0, s, d_desc);
   XTRG_HIP(hipGetLastError());
 }
 
