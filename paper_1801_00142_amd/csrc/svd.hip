@@ -521,6 +521,24 @@ __global__ void column_norms(const double* __restrict__ Y, int len, int glen, in
   if (lane == 0) out[col] = sqrt(s);
 }
 
+// Columns still above the numerical zero: how many of the descending norms
+// have norm^2 > zth / 2 (the margin keeps every column that a Gram diagonal
+// could find above zth; the others are never rotated again).
+__global__ __launch_bounds__(256) void count_alive(const double* __restrict__ sorted, int p,
+                                                   const double* __restrict__ fro2, double zrel2, int* __restrict__ out) {
+  __shared__ int part[256];
+  const double th = 0.5 * zrel2 * fro2[0];
+  int c = 0;
+  for (int i = threadIdx.x; i < p; i += 256) c += sorted[i] * sorted[i] > th;
+  part[threadIdx.x] = c;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = part[0];
+}
+
 // *out = sum of x[i]^2 for i < n, one workgroup, a fixed summation order.
 __global__ __launch_bounds__(256) void sum_squares_ordered(const double* __restrict__ x, int n,
                                                            double* __restrict__ out) {
@@ -598,7 +616,8 @@ static int* sv_perm(double* work, int len, int p) {
 
 // [descs: n][off: n][pad to 256 B][Gram partials: n x kMaxPairs x kMaxSplit x kGramVals doubles]
 static size_t parts_offset(int n) {
-  return (sizeof(JacobiDesc) * (size_t)n + sizeof(unsigned long long) * (size_t)n + 255) / 256 * 256;
+  return (sizeof(JacobiDesc) * (size_t)n + sizeof(unsigned long long) * (size_t)n + sizeof(int) * (size_t)n + 255) /
+         256 * 256;
 }
 size_t svd_desc_bytes(int n) {
   return parts_offset(n) + sizeof(double) * (size_t)n * kMaxPairs * kMaxSplit * kGramVals;
@@ -619,6 +638,7 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
   if (n == 0) return;
   JacobiDesc* d_desc = reinterpret_cast<JacobiDesc*>(desc_dev);
   unsigned long long* d_off = reinterpret_cast<unsigned long long*>(d_desc + n);
+  int* d_alive = reinterpret_cast<int*>(d_off + n);
   double* d_parts = reinterpret_cast<double*>(static_cast<char*>(desc_dev) + parts_offset(n));
   std::vector<JacobiDesc> h(n);
   std::vector<int> n2(n);
@@ -666,9 +686,9 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
     }
     n2[j] = 1;
     while (n2[j] < J.p) n2[j] <<= 1;
-    max_nbk = std::max(max_nbk, D.nbk);
-    max_half = std::max(max_half, D.nbk / 2);
   }
+  std::vector<int> full_nbk(n), hal(n, 0);
+  for (int j = 0; j < n; ++j) full_nbk[j] = h[j].nbk;
   auto rank_columns = [&](int j) {
     const SvdJob& J = jobs[j];
     double* w = J.work;
@@ -678,16 +698,49 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
                        sv_sorted(w, J.len, J.p), sv_perm(w, J.len, J.p));
     XTRG_HIP(hipGetLastError());
   };
+  // Ranks for the next sweep and the count of columns still above the
+  // numerical zero: the rest sort last, are never rotated again (a pair is
+  // rotated only if both columns are above it, and rotations alone change
+  // a column), and are left out of the block schedule.
+  auto prepare = [&](int j) {
+    rank_columns(j);
+    const SvdJob& J = jobs[j];
+    hipLaunchKernelGGL(count_alive, dim3(1), dim3(256), 0, s, sv_sorted(J.work, J.len, J.p), J.p, h[j].fro2,
+                       h[j].zrel2, d_alive + j);
+  };
+  bool dirty = true;
+  auto set_nbk = [&](int j) {
+    int nb = (std::max(hal[j], 2) + kBlk - 1) / kBlk;
+    if (nb % 2) ++nb;
+    nb = std::min(nb, full_nbk[j]);
+    if (nb != h[j].nbk) {
+      h[j].nbk = nb;
+      dirty = true;
+    }
+  };
+  for (int j = 0; j < n; ++j)
+    if (h[j].active) prepare(j);
+  XTRG_HIP(hipMemcpyAsync(hal.data(), d_alive, sizeof(int) * n, hipMemcpyDeviceToHost, s));
+  XTRG_HIP(hipStreamSynchronize(s));
+  for (int j = 0; j < n; ++j)
+    if (h[j].active) set_nbk(j);
   // Sliced launches pay off while the fused rounds would leave most compute
   // units idle; the results are the same either way.
   int smax = 1;
-  long wgs = 0;
-  for (const auto& D : h)
-    if (D.active) {
-      smax = std::max(smax, D.split);
-      wgs += (long)(D.nbk / 2) * D.split;
-    }
-  if (wgs > 256) smax = 1;
+  auto plan = [&]() {
+    max_nbk = 0;
+    max_half = 0;
+    smax = 1;
+    long wgs = 0;
+    for (const auto& D : h)
+      if (D.active) {
+        smax = std::max(smax, D.split);
+        wgs += (long)(D.nbk / 2) * D.split;
+        max_nbk = std::max(max_nbk, D.nbk);
+        max_half = std::max(max_half, D.nbk / 2);
+      }
+    if (wgs > 256) smax = 1;
+  };
   auto round = [&](int r) {
     if (smax == 1) {
       hipLaunchKernelGGL(jacobi_round<ROUND_FUSED>, dim3(max_half, n), dim3(kWT), 0, s, d_desc, r, 1, d_parts);
@@ -702,7 +755,6 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
   std::vector<double> last(n, 0.0);
   int n_active = 0;
   for (auto& D : h) n_active += D.active;
-  bool dirty = true;
   for (int sweep = 0; n_active > 0; ++sweep) {
     if (sweep >= kMaxSweeps) {
       for (int j = 0; j < n; ++j)
@@ -710,9 +762,8 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
           throw Error(-4, "svd: Jacobi did not converge (len " + std::to_string(h[j].len) + ", p " +
                               std::to_string(h[j].p) + ", largest cosine " + std::to_string(last[j]) + ")");
     }
-    for (int j = 0; j < n; ++j)
-      if (h[j].active) rank_columns(j);
-    if (dirty) {   // the active set changed: refresh the device descriptors
+    plan();
+    if (dirty) {   // the active set or a block count changed: refresh the device descriptors
       XTRG_HIP(hipMemcpyAsync(d_desc, h.data(), sizeof(JacobiDesc) * n, hipMemcpyHostToDevice, s));
       dirty = false;
     }
@@ -730,7 +781,10 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
         }
       timer->end(s, max_nbk - 1, fl, by);
     }
+    for (int j = 0; j < n; ++j)
+      if (h[j].active) prepare(j);
     XTRG_HIP(hipMemcpyAsync(hoff.data(), d_off, sizeof(unsigned long long) * n, hipMemcpyDeviceToHost, s));
+    XTRG_HIP(hipMemcpyAsync(hal.data(), d_alive, sizeof(int) * n, hipMemcpyDeviceToHost, s));
     XTRG_HIP(hipStreamSynchronize(s));
     std::vector<int> chk;
     for (int j = 0; j < n; ++j) {
@@ -783,6 +837,8 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
           dirty = true;
         }
     }
+    for (int j = 0; j < n; ++j)
+      if (h[j].active) set_nbk(j);
   }
   for (int j = 0; j < n; ++j)
     if (jobs[j].len > 0 && jobs[j].p > 0) rank_columns(j);
