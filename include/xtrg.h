@@ -213,9 +213,10 @@ int xtrg_gemm_bf16x3(xtrg_ctx ctx, int M, int N, int K, int transA, int transB,
  * (Hestenes) Jacobi with column blocks. */
 int xtrg_dsvd_left(xtrg_ctx ctx, int len, int p, const double* Y, double* sigma, int k, double* U);
 /* xtrg_dqrcp: Householder QR with column pivoting of Y (len x p stored
- * column-major, device, not modified), triangular factor only: the start of
- * the truncated SVD of App. D.1 on a first visit (a preconditioner; the
- * result of the SVD does not depend on it).  Step r pivots the remaining
+ * column-major, device, not modified), triangular factor only: the first
+ * stage of the truncated SVD of App. D.1 on a first visit of a bond (the
+ * one-sided Jacobi then runs on R^T; the singular values and vectors agree
+ * with the Jacobi on Y to rounding).  Step r pivots the remaining
  * column of largest norm below row r, so that Y[:, piv] = Q R with R upper
  * triangular and |R_rr| non-increasing.  The factorisation stops when every
  * remaining column has norm^2 <= stop_rel^2 ||Y||_F^2 (stop_rel = 0: after
