@@ -39,16 +39,15 @@ def footprint_bytes(n_sites: int, D: int) -> int:
     """Device bytes one chain holds during a doubling at bond budget D (FP64):
     the per-site environment blocks 4 D^3 (L - 1), the warm-start bases
     (4D)(4D + 32) (L - 1), sites and their copies 4 x 4 D^2 L, environments,
-    the two-site overlap, SVD workspaces and those of the QR start of
-    first visits (factor, R^T, its Jacobi, basis block) and the Jacobi's
-    closing check (Z^T Z)."""
+    the two-site overlap, SVD workspaces, those of the QR route of first
+    visits and the Jacobi's closing check (Z^T Z)."""
     L = n_sites
     blocks = 4.0 * D ** 3 * (L - 1)
     warm = (4.0 * D) * (4.0 * D + 32) * (L - 1)
     sites = 4 * 4.0 * D * D * L
     envs = 2.0 * D ** 3 + 4.0 * D ** 3
     svd = 4 * (4.0 * D) * (4.0 * D + 32)
-    qr = 4 * (4.0 * D) * (4.0 * D + 32)
+    qr = 6 * (4.0 * D) * (4.0 * D + 32)      # factor, [R^T; I] and its Jacobi, Q [W S; 0], Gram check
     check = (4.0 * D + 32) ** 2
     return int(8 * (blocks + warm + sites + envs + svd + qr + check))
 
