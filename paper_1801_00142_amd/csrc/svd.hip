@@ -160,22 +160,35 @@ __device__ inline int xor_pair_x(int rr, int qq) {
 template <int MODE>
 __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict__ descs, int r, int smax,
                                                     double* __restrict__ parts) {
-  const JacobiDesc d = descs[blockIdx.y];
   const int pair = (int)blockIdx.x / smax, sl = (int)blockIdx.x % smax;
+  // A rotate launch's Gram values (this thread's entries of the slices'
+  // partials) sit at addresses fixed by the launch alone: their loads go out
+  // before the descriptor is read.  Every slot up to kMaxSplit is allocated;
+  // those past the problem's split are loaded and not used.
+  double* __restrict__ part = parts + ((size_t)blockIdx.y * kMaxPairs + pair) * kMaxSplit * kGramVals;
+  double pq[2][kMaxSplit];
+  if (MODE == ROUND_ROTATE) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int idx = threadIdx.x + k * kWT;
+#pragma unroll
+      for (int s2 = 0; s2 < kMaxSplit; ++s2) pq[k][s2] = idx < kGramVals ? part[s2 * kGramVals + idx] : 0.0;
+    }
+  }
+  const JacobiDesc d = descs[blockIdx.y];
   const int split = d.split;
   if (!d.active || r >= d.nbk - 1 || pair >= d.nbk / 2 || sl >= (MODE == ROUND_FUSED ? 1 : split)) return;
   int ra = 0, rb = d.len;                       // rows this workgroup rotates
   if (MODE != ROUND_FUSED) slice_rows(d.len, split, sl, &ra, &rb);
   int ga = 0, gb = d.glen;                      // rows of its Gram partial
   if (MODE == ROUND_GRAM) slice_rows(d.glen, split, sl, &ga, &gb);
-  double* __restrict__ part = parts + ((size_t)blockIdx.y * kMaxPairs + pair) * kMaxSplit * kGramVals;
   double* __restrict__ Y = d.Z;
   const int len = d.len, p = d.p, nbk = d.nbk;
   const double tol = d.tol;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  // loads whose latency overlaps the column lookup: ||Y||_F^2 for the zero
-  // threshold and, in a rotate launch, this thread's Gram values (the
-  // slices' partials summed in slice order)
+  // ||Y||_F^2 for the zero threshold (its latency overlaps the column
+  // lookup) and, in a rotate launch, the Gram values: the slices' partials
+  // summed in slice order
   const double fro2v = MODE == ROUND_GRAM ? 0.0 : d.fro2[0];
   double pv[2] = {0.0, 0.0};
   if (MODE == ROUND_ROTATE) {
@@ -183,10 +196,10 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
     for (int k = 0; k < 2; ++k) {
       const int idx = t + k * kWT;
       if (idx < kGramVals) {
-        double v = part[idx];
+        double v = pq[k][0];
 #pragma unroll
         for (int s2 = 1; s2 < kMaxSplit; ++s2)
-          if (s2 < split) v += part[s2 * kGramVals + idx];
+          if (s2 < split) v += pq[k][s2];
         pv[k] = v;
       }
     }
@@ -201,11 +214,16 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   __shared__ unsigned wmask[kWW];
   int bi, bj;
   rr_pair(nbk, r, pair, &bi, &bj);
-  if (t < kNC) {
-    const int rank = (t < kBlk ? bi : bj) * kBlk + (t % kBlk);
-    colid[t] = rank < p ? d.perm[rank] : -1;
-  }
-  __syncthreads();
+  // Column of member k (0 .. kNC-1) of the pair, -1 past the last column.
+  // A Gram launch's lanes look up their own columns (no LDS hop and no
+  // barrier before the column loads); a rotate launch first reads colid
+  // after the barrier that follows the Gram fill.
+  auto col_of = [&](int k) {
+    const int rank = (k < kBlk ? bi : bj) * kBlk + (k % kBlk);
+    return rank < p ? d.perm[rank] : -1;
+  };
+  if (MODE != ROUND_GRAM && t < kNC) colid[t] = col_of(t);
+  if (MODE == ROUND_FUSED) __syncthreads();
 
   // 1. Gram tiles (0,0), (0,1), (1,1) of the pair on the matrix cores,
   // operands straight from memory: per MFMA step a wave takes 4 rows, lane l
@@ -220,7 +238,8 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
 #pragma unroll
     for (int q = 0; q < 3; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
     const int lr = lane & 15, lk = lane >> 4;
-    const int c0 = colid[lr], c1 = colid[kBlk + lr];
+    const int c0 = MODE == ROUND_GRAM ? col_of(lr) : colid[lr];
+    const int c1 = MODE == ROUND_GRAM ? col_of(kBlk + lr) : colid[kBlk + lr];
     const double* __restrict__ y0 = Y + (long)(c0 >= 0 ? c0 : 0) * len;
     const double* __restrict__ y1 = Y + (long)(c1 >= 0 ? c1 : 0) * len;
     constexpr int U = 16;                      // row groups in flight per wave
