@@ -17,6 +17,16 @@ struct Error : std::runtime_error {
   Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
 };
 
+// Global-memory view of a pointer that a kernel reads from a descriptor in
+// memory (the compiler cannot tell its address space and would emit flat
+// accesses).  Flat loads and stores also count against the LDS wait that
+// precedes every barrier, so a load in flight or a store not yet
+// acknowledged holds up the next barrier; through this view they do not.
+template <class T>
+__device__ inline __attribute__((address_space(1))) T* gptr(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 #define XTRG_HIP(call)                                                              \
   do {                                                                              \
     hipError_t e_ = (call);                                                         \

@@ -37,6 +37,8 @@ constexpr int kIdxBits = 12;                  // column index in the low bits of
 constexpr unsigned long long kIdxMask = (1ull << kIdxBits) - 1;
 constexpr int kChunk = 64;                    // steps launched between checks for the stop
 
+// The kernels reach these pointers through their global views (gptr): no
+// flat access, so no store in flight holds up a barrier.
 struct QrDesc {
   double* A;                                  // len x p column-major, overwritten
   unsigned long long* keys;                   // 2 x nslot: workgroup keys, by step parity
@@ -84,7 +86,7 @@ __device__ inline void qr_post(const QrDesc& d, int parity, unsigned long long k
   if (t == 0 && (int)blockIdx.x < d.nslot) {
     unsigned long long m = red[0];
     for (int w = 1; w < kQT / 64; ++w) m = red[w] > m ? red[w] : m;
-    d.keys[(size_t)parity * d.nslot + blockIdx.x] = m;
+    gptr(d.keys)[(size_t)parity * d.nslot + blockIdx.x] = m;
   }
 }
 
@@ -93,7 +95,7 @@ __device__ inline unsigned long long qr_pivot_key(const QrDesc& d, int parity, u
   const int t = threadIdx.x;
   unsigned long long m = 0;
   for (int q = t; q < d.nslot; q += kQT) {
-    const unsigned long long k = d.keys[(size_t)parity * d.nslot + q];
+    const unsigned long long k = gptr(d.keys)[(size_t)parity * d.nslot + q];
     m = k > m ? k : m;
   }
   m = qr_wave_max(m);
@@ -112,11 +114,11 @@ __global__ __launch_bounds__(kQT) void qr_init(const QrDesc* __restrict__ descs)
   __shared__ unsigned long long red[kQT / 64];
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int gt = blockIdx.x * kQT + t;
-  if (gt < d.p) d.stepof[gt] = INT_MAX;
+  if (gt < d.p) gptr(d.stepof)[gt] = INT_MAX;
   const int c = blockIdx.x * (kQT / 64) + wave;
   double ss = 0.0;
   if (c < d.p) {
-    const double* __restrict__ y = d.A + (size_t)c * d.len;
+    const auto y = gptr(d.A) + (size_t)c * d.len;
     for (int r = lane; r < d.len; r += 64) ss = fma(y[r], y[r], ss);
   }
   ss = qr_wave_sum(ss);
@@ -133,8 +135,8 @@ __global__ __launch_bounds__(kQT) void qr_step(const QrDesc* __restrict__ descs,
   const int c = blockIdx.x * (kQT / 64) + wave;
   // this wave's column if not pivoted before: its loads are issued first,
   // the pivot (which it may turn out to be) is known after the reduction
-  bool mine = c < d.p && d.stepof[c] > i;
-  double* __restrict__ yc = d.A + (size_t)(mine ? c : 0) * d.len + i;
+  bool mine = c < d.p && gptr(d.stepof)[c] > i;
+  const auto yc = gptr(d.A) + (size_t)(mine ? c : 0) * d.len + i;
   double y[R];
 #pragma unroll
   for (int u = 0; u < R; ++u) {
@@ -143,10 +145,10 @@ __global__ __launch_bounds__(kQT) void qr_step(const QrDesc* __restrict__ descs,
   }
   __shared__ unsigned long long red[kQT / 64];
   const unsigned long long key = qr_pivot_key(d, i & 1, red);
-  if (!(qr_key_norm2(key) > d.stop_rel2 * d.fro2[0])) {     // every remaining column is numerically zero
+  if (!(qr_key_norm2(key) > d.stop_rel2 * gptr(d.fro2)[0])) {     // every remaining column is numerically zero
     if (t == 0) {
-      d.keys[(size_t)((i + 1) & 1) * d.nslot + blockIdx.x] = 0;   // so that every later step stops too
-      if (blockIdx.x == 0) atomicMin(d.keff, i);
+      gptr(d.keys)[(size_t)((i + 1) & 1) * d.nslot + blockIdx.x] = 0;   // so that every later step stops too
+      if (blockIdx.x == 0) __hip_atomic_fetch_min(gptr(d.keff), i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     return;
   }
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(kQT) void qr_step(const QrDesc* __restrict__ descs,
   // the reflector, from the pivot column (read only in this step)
   __shared__ double v[64 * R];
   __shared__ double rsum[kQT / 64];
-  const double* __restrict__ xc = d.A + (size_t)ci * d.len + i;
+  const auto xc = gptr(static_cast<const double*>(d.A)) + (size_t)ci * d.len + i;
   double ss = 0.0;
   for (int r = t; r < m; r += kQT) {
     const double x = xc[r];
@@ -173,35 +175,41 @@ __global__ __launch_bounds__(kQT) void qr_step(const QrDesc* __restrict__ descs,
   __syncthreads();                            // v[0] read by all before it is overwritten
   for (int r = t; r < m; r += kQT) v[r] = r == 0 ? 1.0 : v[r] * sc;
   __syncthreads();
+  // y <- (I - tau v v^T) y; norm^2 of rows i+1.. for the next pivot.  Every
+  // wave runs it on all its registers (rows past m and the columns of a
+  // wave with none hold zeros and stay zero): no register keeps a
+  // predicated-off load, so the stores below need no wait on memory.
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int r = lane + 64 * u;
+    s = fma(r < m ? v[r] : 0.0, y[u], s);
+  }
+  s = qr_wave_sum(s) * tau;
+  double n2 = 0.0;
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int r = lane + 64 * u;
+    y[u] = fma(-s, r < m ? v[r] : 0.0, y[u]);
+    const double w = r > 0 ? y[u] : 0.0;
+    n2 = fma(w, w, n2);
+  }
+  n2 = qr_wave_sum(n2);
+  qr_post(d, (i + 1) & 1, mine ? qr_key(n2, c) : 0ull, red);
+  // Stores after the key: nothing in this launch waits for them, so their
+  // latency overlaps that of the key's store (the next step reads both).
   if (blockIdx.x == 0 && t == 0) {
-    d.piv[i] = ci;
-    d.rdiag[i] = beta;
-    d.stepof[ci] = i;
+    gptr(d.piv)[i] = ci;
+    gptr(d.rdiag)[i] = beta;
+    gptr(d.stepof)[ci] = i;
   }
-  // y <- (I - tau v v^T) y; norm^2 of rows i+1.. for the next pivot
-  unsigned long long mykey = 0;
   if (mine) {
-    double s = 0.0;
 #pragma unroll
     for (int u = 0; u < R; ++u) {
       const int r = lane + 64 * u;
-      if (r < m) s = fma(v[r], y[u], s);
+      if (r < m) yc[r] = y[u];
     }
-    s = qr_wave_sum(s) * tau;
-    double n2 = 0.0;
-#pragma unroll
-    for (int u = 0; u < R; ++u) {
-      const int r = lane + 64 * u;
-      if (r < m) {
-        const double z = fma(-s, v[r], y[u]);
-        yc[r] = z;
-        if (r > 0) n2 = fma(z, z, n2);
-      }
-    }
-    n2 = qr_wave_sum(n2);
-    mykey = qr_key(n2, c);
   }
-  qr_post(d, (i + 1) & 1, mykey, red);
 }
 
 // R^T (p x keff, column-major, leading dimension ld): entry (c, r) is R's
@@ -256,7 +264,7 @@ __global__ __launch_bounds__(kQT) void qr_apply_kernel(const QrApply* __restrict
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int c = blockIdx.x * (kQT / 64) + wave;
   const bool mine = c < d.ncols;
-  double* __restrict__ mc = d.M + (size_t)(mine ? c : 0) * d.len;
+  const auto mc = gptr(d.M) + (size_t)(mine ? c : 0) * d.len;
   double y[R];
 #pragma unroll
   for (int u = 0; u < R; ++u) {
@@ -270,8 +278,8 @@ __global__ __launch_bounds__(kQT) void qr_apply_kernel(const QrApply* __restrict
     __syncthreads();                          // the previous stage's reflectors are used up
     for (int q = 0; q < i1 - i0; ++q) {
       const int i = i0 + q;
-      const double* __restrict__ xc = d.A + (size_t)d.piv[i] * d.len;
-      const double alpha = xc[i], beta = d.rdiag[i];
+      const auto xc = gptr(d.A) + (size_t)gptr(d.piv)[i] * d.len;
+      const double alpha = xc[i], beta = gptr(d.rdiag)[i];
       const double sc = 1.0 / (alpha - beta);
       for (int r = t; r < 64 * R; r += kQT) v[q][r] = (r < i || r >= d.len) ? 0.0 : r == i ? 1.0 : xc[r] * sc;
       if (t == 0) tau[q] = (beta - alpha) / beta;

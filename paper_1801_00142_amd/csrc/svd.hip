@@ -182,14 +182,17 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   if (MODE != ROUND_FUSED) slice_rows(d.len, split, sl, &ra, &rb);
   int ga = 0, gb = d.glen;                      // rows of its Gram partial
   if (MODE == ROUND_GRAM) slice_rows(d.glen, split, sl, &ga, &gb);
-  double* __restrict__ Y = d.Z;
+  // every pointer of the descriptor is read through its global view, so
+  // that the tiles loaded before the small Jacobi sweep stay in flight
+  // through its barriers
+  const auto Y = gptr(d.Z);
   const int len = d.len, p = d.p, nbk = d.nbk;
   const double tol = d.tol;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   // ||Y||_F^2 for the zero threshold (its latency overlaps the column
   // lookup) and, in a rotate launch, the Gram values: the slices' partials
   // summed in slice order
-  const double fro2v = MODE == ROUND_GRAM ? 0.0 : d.fro2[0];
+  const double fro2v = MODE == ROUND_GRAM ? 0.0 : gptr(d.fro2)[0];
   double pv[2] = {0.0, 0.0};
   if (MODE == ROUND_ROTATE) {
 #pragma unroll
@@ -220,7 +223,7 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   // after the barrier that follows the Gram fill.
   auto col_of = [&](int k) {
     const int rank = (k < kBlk ? bi : bj) * kBlk + (k % kBlk);
-    return rank < p ? d.perm[rank] : -1;
+    return rank < p ? gptr(d.perm)[rank] : -1;
   };
   if (MODE != ROUND_GRAM && t < kNC) colid[t] = col_of(t);
   if (MODE == ROUND_FUSED) __syncthreads();
@@ -240,8 +243,8 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
     const int lr = lane & 15, lk = lane >> 4;
     const int c0 = MODE == ROUND_GRAM ? col_of(lr) : colid[lr];
     const int c1 = MODE == ROUND_GRAM ? col_of(kBlk + lr) : colid[kBlk + lr];
-    const double* __restrict__ y0 = Y + (long)(c0 >= 0 ? c0 : 0) * len;
-    const double* __restrict__ y1 = Y + (long)(c1 >= 0 ? c1 : 0) * len;
+    const auto y0 = Y + (long)(c0 >= 0 ? c0 : 0) * len;
+    const auto y1 = Y + (long)(c1 >= 0 ? c1 : 0) * len;
     constexpr int U = 16;                      // row groups in flight per wave
     for (int g0 = a + wave * 4; g0 < b; g0 += kUW * 4 * U) {
       double a0[U], a1[U];
@@ -348,7 +351,9 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   worst = sqrt(worst);
   // block maximum published as the bit pattern of a non-negative double
   // (monotone under unsigned comparison)
-  if (t == 0 && sl == 0 && worst > 0.0) atomicMax(d.off, (unsigned long long)__double_as_longlong(worst));
+  if (t == 0 && sl == 0 && worst > 0.0)
+    __hip_atomic_fetch_max(gptr(d.off), (unsigned long long)__double_as_longlong(worst), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
   if (worst == 0.0) return;          // uniform: every thread read the same wmax
 
   // The first tiles that step 4 rotates are loaded now: their latency
