@@ -176,8 +176,9 @@ __global__ __launch_bounds__(kQT) void qr_step(const QrDesc* __restrict__ descs,
   for (int r = t; r < m; r += kQT) v[r] = r == 0 ? 1.0 : v[r] * sc;
   __syncthreads();
   // y <- (I - tau v v^T) y; norm^2 of rows i+1.. for the next pivot.  Every
-  // wave runs it on all its registers (rows past m and the columns of a
-  // wave with none hold zeros and stay zero): no register keeps a
+  // wave runs it on all its registers (rows past m hold zeros and stay
+  // zero; a wave with no column of its own, or with the pivot column,
+  // computes values that it neither stores nor posts): no register keeps a
   // predicated-off load, so the stores below need no wait on memory.
   double s = 0.0;
 #pragma unroll
