@@ -131,16 +131,17 @@ __device__ inline bool needs_rot(double a, double b, double g, double tol2, doub
 // tan = sign(d) h / (|d| + r) with d = b - a, h = 2g, r = |(d, h)|), in the
 // form c = sqrt(u / 2r), s = sign(d) h / sqrt(2 r u), u = |d| + r, which
 // needs one square root and one reciprocal square root in sequence (no
-// cancellation: u >= r); d and h are first scaled by a power of two so that
-// the squares cannot overflow or underflow.  c^2 + s^2 = 1 to a few ulp.
-// Identity if the pair needs none.  Branch-free (the value is selected at
-// the end), so that two rotations in one thread interleave their chains.
-__device__ inline void jacobi_rot(double a, double b, double g, double tol2, double zth, double* c, double* s) {
+// cancellation: u >= r).  d and h are first multiplied by fsc, the power
+// of two that brings ||Y||_F^2 into [1/2, 1): every Gram entry is at most
+// ||Y||_F^2, so |d| < 1 and |h| < 2, and a pair that needs a rotation has
+// |h| > 2 tol zth (a fixed fraction ~1e-38 of ||Y||_F^2): the squares can
+// neither overflow nor underflow.  c^2 + s^2 = 1 to a few ulp.  Identity
+// if the pair needs none.  Branch-free (the value is selected at the end),
+// so that two rotations in one thread interleave their chains.
+__device__ inline void jacobi_rot(double a, double b, double g, double tol2, double zth, double fsc, double* c,
+                                  double* s) {
   const bool need = needs_rot(a, b, g, tol2, zth);
-  const double d0 = b - a, h0 = need ? 2.0 * g : 1.0;
-  int e;
-  (void)frexp(fmax(fabs(d0), fabs(h0)), &e);
-  const double d = ldexp(d0, -e), h = ldexp(h0, -e);     // max(|d|, |h|) in [1/2, 1)
+  const double d = (b - a) * fsc, h = need ? 2.0 * g * fsc : 1.0;
   const double x = fma(d, d, h * h);
   const double r = x * rsq_refined(x);
   const double u = fabs(d) + r;
@@ -320,6 +321,9 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   // 2. Convergence measure.
   const double zth = d.zrel2 * fro2v;
   const double tol2 = tol * tol;
+  int efro;
+  (void)frexp(fro2v, &efro);
+  const double fsc = fro2v > 0.0 && isfinite(fro2v) ? ldexp(1.0, -efro) : 1.0;   // the rotations' scale
   double off = 0.0;                  // largest squared cosine
   unsigned mask = 0;                 // bit r: some pair (k, k ^ r) needs a rotation
   for (int idx = t; idx < (kNC / 2) * (kNC - 1); idx += kWT) {   // pair qq of XOR round rr
@@ -388,10 +392,9 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
     const bool gupd = t < 256, wupd = t >= 256 && t < 512;
     const int qc = (t >> 4) & 15, lo = t & 15;
     const int qr = t - 512;                   // rotation lane: pair index
-    auto next_round = [&](int r0) {
-      for (int r2 = r0 + 1; r2 < kNC; ++r2)
-        if ((mask >> r2) & 1u) return r2;
-      return 0;
+    auto next_round = [&](int r0) {            // next round after r0 with a rotation, 0 if none
+      const unsigned later = mask & ~((2u << r0) - 1u);
+      return later ? __builtin_ctz(later) : 0;
     };
     auto pair_x = [](int rr, int qq) { return xor_pair_x(rr, qq); };
     // pair index of member a in round rr
@@ -404,7 +407,7 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
     if (qr >= 0 && qr < kNC / 2 && rc) {
       const int x = pair_x(rc, qr), y = x ^ rc;
       double c, sn;
-      jacobi_rot(G[0][x][x], G[0][y][y], G[0][x][y], tol2, zth, &c, &sn);
+      jacobi_rot(G[0][x][x], G[0][y][y], G[0][x][y], tol2, zth, fsc, &c, &sn);
       rot[0][qr] = make_double2(c, sn);
     }
     __syncthreads();
@@ -455,7 +458,7 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
         const double nb = uy * (uy * gyy + vy * gyY) + vy * (uy * gYy + vy * gYY);
         const double ng = ux * (uy * gxy + vy * gxY) + vx * (uy * gXy + vy * gXY);
         double c, sn;
-        jacobi_rot(na, nb, ng, tol2, zth, &c, &sn);
+        jacobi_rot(na, nb, ng, tol2, zth, fsc, &c, &sn);
         rot[rb ^ 1][qr] = make_double2(c, sn);
       }
       src ^= 1;
