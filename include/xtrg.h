@@ -210,7 +210,11 @@ int xtrg_gemm_bf16x3(xtrg_ctx ctx, int M, int N, int K, int transA, int transB,
  * column-major (column j at Y + j*len, device), descending, into sigma
  * (device, p entries), and the left singular vectors of the first k of them
  * into U (device, column-major len x k).  Y is not modified.  One-sided
- * (Hestenes) Jacobi with column blocks. */
+ * (Hestenes) Jacobi with column blocks.  Range: ||Y||_F^2 must be a finite
+ * double (||Y||_F below ~1.3e154); the results scale exactly with a
+ * power-of-two scaling of Y as long as no squared column norm leaves the
+ * normal double range.  Len or p above 4096, or a NaN in Y, gives an
+ * error status. */
 int xtrg_dsvd_left(xtrg_ctx ctx, int len, int p, const double* Y, double* sigma, int k, double* U);
 /* xtrg_dqrcp: Householder QR with column pivoting of Y (len x p stored
  * column-major, device, not modified), triangular factor only: the first

@@ -118,12 +118,32 @@ __device__ inline double rsq_refined(double x) {
   return fma(y * r, fma(0.375, r, 0.5), y);
 }
 
+// The power of two that brings ||Y||_F^2 into [1/2, 1) (1 if it is zero or
+// not finite).  Every Gram entry is at most ||Y||_F^2, so entries times it
+// are at most 1 in magnitude and products of two of them cannot overflow;
+// the scaling is exact, so every test and ratio formed from scaled entries
+// is the one formed from the entries themselves wherever those do not
+// overflow or underflow.
+__device__ inline double gram_scale(double fro2) {
+  int e;
+  (void)frexp(fro2, &e);
+  return fro2 > 0.0 && isfinite(fro2) ? ldexp(1.0, -e) : 1.0;
+}
+
 // Whether the pair with Gram entries [[a, g], [g, b]] needs a rotation:
 // both columns above the numerical-zero threshold zth and the cosine
-// |g| / sqrt(a b) above tol (tested as g^2 > tol^2 a b).  The convergence
-// measure and the rotations use this one test.
-__device__ inline bool needs_rot(double a, double b, double g, double tol2, double zth) {
-  return a > zth && b > zth && g * g > tol2 * (a * b);
+// |g| / sqrt(a b) above tol (tested as g^2 > tol^2 a b on the entries times
+// fsc = gram_scale(||Y||_F^2)).  The convergence measure and the rotations
+// use this one test.
+__device__ inline bool needs_rot(double a, double b, double g, double tol2, double zth, double fsc) {
+  const double as = a * fsc, bs = b * fsc, gs = g * fsc;
+  return a > zth && b > zth && gs * gs > tol2 * (as * bs);
+}
+
+// Squared cosine g^2 / (a b) of a pair, from the scaled entries.
+__device__ inline double cos2(double a, double b, double g, double fsc) {
+  const double gs = g * fsc;
+  return gs * gs / ((a * fsc) * (b * fsc));
 }
 
 // Rotation (c, s) that zeroes the off-diagonal of [[a, g], [g, b]] under
@@ -131,16 +151,15 @@ __device__ inline bool needs_rot(double a, double b, double g, double tol2, doub
 // tan = sign(d) h / (|d| + r) with d = b - a, h = 2g, r = |(d, h)|), in the
 // form c = sqrt(u / 2r), s = sign(d) h / sqrt(2 r u), u = |d| + r, which
 // needs one square root and one reciprocal square root in sequence (no
-// cancellation: u >= r).  d and h are first multiplied by fsc, the power
-// of two that brings ||Y||_F^2 into [1/2, 1): every Gram entry is at most
-// ||Y||_F^2, so |d| < 1 and |h| < 2, and a pair that needs a rotation has
-// |h| > 2 tol zth (a fixed fraction ~1e-38 of ||Y||_F^2): the squares can
-// neither overflow nor underflow.  c^2 + s^2 = 1 to a few ulp.  Identity
+// cancellation: u >= r).  d and h are first multiplied by
+// fsc = gram_scale(||Y||_F^2), so |d| < 1 and |h| < 2, and a pair that
+// needs a rotation has |h| > 2 tol zth (a fixed fraction ~1e-38 of
+// ||Y||_F^2): the squares can neither overflow nor underflow.  c^2 + s^2 = 1 to a few ulp.  Identity
 // if the pair needs none.  Branch-free (the value is selected at the end),
 // so that two rotations in one thread interleave their chains.
 __device__ inline void jacobi_rot(double a, double b, double g, double tol2, double zth, double fsc, double* c,
                                   double* s) {
-  const bool need = needs_rot(a, b, g, tol2, zth);
+  const bool need = needs_rot(a, b, g, tol2, zth, fsc);
   const double d = (b - a) * fsc, h = need ? 2.0 * g * fsc : 1.0;
   const double x = fma(d, d, h * h);
   const double r = x * rsq_refined(x);
@@ -321,17 +340,15 @@ __global__ __launch_bounds__(kWT) void jacobi_round(const JacobiDesc* __restrict
   // 2. Convergence measure.
   const double zth = d.zrel2 * fro2v;
   const double tol2 = tol * tol;
-  int efro;
-  (void)frexp(fro2v, &efro);
-  const double fsc = fro2v > 0.0 && isfinite(fro2v) ? ldexp(1.0, -efro) : 1.0;   // the rotations' scale
+  const double fsc = gram_scale(fro2v);
   double off = 0.0;                  // largest squared cosine
   unsigned mask = 0;                 // bit r: some pair (k, k ^ r) needs a rotation
   for (int idx = t; idx < (kNC / 2) * (kNC - 1); idx += kWT) {   // pair qq of XOR round rr
     const int rr = 1 + idx / (kNC / 2), qq = idx % (kNC / 2);
     const int x = xor_pair_x(rr, qq), y = x ^ rr;
     const double a = G[0][x][x], b = G[0][y][y], g = G[0][x][y];
-    if (needs_rot(a, b, g, tol2, zth)) {
-      off = fmax(off, g * g / (a * b));
+    if (needs_rot(a, b, g, tol2, zth, fsc)) {
+      off = fmax(off, cos2(a, b, g, fsc));
       mask |= 1u << rr;
     }
   }
@@ -528,7 +545,8 @@ __global__ __launch_bounds__(256) void gram_check(const double* __restrict__ G, 
     const int x = (int)(idx / p), y = (int)(idx % p);
     if (y > x) {
       const double a = G[(long)x * p + x], b = G[(long)y * p + y], g = G[(long)x * p + y];
-      if (needs_rot(a, b, g, tol2, zrel2 * fro2[0])) worst = g * g / (a * b);
+      const double f2 = fro2[0], fsc = gram_scale(f2);
+      if (needs_rot(a, b, g, tol2, zrel2 * f2, fsc)) worst = cos2(a, b, g, fsc);
     }
   }
 #pragma unroll
@@ -748,7 +766,15 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
   for (int j = 0; j < n; ++j)
     if (h[j].active) prepare(j);
   XTRG_HIP(hipMemcpyAsync(hal.data(), d_alive, sizeof(int) * n, hipMemcpyDeviceToHost, s));
+  // ||Y||_F^2 must be finite: a NaN or Inf entry, or a norm beyond the
+  // double range, would leave every rotation test false
+  std::vector<double> f2(n, 0.0);
+  for (int j = 0; j < n; ++j)
+    if (h[j].active) XTRG_HIP(hipMemcpyAsync(&f2[j], h[j].fro2, sizeof(double), hipMemcpyDeviceToHost, s));
   XTRG_HIP(hipStreamSynchronize(s));
+  for (int j = 0; j < n; ++j)
+    if (h[j].active && !std::isfinite(f2[j]))
+      throw Error(-4, "svd: non-finite entry or ||Y||_F^2 beyond the double range");
   for (int j = 0; j < n; ++j)
     if (h[j].active) set_nbk(j);
   // Sliced launches pay off while the fused rounds would leave most compute

@@ -139,6 +139,57 @@ def test_svd_graded_spectrum(ctx, length, p):
         assert abs(abs(U[:, j] @ Ur[:, j]) - 1) < 1e-8
 
 
+@pytest.mark.parametrize("k", [400, -400])
+def test_svd_power_of_two_scale(ctx, k):
+    """Scaling Y by 2^k scales every Gram entry by 4^k and leaves the
+    rotations' operands (entries times one power of two fixed by ||Y||_F^2)
+    unchanged, so with no underflow or overflow anywhere the singular values
+    are exactly 2^k times those of Y and the left vectors are identical."""
+    import torch
+    length, p = 300, 256
+    rng = np.random.default_rng(77)
+    U0, _ = np.linalg.qr(rng.standard_normal((length, p)))
+    V0, _ = np.linalg.qr(rng.standard_normal((p, p)))
+    Y = (U0 * 10.0 ** -np.linspace(0, 14, p)) @ V0.T
+    kk = 64
+
+    def run(M):
+        sig = torch.zeros(p, dtype=torch.float64, device="cuda")
+        dU = torch.zeros((kk, length), dtype=torch.float64, device="cuda")
+        ctx.dsvd_left(length, p, _dev(M.T.copy()).data_ptr(), sig.data_ptr(), kk, dU.data_ptr())
+        torch.cuda.synchronize()
+        return sig.cpu().numpy(), dU.cpu().numpy()
+
+    s1, U1 = run(Y)
+    s2, U2 = run(np.ldexp(Y, k))
+    assert np.array_equal(s2, np.ldexp(s1, k))
+    assert np.array_equal(U2, U1)
+    s_ref = np.linalg.svd(np.ldexp(Y, k), compute_uv=False)
+    assert np.abs(s2 - s_ref).max() <= 100 * 2.2e-16 * s_ref[0] * math.sqrt(length)
+
+
+def test_svd_rejects_non_finite(ctx):
+    """A NaN or Inf entry, or a matrix whose ||Y||_F^2 overflows, is an error
+    (XTRG_ENUMERIC), not a silent result; the context stays usable."""
+    from paper_1801_00142_amd import XtrgError
+    import torch
+    rng = np.random.default_rng(9)
+    sig = torch.zeros(24, dtype=torch.float64, device="cuda")
+    bads = []
+    for v in (float("nan"), float("inf")):
+        Y = rng.standard_normal((40, 24))
+        Y[3, 5] = v
+        bads.append(Y)
+    bads.append(np.ldexp(rng.standard_normal((40, 24)), 520))     # entries ~1e156: the squares overflow
+    for Y in bads:
+        with pytest.raises(XtrgError, match="-4"):
+            ctx.dsvd_left(40, 24, _dev(Y.T.copy()).data_ptr(), sig.data_ptr(), 0, None)
+    Y = rng.standard_normal((40, 24))
+    ctx.dsvd_left(40, 24, _dev(Y.T.copy()).data_ptr(), sig.data_ptr(), 0, None)
+    torch.cuda.synchronize()
+    assert np.allclose(sig.cpu().numpy(), np.linalg.svd(Y, compute_uv=False), rtol=1e-13, atol=0)
+
+
 def test_svd_rank_deficient(ctx):
     """Exact rank 21 in a 64 x 64 matrix: the values beyond the rank are
     below the keep floor (40 eps sqrt(64) ||Y||_F), the leading ones exact."""
