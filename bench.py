@@ -37,7 +37,7 @@ PEAK_HBM_GBS = 8000.0
 # FETCH_SIZE + WRITE_SIZE scaled by a plain 1 GiB copy (FETCH x2.0, WRITE
 # x1.0); see the counters summary in profiles/.  Valid for the kernels as
 # measured: reset to None when they change.
-JACOBI_ROUND_TRAFFIC_1024 = None
+JACOBI_ROUND_TRAFFIC_1024 = 26.82e6
 
 
 def parse():

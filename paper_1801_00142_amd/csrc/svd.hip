@@ -154,13 +154,17 @@ __device__ inline double cos2(double a, double b, double g, double fsc) {
 // cancellation: u >= r).  d and h are first multiplied by
 // fsc = gram_scale(||Y||_F^2), so |d| < 1 and |h| < 2, and a pair that
 // needs a rotation has |h| > 2 tol zth (a fixed fraction ~1e-38 of
-// ||Y||_F^2): the squares can neither overflow nor underflow.  c^2 + s^2 = 1 to a few ulp.  Identity
-// if the pair needs none.  Branch-free (the value is selected at the end),
-// so that two rotations in one thread interleave their chains.
+// ||Y||_F^2): the squares can neither overflow nor underflow.
+// c^2 + s^2 = 1 to a few ulp.  Identity if the pair needs none.
+// Branch-free (the value is selected at the end), so that two rotations in
+// one thread interleave their chains.
 __device__ inline void jacobi_rot(double a, double b, double g, double tol2, double zth, double fsc, double* c,
                                   double* s) {
   const bool need = needs_rot(a, b, g, tol2, zth, fsc);
-  const double d = (b - a) * fsc, h = need ? 2.0 * g * fsc : 1.0;
+  // computed whether or not it is needed (a pair that needs none may give
+  // NaN here, which the selection drops), so that the test is not on the
+  // chain of the square roots
+  const double d = b * fsc - a * fsc, h = 2.0 * (g * fsc);
   const double x = fma(d, d, h * h);
   const double r = x * rsq_refined(x);
   const double u = fabs(d) + r;
