@@ -209,7 +209,8 @@ int xtrg_gemm_bf16x3(xtrg_ctx ctx, int M, int N, int K, int transA, int transB,
 /* xtrg_dsvd_left: singular values of the len x p matrix Y stored
  * column-major (column j at Y + j*len, device), descending, into sigma
  * (device, p entries), and the left singular vectors of the first k of them
- * into U (device, column-major len x k).  Y is not modified.  One-sided
+ * into U (device, column-major len x k; a zero column for a zero singular
+ * value).  Y is not modified.  One-sided
  * (Hestenes) Jacobi with column blocks.  Range: ||Y||_F^2 must be a finite
  * double (||Y||_F below ~1.3e154); the results scale exactly with a
  * power-of-two scaling of Y as long as no squared column norm leaves the

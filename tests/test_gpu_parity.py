@@ -190,6 +190,30 @@ def test_svd_rejects_non_finite(ctx):
     assert np.allclose(sig.cpu().numpy(), np.linalg.svd(Y, compute_uv=False), rtol=1e-13, atol=0)
 
 
+def test_svd_zero_and_rank_one(ctx):
+    """A zero matrix: every value 0 and zero vectors (no NaN).  Rank one:
+    sigma_1 = |u||v|, the rest below the keep floor, U[:, 0] = +-u/|u|
+    (vectors past the numerical rank are not defined: columns below the
+    zero threshold are never rotated)."""
+    import torch
+    sig = torch.full((12,), float("nan"), dtype=torch.float64, device="cuda")
+    dU = torch.full((3, 20), float("nan"), dtype=torch.float64, device="cuda")
+    ctx.dsvd_left(20, 12, _dev(np.zeros((12, 20))).data_ptr(), sig.data_ptr(), 3, dU.data_ptr())
+    torch.cuda.synchronize()
+    assert np.all(sig.cpu().numpy() == 0.0) and np.all(dU.cpu().numpy() == 0.0)
+    rng = np.random.default_rng(21)
+    u, v = rng.standard_normal(20), rng.standard_normal(12)
+    Y = np.outer(u, v)
+    ctx.dsvd_left(20, 12, _dev(Y.T.copy()).data_ptr(), sig.data_ptr(), 1, dU.data_ptr())
+    torch.cuda.synchronize()
+    s = sig.cpu().numpy()
+    u0 = dU.cpu().numpy()[0]
+    nrm = np.linalg.norm(u) * np.linalg.norm(v)
+    assert abs(s[0] - nrm) <= 1e-14 * nrm
+    assert np.all(s[1:] <= 40 * 2.220446049250313e-16 * math.sqrt(20) * nrm)
+    assert abs(abs(u0 @ u) / np.linalg.norm(u) - 1.0) < 1e-13
+
+
 def test_svd_rank_deficient(ctx):
     """Exact rank 21 in a 64 x 64 matrix: the values beyond the rank are
     below the keep floor (40 eps sqrt(64) ||Y||_F), the leading ones exact."""
