@@ -335,6 +335,21 @@ def test_dqrcp_degenerate_inputs(ctx):
     assert k == 12
 
 
+@pytest.mark.parametrize("k", [400, -400])
+def test_dqrcp_power_of_two_scale(ctx, k):
+    """Every step of the factorisation (squared norms, square roots, the
+    reflector's divisions, the pivot keys, which drop only mantissa bits,
+    and the relative stop) commutes with an exact scaling by 2^k: the same
+    pivots, the same number of rows, and R exactly 2^k times R of Y."""
+    rng = np.random.default_rng(41)
+    Y = rng.standard_normal((200, 150)) @ np.diag(10.0 ** -np.linspace(0, 12, 150))
+    k1, p1, R1 = _dqrcp(ctx, Y, 1e-9)
+    k2, p2, R2 = _dqrcp(ctx, np.ldexp(Y, k), 1e-9)
+    assert 0 < k1 < 150 and k2 == k1
+    assert np.array_equal(p2, p1)
+    assert np.array_equal(R2, np.ldexp(R1, k))
+
+
 def test_dqrcp_rejects_out_of_range(ctx):
     from paper_1801_00142_amd import XtrgError
     import torch
