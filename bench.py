@@ -247,7 +247,7 @@ def main():
         "svd_qr_start": {"factorizations": qr_stats["qr_calls"], "used": qr_stats["qr_used"],
                          "rejected": qr_stats["qr_rejected"],
                          "mean_rows": round(qr_stats["qr_rows"] / max(qr_stats["qr_calls"], 1), 1),
-                         "rt_sweeps_avg": round(qr_stats["qr_sweeps"] / max(qr_stats["qr_used"] + qr_stats["qr_rejected"], 1), 2)},
+                         "rt_sweeps_avg": round(qr_stats["qr_sweeps"] / max(qr_stats["qr_used"], 1), 2)},
         # the dominant kernel: the Jacobi rounds of the SVD (bytes = each
         # column of the visited pairs read and written once per round)
         "roofline": {"bound": "hbm", "kernel": "jacobi_round (one block-Jacobi SVD round: Gram + rotate launches over row slices)",

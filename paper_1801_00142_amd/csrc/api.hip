@@ -908,7 +908,10 @@ void qr_start(xtrg_ctx c, const std::vector<Chain*>& pre, xtrg::RoundTimer* rt) 
     const auto& J = qj[q];
     c->qr_calls += 1;
     c->qr_rows += J.keff;
-    if (4 * J.keff < C->p) continue;         // mostly noise: the Jacobi on Y itself
+    if (4 * J.keff < C->p) {                 // mostly noise: the Jacobi on Y itself
+      c->qr_rejected += 1;
+      continue;
+    }
     const long ld = (long)C->p + J.keff;
     double* RT = c->need("qr_rt" + C->tag, (size_t)ld * J.keff);
     xtrg::qr_rt(J, RT, ld, true, s);
