@@ -243,7 +243,7 @@ def main():
                      "bases_built": warm_stats["warm_built"], "bases_rejected": warm_stats["warm_rejected"],
                      "mean_completion": round(warm_stats["warm_m"] /
                                               max(warm_stats["warm_built"] + warm_stats["warm_rejected"], 1), 1)},
-        # first visits: column-pivoted QR, Jacobi on R^T, then the SVD from that basis
+        # first visits: column-pivoted QR, then the Jacobi on [R^T; I] (none on the tensor itself)
         "svd_qr_start": {"factorizations": qr_stats["qr_calls"], "used": qr_stats["qr_used"],
                          "rejected": qr_stats["qr_rejected"],
                          "mean_rows": round(qr_stats["qr_rows"] / max(qr_stats["qr_calls"], 1), 1),

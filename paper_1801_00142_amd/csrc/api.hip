@@ -881,14 +881,18 @@ void build_warm(xtrg_ctx c, Chain& C, const std::vector<double>& S, double keep_
   w.cols = cols;
 }
 
-// First visits of a bond (no basis from an earlier visit): a start for the
-// Jacobi from a column-pivoted QR of Y.  With Y P = Q R, the right singular
-// vectors of Y are those of R; the one-sided Jacobi on R^T (p x keff) finds
-// them in a fraction of the sweeps that it needs on Y (the pivoted factor is
-// graded), and they make a basis block as after a visit; the SVD then runs
-// on Y [Q0 X].  The QR stops at the Jacobi's numerical zero (a quarter of
-// the keep floor), since directions below it are never rotated.  All
-// chains at once: one grouped QR and one grouped Jacobi.
+// First visits of a bond (no basis from an earlier visit): the SVD of Y
+// through a column-pivoted QR.  With Y P = Q R, the one-sided Jacobi runs
+// on [R^T; I] (the Gram matrices from the first p rows): it converges in a
+// fraction of the sweeps that it needs on Y (the pivoted factor is graded)
+// and accumulates its rotations W in the identity rows, R^T W = U_R Sigma.
+// Then R = W Sigma U_R^T, and Q [W Sigma; 0] (Y's left singular vectors
+// times their values) becomes Y's SVD workspace: no Jacobi runs on Y.  The
+// QR stops at the Jacobi's numerical zero (a quarter of the keep floor),
+// since directions below it are never rotated; a factorisation with fewer
+// than a quarter as many rows as Y has columns is mostly noise, and that
+// chain runs the Jacobi on Y itself.  All chains at once: one grouped QR
+// and one grouped Jacobi.
 constexpr int kQrMin = 256;   // smallest SVD (rows and columns) that gets the QR start
 
 void qr_start(xtrg_ctx c, const std::vector<Chain*>& pre, xtrg::RoundTimer* rt) {
