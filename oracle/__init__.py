@@ -12,7 +12,7 @@ from the product path: the two share only the input descriptions in
 Modules
   ed           exact diagonalisation: dense H as a sum of Kronecker products
   mpo          automaton Hamiltonian MPO (App. B.1) and plain MPO algebra
-  xtrg         initial state (Sec. II.C, App. C.2), variational product
+  xtrg         initial state (Sec. II.C, Eq. RhoTau; App. C.2), variational product
                compression (App. D.1, Eq. LSEProd, Fig. VMPO), doubling
                (Eqs. rhoinit, rho:scale2), observables (Eq. ThermalQuan),
                MPO entanglement (Eq. purif)

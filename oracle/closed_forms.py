@@ -2,7 +2,7 @@
 
 * App. F: open XY chain, H = (J/2) sum (S+S- + S-S+), maps to free fermions
   with eps_k = J cos(k pi/(L+1)); Z = prod_k (1 + exp(-beta eps_k)).
-* High-temperature expansion (Sec. IV.A text around the c_V ~ 1/T^2 fit):
+* High-temperature expansion (Sec. III.B, next to the c_V ~ 1/T^2 fit):
   with Z0 = Tr I and Tr H = 0, ln Z = N ln 2 + beta^2 Tr(H^2)/(2 Z0)
   - beta^3 Tr(H^3)/(6 Z0) + O(beta^4).  For spin-1/2 XXZ bonds,
   Tr(h_b^2)/4 = (2 jxy^2 + jz^2)/16 per bond and distinct bonds are

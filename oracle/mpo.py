@@ -98,6 +98,20 @@ def hamiltonian(n, bonds, jxy, jz) -> List[np.ndarray]:
     return cap(xxz_automaton(n, bonds, jxy, jz), np.array([1.0, 0.0]), np.array([0.0, 1.0]))
 
 
+def local_sum(op: np.ndarray, n: int) -> List[np.ndarray]:
+    """MPO of sum_i op_i (op a single-site 2 x 2 operator) by the automaton
+    of App. B.1 with one operator per term: start -> start (I), start ->
+    stop (op), stop -> stop (I)."""
+    W = []
+    for _ in range(n):
+        T = np.zeros((2, 2, 2, 2))
+        T[0, :, :, 0] = I2
+        T[1, :, :, 1] = I2
+        T[0, :, :, 1] = op
+        W.append(T)
+    return cap(W, np.array([1.0, 0.0]), np.array([0.0, 1.0]))
+
+
 def to_dense(W: List[np.ndarray]) -> np.ndarray:
     """Contract an MPO into a dense 2^n x 2^n matrix (brute force)."""
     T = W[0]                                     # (1, s, s', D)
@@ -180,23 +194,6 @@ def norm(W: List[np.ndarray]) -> float:
 
 def bond_dims(W: List[np.ndarray]) -> List[int]:
     return [W[0].shape[0]] + [w.shape[3] for w in W]
-
-
-def right_canonicalize(W: List[np.ndarray], rel_floor: float = 0.0) -> List[np.ndarray]:
-    """Bring an MPO into right-canonical form by a right-to-left sweep of
-    SVDs (sites 1..n-1 right-isometric, the norm sits on site 0).  Singular
-    values <= rel_floor * sigma_max are dropped (exact zeros only, for
-    rel_floor at the rounding level)."""
-    W = [w.copy() for w in W]
-    for i in range(len(W) - 1, 0, -1):
-        Dl, d1, d2, Dr = W[i].shape
-        M = W[i].reshape(Dl, d1 * d2 * Dr)
-        U, S, Vt = np.linalg.svd(M, full_matrices=False)
-        k = int(np.sum(S > rel_floor * S[0])) if S.size and S[0] > 0 else 1
-        k = max(k, 1)
-        W[i] = Vt[:k].reshape(k, d1, d2, Dr)
-        W[i - 1] = np.einsum("astb,bk->astk", W[i - 1], U[:, :k] * S[:k])
-    return W
 
 
 def left_canonicalize(W: List[np.ndarray]) -> List[np.ndarray]:

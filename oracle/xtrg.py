@@ -2,12 +2,12 @@
 
 Test infrastructure: see the package docstring.  Follows, in order:
 
-* Sec. II.C, Eqs. (rhoinit) and (rho:scale2): rho_n = rho_{n-1} * rho_{n-1},
+* Sec. II.B, Eqs. (rhoinit) and (rho:scale2): rho_n = rho_{n-1} * rho_{n-1},
   tau_n = 2^n tau0, starting from rho(tau0) at tiny tau0.
-* Sec. II.D, Eq. (RhoTau) and App. C.2: rho(tau0) as the truncated
+* Sec. II.C, Eq. (RhoTau) and App. C.2: rho(tau0) as the truncated
   Maclaurin series sum_k (-tau0)^k/k! H^k; order 1 is I - tau0 H, exact at
   the bond dimension of H.
-* Sec. II.E: truncate by a fixed number of kept states, never by discarded
+* Sec. II.D: truncate by a fixed number of kept states, never by discarded
   weight.
 * App. D.1, Eqs. (MPO:prod), (LSEProd), Fig. VMPO: minimise
   ||A*B - C||_F^2 by two-site sweeps.  For C canonical about (i, i+1) the
@@ -16,9 +16,9 @@ Test infrastructure: see the package docstring.  Follows, in order:
   site (Fig. VMPO(c)); C_E is split by an SVD, U goes to C_i and Lambda V^T
   to C_{i+1} in a left-to-right sweep, Lambda joins U in a right-to-left
   sweep (Fig. VMPO(d)); a few full sweeps suffice.
-* Sec. II.C: Z(2 tau_n) = Tr(rho_n^T rho_n) = ||rho_n||_F^2.
+* Sec. II.B: Z(2 tau_n) = Tr(rho_n^T rho_n) = ||rho_n||_F^2.
 * Eq. (ThermalQuan): f, u, c_V.
-* Sec. V.A, Eq. (purif): entanglement of the vectorised MPO.
+* Sec. IV.A, Eq. (purif): entanglement of the vectorised MPO.
 
 Readings where the paper is silent (the same rules are used by the GPU
 library, implemented independently):
@@ -46,7 +46,7 @@ from . import mpo as M
 
 
 # --------------------------------------------------------------------------
-# Truncation rule (Sec. II.E: a fixed number of states; multiplet-safe cut)
+# Truncation rule (Sec. II.D: a fixed number of states; multiplet-safe cut)
 # --------------------------------------------------------------------------
 
 EPS = 2.220446049250313e-16
@@ -192,13 +192,17 @@ class CompressInfo:
 
 
 def square_compress(rho: List[np.ndarray], D: int, n_sweeps: int = 4,
-                    deg_rtol: float = 1e-6, sv_floor: float = 1e-14):
+                    deg_rtol: float = 1e-6, sv_floor: float = 1e-14, svd=None):
     """One doubling: C ~ rho*rho, compressed variationally to bond <= D.
 
     ``rho`` must be right-canonical with ||rho||_F = 1.  Returns the new
     normalised right-canonical MPO and a CompressInfo with ln c, where
     c = ||C||_F before normalisation, so lambda_{n+1} = 2 lambda_n + ln c.
+    ``svd`` factorises C_E (default: LAPACK gesdd through numpy); the tests
+    substitute other factorisations to measure how the result depends on it.
     """
+    if svd is None:
+        svd = lambda a: np.linalg.svd(a, full_matrices=False)
     n = len(rho)
     if n < 2:
         raise ValueError("need at least two sites")
@@ -222,7 +226,7 @@ def square_compress(rho: List[np.ndarray], D: int, n_sweeps: int = 4,
         Rb = right_block(R[i + 2], A[i + 1], B[i + 1])
         th = two_site_overlap(Lb, Rb)
         flops += _step_flops(L[i].shape, A[i].shape[3], B[i].shape[3], R[i + 2].shape)
-        U, S, Vt = np.linalg.svd(th, full_matrices=False)
+        U, S, Vt = svd(th)
         k = keep_count(S, D, deg_rtol, sv_floor, noise_floor(th))
         tot = float(np.sum(S * S))
         sv[i] = S.copy()
@@ -262,29 +266,44 @@ def _step_flops(Lshape, Da2, Db2, Rshape) -> float:
 
 
 # --------------------------------------------------------------------------
-# Observables (Eq. ThermalQuan; Sec. II.C for beta = 2 tau_n)
+# Observables (Eq. ThermalQuan; Sec. II.B for beta = 2 tau_n)
 # --------------------------------------------------------------------------
 
 def observables(rho: List[np.ndarray], lam: float, tau: float, H: List[np.ndarray],
                 n_sites: int) -> Dict[str, Dict[str, float]]:
     """f, u, c per site at beta = tau (Z = Tr rho) and at beta = 2 tau
-    (Z = Tr rho^T rho).  ``rho`` is the normalised MPO, rho_true = e^lam rho."""
+    (Z = Tr rho^T rho).  ``rho`` is the normalised MPO, rho_true = e^lam rho.
+
+    Also the invariants of the exact thermal state that the compression
+    must keep: herm_resid = ||rho - rho^T||^2 / ||rho||^2, <S^z_tot>, and
+    su2_resid = (<(S^x_tot)^2> - <(S^z_tot)^2>) / max(<(S^z_tot)^2>, 1)
+    (zero for an SU(2)-symmetric H while no multiplet is split)."""
+    n = len(rho)
+    SZ = M.local_sum(M.SZ, n)
+    SX = M.local_sum(0.5 * (M.SPLUS + M.SMINUS), n)
     out = {}
+    rt = M.transpose(rho)
+    nrm = M.inner(rho, rho)
+    herm = (M.inner(rho, rho) + M.inner(rt, rt) - 2.0 * M.inner(rho, rt)) / nrm
     tr = M.trace(rho)
     e1 = M.trace_of_product(H, rho) / tr
     e2 = M.trace_of_product(H, H, rho) / tr
+    z2 = M.trace_of_product(SZ, SZ, rho) / tr
+    x2 = M.trace_of_product(SX, SX, rho) / tr
     b = tau
     lnZ = lam + math.log(tr)
     out["tau"] = dict(beta=b, lnZ=lnZ, f=-lnZ / (n_sites * b), u=e1 / n_sites,
-                      c=b * b * (e2 - e1 * e1) / n_sites, tr=tr)
-    rt = M.transpose(rho)
-    nrm = M.inner(rho, rho)
+                      c=b * b * (e2 - e1 * e1) / n_sites, tr=tr, herm_resid=herm,
+                      sz_tot=M.trace_of_product(SZ, rho) / tr, su2_resid=(x2 - z2) / max(z2, 1.0))
     g1 = M.trace_of_product(H, rt, rho) / nrm
     g2 = M.trace_of_product(H, H, rt, rho) / nrm
+    z2 = M.trace_of_product(SZ, SZ, rt, rho) / nrm
+    x2 = M.trace_of_product(SX, SX, rt, rho) / nrm
     b = 2 * tau
     lnZ = 2 * lam + math.log(nrm)
     out["2tau"] = dict(beta=b, lnZ=lnZ, f=-lnZ / (n_sites * b), u=g1 / n_sites,
-                       c=b * b * (g2 - g1 * g1) / n_sites, norm2=nrm)
+                       c=b * b * (g2 - g1 * g1) / n_sites, norm2=nrm, herm_resid=herm,
+                       sz_tot=M.trace_of_product(SZ, rt, rho) / nrm, su2_resid=(x2 - z2) / max(z2, 1.0))
     return out
 
 
@@ -313,7 +332,7 @@ def entanglement(rho: List[np.ndarray]) -> np.ndarray:
 
 def run(n, bonds, jxy, jz, tau0: float, n_doublings: int, D: int, order: int = 1,
         n_sweeps: int = 4, deg_rtol: float = 1e-6, sv_floor: float = 1e-14,
-        with_entropy: bool = False, keep_states: bool = False):
+        with_entropy: bool = False, keep_states: bool = False, svd=None):
     """Full XTRG run; returns a list of per-doubling records."""
     H = M.hamiltonian(n, bonds, jxy, jz)
     rho, lam = init_rho(n, bonds, jxy, jz, tau0, order)
@@ -326,7 +345,7 @@ def run(n, bonds, jxy, jz, tau0: float, n_doublings: int, D: int, order: int = 1
         rec["rho"] = rho
     recs.append(rec)
     for k in range(1, n_doublings + 1):
-        rho, info = square_compress(rho, D, n_sweeps, deg_rtol, sv_floor)
+        rho, info = square_compress(rho, D, n_sweeps, deg_rtol, sv_floor, svd=svd)
         lam = 2 * lam + info.dlog_norm
         tau = 2 * tau
         rec = dict(n=k, tau=tau, lam=lam, obs=observables(rho, lam, tau, H, n),

@@ -18,6 +18,11 @@ from oracle import xtrg  # noqa: E402
 CASES = {
     # the L=10 chain workload: 2nd-order start at tau0 = 2^-10, 14 doublings, D = 64
     "chain10_D64": dict(workload="chain10", D=64, n_sweeps=4),
+    # L=12 chains whose centre bonds saturate at D = 128 and D = 256 (two-site
+    # tensors of 512 x 512 and 1024 x 1024, the shapes of the L=64 chain at
+    # those budgets): linear start at tau0 = 2^-8, 11 doublings, 2 sweeps
+    "chain12_D128": dict(workload="chain12", D=128, n_sweeps=2),
+    "chain12_D256": dict(workload="chain12", D=256, n_sweeps=2),
 }
 
 

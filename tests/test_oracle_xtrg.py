@@ -220,6 +220,64 @@ def _local_sum_mpo(op, n):
     return M.cap(W_, np.array([1.0, 0.0]), np.array([0.0, 1.0]))
 
 
+def test_local_sum_mpo_is_the_kronecker_sum():
+    """M.local_sum(op, n) == sum_i I x .. x op_i x .. x I (brute force)."""
+    n = 5
+    for op in (ed.SZ, ed.SX, np.array([[0.3, -1.2], [0.7, 2.0]])):
+        want = sum(np.kron(np.kron(np.eye(2 ** i), op), np.eye(2 ** (n - 1 - i))) for i in range(n))
+        assert np.abs(M.to_dense(M.local_sum(op, n)) - want).max() < 1e-14
+
+
+def test_invariant_fields_detect_what_they_measure():
+    """The invariant fields of observables() are zero where the symmetry
+    holds and measure its breaking where it does not: an XXZ chain
+    (jz != jxy) keeps <S^z_tot> = 0 and rho = rho^T but not SU(2); a
+    non-symmetric operator gives the closed-form herm_resid."""
+    lat = W.with_couplings(W.chain(6), 1.0, 2.0)
+    Hd = _dense_H(lat)
+    rh, lam = xtrg.init_rho(lat.n_sites, lat.bonds, lat.jxy, lat.jz, 0.5, 2)
+    H = M.hamiltonian(lat.n_sites, lat.bonds, lat.jxy, lat.jz)
+    o = xtrg.observables(rh, lam, 0.5, H, lat.n_sites)
+    R = M.to_dense(rh)
+    n = lat.n_sites
+    Sz = sum(np.kron(np.kron(np.eye(2 ** i), ed.SZ), np.eye(2 ** (n - 1 - i))) for i in range(n))
+    Sx = sum(np.kron(np.kron(np.eye(2 ** i), ed.SX), np.eye(2 ** (n - 1 - i))) for i in range(n))
+    for key, Rho in (("tau", R), ("2tau", R.T @ R)):
+        tr = np.trace(Rho)
+        z2, x2 = np.trace(Sz @ Sz @ Rho) / tr, np.trace(Sx @ Sx @ Rho) / tr
+        assert abs(o[key]["sz_tot"]) < 1e-13
+        assert abs(o[key]["su2_resid"] - (x2 - z2) / max(z2, 1.0)) < 1e-12
+        assert abs(o[key]["su2_resid"]) > 1e-3            # XXZ: no SU(2)
+        assert o[key]["herm_resid"] < 1e-14
+    # a non-symmetric operator: rho' = rho (I + a Sz S+) has
+    # ||rho' - rho'^T||^2 / ||rho'||^2 computed densely
+    X = R @ (np.eye(2 ** n) + 0.3 * Sz @ np.kron(np.array([[0.0, 1.0], [0.0, 0.0]]), np.eye(2 ** (n - 1))))
+    A = M.svd_compress(_dense_to_mpo(X, n), 10 ** 6)
+    nrm = M.inner(A, A)
+    o2 = xtrg.observables(M.scale(A, 1 / math.sqrt(nrm)), 0.0, 0.5, H, n)
+    Xd = M.to_dense(A)
+    want = np.linalg.norm(Xd - Xd.T) ** 2 / np.linalg.norm(Xd) ** 2
+    assert abs(o2["tau"]["herm_resid"] - want) < 1e-12 and want > 1e-3
+
+
+def _dense_to_mpo(X, n):
+    """Exact MPO of a dense 2^n x 2^n operator (successive reshapes and SVDs)."""
+    T = X.reshape([2] * (2 * n))
+    T = T.transpose([x for i in range(n) for x in (i, n + i)])   # (s0 s0' s1 s1' ...)
+    W = []
+    left = 1
+    rest = T.reshape(1, -1)
+    for i in range(n - 1):
+        rest = rest.reshape(left * 4, -1)
+        U, S, Vt = np.linalg.svd(rest, full_matrices=False)
+        k = int(np.sum(S > 1e-14 * S[0]))
+        W.append(U[:, :k].reshape(left, 2, 2, k))
+        rest = S[:k, None] * Vt[:k]
+        left = k
+    W.append(rest.reshape(left, 2, 2, 1))
+    return W
+
+
 def test_invariants_truncated():
     """T6: Tr rho > 0, Hermiticity, SU(2): <(Sx_tot)^2> = <(Sz_tot)^2>
     when no multiplet is split, <Sz_tot> = 0."""
@@ -239,6 +297,11 @@ def test_invariants_truncated():
         z2 = M.trace_of_product(sz, sz, rh) / tr
         assert abs(x2 - z2) < 1e-8 * max(1.0, z2)
         assert abs(M.trace_of_product(sz, rh) / tr) < 1e-12
+        o = r["obs"]
+        for key in ("tau", "2tau"):
+            assert o[key]["herm_resid"] < 1e-10
+            assert abs(o[key]["sz_tot"]) < 1e-12
+            assert abs(o[key]["su2_resid"]) < 1e-8
 
 
 def test_entanglement_brute_force_and_high_t():

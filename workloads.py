@@ -7,9 +7,9 @@ no tensor, no contraction), so that the FP64 oracle and the HIP library can
 both consume it without sharing any computation.
 
 Geometries follow the paper's models: the spin-1/2 Heisenberg / XXZ chain
-(Sec. IV, "Heisenberg chain"), the square lattice mapped to a 1D snake
+(Sec. III.B, "Heisenberg chain"), the square lattice (Sec. III.C) mapped to a 1D snake
 (Sec. II.A: range up to 2W-1, D_H = 3W+2 with open boundaries) and
-triangular-lattice YC cylinders (Sec. IV.C).  Cylinder embeddings where the
+triangular-lattice YC cylinders (Sec. III.D).  Cylinder embeddings where the
 paper only shows a figure are a stated reading: column-major site index
 j = x*W + y with y periodic.
 """
@@ -150,6 +150,9 @@ def workload(name: str, D: int | None = None) -> Workload:
 
     chain10   : Heisenberg chain L=10, tau0=2^-10, 2nd-order series start,
                 14 doublings (beta = 16), D = 64.
+    chain12   : Heisenberg chain L=12, tau0=2^-8, linear start, 11 doublings
+                (beta = 8, 16 via the Frobenius estimator); its centre bonds
+                saturate at D = 128 or 256 (parity case at full tensor shape).
     chain64   : Heisenberg chain L=64, tau0=2^-12, 18 doublings (beta = 64),
                 D = 128 or 256.
     square4x12: square YC W=4, L=12 (48 sites), tau0=2^-10, 15 doublings
@@ -159,6 +162,8 @@ def workload(name: str, D: int | None = None) -> Workload:
     """
     if name == "chain10":
         return Workload(name, chain(10), 2.0 ** -10, 14, D or 64, 2)
+    if name == "chain12":
+        return Workload(name, chain(12), 2.0 ** -8, 11, D or 256, 1)
     if name == "chain64":
         return Workload(name, chain(64), 2.0 ** -12, 18, D or 256, 1)
     if name == "square4x12":
