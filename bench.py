@@ -13,7 +13,7 @@ the actual bond dimensions) divided by the wall time of the timed steps.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--D 256] [--sweeps 2] [--batch N]
 
 --batch N runs N independent chains with interleaved temperature grids
-(tau0 * 2^(i/N), the z-shifts of Sec. II.C) through the batched doubling;
+(tau0 * 2^(i/N), the z-shifts of Sec. II.B) through the batched doubling;
 the value is then the whole batch's flops over its wall time.
 
 Prints one JSON line.  Only one GPU is used: --gpus above 1 exits.
@@ -111,6 +111,9 @@ def serve_main(args):
     dt = time.perf_counter() - t0
     prof = ctx.profile_report()
     ctx.profile(False)
+    failed = [k for k, v in res.items() if v["status"] != 0]
+    if failed:
+        print(f"requests that failed: {failed}", file=sys.stderr)
     lat = [v["latency_s"] for v in res.values()]
     flops = sum(v["flops"] for k, v in prof.items() if isinstance(v, dict) and k in
                 ("theta_gemm", "block_gemm", "env_gemm"))

@@ -4,7 +4,7 @@
  * XTRG (exponential thermal tensor renormalization group) cools a thermal
  * state by repeated squaring, rho(2 tau) = rho(tau) * rho(tau), with the
  * product of two matrix product operators (MPOs) compressed back to a bond
- * dimension D by variational two-site sweeps (paper: Sec. II.C, Eqs.
+ * dimension D by variational two-site sweeps (paper: Sec. II.B, Eqs.
  * (rhoinit), (rho:scale2); App. D.1, Eqs. (MPO:prod), (LSEProd), Fig. VMPO).
  *
  * Conventions for every call:
@@ -133,6 +133,7 @@ typedef struct {
   double flops;         /* algorithmic flops of the contractions (64 D^4 per uniform step) */
   double* sv;           /* optional, caller-sized (L-1)*sv_stride: per-bond sigma of the last visit */
   int sv_stride;        /* entries per bond in sv (values beyond the bond's count are zero) */
+  int status;           /* out: XTRG_OK, or the code that stopped this chain (batched call) */
 } xtrg_compress_info;
 
 /* One XTRG doubling (Eqs. rhoinit, rho:scale2): rho_out ~ rho_in * rho_in
@@ -149,7 +150,7 @@ int xtrg_square_compress(xtrg_ctx ctx, xtrg_mpo rho_in, const xtrg_compress_opts
                          xtrg_mpo* rho_out, xtrg_compress_info* info);
 
 /* The same doubling for n independent chains at once, e.g. the interleaved
- * temperature grids tau0 = 2^(z-1) tau0' of the z-shift average (Sec. II.C),
+ * temperature grids tau0 = 2^(z-1) tau0' of the z-shift average (Sec. II.B, Eq. zshift),
  * other couplings, lengths or bond budgets.  Chain q runs with opts[q]; the
  * chains advance one two-site step each per batch step (each on its own bond
  * schedule, so lengths and sweep counts may differ), and the latency-bound
@@ -157,7 +158,15 @@ int xtrg_square_compress(xtrg_ctx ctx, xtrg_mpo rho_in, const xtrg_compress_opts
  * what xtrg_square_compress returns for that chain alone: the same kernels
  * on the same data in the same order.
  * rho_in, opts, rho_out: n entries each.  rho_out entries are set to NULL on
- * entry; on success all n are new handles, on failure none is left to release.
+ * entry.  The chains are independent (Sec. II.B: each z-shift is its own
+ * run), and so are their failures: a chain whose tensors turn non-finite
+ * (XTRG_ENUMERIC) or whose memory the HBM budget refuses (XTRG_ENOMEM) stops
+ * with rho_out[q] = NULL and info[q].status set, while every other chain
+ * finishes with the result it would have had alone.  Return value: XTRG_OK
+ * if every chain finished; otherwise the status of the first chain that
+ * stopped (the finished chains' handles are still returned and must be
+ * released; xtrg_last_error names the chain).  Argument and runtime errors
+ * (XTRG_EINVAL, XTRG_EDEVICE) stop the whole call with no handle to release.
  * info: NULL or n entries (each with its own optional sv buffer).
  * Device memory grows with n: one set of per-site environment blocks per
  * chain (about 4 D^3 (L-1) doubles at bond D). */
@@ -168,17 +177,67 @@ int xtrg_square_compress_batched(xtrg_ctx ctx, int n, const xtrg_mpo* rho_in,
 /* Thermodynamics of a normalised MPO rho (rho_true = exp(log_norm) rho),
  * Eq. (ThermalQuan): f = -ln Z/(N beta), u = <H>/N, c = beta^2 (<H^2> - <H>^2)/N.
  * at_tau : beta = tau_n, Z = Tr rho.
- * at_2tau: beta = 2 tau_n, Z = Tr rho^T rho = ||rho||_F^2 (Sec. II.C).
+ * at_2tau: beta = 2 tau_n, Z = Tr rho^T rho = ||rho||_F^2 (Sec. II.B).
  * S_E_per_bond (optional, L-1 entries): von Neumann entropy of the
- * normalised vectorised MPO across every bond (Eq. purif), at beta = 2 tau_n. */
+ * normalised vectorised MPO across every bond (Eq. purif), at beta = 2 tau_n;
+ * at_2tau->S_E_center / S_E_max are filled only when it is given (the
+ * canonical pass it needs costs a sweep of SVDs), else 0. */
 typedef struct {
   double beta, lnZ, f, u, c;
   double tr_rho;      /* Tr rho (at_tau) or ||rho||_F^2 (at_2tau) of the normalised MPO */
   double S_E_center, S_E_max;
+  /* Invariants of the exact thermal state, as checks of the compression:
+   * herm_resid = ||rho - rho^T||_F^2 / ||rho||_F^2 (0: rho is symmetric),
+   * sz_tot     = <S^z_tot> (0 for any XXZ Hamiltonian: U(1) symmetry),
+   * su2_resid  = (<(S^x_tot)^2> - <(S^z_tot)^2>) / max(<(S^z_tot)^2>, 1)
+   *              (0 for the SU(2)-symmetric Heisenberg case jxy = jz, and
+   *              only while no multiplet is split), with the expectation
+   *              values of the row's estimator. */
+  double herm_resid, sz_tot, su2_resid;
 } xtrg_obs;
 
 int xtrg_observables(xtrg_ctx ctx, xtrg_mpo rho, double log_norm, double tau_n, xtrg_mpo H,
                      int n_sites, xtrg_obs* at_tau, xtrg_obs* at_2tau, double* S_E_per_bond);
+
+/* Serving (continuous batching of thermal solves, Sec. II.B: independent
+ * runs such as the z-shifted grids of Eq. (zshift) advance together).
+ *
+ * xtrg_serve_submit queues one XTRG run given as a JSON object:
+ *   {"n_sites": L, "bonds": [[i, j], ...], "jxy": x or [x per bond],
+ *    "jz": x or [...], "tau0": t, "n_doublings": n, "D": D,
+ *    "n_sweeps": 2, "order": 1, "precision": "fp64"|"fp32"|"bf16x3",
+ *    "beta_mix": 1.0}
+ * (the last five optional, with these defaults; precision applies to the
+ * doublings that reach beta >= beta_mix, earlier ones run in FP64) and
+ * returns its id.  A worker thread owned by the context admits queued runs
+ * in arrival order whenever their device-memory estimates fit the budget
+ * (the context's hbm_budget, or 85% of the free device memory when the
+ * worker starts if that is 0), after the context's shared workspaces
+ * (64 MiB plus 128 (4D)^2 bytes for the largest D admitted); per run
+ * 8 [4 D^3 (L-1) + (4D)(4D+32)(L+9) + 16 D^2 L + 6 D^3 + (4D+32)^2] bytes
+ * plus 4 MiB.  A run that could not fit even alone fails with XTRG_ENOMEM.
+ * The allocator enforces the same budget, so an estimate that falls short
+ * fails that run with XTRG_ENOMEM, not the others.  It advances all admitted runs by one doubling per batch
+ * step with xtrg_square_compress_batched, accumulates lambda and the
+ * observables after every doubling, and retires finished runs at once;
+ * runs submitted meanwhile join at the next step.  A run whose numbers turn
+ * non-finite or whose memory the budget refuses fails alone.  Each run's
+ * records equal those of the same run served alone.
+ * While the worker has work, the context's other compute calls return
+ * XTRG_EBUSY; submit and poll may be called from any thread.
+ * Errors: XTRG_EINVAL for malformed requests (nothing queued).
+ *
+ * xtrg_serve_poll: XTRG_EBUSY while the run is queued or running, XTRG_EINVAL
+ * for an unknown id or a buffer (cap bytes) too small; otherwise XTRG_OK
+ * and the result JSON:
+ *   {"id", "status" (XTRG_OK or the code that stopped the run), "error",
+ *    "submitted_s", "admitted_s", "finished_s", "latency_s" (seconds on the
+ *    server's clock), "doublings", "records": [{"n", "tau", "lam",
+ *    "bond_dims", "f_tau", "u_tau", "c_tau", "f_2tau", "u_2tau", "c_2tau",
+ *    "herm_resid", "sz_tot", "su2_resid", "trunc_err"}, ...]}
+ * with one record for rho(tau0) and one per completed doubling. */
+int xtrg_serve_submit(xtrg_ctx ctx, const char* request_json, unsigned long long* id);
+int xtrg_serve_poll(xtrg_ctx ctx, unsigned long long id, char* result_json, size_t cap);
 
 /* Timing of the doubling's phases (two-site overlap GEMM, left/right block
  * GEMMs, environment GEMMs, SVD, split/projection) with HIP events on the
@@ -217,6 +276,17 @@ int xtrg_gemm_bf16x3(xtrg_ctx ctx, int M, int N, int K, int transA, int transB,
  * normal double range.  Len or p above 4096, or a NaN in Y, gives an
  * error status. */
 int xtrg_dsvd_left(xtrg_ctx ctx, int len, int p, const double* Y, double* sigma, int k, double* U);
+/* xtrg_dsvd_left_qr: the same truncated SVD routed as a first visit of a
+ * bond is in xtrg_square_compress (App. D.1, SVD of C_E): column-pivoted
+ * QR Y P = Q R stopped at a quarter of the numerical-zero level, one-sided
+ * Jacobi on [R^T; I] with its rotations W accumulated, left singular
+ * vectors Q W.  sigma (device, p entries): the *keff (host) resolved values
+ * descending, zeros after them; U (device, column-major len x k, k <= *keff):
+ * the leading left singular vectors.  Y is not modified.  Requires
+ * 1 <= len <= 2048, 1 <= p <= 2048; XTRG_EINVAL otherwise, XTRG_ENUMERIC if
+ * fewer than p/4 rows of R lie above the stop (a matrix that is mostly
+ * rounding noise, which the doubling factorises by the Jacobi on Y). */
+int xtrg_dsvd_left_qr(xtrg_ctx ctx, int len, int p, const double* Y, double* sigma, int k, double* U, int* keff);
 /* xtrg_dqrcp: Householder QR with column pivoting of Y (len x p stored
  * column-major, device, not modified), triangular factor only: the first
  * stage of the truncated SVD of App. D.1 on a first visit of a bond (the

@@ -15,7 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["api.hip", "gemm.hip", "svd.hip", "qr.hip", "misc.hip"]
+SOURCES = ["api.hip", "serve.hip", "gemm.hip", "svd.hip", "qr.hip", "misc.hip"]
 LIB = os.path.join(HERE, "libxtrg.so")
 
 

@@ -10,103 +10,17 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
 
 #include "internal.h"
+#include "context.h"
 
 using xtrg::Error;
 using xtrg::Gemm;
 
-// ---------------------------------------------------------------------------
-// Context and device memory
-// ---------------------------------------------------------------------------
-
-struct DevBuf {
-  double* p = nullptr;
-  size_t cap = 0;  // doubles
-};
-
-struct xtrg_ctx_s {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  size_t budget = 0;
-  size_t bytes = 0;
-  std::string err;
-  std::map<std::string, DevBuf> ws;   // named, grow-only workspaces
-  double* scratch = nullptr;          // 2048 doubles: reductions, small vectors
-
-  // Optional timing of the doubling's phases with HIP events on `stream`.
-  struct Prof {
-    int cat;
-    hipEvent_t a, b;
-    double flops, bytes;
-    long launches;
-  };
-  bool prof = false;
-  std::vector<Prof> prof_recs;
-  long svd_calls = 0, svd_sweeps = 0;
-  // warm-start statistics: bases built, rejected, used; sum of completion sizes m
-  long warm_built = 0, warm_rejected = 0, warm_used = 0, warm_m = 0;
-  // QR-preconditioned first visits: factorisations, their rows, Jacobi
-  // sweeps on R^T, starts used, bases rejected by the orthogonality check
-  long qr_calls = 0, qr_rows = 0, qr_sweeps = 0, qr_used = 0, qr_rejected = 0;
-
-  double* alloc(size_t n) {
-    const size_t b = std::max<size_t>(n, 1) * sizeof(double);
-    if (budget && bytes + b > budget)
-      throw Error(XTRG_ENOMEM, "HBM budget exceeded (" + std::to_string(bytes + b) + " > " +
-                                   std::to_string(budget) + " bytes)");
-    double* p = nullptr;
-    if (hipMalloc(&p, b) != hipSuccess) {
-      (void)hipGetLastError();
-      throw Error(XTRG_ENOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed");
-    }
-    bytes += b;
-    return p;
-  }
-  void release(double* p, size_t n) {
-    if (!p) return;
-    // work queued on the stream may still read p
-    if (stream) (void)hipStreamSynchronize(stream);
-    else (void)hipDeviceSynchronize();
-    (void)hipFree(p);
-    bytes -= std::max<size_t>(n, 1) * sizeof(double);
-  }
-  double* need(const std::string& name, size_t n) {
-    DevBuf& d = ws[name];
-    if (d.cap < n) {
-      release(d.p, d.cap);
-      d.p = nullptr;
-      d.cap = 0;
-      d.p = alloc(n);
-      d.cap = n;
-    }
-    return d.p;
-  }
-};
-
-struct Site {
-  double* p = nullptr;
-  size_t n = 0;
-};
-
-struct xtrg_mpo_s {
-  xtrg_ctx ctx = nullptr;
-  int L = 0;
-  std::vector<int> dims;      // L+1
-  std::vector<Site> site;     // device [Dl][2][2][Dr]
-  // Hamiltonians built here keep the un-capped right end ([Dl][2][2][2],
-  // last index: start, stop) on the host for the series start.
-  bool has_open = false;
-  std::vector<double> open_last;
-
-  ~xtrg_mpo_s() {
-    for (auto& s : site) ctx->release(s.p, s.n);
-  }
-  size_t elems(int i) const { return (size_t)dims[i] * 4 * dims[i + 1]; }
-};
 
 namespace {
 
@@ -141,6 +55,7 @@ struct Timed {
 
 template <class F>
 int guarded(xtrg_ctx ctx, F&& f) {
+  if (ctx && ctx->serving.load()) return XTRG_EBUSY;   // the serving loop owns the stream
   try {
     f();
     if (ctx) ctx->err.clear();
@@ -644,6 +559,9 @@ struct Chain {
   int mL = 0, mR = 0, Kt = 0, len = 0, p = 0;
   int psvd = 0;                           // columns of the SVD input (p, or p + extra with a warm start)
   bool svd_done = false;                  // the QR start produced this step's factorisation
+  bool warm_now = false;                  // this step's SVD input was rotated by a warm basis
+  int status = 0;                         // XTRG_OK, or the code that stopped this chain
+  std::string err;                        // and its message
 };
 
 void check_opts(const xtrg_compress_opts& o) {
@@ -895,32 +813,45 @@ void build_warm(xtrg_ctx c, Chain& C, const std::vector<double>& S, double keep_
 // and one grouped Jacobi.
 constexpr int kQrMin = 256;   // smallest SVD (rows and columns) that gets the QR start
 
-void qr_start(xtrg_ctx c, const std::vector<Chain*>& pre, xtrg::RoundTimer* rt) {
+// One SVD routed through the QR: Y (len x p, column-major) in, on success
+// an SVD workspace of len x psvd columns (Q [W Sigma; 0]) that the Jacobi
+// would have left, with done = true.  `tag` names the workspaces.
+struct QrTask {
+  int len = 0, p = 0;
+  const double* Y = nullptr;
+  std::string tag;
+  double* work = nullptr;   // out: SVD workspace
+  int psvd = 0;             // out: its columns (the rows of R kept)
+  bool done = false;        // out: false if the factorisation was rejected (mostly noise)
+  bool failed = false;      // out: the Jacobi on [R^T; I] failed (non-finite input, no convergence)
+};
+
+void qr_factorise(xtrg_ctx c, std::vector<QrTask*>& tasks, xtrg::RoundTimer* rt) {
   hipStream_t s = c->stream;
-  const int n = (int)pre.size();
+  const int n = (int)tasks.size();
   std::vector<xtrg::QrJob> qj;
-  for (Chain* C : pre)
-    qj.push_back(xtrg::QrJob{C->len, C->p, C->th, c->need("qr" + C->tag, xtrg::qr_work(C->len, C->p)),
-                             0.25 * xtrg::svd_keep_rel(C->len, C->p), 0});
+  for (QrTask* T : tasks)
+    qj.push_back(xtrg::QrJob{T->len, T->p, T->Y, c->need("qr" + T->tag, xtrg::qr_work(T->len, T->p)),
+                             0.25 * xtrg::svd_keep_rel(T->len, T->p), 0});
   xtrg::qrcp_batched(qj, qr_desc(c, n), s);
   // Jacobi on [R^T; I]: orthogonal columns on the first p rows, the
   // accumulated rotation W below
   std::vector<xtrg::SvdJob> sj;
   std::vector<int> at;
   for (int q = 0; q < n; ++q) {
-    Chain* C = pre[q];
+    QrTask* T = tasks[q];
     const auto& J = qj[q];
     c->qr_calls += 1;
     c->qr_rows += J.keff;
-    if (4 * J.keff < C->p) {                 // mostly noise: the Jacobi on Y itself
+    if (4 * J.keff < T->p) {                 // mostly noise: the Jacobi on Y itself
       c->qr_rejected += 1;
       continue;
     }
-    const long ld = (long)C->p + J.keff;
-    double* RT = c->need("qr_rt" + C->tag, (size_t)ld * J.keff);
+    const long ld = (long)T->p + J.keff;
+    double* RT = c->need("qr_rt" + T->tag, (size_t)ld * J.keff);
     xtrg::qr_rt(J, RT, ld, true, s);
-    sj.push_back(xtrg::SvdJob{(int)ld, J.keff, RT, c->need("qr_svd" + C->tag, xtrg::svd_work((int)ld, J.keff)), 0,
-                              svd_gram(c, C->tag, J.keff), C->p});
+    sj.push_back(xtrg::SvdJob{(int)ld, J.keff, RT, c->need("qr_svd" + T->tag, xtrg::svd_work((int)ld, J.keff)), 0,
+                              svd_gram(c, T->tag, J.keff), T->p});
     at.push_back(q);
   }
   if (sj.empty()) return;
@@ -931,25 +862,53 @@ void qr_start(xtrg_ctx c, const std::vector<Chain*>& pre, xtrg::RoundTimer* rt) 
   std::vector<double*> Ms;
   std::vector<int> nc;
   for (size_t t = 0; t < sj.size(); ++t) {
-    Chain* C = pre[at[t]];
+    QrTask* T = tasks[at[t]];
+    if (sj[t].status != 0) {
+      T->failed = true;
+      continue;
+    }
     const int keff = sj[t].p;
     c->qr_sweeps += sj[t].sweeps;
-    double* M = c->need("qr_M" + C->tag, (size_t)C->len * keff);
-    xtrg::qr_lift(sj[t].work, sj[t].len, C->p, keff, xtrg::svd_column_norms(sj[t].work, sj[t].len, keff), M, C->len, s);
+    double* Mm = c->need("qr_M" + T->tag, (size_t)T->len * keff);
+    xtrg::qr_lift(sj[t].work, sj[t].len, T->p, keff, xtrg::svd_column_norms(sj[t].work, sj[t].len, keff), Mm,
+                  T->len, s);
     aj.push_back(qj[at[t]]);
-    Ms.push_back(M);
+    Ms.push_back(Mm);
     nc.push_back(keff);
   }
-  xtrg::qr_apply_q(aj, Ms, nc, qr_desc(c, n), s);
+  if (!aj.empty()) xtrg::qr_apply_q(aj, Ms, nc, qr_desc(c, n), s);
   for (size_t t = 0; t < sj.size(); ++t) {
-    Chain* C = pre[at[t]];
+    QrTask* T = tasks[at[t]];
+    if (T->failed) continue;
     const int keff = sj[t].p;
-    C->work = c->need("svd" + C->tag, xtrg::svd_work(C->len, keff));
-    xtrg::svd_adopt(C->len, keff, Ms[t], C->work, s);
-    C->psvd = keff;
-    C->svd_done = true;
+    T->work = c->need("svd" + T->tag, xtrg::svd_work(T->len, keff));
+    xtrg::svd_adopt(T->len, keff, Ms[t], T->work, s);
+    T->psvd = keff;
+    T->done = true;
     c->qr_used += 1;
   }
+}
+
+void qr_start(xtrg_ctx c, const std::vector<Chain*>& pre, xtrg::RoundTimer* rt) {
+  std::vector<QrTask> tk(pre.size());
+  std::vector<QrTask*> tp;
+  for (size_t q = 0; q < pre.size(); ++q) {
+    tk[q].len = pre[q]->len;
+    tk[q].p = pre[q]->p;
+    tk[q].Y = pre[q]->th;
+    tk[q].tag = pre[q]->tag;
+    tp.push_back(&tk[q]);
+  }
+  qr_factorise(c, tp, rt);
+  for (size_t q = 0; q < pre.size(); ++q)
+    if (tk[q].failed) {
+      pre[q]->status = XTRG_ENUMERIC;
+      pre[q]->err = "two-site tensor: non-finite entries or no convergence of the SVD (QR route)";
+    } else if (tk[q].done) {
+      pre[q]->work = tk[q].work;
+      pre[q]->psvd = tk[q].psvd;
+      pre[q]->svd_done = true;
+    }
 }
 
 // After the SVD of the chain's two-site overlap: choose k, split into C_i and
@@ -1007,13 +966,31 @@ void chain_truncate_split(xtrg_ctx c, Chain& C) {
   }
 }
 
+// Runs f for one chain; an error that belongs to that chain alone (bad
+// numbers in its tensors, its memory refused by the budget) stops only
+// that chain, runtime errors stop the call.
+template <class F>
+void per_chain(Chain& C, F&& f) {
+  if (C.status != XTRG_OK) return;
+  try {
+    f();
+  } catch (const Error& e) {
+    if (e.code != XTRG_ENUMERIC && e.code != XTRG_ENOMEM) throw;
+    C.status = e.code;
+    C.err = e.what();
+  }
+}
+
 // One XTRG doubling of n independent chains at once.  Every chain follows
 // its own bond schedule (lengths and sweep counts may differ); step st of
 // all chains that still have one is issued together: the GEMMs per chain on
 // the one stream, and the Jacobi rounds of all their SVDs as one grouped
-// launch per round.  n = 1 is the plain single-chain doubling.
-void square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_compress_opts* opts,
-                          xtrg_mpo* outs, xtrg_compress_info* infos) {
+// launch per round.  n = 1 is the plain single-chain doubling.  A chain
+// whose numbers turn non-finite or whose memory the budget refuses stops
+// with its own status (outs[q] = NULL, infos[q].status); the others finish.
+// Returns the number of chains that failed.
+int square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_compress_opts* opts,
+                         xtrg_mpo* outs, xtrg_compress_info* infos, std::string* first_err) {
   if (n < 1) throw Error(XTRG_EINVAL, "need at least one chain");
   for (int q = 0; q < n; ++q) {
     if (!ins[q]) throw Error(XTRG_EINVAL, "null input MPO");
@@ -1026,16 +1003,17 @@ void square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_com
   size_t n_steps = 0;
   for (int q = 0; q < n; ++q) {
     ch[q].o = opts[q];
-    chain_setup(c, ch[q], ins[q], q);
+    per_chain(ch[q], [&] { chain_setup(c, ch[q], ins[q], q); });
     n_steps = std::max(n_steps, ch[q].sched.size());
   }
 
   std::vector<Chain*> act;
   std::vector<xtrg::SvdJob> jobs;
+  std::vector<Chain*> job_chain;
   for (size_t st = 0; st < n_steps; ++st) {
     act.clear();
     for (auto& C : ch) {
-      if (st >= C.sched.size()) continue;
+      if (C.status != XTRG_OK || st >= C.sched.size()) continue;
       const Step& sp = C.sched[st];
       const bool final_step = st + 1 == C.sched.size();
       C.i = sp.bond;
@@ -1043,6 +1021,7 @@ void square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_com
       C.gauge_right = final_step ? false : (sp.dir > 0) != sp.last;
       act.push_back(&C);
     }
+    if (act.empty()) break;
     {
       // left block: 8 Dc Da Db Da' + 16 Dc Da' Db Db' (two substeps of Fig. VMPO(c));
       // the right block mirrors it with the right bond of C
@@ -1058,23 +1037,25 @@ void square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_com
                 16.0 * d.Dc[i + 2] * d.Da[i + 1] * (double)d.Da[i + 2] * d.Da[i + 1];
       }
       Timed tm(c, P_BLOCK, fb, 0.0);
-      for (Chain* C : act) {
-        auto& d = C->d;
-        const int i = C->i;
-        if (C->sched[st].dir > 0) {
-          C->Lb = d.slot_need(i);
-          d.left_block(i, C->E, C->Lb);
-          C->Rb = d.slot.at(i + 1);
-        } else {
-          C->Rb = d.slot_need(i + 1);
-          d.right_block(i + 1, C->F, C->Rb);
-          C->Lb = d.slot.at(i);
-        }
-      }
+      for (Chain* C : act)
+        per_chain(*C, [&] {
+          auto& d = C->d;
+          const int i = C->i;
+          if (C->sched[st].dir > 0) {
+            C->Lb = d.slot_need(i);
+            d.left_block(i, C->E, C->Lb);
+            C->Rb = d.slot.at(i + 1);
+          } else {
+            C->Rb = d.slot_need(i + 1);
+            d.right_block(i + 1, C->F, C->Rb);
+            C->Lb = d.slot.at(i);
+          }
+        });
     }
     {
       double fth = 0.0, bth = 0.0;
       for (Chain* C : act) {
+        if (C->status != XTRG_OK) continue;
         const auto& d = C->d;
         const int i = C->i;
         C->mL = 4 * d.Dc[i];
@@ -1082,80 +1063,117 @@ void square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_com
         C->Kt = d.Da[i + 1] * d.Da[i + 1];
         C->len = C->gauge_right ? C->mL : C->mR;
         C->p = C->gauge_right ? C->mR : C->mL;
-        C->flops += Doubler::step_flops(d.Dc[i], d.Da[i], d.Da[i], d.Da[i + 1], d.Da[i + 1], d.Dc[i + 2]);
-        C->th = c->need("theta" + C->tag, (size_t)C->mL * C->mR);
         fth += 2.0 * C->mL * (double)C->mR * C->Kt;
         bth += 8.0 * ((double)C->mL * C->Kt + (double)C->Kt * C->mR + (double)C->mL * C->mR);
       }
       Timed tm(c, P_THETA, fth, bth);
-      for (Chain* C : act) {
-        const int pr = C->d.prec;   // FP64 output in every precision: the SVD is FP64
-        Gemm g = C->gauge_right
-                     ? plain(C->mR, C->mL, C->Kt, C->Rb, C->mR, true, C->Lb, C->Kt, true, C->th, C->mL, pr, 1)  // column-major
-                     : plain(C->mL, C->mR, C->Kt, C->Lb, C->Kt, false, C->Rb, C->mR, false, C->th, C->mR, pr, 1);
-        g.tag = 1;
-        gemm(c, g);
-      }
+      for (Chain* C : act)
+        per_chain(*C, [&] {
+          const auto& d = C->d;
+          const int i = C->i;
+          C->flops += Doubler::step_flops(d.Dc[i], d.Da[i], d.Da[i], d.Da[i + 1], d.Da[i + 1], d.Dc[i + 2]);
+          C->th = c->need("theta" + C->tag, (size_t)C->mL * C->mR);
+          const int pr = C->d.prec;   // FP64 output in every precision: the SVD is FP64
+          Gemm g = C->gauge_right
+                       ? plain(C->mR, C->mL, C->Kt, C->Rb, C->mR, true, C->Lb, C->Kt, true, C->th, C->mL, pr, 1)  // column-major
+                       : plain(C->mL, C->mR, C->Kt, C->Lb, C->Kt, false, C->Rb, C->mR, false, C->th, C->mR, pr, 1);
+          g.tag = 1;
+          gemm(c, g);
+        });
     }
-    for (Chain* C : act) {
-      C->Y = C->th;
-      C->psvd = C->p;
-      C->svd_done = false;
-      const auto& w = C->warm[C->i];
-      const int need_side = C->gauge_right ? 1 : 0;   // the column index of Y
-      if (!C->o.no_warm_start && C->p >= kWarmMin && w.side == need_side && w.dim == C->p) {
-        Timed tm(c, P_WARM, 2.0 * C->len * (double)C->p * w.cols, 0.0);
-        const double* Q = c->need("wq" + std::to_string(C->i) + C->tag, (size_t)C->p * w.cols);
-        double* Yw = c->need("svd_in" + C->tag, (size_t)C->len * w.cols);
-        gemm(c, plain(w.cols, C->len, C->p, Q, C->p, false, C->th, C->len, false, Yw, C->len));   // Y [Q0 X]
-        C->Y = Yw;
-        C->psvd = w.cols;
-        c->warm_used += 1;
-      }
-      C->work = c->need("svd" + C->tag, xtrg::svd_work(C->len, C->psvd));
-    }
+    for (Chain* C : act)
+      per_chain(*C, [&] {
+        C->Y = C->th;
+        C->psvd = C->p;
+        C->svd_done = false;
+        C->warm_now = false;
+        const auto& w = C->warm[C->i];
+        const int need_side = C->gauge_right ? 1 : 0;   // the column index of Y
+        if (!C->o.no_warm_start && C->p >= kWarmMin && w.side == need_side && w.dim == C->p) {
+          Timed tm(c, P_WARM, 2.0 * C->len * (double)C->p * w.cols, 0.0);
+          const double* Q = c->need("wq" + std::to_string(C->i) + C->tag, (size_t)C->p * w.cols);
+          double* Yw = c->need("svd_in" + C->tag, (size_t)C->len * w.cols);
+          gemm(c, plain(w.cols, C->len, C->p, Q, C->p, false, C->th, C->len, false, Yw, C->len));   // Y [Q0 X]
+          C->Y = Yw;
+          C->psvd = w.cols;
+          C->warm_now = true;
+          c->warm_used += 1;
+        }
+        C->work = c->need("svd" + C->tag, xtrg::svd_work(C->len, C->psvd));
+      });
     {
       std::vector<Chain*> pre;
       for (Chain* C : act)
-        if (C->psvd == C->p && !C->o.no_warm_start && !C->o.no_qr_start && C->p >= kQrMin && C->len >= kQrMin &&
-            C->len <= xtrg::kQrMaxLen && C->p <= 2048)
+        // first visits only: a warm basis (square when the previous visit's
+        // spectrum was all above the noise) already gives a cheap Jacobi
+        if (C->status == XTRG_OK && !C->warm_now && !C->o.no_warm_start && !C->o.no_qr_start &&
+            C->p >= kQrMin && C->len >= kQrMin && C->len <= xtrg::kQrMaxLen && C->p <= 2048)
           pre.push_back(C);
       if (!pre.empty()) {
         Timed tm(c, P_QR, 0.0, 0.0);
         RoundProf rp(c);
-        qr_start(c, pre, &rp);
+        // workspace allocations that the budget refuses stop the chains of this QR group
+        try {
+          qr_start(c, pre, &rp);
+        } catch (const Error& e) {
+          if (e.code != XTRG_ENOMEM) throw;
+          for (Chain* C : pre) {
+            C->status = e.code;
+            C->err = e.what();
+          }
+        }
       }
     }
     {
       double bs = 0.0;
       jobs.clear();
+      job_chain.clear();
       for (Chain* C : act) {
-        if (C->svd_done) continue;
+        if (C->status != XTRG_OK || C->svd_done) continue;
         jobs.push_back(xtrg::SvdJob{C->len, C->psvd, C->Y, C->work, 0, svd_gram(c, C->tag, C->psvd)});
+        job_chain.push_back(C);
         bs += 8.0 * C->len * (double)C->psvd;
       }
       Timed tm(c, P_SVD, 0.0, bs);
       RoundProf rp(c);
       xtrg::svd_batched(jobs, svd_desc(c, (int)jobs.size()), s, &rp);
-      for (auto& J : jobs) {
+      for (size_t j = 0; j < jobs.size(); ++j) {
+        if (jobs[j].status != 0) {
+          job_chain[j]->status = XTRG_ENUMERIC;
+          job_chain[j]->err = "two-site tensor: non-finite entries or no convergence of the SVD";
+          continue;
+        }
         c->svd_calls += 1;
-        c->svd_sweeps += J.sweeps;
+        c->svd_sweeps += jobs[j].sweeps;
       }
     }
-    for (Chain* C : act) chain_truncate_split(c, *C);
+    for (Chain* C : act) per_chain(*C, [&] { chain_truncate_split(c, *C); });
   }
   // normalise: the centre is site 0 after the final right-to-left step
   std::vector<std::unique_ptr<xtrg_mpo_s>> res(n);
-  for (int q = 0; q < n; ++q) {
-    auto& d = ch[q].d;
-    xtrg::scale(d.C[0].p, 1.0 / ch[q].last_norm, (size_t)4 * d.Dc[1], s);
-    res[q] = new_mpo(c, d.Dc);
-    for (int i = 0; i < d.L; ++i) xtrg::copy(res[q]->site[i].p, d.C[i].p, res[q]->elems(i), s);
-  }
+  for (int q = 0; q < n; ++q)
+    per_chain(ch[q], [&] {
+      auto& d = ch[q].d;
+      if (!(ch[q].last_norm > 0) || !std::isfinite(ch[q].last_norm))
+        throw Error(XTRG_ENUMERIC, "non-finite or zero norm of the compressed product");
+      xtrg::scale(d.C[0].p, 1.0 / ch[q].last_norm, (size_t)4 * d.Dc[1], s);
+      res[q] = new_mpo(c, d.Dc);
+      for (int i = 0; i < d.L; ++i) xtrg::copy(res[q]->site[i].p, d.C[i].p, res[q]->elems(i), s);
+    });
   XTRG_HIP(hipStreamSynchronize(s));
+  int failed = 0;
   for (int q = 0; q < n; ++q) {
     const Chain& C = ch[q];
-    if (xtrg_compress_info* info = infos ? infos + q : nullptr) {
+    xtrg_compress_info* info = infos ? infos + q : nullptr;
+    if (C.status != XTRG_OK) {
+      ++failed;
+      if (first_err && first_err->empty()) *first_err = "chain " + std::to_string(q) + ": " + C.err;
+      if (info) info->status = C.status;
+      outs[q] = nullptr;
+      continue;
+    }
+    if (info) {
+      info->status = XTRG_OK;
       info->dlog_norm = std::log(C.last_norm);
       info->trunc_err_max = *std::max_element(C.disc.begin(), C.disc.end());
       info->sweeps_done = C.o.n_sweeps;
@@ -1167,8 +1185,9 @@ void square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_com
           for (int k = 0; k < info->sv_stride; ++k)
             info->sv[(size_t)b * info->sv_stride + k] = k < (int)C.sv[b].size() ? C.sv[b][k] : 0.0;
     }
+    outs[q] = res[q].release();
   }
-  for (int q = 0; q < n; ++q) outs[q] = res[q].release();
+  return failed;
 }
 
 // ---------------------------------------------------------------------------
@@ -1295,21 +1314,64 @@ double trace_chain(xtrg_ctx c, const std::vector<xtrg_mpo>& M, const std::vector
   return read_scalar(c, cur);
 }
 
+// MPO of sum_i O_i for a single-site operator O (2 x 2, row = output
+// index): bond 2 (states "before" and "after" the site that carries O).
+std::unique_ptr<xtrg_mpo_s> local_sum_mpo(xtrg_ctx c, int L, const double O[2][2]) {
+  std::vector<int> dims(L + 1, 2);
+  dims[0] = dims[L] = 1;
+  auto m = new_mpo(c, dims);
+  for (int i = 0; i < L; ++i) {
+    const int Dl = dims[i], Dr = dims[i + 1];
+    std::vector<double> T((size_t)Dl * 4 * Dr, 0.0);
+    for (int a = 0; a < Dl; ++a)
+      for (int b = 0; b < Dr; ++b) {
+        // virtual state 0: O not placed yet, 1: placed; the left edge is in
+        // state 0, the right edge in state 1
+        const int ga = L == 1 ? 0 : (i == 0 ? 0 : a), gb = L == 1 ? 1 : (i == L - 1 ? 1 : b);
+        for (int s1 = 0; s1 < 2; ++s1)
+          for (int s2 = 0; s2 < 2; ++s2) {
+            double v = 0.0;
+            if (ga == gb) v = s1 == s2 ? 1.0 : 0.0;     // identity while the state is kept
+            else if (ga == 0 && gb == 1) v = O[s1][s2];  // the site that carries O
+            T[(((size_t)a * 2 + s1) * 2 + s2) * Dr + b] = v;
+          }
+      }
+    upload(c, m->site[i].p, T.data(), T.size());
+  }
+  return m;
+}
+
 void observables_impl(xtrg_ctx c, xtrg_mpo rho, double lam, double tau, xtrg_mpo H, int n_sites,
                       xtrg_obs* at_tau, xtrg_obs* at_2tau, double* SE) {
   if (H->L != rho->L) throw Error(XTRG_EINVAL, "H and rho differ in length");
   if (n_sites <= 0) n_sites = rho->L;
   const double N = n_sites;
+  const int L = rho->L;
+  // total-spin MPOs for the invariants (real form: S^x = (S^+ + S^-)/2)
+  const double Sz[2][2] = {{0.5, 0.0}, {0.0, -0.5}}, Sx[2][2] = {{0.0, 0.5}, {0.5, 0.0}};
+  auto SZ = local_sum_mpo(c, L, Sz);
+  auto SX = local_sum_mpo(c, L, Sx);
+  // ||rho - rho^T||_F^2 / ||rho||_F^2 = 2 (1 - Tr(rho rho) / Tr(rho^T rho))
+  double nrm = 0.0, herm = 0.0;
+  if (at_tau || at_2tau) {
+    nrm = trace_chain(c, {rho, rho}, {true, false});
+    if (!(nrm > 0)) throw Error(XTRG_ENUMERIC, "||rho|| = 0");
+    herm = 2.0 * (1.0 - trace_chain(c, {rho, rho}, {false, false}) / nrm);
+  }
   if (at_tau) {
     const double tr = trace_chain(c, {rho}, {false});
     if (!(tr > 0)) throw Error(XTRG_ENUMERIC, "Tr rho <= 0");
     const double e1 = trace_chain(c, {H, rho}, {false, false}) / tr;
     const double e2 = trace_chain(c, {H, H, rho}, {false, false, false}) / tr;
+    const double sz = trace_chain(c, {SZ.get(), rho}, {false, false}) / tr;
+    const double z2 = trace_chain(c, {SZ.get(), SZ.get(), rho}, {false, false, false}) / tr;
+    const double x2 = trace_chain(c, {SX.get(), SX.get(), rho}, {false, false, false}) / tr;
     const double b = tau, lnZ = lam + std::log(tr);
-    *at_tau = xtrg_obs{b, lnZ, -lnZ / (N * b), e1 / N, b * b * (e2 - e1 * e1) / N, tr, 0.0, 0.0};
+    *at_tau = xtrg_obs{b, lnZ, -lnZ / (N * b), e1 / N, b * b * (e2 - e1 * e1) / N, tr, 0.0, 0.0,
+                       herm, sz, (x2 - z2) / std::max(z2, 1.0)};
   }
   double Sc = 0.0, Smax = 0.0;
-  if (SE || at_2tau) {
+  if (SE) {
     auto m = clone(rho);
     left_sweep(m.get(), 0.0, nullptr);
     std::vector<std::vector<double>> sv;
@@ -1328,16 +1390,104 @@ void observables_impl(xtrg_ctx c, xtrg_mpo rho, double lam, double tau, xtrg_mpo
     }
   }
   if (at_2tau) {
-    const double nrm = trace_chain(c, {rho, rho}, {true, false});
-    if (!(nrm > 0)) throw Error(XTRG_ENUMERIC, "||rho|| = 0");
     const double g1 = trace_chain(c, {H, rho, rho}, {false, true, false}) / nrm;
     const double g2 = trace_chain(c, {H, H, rho, rho}, {false, false, true, false}) / nrm;
+    const double sz = trace_chain(c, {SZ.get(), rho, rho}, {false, true, false}) / nrm;
+    const double z2 = trace_chain(c, {SZ.get(), SZ.get(), rho, rho}, {false, false, true, false}) / nrm;
+    const double x2 = trace_chain(c, {SX.get(), SX.get(), rho, rho}, {false, false, true, false}) / nrm;
     const double b = 2 * tau, lnZ = 2 * lam + std::log(nrm);
-    *at_2tau = xtrg_obs{b, lnZ, -lnZ / (N * b), g1 / N, b * b * (g2 - g1 * g1) / N, nrm, Sc, Smax};
+    *at_2tau = xtrg_obs{b, lnZ, -lnZ / (N * b), g1 / N, b * b * (g2 - g1 * g1) / N, nrm, Sc, Smax,
+                        herm, sz, (x2 - z2) / std::max(z2, 1.0)};
   }
 }
 
 }  // namespace
+
+namespace xtrg_impl {
+
+std::unique_ptr<xtrg_mpo_s> hamiltonian(xtrg_ctx c, int n_sites, int n_bonds, const int* bonds, const double* jxy,
+                                        const double* jz) {
+  Automaton A = build_automaton(n_sites, n_bonds, bonds, jxy, jz);
+  const double r[2] = {0.0, 1.0};   // stop state: H
+  std::vector<int> dims;
+  auto S = cap(A, r, &dims);
+  auto m = new_mpo(c, dims);
+  for (int i = 0; i < n_sites; ++i) upload(c, m->site[i].p, S[i].data(), S[i].size());
+  m->has_open = true;
+  m->open_last = A.T[n_sites - 1];
+  XTRG_HIP(hipStreamSynchronize(c->stream));
+  return m;
+}
+
+std::unique_ptr<xtrg_mpo_s> init_rho(xtrg_ctx c, xtrg_mpo H, double tau0, int order, int D0_max,
+                                   double* log_norm) {
+  if (!H->has_open || order < 1 || order > 2 || !(tau0 > 0))
+  throw Error(XTRG_EINVAL, "init_rho: H from xtrg_hamiltonian_xxz, order 1 or 2, tau0 > 0");
+  hipStream_t s = c->stream;
+  const int L = H->L;
+  // The right end of the automaton is left open over {start, stop}; a
+  // right boundary r selects r_start * I + r_stop * H (App. B.1, App. C.2).
+  std::unique_ptr<xtrg_mpo_s> m;
+  if (order == 1) {
+    std::vector<int> dims = H->dims;
+    m = new_mpo(c, dims);
+    for (int i = 0; i + 1 < L; ++i) xtrg::copy(m->site[i].p, H->site[i].p, H->elems(i), s);
+    const int Dl = H->dims[L - 1];
+    std::vector<double> last((size_t)Dl * 4);
+    for (size_t q = 0; q < last.size(); ++q)
+      last[q] = H->open_last[2 * q + 0] * 1.0 + H->open_last[2 * q + 1] * (-tau0);
+    upload(c, m->site[L - 1].p, last.data(), last.size());
+  } else {
+    // exact product of two automata; each factor ends in start (I) or stop (H):
+    // weights r[(x,y)] with x,y in {start, stop} give I - tau H + tau^2/2 H^2
+    std::vector<int> dims(L + 1);
+    for (int i = 0; i <= L; ++i) dims[i] = H->dims[i] * H->dims[i];
+    dims[L] = 1;
+    m = new_mpo(c, dims);
+    for (int i = 0; i + 1 < L; ++i)
+      xtrg::site_product(m->site[i].p, H->site[i].p, H->dims[i], H->dims[i + 1], H->site[i].p, H->dims[i],
+                         H->dims[i + 1], s);
+    const int Dl = H->dims[L - 1];
+    double* openp = c->need("init_open", (size_t)Dl * 4 * 2);
+    upload(c, openp, H->open_last.data(), H->open_last.size());
+    double* prod = c->need("init_prod", (size_t)Dl * Dl * 4 * 4);
+    xtrg::site_product(prod, openp, Dl, 2, openp, Dl, 2, s);     // [(a,b)][s][u][(x,y)]
+    const double r[4] = {1.0, -0.5 * tau0, -0.5 * tau0, 0.5 * tau0 * tau0};
+    double* rv = c->need("init_r", 4);
+    upload(c, rv, r, 4);
+    gemm(c, plain(Dl * Dl * 4, 1, 4, prod, 4, false, rv, 1, false, m->site[L - 1].p, 1));
+  }
+  // lossless compression to canonical form: exact zeros dropped
+  left_sweep(m.get(), 1e-14, nullptr);
+  right_sweep(m.get(), 1e-14, D0_max, nullptr);
+  const double nrm = site_norm(m.get(), 0);
+  if (!(nrm > 0) || !std::isfinite(nrm)) throw Error(XTRG_ENUMERIC, "rho(tau0) has zero norm");
+  xtrg::scale(m->site[0].p, 1.0 / nrm, m->elems(0), s);
+  XTRG_HIP(hipStreamSynchronize(s));
+  *log_norm = std::log(nrm);
+  // shrink the buffers to the final shapes
+  auto fin = clone(m.get());
+  XTRG_HIP(hipStreamSynchronize(s));
+  return fin;
+}
+
+int square_compress(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_compress_opts* opts, xtrg_mpo* outs,
+                    xtrg_compress_info* infos, std::string* first_err) {
+  return square_compress_impl(c, n, ins, opts, outs, infos, first_err);
+}
+
+void observables(xtrg_ctx c, xtrg_mpo rho, double lam, double tau, xtrg_mpo H, int n_sites, xtrg_obs* at_tau,
+                 xtrg_obs* at_2tau, double* S_E) {
+  observables_impl(c, rho, lam, tau, H, n_sites, at_tau, at_2tau, S_E);
+}
+
+void trim(xtrg_ctx c) {
+  XTRG_HIP(hipStreamSynchronize(c->stream));
+  for (auto& kv : c->ws) c->release(kv.second.p, kv.second.cap);
+  c->ws.clear();
+}
+
+}  // namespace xtrg_impl
 
 // ---------------------------------------------------------------------------
 // C ABI
@@ -1369,6 +1519,7 @@ int xtrg_ctx_create(int device, void* hip_stream, size_t hbm_budget, xtrg_ctx* o
 
 int xtrg_ctx_destroy(xtrg_ctx c) {
   if (!c) return XTRG_EINVAL;
+  xtrg::server_shutdown(c);
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
@@ -1398,16 +1549,7 @@ int xtrg_hamiltonian_xxz(xtrg_ctx c, int n_sites, int n_bonds, const int* bonds,
     return XTRG_EINVAL;
   return guarded(c, [&] {
     set_device(c);
-    Automaton A = build_automaton(n_sites, n_bonds, bonds, jxy, jz);
-    const double r[2] = {0.0, 1.0};   // stop state: H
-    std::vector<int> dims;
-    auto S = cap(A, r, &dims);
-    auto m = new_mpo(c, dims);
-    for (int i = 0; i < n_sites; ++i) upload(c, m->site[i].p, S[i].data(), S[i].size());
-    m->has_open = true;
-    m->open_last = A.T[n_sites - 1];
-    XTRG_HIP(hipStreamSynchronize(c->stream));
-    *H_out = m.release();
+    *H_out = xtrg_impl::hamiltonian(c, n_sites, n_bonds, bonds, jxy, jz).release();
   });
 }
 
@@ -1465,52 +1607,7 @@ int xtrg_init_rho(xtrg_ctx c, xtrg_mpo H, double tau0, int order, int D0_max, xt
   if (!H->has_open) return XTRG_EINVAL;
   return guarded(c, [&] {
     set_device(c);
-    hipStream_t s = c->stream;
-    const int L = H->L;
-    // The right end of the automaton is left open over {start, stop}; a
-    // right boundary r selects r_start * I + r_stop * H (App. B.1, App. C.2).
-    std::unique_ptr<xtrg_mpo_s> m;
-    if (order == 1) {
-      std::vector<int> dims = H->dims;
-      m = new_mpo(c, dims);
-      for (int i = 0; i + 1 < L; ++i) xtrg::copy(m->site[i].p, H->site[i].p, H->elems(i), s);
-      const int Dl = H->dims[L - 1];
-      std::vector<double> last((size_t)Dl * 4);
-      for (size_t q = 0; q < last.size(); ++q)
-        last[q] = H->open_last[2 * q + 0] * 1.0 + H->open_last[2 * q + 1] * (-tau0);
-      upload(c, m->site[L - 1].p, last.data(), last.size());
-    } else {
-      // exact product of two automata; each factor ends in start (I) or stop (H):
-      // weights r[(x,y)] with x,y in {start, stop} give I - tau H + tau^2/2 H^2
-      std::vector<int> dims(L + 1);
-      for (int i = 0; i <= L; ++i) dims[i] = H->dims[i] * H->dims[i];
-      dims[L] = 1;
-      m = new_mpo(c, dims);
-      for (int i = 0; i + 1 < L; ++i)
-        xtrg::site_product(m->site[i].p, H->site[i].p, H->dims[i], H->dims[i + 1], H->site[i].p, H->dims[i],
-                           H->dims[i + 1], s);
-      const int Dl = H->dims[L - 1];
-      double* openp = c->need("init_open", (size_t)Dl * 4 * 2);
-      upload(c, openp, H->open_last.data(), H->open_last.size());
-      double* prod = c->need("init_prod", (size_t)Dl * Dl * 4 * 4);
-      xtrg::site_product(prod, openp, Dl, 2, openp, Dl, 2, s);     // [(a,b)][s][u][(x,y)]
-      const double r[4] = {1.0, -0.5 * tau0, -0.5 * tau0, 0.5 * tau0 * tau0};
-      double* rv = c->need("init_r", 4);
-      upload(c, rv, r, 4);
-      gemm(c, plain(Dl * Dl * 4, 1, 4, prod, 4, false, rv, 1, false, m->site[L - 1].p, 1));
-    }
-    // lossless compression to canonical form: exact zeros dropped
-    left_sweep(m.get(), 1e-14, nullptr);
-    right_sweep(m.get(), 1e-14, D0_max, nullptr);
-    const double nrm = site_norm(m.get(), 0);
-    if (!(nrm > 0) || !std::isfinite(nrm)) throw Error(XTRG_ENUMERIC, "rho(tau0) has zero norm");
-    xtrg::scale(m->site[0].p, 1.0 / nrm, m->elems(0), s);
-    XTRG_HIP(hipStreamSynchronize(s));
-    *log_norm = std::log(nrm);
-    // shrink the buffers to the final shapes
-    auto fin = clone(m.get());
-    XTRG_HIP(hipStreamSynchronize(s));
-    *rho_out = fin.release();
+    *rho_out = xtrg_impl::init_rho(c, H, tau0, order, D0_max, log_norm).release();
   });
 }
 
@@ -1519,7 +1616,10 @@ int xtrg_square_compress(xtrg_ctx c, xtrg_mpo rho_in, const xtrg_compress_opts* 
   if (!c || !rho_in || !opts || !rho_out) return XTRG_EINVAL;
   return guarded(c, [&] {
     set_device(c);
-    square_compress_impl(c, 1, &rho_in, opts, rho_out, info);
+    std::string err;
+    xtrg_compress_info tmp{};
+    xtrg_compress_info* inf = info ? info : &tmp;
+    if (square_compress_impl(c, 1, &rho_in, opts, rho_out, inf, &err) > 0) throw Error(inf->status, err);
   });
 }
 
@@ -1527,10 +1627,30 @@ int xtrg_square_compress_batched(xtrg_ctx c, int n, const xtrg_mpo* rho_in, cons
                                  xtrg_mpo* rho_out, xtrg_compress_info* info) {
   if (!c || n < 1 || !rho_in || !opts || !rho_out) return XTRG_EINVAL;
   for (int q = 0; q < n; ++q) rho_out[q] = nullptr;
-  return guarded(c, [&] {
+  int first_code = XTRG_OK;
+  std::string err;
+  const int rc = guarded(c, [&] {
     set_device(c);
-    square_compress_impl(c, n, rho_in, opts, rho_out, info);
+    std::vector<xtrg_compress_info> tmp;
+    xtrg_compress_info* inf = info;
+    if (!inf) {
+      tmp.assign(n, xtrg_compress_info{});
+      inf = tmp.data();
+    }
+    if (square_compress_impl(c, n, rho_in, opts, rho_out, inf, &err) > 0)
+      for (int q = 0; q < n && first_code == XTRG_OK; ++q)
+        if (!rho_out[q]) first_code = inf[q].status;
   });
+  if (rc != XTRG_OK) {            // nothing left to release
+    for (int q = 0; q < n; ++q)
+      if (rho_out[q]) {
+        delete rho_out[q];
+        rho_out[q] = nullptr;
+      }
+    return rc;
+  }
+  if (first_code != XTRG_OK) c->err = err;
+  return first_code;
 }
 
 int xtrg_observables(xtrg_ctx c, xtrg_mpo rho, double log_norm, double tau_n, xtrg_mpo H, int n_sites,
@@ -1630,6 +1750,34 @@ int xtrg_dsvd_left(xtrg_ctx c, int len, int p, const double* Y, double* sigma, i
     c->svd_sweeps += sw;
     if (k > 0 && U) orthonormalize(c, U, len, k, false);
     XTRG_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+int xtrg_dsvd_left_qr(xtrg_ctx c, int len, int p, const double* Y, double* sigma, int k, double* U, int* keff) {
+  if (!c || len < 1 || p < 1 || k < 0 || k > p || !Y || !sigma || (k > 0 && !U) || len > xtrg::kQrMaxLen ||
+      p > 2048)
+    return XTRG_EINVAL;
+  return guarded(c, [&] {
+    set_device(c);
+    QrTask T;
+    T.len = len;
+    T.p = p;
+    T.Y = Y;
+    T.tag = "#kernel";
+    std::vector<QrTask*> tp{&T};
+    qr_factorise(c, tp, nullptr);
+    if (T.failed) throw Error(XTRG_ENUMERIC, "QR route: non-finite entries or no convergence of the Jacobi");
+    if (!T.done) throw Error(XTRG_ENUMERIC, "QR route rejected: fewer than p/4 rows of R above the stop");
+    if (k > T.psvd) throw Error(XTRG_EINVAL, "k exceeds the number of values the QR route resolves");
+    XTRG_HIP(hipMemsetAsync(sigma, 0, sizeof(double) * p, c->stream));
+    XTRG_HIP(hipMemcpyAsync(sigma, xtrg::svd_sorted_values(T.work, len, T.psvd), sizeof(double) * T.psvd,
+                            hipMemcpyDeviceToDevice, c->stream));
+    if (k > 0) {
+      xtrg::svd_gather(len, T.psvd, T.work, k, U, len, 0, c->stream);
+      orthonormalize(c, U, len, k, false);
+    }
+    XTRG_HIP(hipStreamSynchronize(c->stream));
+    if (keff) *keff = T.psvd;
   });
 }
 

@@ -89,6 +89,10 @@ struct SvdJob {
   // orthogonalised on their first glen rows and the remaining rows are only
   // rotated with them (rows of an identity appended below accumulate V)
   int glen = 0;
+  // out: 0, or -4 (XTRG_ENUMERIC) if this problem failed (a non-finite
+  // entry, ||Y||_F^2 beyond the double range, no convergence); a failed
+  // problem leaves the others of the grouped launch untouched
+  int status = 0;
 };
 // Optional timing of the Jacobi rounds (event pair around each sweep's
 // back-to-back round launches on the stream).
@@ -99,6 +103,8 @@ struct RoundTimer {
   // rotation of every visited pair; bytes: each column read and written once
   virtual void end(hipStream_t s, long launches, double flops, double bytes) = 0;
 };
+// Problems that fail are marked in their status and dropped from the
+// remaining rounds; the call itself throws only on runtime errors.
 void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, RoundTimer* timer = nullptr);
 
 // Householder QR with column pivoting of Y (len x p, column-major), the

@@ -695,6 +695,7 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
   for (int j = 0; j < n; ++j) {
     SvdJob& J = jobs[j];
     J.sweeps = 0;
+    J.status = 0;
     JacobiDesc& D = h[j];
     D = JacobiDesc{};
     D.len = J.len;
@@ -777,8 +778,10 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
     if (h[j].active) XTRG_HIP(hipMemcpyAsync(&f2[j], h[j].fro2, sizeof(double), hipMemcpyDeviceToHost, s));
   XTRG_HIP(hipStreamSynchronize(s));
   for (int j = 0; j < n; ++j)
-    if (h[j].active && !std::isfinite(f2[j]))
-      throw Error(-4, "svd: non-finite entry or ||Y||_F^2 beyond the double range");
+    if (h[j].active && !std::isfinite(f2[j])) {   // non-finite entry or ||Y||_F^2 beyond the double range
+      jobs[j].status = -4;
+      h[j].active = 0;
+    }
   for (int j = 0; j < n; ++j)
     if (h[j].active) set_nbk(j);
   // Sliced launches pay off while the fused rounds would leave most compute
@@ -813,11 +816,13 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
   int n_active = 0;
   for (auto& D : h) n_active += D.active;
   for (int sweep = 0; n_active > 0; ++sweep) {
-    if (sweep >= kMaxSweeps) {
+    if (sweep >= kMaxSweeps) {   // not converged: the problems still active fail
       for (int j = 0; j < n; ++j)
-        if (h[j].active)
-          throw Error(-4, "svd: Jacobi did not converge (len " + std::to_string(h[j].len) + ", p " +
-                              std::to_string(h[j].p) + ", largest cosine " + std::to_string(last[j]) + ")");
+        if (h[j].active) {
+          jobs[j].status = -4;
+          h[j].active = 0;
+        }
+      break;
     }
     plan();
     if (dirty) {   // the active set or a block count changed: refresh the device descriptors
@@ -848,7 +853,13 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
       if (!h[j].active) continue;
       double m;
       std::memcpy(&m, &hoff[j], sizeof(m));
-      if (!(m == m)) throw Error(-4, "svd: NaN in input");
+      if (!(m == m)) {           // NaN in the input
+        jobs[j].status = -4;
+        h[j].active = 0;
+        --n_active;
+        dirty = true;
+        continue;
+      }
       last[j] = m;
       jobs[j].sweeps = sweep + 1;
       if (m == 0.0) {            // no pair needed a rotation
@@ -898,7 +909,7 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
       if (h[j].active) set_nbk(j);
   }
   for (int j = 0; j < n; ++j)
-    if (jobs[j].len > 0 && jobs[j].p > 0) rank_columns(j);
+    if (jobs[j].len > 0 && jobs[j].p > 0 && jobs[j].status == 0) rank_columns(j);
 }
 
 void svd_left(int len, int p, const double* Y, double* sigma, int k, double* U, long ldu, int u_rowmajor,
@@ -906,6 +917,9 @@ void svd_left(int len, int p, const double* Y, double* sigma, int k, double* U, 
   std::vector<SvdJob> jobs(1);
   jobs[0] = SvdJob{len, p, Y, work, 0};
   svd_batched(jobs, desc_dev, s);
+  if (jobs[0].status != 0)
+    throw Error(-4, "svd: non-finite entry, ||Y||_F^2 beyond the double range, or no convergence (len " +
+                        std::to_string(len) + ", p " + std::to_string(p) + ")");
   if (len > 0 && p > 0) {
     if (sigma) XTRG_HIP(hipMemcpyAsync(sigma, sv_sorted(work, len, p), sizeof(double) * p, hipMemcpyDeviceToDevice, s));
     if (k > 0 && U) svd_gather(len, p, work, k, U, ldu, u_rowmajor, s);

@@ -36,13 +36,14 @@ class CompressOpts(C.Structure):
 class CompressInfo(C.Structure):
     _fields_ = [("dlog_norm", C.c_double), ("trunc_err_max", C.c_double), ("sweeps_done", C.c_int),
                 ("D_kept_max", C.c_int), ("steps", C.c_int), ("flops", C.c_double),
-                ("sv", C.POINTER(C.c_double)), ("sv_stride", C.c_int)]
+                ("sv", C.POINTER(C.c_double)), ("sv_stride", C.c_int), ("status", C.c_int)]
 
 
 class Obs(C.Structure):
     _fields_ = [("beta", C.c_double), ("lnZ", C.c_double), ("f", C.c_double), ("u", C.c_double),
                 ("c", C.c_double), ("tr_rho", C.c_double), ("S_E_center", C.c_double),
-                ("S_E_max", C.c_double)]
+                ("S_E_max", C.c_double), ("herm_resid", C.c_double), ("sz_tot", C.c_double),
+                ("su2_resid", C.c_double)]
 
 
 def load_library(path: Optional[str] = None):
@@ -79,7 +80,10 @@ def load_library(path: Optional[str] = None):
         "xtrg_gemm_bf16x3": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, vp, C.c_long, vp,
                                        C.c_long, vp, C.c_long, C.c_int]),
         "xtrg_dsvd_left": (C.c_int, [vp, C.c_int, C.c_int, vp, vp, C.c_int, vp]),
+        "xtrg_dsvd_left_qr": (C.c_int, [vp, C.c_int, C.c_int, vp, vp, C.c_int, vp, ip]),
         "xtrg_dqrcp": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_double, vp, vp, ip]),
+        "xtrg_serve_submit": (C.c_int, [vp, C.c_char_p, C.POINTER(C.c_ulonglong)]),
+        "xtrg_serve_poll": (C.c_int, [vp, C.c_ulonglong, C.c_char_p, C.c_size_t]),
         "xtrg_profile_enable": (C.c_int, [vp, C.c_int]),
         "xtrg_profile_report": (C.c_int, [vp, C.c_char_p, C.c_size_t]),
     }
@@ -95,7 +99,8 @@ def exported_symbols() -> List[str]:
     return ["xtrg_ctx_create", "xtrg_ctx_destroy", "xtrg_last_error", "xtrg_ctx_bytes", "xtrg_ctx_trim",
             "xtrg_hamiltonian_xxz", "xtrg_mpo_from_host", "xtrg_mpo_shape", "xtrg_mpo_to_host",
             "xtrg_mpo_destroy", "xtrg_init_rho", "xtrg_square_compress", "xtrg_square_compress_batched", "xtrg_observables",
-            "xtrg_dgemm", "xtrg_sgemm", "xtrg_gemm_bf16x3", "xtrg_dsvd_left", "xtrg_dqrcp", "xtrg_profile_enable", "xtrg_profile_report"]
+            "xtrg_dgemm", "xtrg_sgemm", "xtrg_gemm_bf16x3", "xtrg_dsvd_left", "xtrg_dsvd_left_qr", "xtrg_dqrcp", "xtrg_serve_submit", "xtrg_serve_poll", "xtrg_profile_enable",
+            "xtrg_profile_report"]
 
 
 class MPO:
@@ -226,16 +231,22 @@ class Context:
 
     def square_compress_batched(self, rhos: Sequence[MPO], D_max, n_sweeps=4,
                                 degen_rtol: float = 1e-6, sv_floor: float = 1e-14, sv_stride: int = 0,
-                                precision: int = XTRG_FP64, warm_start: bool = True, qr_start: bool = True):
-        """One doubling of every chain in `rhos` together.  D_max and n_sweeps
-        are one value for all chains or a sequence with one per chain.
-        Returns ([new MPO per chain], [info dict per chain])."""
+                                precision=XTRG_FP64, warm_start: bool = True, qr_start: bool = True):
+        """One doubling of every chain in `rhos` together.  D_max, n_sweeps and
+        precision are one value for all chains or a sequence with one per
+        chain.  Returns ([new MPO per chain], [info dict per chain]).  A chain
+        that the library stopped (non-finite tensors, memory refused by the
+        budget) has None in place of its MPO and its code in info["status"];
+        the other chains' results are unaffected."""
         n = len(rhos)
-        Ds = list(D_max) if isinstance(D_max, (list, tuple)) else [D_max] * n
-        Ss = list(n_sweeps) if isinstance(n_sweeps, (list, tuple)) else [n_sweeps] * n
-        if len(Ds) != n or len(Ss) != n:
-            raise ValueError("one D_max and n_sweeps per chain")
-        o = (CompressOpts * n)(*[CompressOpts(Ds[q], Ss[q], precision, degen_rtol, sv_floor, int(not warm_start),
+
+        def per(v, name):
+            out = list(v) if isinstance(v, (list, tuple)) else [v] * n
+            if len(out) != n:
+                raise ValueError(f"one {name} per chain")
+            return out
+        Ds, Ss, Ps = per(D_max, "D_max"), per(n_sweeps, "n_sweeps"), per(precision, "precision")
+        o = (CompressOpts * n)(*[CompressOpts(Ds[q], Ss[q], Ps[q], degen_rtol, sv_floor, int(not warm_start),
                                               int(not qr_start))
                                for q in range(n)])
         infos = (CompressInfo * n)()
@@ -248,15 +259,23 @@ class Context:
                 bufs.append(b)
         hin = (C.c_void_p * n)(*[r.h for r in rhos])
         hout = (C.c_void_p * n)()
-        _check(self, _lib.xtrg_square_compress_batched(self.h, n, hin, o, hout, infos))
+        rc = _lib.xtrg_square_compress_batched(self.h, n, hin, o, hout, infos)
+        if rc != 0 and not any(hout[q] for q in range(n)) and not any(infos[q].status for q in range(n)):
+            _check(self, rc)                     # the whole call failed
+        err = _lib.xtrg_last_error(self.h).decode() if rc != 0 else ""
         outs, dicts = [], []
         for q in range(n):
-            outs.append(MPO(self, C.c_void_p(hout[q])))
-            d = dict(dlog_norm=infos[q].dlog_norm, trunc_err_max=infos[q].trunc_err_max,
-                     sweeps=infos[q].sweeps_done, D_kept_max=infos[q].D_kept_max, steps=infos[q].steps,
-                     flops=infos[q].flops)
-            if bufs:
-                d["sv"] = bufs[q]
+            st = infos[q].status
+            outs.append(MPO(self, C.c_void_p(hout[q])) if hout[q] else None)
+            d = dict(status=st)
+            if st == 0:
+                d.update(dlog_norm=infos[q].dlog_norm, trunc_err_max=infos[q].trunc_err_max,
+                         sweeps=infos[q].sweeps_done, D_kept_max=infos[q].D_kept_max, steps=infos[q].steps,
+                         flops=infos[q].flops)
+                if bufs:
+                    d["sv"] = bufs[q]
+            else:
+                d["error"] = err
             dicts.append(d)
         return outs, dicts
 
@@ -275,6 +294,26 @@ class Context:
         if entropy:
             out["S_E"] = se[: L - 1]
         return out
+
+    # serving: the library's continuous-batching loop (include/xtrg.h)
+    def serve_submit(self, request: dict) -> int:
+        """Queue one XTRG run (the JSON fields of xtrg_serve_submit); returns its id."""
+        import json
+        rid = C.c_ulonglong()
+        _check(self, _lib.xtrg_serve_submit(self.h, json.dumps(request).encode(), C.byref(rid)))
+        return rid.value
+
+    def serve_poll(self, rid: int, cap: int = 1 << 20):
+        """The run's result dict once it is finished (or failed), else None."""
+        import json
+        buf = C.create_string_buffer(cap)
+        rc = _lib.xtrg_serve_poll(self.h, rid, buf, cap)
+        if rc == -5:                               # XTRG_EBUSY: queued or running
+            return None
+        if rc != 0 and cap < (1 << 26):
+            return self.serve_poll(rid, cap * 8)   # grow the buffer for long runs
+        _check(self, rc)
+        return json.loads(buf.value.decode())
 
     def profile(self, on: bool = True):
         _check(self, _lib.xtrg_profile_enable(self.h, int(on)))
@@ -301,6 +340,13 @@ class Context:
     def dsvd_left(self, length, p, Y, sigma, k=0, U=None):
         _check(self, _lib.xtrg_dsvd_left(self.h, length, p, C.c_void_p(Y), C.c_void_p(sigma), k,
                                          C.c_void_p(U) if U else None))
+
+    def dsvd_left_qr(self, length, p, Y, sigma, k=0, U=None):
+        """The first-visit route (pivoted QR, Jacobi on [R^T; I]); returns keff."""
+        ke = C.c_int()
+        _check(self, _lib.xtrg_dsvd_left_qr(self.h, length, p, C.c_void_p(Y), C.c_void_p(sigma), k,
+                                            C.c_void_p(U) if U else None, C.byref(ke)))
+        return ke.value
 
     def dqrcp(self, length, p, Y, stop_rel, piv, RT):
         """Column-pivoted QR (triangular factor) of the device matrix Y; returns keff."""
