@@ -255,6 +255,21 @@ int xtrg_profile_report(xtrg_ctx ctx, char* buf, size_t cap);
  * C (M x N) row-major (ldc).  Inputs and output must not alias. */
 int xtrg_dgemm(xtrg_ctx ctx, int M, int N, int K, int transA, int transB,
                const double* A, long lda, const double* B, long ldb, double* C, long ldc);
+/* xtrg_dgemm_noalloc: the product of xtrg_dgemm (same kernels, same
+ * result bit for bit) for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  It allocates nothing: the split-K partial products live in a
+ * fixed device array of 8 Mi doubles (64 MiB) per GPU, part of the library
+ * and held until the process ends.  Shapes whose partials need more
+ * (xtrg_dgemm splits K for small M*N and large K) are rejected with
+ * XTRG_EINVAL and a message naming the size.  The call is enqueued on the
+ * context stream and returns without waiting.  Every call on one GPU
+ * shares that GPU's array: calls that overlap in time on one GPU (other
+ * streams or contexts) race; calls ordered on one stream do not.  Nothing
+ * in the array needs to start at zero (every partial is written before it
+ * is read). */
+int xtrg_dgemm_noalloc(xtrg_ctx ctx, int M, int N, int K, int transA, int transB, const double* A, long lda,
+                       const double* B, long ldb, double* C, long ldc);
 /* xtrg_sgemm: the same product in the XTRG_FP32 contraction precision:
  * A, B float (device), FP32 matrix cores with FP32 accumulation (split-K
  * partials summed in FP64); C is double if c_double, else float. */

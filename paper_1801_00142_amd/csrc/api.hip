@@ -21,6 +21,31 @@
 using xtrg::Error;
 using xtrg::Gemm;
 
+// Device scratch of xtrg_dgemm_noalloc (the split-K partial products):
+// one fixed array per GPU, in the library's code object, held until the
+// process ends.  Host code never passes `scratch` itself to a kernel (in
+// host code the name is a stand-in, not a device address): the address is
+// looked up once per device when a context is created there.
+constexpr size_t kNoAllocDoubles = size_t(1) << 23;   // 8 Mi doubles = 64 MiB
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// With `device` current: the device address of this device's scratch.
+double* scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) throw Error(XTRG_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    XTRG_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) throw Error(XTRG_EDEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[device] = static_cast<double*>(ptr);
+  }
+  return g_scratch_ptr[device];
+}
+}  // namespace
 
 namespace {
 
@@ -1508,6 +1533,7 @@ int xtrg_ctx_create(int device, void* hip_stream, size_t hbm_budget, xtrg_ctx* o
     if (device < 0 || device >= n) throw Error(XTRG_EINVAL, "no such device");
     set_device(c);
     c->scratch = c->alloc(2048);
+    (void)scratch_address(device);   // the no-allocation entry point's scratch on this device
   });
   if (rc != XTRG_OK) {
     delete c;
@@ -1716,6 +1742,22 @@ int xtrg_dgemm(xtrg_ctx c, int M, int N, int K, int transA, int transB, const do
     set_device(c);
     gemm(c, plain(M, N, K, A, lda, transA != 0, B, ldb, transB != 0, C, ldc));
     XTRG_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+int xtrg_dgemm_noalloc(xtrg_ctx c, int M, int N, int K, int transA, int transB, const double* A, long lda,
+                       const double* B, long ldb, double* C, long ldc) {
+  if (!c || M < 0 || N < 0 || K < 0 || (M * (long)N > 0 && (!A || !B || !C))) return XTRG_EINVAL;
+  return guarded(c, [&] {
+    set_device(c);
+    const Gemm g = plain(M, N, K, A, lda, transA != 0, B, ldb, transB != 0, C, ldc);
+    const size_t need = xtrg::gemm_splitk_work(g);
+    if (need > kNoAllocDoubles)
+      throw Error(XTRG_EINVAL, "xtrg_dgemm_noalloc: the split-K partials of this shape need " + std::to_string(need) +
+                                   " doubles, the fixed scratch holds " + std::to_string(kNoAllocDoubles));
+    // every partial is written before it is read: nothing to clear
+    xtrg::gemm(g, c->stream, need ? scratch_address(c->device) : nullptr, kNoAllocDoubles);
+    XTRG_HIP(hipGetLastError());
   });
 }
 

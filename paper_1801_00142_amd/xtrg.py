@@ -75,6 +75,8 @@ def load_library(path: Optional[str] = None):
                                        C.POINTER(Obs), dp]),
         "xtrg_dgemm": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, vp, C.c_long, vp,
                                  C.c_long, vp, C.c_long]),
+        "xtrg_dgemm_noalloc": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, vp, C.c_long, vp,
+                                         C.c_long, vp, C.c_long]),
         "xtrg_sgemm": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, vp, C.c_long, vp,
                                  C.c_long, vp, C.c_long, C.c_int]),
         "xtrg_gemm_bf16x3": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, vp, C.c_long, vp,
@@ -99,7 +101,7 @@ def exported_symbols() -> List[str]:
     return ["xtrg_ctx_create", "xtrg_ctx_destroy", "xtrg_last_error", "xtrg_ctx_bytes", "xtrg_ctx_trim",
             "xtrg_hamiltonian_xxz", "xtrg_mpo_from_host", "xtrg_mpo_shape", "xtrg_mpo_to_host",
             "xtrg_mpo_destroy", "xtrg_init_rho", "xtrg_square_compress", "xtrg_square_compress_batched", "xtrg_observables",
-            "xtrg_dgemm", "xtrg_sgemm", "xtrg_gemm_bf16x3", "xtrg_dsvd_left", "xtrg_dsvd_left_qr", "xtrg_dqrcp", "xtrg_serve_submit", "xtrg_serve_poll", "xtrg_profile_enable",
+            "xtrg_dgemm", "xtrg_dgemm_noalloc", "xtrg_sgemm", "xtrg_gemm_bf16x3", "xtrg_dsvd_left", "xtrg_dsvd_left_qr", "xtrg_dqrcp", "xtrg_serve_submit", "xtrg_serve_poll", "xtrg_profile_enable",
             "xtrg_profile_report"]
 
 
@@ -328,6 +330,11 @@ class Context:
     def dgemm(self, M, N, K, transA, transB, A, lda, B, ldb, Cp, ldc):
         _check(self, _lib.xtrg_dgemm(self.h, M, N, K, int(transA), int(transB), C.c_void_p(A), lda,
                                      C.c_void_p(B), ldb, C.c_void_p(Cp), ldc))
+
+    def dgemm_noalloc(self, M, N, K, transA, transB, A, lda, B, ldb, Cp, ldc):
+        """xtrg_dgemm without device allocation (enqueued; does not wait)."""
+        _check(self, _lib.xtrg_dgemm_noalloc(self.h, M, N, K, int(transA), int(transB), C.c_void_p(A), lda,
+                                             C.c_void_p(B), ldb, C.c_void_p(Cp), ldc))
 
     def sgemm(self, M, N, K, transA, transB, A, lda, B, ldb, Cp, ldc, c_double=True):
         _check(self, _lib.xtrg_sgemm(self.h, M, N, K, int(transA), int(transB), C.c_void_p(A), lda,
