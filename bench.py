@@ -10,7 +10,7 @@ runs at the saturated bond dimension.  The metric counts the algorithmic
 flops of the contractions (64 D^4 per uniform two-site step, counted with
 the actual bond dimensions) divided by the wall time of the timed steps.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--D 256] [--sweeps 2] [--batch N]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--D 256] [--sweeps 4] [--batch N]
 
 --batch N runs N independent chains with interleaved temperature grids
 (tau0 * 2^(i/N), the z-shifts of Sec. II.B) through the batched doubling;
@@ -38,6 +38,7 @@ PEAK_HBM_GBS = 8000.0
 # x1.0); see the counters summary in profiles/.  Valid for the kernels as
 # measured: reset to None when they change.
 JACOBI_ROUND_TRAFFIC_1024 = 26.82e6
+JACOBI_ROUND_BYTES_1024 = 16.0 * 1024 * 1024   # algorithmic: every column read and written once
 
 
 def parse():
@@ -47,7 +48,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="chain64")
     ap.add_argument("--D", type=int, default=256)
-    ap.add_argument("--sweeps", type=int, default=2)
+    ap.add_argument("--sweeps", type=int, default=4, help="full sweeps per doubling (the default of the method)")
+    ap.add_argument("--side-sweeps", type=int, default=2,
+                    help="also time this many doublings at 2 sweeps (0: skip)")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the accuracy legs (stored-oracle parity run, SVD of a centre two-site tensor)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--batch", type=int, default=1)
@@ -88,7 +93,64 @@ def cpu_baseline(sites, D, n_steps):
         flops += OX._step_flops(E.shape, Dm, Dm, R.shape)
     dt = time.perf_counter() - t0
     threads = os.environ.get("OPENBLAS_NUM_THREADS") or os.environ.get("OMP_NUM_THREADS") or "default"
-    return flops / dt / 1e12, dt, flops, threads
+    return flops / dt / 1e12, dt, flops, threads, (th, S)
+
+
+def svd_accuracy(ctx, th, S_ref, D):
+    """The GPU's truncated SVD of the oracle's two-site tensor (both routes:
+    the Jacobi on the tensor, and the pivoted QR + Jacobi of first visits)
+    against LAPACK's values of the same tensor: max |d sigma| / sigma_1 over
+    the resolved values, and whether the cut rule keeps the same count."""
+    import numpy as np
+    import torch
+    from oracle import xtrg as OX
+    m, n = th.shape
+    dY = torch.from_numpy(np.ascontiguousarray(th)).to("cuda")     # row-major m x n = column-major n x m
+    nf = OX.noise_floor(th)
+    k_ref = OX.keep_count(S_ref, D, 1e-6, 1e-14, nf)
+    out = {"shape": [m, n], "k_lapack": k_ref}
+    for route in ("jacobi", "qr"):
+        sig = torch.zeros(m, dtype=torch.float64, device="cuda")
+        if route == "jacobi":
+            ctx.dsvd_left(n, m, dY.data_ptr(), sig.data_ptr(), 0, None)
+            keff = min(m, n)
+        else:
+            keff = ctx.dsvd_left_qr(n, m, dY.data_ptr(), sig.data_ptr(), 0, None)
+        torch.cuda.synchronize()
+        s = sig.cpu().numpy()[:min(m, n)]
+        r = min(keff, len(S_ref))
+        out[route] = {"max_dsigma_rel": float(np.abs(s[:r] - S_ref[:r]).max() / S_ref[0]),
+                      "k": OX.keep_count(s, D, 1e-6, 1e-14, nf), "resolved": int(keff)}
+    return out
+
+
+def parity_leg(ctx, name="chain12_D256"):
+    """The stored FP64 oracle run of the L=12 chain at D=256 (two-site
+    tensors of 1024 x 1024, 11 doublings, 2 sweeps) rerun through the
+    library: largest relative deviation of f, u, c over both estimators and
+    every beta, and whether every doubling kept the same bond dimensions."""
+    import json
+    import workloads as W
+    from paper_1801_00142_amd import run
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_{name}.json")
+    ref = json.load(open(path))
+    lat = W.workload(ref["workload"], ref["D"]).lattice
+    t0 = time.perf_counter()
+    gpu = run(ctx, lat.n_sites, lat.bonds, lat.jxy, lat.jz, ref["tau0"], ref["n_doublings"], ref["D"],
+              order=ref["order"], n_sweeps=ref["n_sweeps"])
+    dt = time.perf_counter() - t0
+    err = {"f": 0.0, "u": 0.0, "c": 0.0}
+    same = True
+    for g, o in zip(gpu, ref["records"]):
+        same &= g["bond_dims"] == o["bond_dims"]
+        for key, okey in (("tau", "tau_obs"), ("2tau", "two_tau_obs")):
+            for q, floor in (("f", 0.0), ("u", 1e-3), ("c", 1e-3)):
+                vo = o[okey][q]
+                err[q] = max(err[q], abs(g["obs"][key][q] - vo) / max(abs(vo), floor))
+    return {"workload": f"{name}: chain L=12, D={ref['D']}, {ref['n_doublings']} doublings, "
+                        f"{ref['n_sweeps']} sweeps, vs the stored FP64 oracle run",
+            "max_rel_df": err["f"], "max_rel_du": err["u"], "max_rel_dc": err["c"],
+            "bond_dims_equal": bool(same), "seconds": round(dt, 2)}
 
 
 def serve_main(args):
@@ -155,16 +217,16 @@ def main():
     mixed = {"fp64": XTRG_FP64, "fp32": XTRG_FP32, "bf16x3": XTRG_BF16X3}[args.precision]
     tau = [wl.tau0]
 
-    def doubling():
+    def doubling(n_sweeps):
         nonlocal rhos
         # the result reaches beta = 2 tau_{n+1} = 4 tau_n (the schedule of run())
         prec = mixed if 4 * tau[0] >= args.beta_mix else XTRG_FP64
         tau[0] *= 2
         if nb == 1:
-            new, info = ctx.square_compress(rhos[0], args.D, args.sweeps, precision=prec)
+            new, info = ctx.square_compress(rhos[0], args.D, n_sweeps, precision=prec)
             news, infos = [new], [info]
         else:
-            news, infos = ctx.square_compress_batched(rhos, args.D, args.sweeps, precision=prec)
+            news, infos = ctx.square_compress_batched(rhos, args.D, n_sweeps, precision=prec)
         for r in rhos:
             r.close()
         rhos = news
@@ -174,7 +236,7 @@ def main():
     n_done = 0
     saturated_at = None
     while True:
-        infos = doubling()
+        infos = doubling(args.sweeps)
         n_done += 1
         dmax = min(i["D_kept_max"] for i in infos)
         if saturated_at is None and dmax >= args.D:
@@ -185,41 +247,65 @@ def main():
         if n_done >= wl.n_doublings:
             break
 
-    torch.cuda.synchronize()
-    ctx.profile(True)
-    ctx.profile_report()                       # reset
-    flops = 0.0
-    steps_2site = 0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        infos = doubling()
-        flops += sum(i["flops"] for i in infos)
-        steps_2site += sum(i["steps"] for i in infos)
-        print(f"timed doubling done: {steps_2site} two-site steps", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    prof = ctx.profile_report()
-    ctx.profile(False)
+    def timed(n_steps, n_sweeps, label):
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ctx.profile_report()                       # reset
+        flops = 0.0
+        steps_2site = 0
+        t0 = time.perf_counter()
+        for _ in range(n_steps):
+            infos = doubling(n_sweeps)
+            flops += sum(i["flops"] for i in infos)
+            steps_2site += sum(i["steps"] for i in infos)
+            print(f"{label} doubling done: {steps_2site} two-site steps", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = ctx.profile_report()
+        ctx.profile(False)
+        return flops, steps_2site, dt, prof
 
+    flops, steps_2site, dt, prof = timed(args.steps, args.sweeps, "timed")
     value = flops / dt / 1e12
+    side = None
+    if args.side_sweeps > 0 and args.sweeps != 2:
+        f2, s2, d2, _ = timed(args.side_sweeps, 2, "2-sweep")
+        side = {"value": round(f2 / d2 / 1e12, 4), "n_sweeps": 2, "doublings": args.side_sweeps,
+                "ms_per_step": round(d2 / args.side_sweeps * 1e3, 3)}
+
     svd_calls = prof.pop("svd_calls", 0)
     svd_sweeps = prof.pop("svd_sweeps", 0)
     warm_stats = {k: prof.pop(k, 0) for k in ("warm_built", "warm_rejected", "warm_used", "warm_m")}
     qr_stats = {k: prof.pop(k, 0) for k in ("qr_calls", "qr_rows", "qr_sweeps", "qr_used", "qr_rejected")}
-    rounds = prof.pop("svd_rounds")
+    rounds = prof.pop("svd_rounds")                 # sliced rounds: a Gram and a rotate launch each
+    rounds_fused = prof.pop("svd_rounds_fused")
     th = prof["theta_gemm"]
     th_avg_s = th["ms"] / max(th["calls"], 1) / 1e3
     th_flops = th["flops"] / max(th["calls"], 1)
     th_achieved = th_flops / th_avg_s / 1e12 if th_avg_s > 0 else 0.0
-    rd_avg_s = rounds["ms"] / max(rounds["calls"], 1) / 1e3
-    rd_bytes = rounds["bytes"] / max(rounds["calls"], 1)
-    rd_gbs = rd_bytes / rd_avg_s / 1e9 if rd_avg_s > 0 else 0.0
+    # the dominant kernel: the Jacobi round split over row slices (a Gram
+    # launch and a rotate launch back to back), timed by event pairs around
+    # each sweep's launches; algorithmic bytes: every active column read and
+    # written once per round
+    n_rounds = max(rounds["calls"] // 2, 1)
+    round_us = rounds["ms"] / n_rounds * 1e3
+    round_bytes = rounds["bytes"] / n_rounds
+    round_gbs = round_bytes / (round_us * 1e-6) / 1e9 if round_us > 0 else 0.0
     total_ms = sum(v["ms"] for v in prof.values())
     shares = {k: round(v["ms"] / total_ms, 4) if total_ms else 0.0 for k, v in prof.items()}
     svd_ms = prof["svd"]["ms"] + prof.get("qr_start", {"ms": 0.0})["ms"]
-    shares["svd_rounds_of_svd"] = round(rounds["ms"] / svd_ms, 4) if svd_ms else 0.0
+    shares["svd_rounds_of_svd"] = round((rounds["ms"] + rounds_fused["ms"]) / svd_ms, 4) if svd_ms else 0.0
 
-    wl_name = f"{lat.name} Heisenberg, tau0=2^-12, D={args.D}, {args.sweeps} sweeps/doubling"
+    # observables of the saturated state (what the serving loop evaluates
+    # after every doubling), timed once
+    torch.cuda.synchronize()
+    t_obs = time.perf_counter()
+    ctx.observables(rhos[0], 0.0, tau[0], H, lat.n_sites, entropy=False)
+    torch.cuda.synchronize()
+    obs_s = time.perf_counter() - t_obs
+
+    wl_name = (f"{lat.name} {'Heisenberg' if set(lat.jz) == set(lat.jxy) == {1.0} else 'XXZ'}, "
+               f"tau0=2^{math.log2(wl.tau0):g}, D={args.D}, {args.sweeps} sweeps/doubling")
     if nb > 1:
         wl_name += f", {nb} z-shifted chains batched"
     out = {
@@ -240,6 +326,7 @@ def main():
                    "chains": nb, "two_site_steps_per_doubling": steps_2site // max(args.steps, 1),
                    "warmup_doublings": n_done, "saturated_after": saturated_at},
         "sweeps_per_s": round(nb * args.steps * args.sweeps / dt, 4),
+        "observables_s": round(obs_s, 3),
         "phase_share": shares,
         "svd_sweeps_avg": round(svd_sweeps / max(svd_calls, 1), 2),
         "svd_warm": {"calls": svd_calls, "warm_started": warm_stats["warm_used"],
@@ -251,30 +338,40 @@ def main():
                          "rejected": qr_stats["qr_rejected"],
                          "mean_rows": round(qr_stats["qr_rows"] / max(qr_stats["qr_calls"], 1), 1),
                          "rt_sweeps_avg": round(qr_stats["qr_sweeps"] / max(qr_stats["qr_used"], 1), 2)},
-        # the dominant kernel: the Jacobi rounds of the SVD (bytes = each
-        # column of the visited pairs read and written once per round)
-        "roofline": {"bound": "hbm", "kernel": "jacobi_round (one block-Jacobi SVD round: Gram + rotate launches over row slices)",
-                     "achieved": round(rd_gbs, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(rd_gbs / PEAK_HBM_GBS, 4), "traffic": JACOBI_ROUND_TRAFFIC_1024,
-                     "traffic_note": "HBM bytes per round of a 1024 x 1024 SVD, sliced form (rocprofv3 counters, copy-scaled)",
-                     "rounds": rounds["calls"], "avg_round_us": round(rd_avg_s * 1e6, 3),
-                     "bytes_per_round": rd_bytes,
-                     "flops_per_round": rounds["flops"] / max(rounds["calls"], 1)},
+        "roofline": {"bound": "hbm",
+                     "kernel": "jacobi_round<1> + jacobi_round<2> (one block-Jacobi SVD round split over row "
+                               "slices: Gram launch, rotate launch)",
+                     "achieved": round(round_gbs, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(round_gbs / PEAK_HBM_GBS, 4),
+                     "traffic": JACOBI_ROUND_TRAFFIC_1024 * round_bytes / JACOBI_ROUND_BYTES_1024,
+                     "traffic_note": "rocprofv3 FETCH_SIZE + WRITE_SIZE of the 1024-column round, copy-scaled, "
+                                     "scaled to this run's mean algorithmic bytes per round",
+                     "rounds": n_rounds, "avg_round_us": round(round_us, 3), "bytes_per_round": round_bytes},
         "roofline_theta": {"bound": "mfma", "kernel": "two-site overlap C_E (gemm_kernel<128,128,...,1,double,double>)",
                            "achieved": round(th_achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                            "frac": round(th_achieved / PEAK_FP64_TFLOPS, 4),
                            "launches": th["calls"], "avg_launch_ms": round(th_avg_s * 1e3, 4),
                            "flops_per_launch": th_flops},
     }
-    if not args.no_cpu_baseline:
+    if side:
+        out["value_2_sweeps"] = side
+    sites = None
+    if not args.no_cpu_baseline or not args.no_accuracy:
         sites = rhos[0].to_host()
-        tf, cdt, cfl, threads = cpu_baseline(sites, args.D, args.cpu_steps)
+    if not args.no_accuracy:
+        print("accuracy: stored-oracle parity run", file=sys.stderr, flush=True)
+        out["accuracy"] = {"parity": parity_leg(ctx)}
+    if not args.no_cpu_baseline:
+        tf, cdt, cfl, threads, (th_c, S_c) = cpu_baseline(sites, args.D, args.cpu_steps)
         out["cpu_baseline"] = {"value": round(tf, 5), "unit": "TFLOP/s",
                                "cores": len(os.sched_getaffinity(0)), "blas_threads": threads,
                                "kind": "oracle", "seconds": round(cdt, 2),
                                "sample": f"{args.cpu_steps} two-site steps (left/right block, C_E, LAPACK SVD, "
                                          f"environment) at the centre bond of the saturated D={args.D} MPO, "
                                          "seeded environments"}
+        if not args.no_accuracy:
+            print("accuracy: SVD of the centre two-site tensor", file=sys.stderr, flush=True)
+            out["accuracy"]["svd_centre"] = svd_accuracy(ctx, th_c, S_c, args.D)
     for r in rhos:
         r.close()
     H.close()

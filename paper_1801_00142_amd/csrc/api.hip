@@ -53,9 +53,11 @@ namespace {
 // svd_rounds is the part of svd spent in the Jacobi round kernels; its
 // "calls" count kernel launches.
 // warm is the building of the warm-start bases and the rotation of the SVD input.
-enum { P_THETA = 0, P_BLOCK, P_ENV, P_SVD, P_SPLIT, P_ROUNDS, P_WARM, P_QR, P_NCAT };
+// svd_rounds: the sweeps of rounds split over row slices (a Gram and a
+// rotate launch per round); svd_rounds_fused: those of one-launch rounds.
+enum { P_THETA = 0, P_BLOCK, P_ENV, P_SVD, P_SPLIT, P_ROUNDS, P_WARM, P_QR, P_ROUNDS0, P_NCAT };
 const char* const kPhase[P_NCAT] = {"theta_gemm", "block_gemm", "env_gemm", "svd",
-                                    "split", "svd_rounds", "warm", "qr_start"};
+                                    "split", "svd_rounds", "warm", "qr_start", "svd_rounds_fused"};
 
 // RAII event pair around the work enqueued in its scope.
 struct Timed {
@@ -123,7 +125,9 @@ double read_scalar(xtrg_ctx c, const double* d) {
   return h;
 }
 
-// Event pairs around the Jacobi round launches of each sweep.
+// Event pairs around the Jacobi round launches of each sweep (back to back
+// on the stream, so the bracket over a sweep's launches divided by their
+// number is the mean launch duration).
 struct RoundProf : xtrg::RoundTimer {
   xtrg_ctx c;
   xtrg_ctx_s::Prof r{};
@@ -134,10 +138,10 @@ struct RoundProf : xtrg::RoundTimer {
     XTRG_HIP(hipEventCreate(&r.b));
     XTRG_HIP(hipEventRecord(r.a, s));
   }
-  void end(hipStream_t s, long launches, double flops, double bytes) override {
+  void end(hipStream_t s, long launches, double flops, double bytes, bool sliced) override {
     if (!c->prof) return;
     XTRG_HIP(hipEventRecord(r.b, s));
-    r.cat = P_ROUNDS;
+    r.cat = sliced ? P_ROUNDS : P_ROUNDS0;
     r.flops = flops;
     r.bytes = bytes;
     r.launches = launches;
@@ -157,6 +161,14 @@ void gemm(xtrg_ctx c, const Gemm& g) {
   const size_t w = xtrg::gemm_splitk_work(g);
   double* work = w ? c->need("splitk", w) : nullptr;
   xtrg::gemm(g, c->stream, work, w);
+}
+
+// Independent GEMMs (one per chain of a batch step) in grouped launches.
+void gemm_group(xtrg_ctx c, const std::vector<Gemm>& gs) {
+  if (gs.empty()) return;
+  const size_t w = xtrg::gemm_grouped_work(gs);
+  double* work = w ? c->need("splitk_group", w) : nullptr;
+  xtrg::gemm_grouped(gs, c->stream, work, w);
 }
 
 // Plain row-major C[MxN] = op(A) op(B).
@@ -494,10 +506,11 @@ struct Doubler {
     return slot[i] = needw("slot" + std::to_string(i) + tag, n);
   }
 
-  // Lb[(c,s,s'')][(a',b')] = sum_{a,b,s'} E[c][a][b] A_i[a][s][s'][a'] A_i[b][s'][s''][b']
-  void left_block(int i, const void* E, void* out) {
+  // Lb[(c,s,s'')][(a',b')] = sum_{a,b,s'} E[c][a][b] A_i[a][s][s'][a'] A_i[b][s'][s''][b']:
+  // two batched GEMMs, the second reading the first's output X (the chain's own)
+  std::pair<Gemm, Gemm> left_block_gemms(int i, const void* E, void* out) {
     const int dc = Dc[i], da = Da[i], db = Da[i], da2 = Da[i + 1], db2 = Da[i + 1];
-    void* X = needw("X", (size_t)dc * 4 * db * da2);
+    void* X = needw("X" + tag, (size_t)dc * 4 * db * da2);
     Gemm g1;
     g1.prec = prec; g1.out64 = 0;   // X[c][s][b][(s',a')] = sum_a E[c][a][b] A[a][s][(s',a')]   batch (c, s)
     g1.M = db; g1.N = 2 * da2; g1.K = da;
@@ -508,7 +521,6 @@ struct Doubler {
     g1.sA[0] = (long)da * db;
     g1.sB[1] = 2L * da2;
     g1.sC[0] = 4L * db * da2; g1.sC[1] = 2L * db * da2;
-    gemm(c, g1);
     Gemm g2;
     g2.prec = prec; g2.out64 = 0;
     //         Lb[c][s][s''][a'][b'] = sum_{(b,s')} X[c][s][(b,s')][a'] B[(b,s')][s''][b']  batch (c,s,s'')
@@ -520,14 +532,14 @@ struct Doubler {
     g2.sA[0] = 4L * db * da2; g2.sA[1] = 2L * db * da2;
     g2.sB[2] = db2;
     g2.sC[0] = 4L * da2 * db2; g2.sC[1] = 2L * da2 * db2; g2.sC[2] = (long)da2 * db2;
-    gemm(c, g2);
+    return {g1, g2};
   }
 
   // Rb[(a,b)][(t,t'',c'')] = sum_{a'',b'',t'} A_j[a][t][t'][a''] A_j[b][t'][t''][b''] F[a''][b''][c'']
-  void right_block(int j, const void* F, void* out) {
+  std::pair<Gemm, Gemm> right_block_gemms(int j, const void* F, void* out) {
     const int da = Da[j], db = Da[j], da2 = Da[j + 1], db2 = Da[j + 1], dc2 = Dc[j + 1];
-    void* Z = needw("X", (size_t)4 * da * db2 * dc2);
-    gemm(c, wplain(4 * da, db2 * dc2, da2, A[j], da2, false, F, (long)db2 * dc2, false, Z, (long)db2 * dc2));
+    void* Z = needw("X" + tag, (size_t)4 * da * db2 * dc2);
+    const Gemm g1 = wplain(4 * da, db2 * dc2, da2, A[j], da2, false, F, (long)db2 * dc2, false, Z, (long)db2 * dc2);
     Gemm g;
     g.prec = prec; g.out64 = 0;
     //         batch (a, t, t''): Rb[a][b][t][t''][c''] = sum_{(t',b'')} Bp[b][t''][(t',b'')] Z[a][t][(t',b'')][c'']
@@ -539,7 +551,18 @@ struct Doubler {
     g.sA[2] = 2L * db2;
     g.sB[0] = 4L * db2 * dc2; g.sB[1] = 2L * db2 * dc2;
     g.sC[0] = 4L * db * dc2; g.sC[1] = 2L * dc2; g.sC[2] = dc2;
-    gemm(c, g);
+    return {g1, g};
+  }
+
+  void left_block(int i, const void* E, void* out) {
+    const auto g = left_block_gemms(i, E, out);
+    gemm(c, g.first);
+    gemm(c, g.second);
+  }
+  void right_block(int j, const void* F, void* out) {
+    const auto g = right_block_gemms(j, F, out);
+    gemm(c, g.first);
+    gemm(c, g.second);
   }
 
   static double step_flops(int dc, int da, int db, int da2, int db2, int dc2) {
@@ -587,6 +610,7 @@ struct Chain {
   bool warm_now = false;                  // this step's SVD input was rotated by a warm basis
   int status = 0;                         // XTRG_OK, or the code that stopped this chain
   std::string err;                        // and its message
+
 };
 
 void check_opts(const xtrg_compress_opts& o) {
@@ -1062,20 +1086,26 @@ int square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_comp
                 16.0 * d.Dc[i + 2] * d.Da[i + 1] * (double)d.Da[i + 2] * d.Da[i + 1];
       }
       Timed tm(c, P_BLOCK, fb, 0.0);
+      std::vector<Gemm> g1, g2;   // the two substeps of every chain, each stage one grouped launch
       for (Chain* C : act)
         per_chain(*C, [&] {
           auto& d = C->d;
           const int i = C->i;
+          std::pair<Gemm, Gemm> gg;
           if (C->sched[st].dir > 0) {
             C->Lb = d.slot_need(i);
-            d.left_block(i, C->E, C->Lb);
+            gg = d.left_block_gemms(i, C->E, C->Lb);
             C->Rb = d.slot.at(i + 1);
           } else {
             C->Rb = d.slot_need(i + 1);
-            d.right_block(i + 1, C->F, C->Rb);
+            gg = d.right_block_gemms(i + 1, C->F, C->Rb);
             C->Lb = d.slot.at(i);
           }
+          g1.push_back(gg.first);
+          g2.push_back(gg.second);
         });
+      gemm_group(c, g1);
+      gemm_group(c, g2);
     }
     {
       double fth = 0.0, bth = 0.0;
@@ -1092,6 +1122,7 @@ int square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_comp
         bth += 8.0 * ((double)C->mL * C->Kt + (double)C->Kt * C->mR + (double)C->mL * C->mR);
       }
       Timed tm(c, P_THETA, fth, bth);
+      std::vector<Gemm> gt;
       for (Chain* C : act)
         per_chain(*C, [&] {
           const auto& d = C->d;
@@ -1103,29 +1134,41 @@ int square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_comp
                        ? plain(C->mR, C->mL, C->Kt, C->Rb, C->mR, true, C->Lb, C->Kt, true, C->th, C->mL, pr, 1)  // column-major
                        : plain(C->mL, C->mR, C->Kt, C->Lb, C->Kt, false, C->Rb, C->mR, false, C->th, C->mR, pr, 1);
           g.tag = 1;
-          gemm(c, g);
+          gt.push_back(g);
         });
+      gemm_group(c, gt);
     }
-    for (Chain* C : act)
-      per_chain(*C, [&] {
-        C->Y = C->th;
-        C->psvd = C->p;
-        C->svd_done = false;
-        C->warm_now = false;
+    {
+      double fw = 0.0;
+      for (Chain* C : act) {
         const auto& w = C->warm[C->i];
-        const int need_side = C->gauge_right ? 1 : 0;   // the column index of Y
-        if (!C->o.no_warm_start && C->p >= kWarmMin && w.side == need_side && w.dim == C->p) {
-          Timed tm(c, P_WARM, 2.0 * C->len * (double)C->p * w.cols, 0.0);
-          const double* Q = c->need("wq" + std::to_string(C->i) + C->tag, (size_t)C->p * w.cols);
-          double* Yw = c->need("svd_in" + C->tag, (size_t)C->len * w.cols);
-          gemm(c, plain(w.cols, C->len, C->p, Q, C->p, false, C->th, C->len, false, Yw, C->len));   // Y [Q0 X]
-          C->Y = Yw;
-          C->psvd = w.cols;
-          C->warm_now = true;
-          c->warm_used += 1;
-        }
-        C->work = c->need("svd" + C->tag, xtrg::svd_work(C->len, C->psvd));
-      });
+        if (C->status == XTRG_OK && !C->o.no_warm_start && C->p >= kWarmMin && w.side == (C->gauge_right ? 1 : 0) &&
+            w.dim == C->p)
+          fw += 2.0 * C->len * (double)C->p * w.cols;
+      }
+      Timed tm(c, P_WARM, fw, 0.0);
+      std::vector<Gemm> gw;
+      for (Chain* C : act)
+        per_chain(*C, [&] {
+          C->Y = C->th;
+          C->psvd = C->p;
+          C->svd_done = false;
+          C->warm_now = false;
+          const auto& w = C->warm[C->i];
+          const int need_side = C->gauge_right ? 1 : 0;   // the column index of Y
+          if (!C->o.no_warm_start && C->p >= kWarmMin && w.side == need_side && w.dim == C->p) {
+            const double* Q = c->need("wq" + std::to_string(C->i) + C->tag, (size_t)C->p * w.cols);
+            double* Yw = c->need("svd_in" + C->tag, (size_t)C->len * w.cols);
+            gw.push_back(plain(w.cols, C->len, C->p, Q, C->p, false, C->th, C->len, false, Yw, C->len));   // Y [Q0 X]
+            C->Y = Yw;
+            C->psvd = w.cols;
+            C->warm_now = true;
+            c->warm_used += 1;
+          }
+          C->work = c->need("svd" + C->tag, xtrg::svd_work(C->len, C->psvd));
+        });
+      gemm_group(c, gw);
+    }
     {
       std::vector<Chain*> pre;
       for (Chain* C : act)

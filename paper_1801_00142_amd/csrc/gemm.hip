@@ -37,9 +37,12 @@ template <> struct Mfma<float> {
   static __device__ inline int row(int lk, int r) { return 4 * lk + r; }
 };
 
-// TAG only separates kernel symbols (1 = two-site overlap C_E) for profilers.
-template <int BM, int BN, bool TA, bool TB, int TAG, typename TI, typename TO>
-__global__ __launch_bounds__(256) void gemm_kernel(Gemm g, int splitk, int kchunk, double* work) {
+// One output tile (BM x BN at m0, n0) of batch / split-K slice z, for the
+// plain and the grouped launches alike (the same arithmetic in the same
+// order, so a problem gets the same bits either way).
+template <int BM, int BN, bool TA, bool TB, typename TI, typename TO>
+__device__ __forceinline__ void gemm_tile(const Gemm& g, int m0, int n0, int z, int splitk, int kchunk,
+                                          double* work) {
   using MF = Mfma<TI>;
   constexpr int WM = BM / 2, WN = BN / 2;     // wave tile
   constexpr int TM = WM / 16, TN = WN / 16;   // MFMA tiles per wave
@@ -54,7 +57,6 @@ __global__ __launch_bounds__(256) void gemm_kernel(Gemm g, int splitk, int kchun
   const int wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
-  int z = blockIdx.z;
   const int ks = z % splitk;
   z /= splitk;
   const int b2 = z % g.nb[2];
@@ -63,8 +65,6 @@ __global__ __launch_bounds__(256) void gemm_kernel(Gemm g, int splitk, int kchun
   const TI* __restrict__ A = static_cast<const TI*>(g.A) + b0 * g.sA[0] + b1 * g.sA[1] + b2 * g.sA[2];
   const TI* __restrict__ B = static_cast<const TI*>(g.B) + b0 * g.sB[0] + b1 * g.sB[1] + b2 * g.sB[2];
 
-  const int m0 = blockIdx.y * BM;
-  const int n0 = blockIdx.x * BN;
   const int kbeg = ks * kchunk;
   const int kend = min(g.K, kbeg + kchunk);
   const int M = g.M, N = g.N;
@@ -183,13 +183,57 @@ __global__ __launch_bounds__(256) void gemm_kernel(Gemm g, int splitk, int kchun
   }
 }
 
+// TAG only separates kernel symbols (1 = two-site overlap C_E) for profilers.
+template <int BM, int BN, bool TA, bool TB, int TAG, typename TI, typename TO>
+__global__ __launch_bounds__(256) void gemm_kernel(Gemm g, int splitk, int kchunk, double* work) {
+  gemm_tile<BM, BN, TA, TB, TI, TO>(g, blockIdx.y * BM, blockIdx.x * BN, blockIdx.z, splitk, kchunk, work);
+}
+
+// Grouped launch: up to kGroup independent problems (one per chain of a
+// batch step, each with its own shapes, strides, pointers and split-K), the
+// workgroups of problem q numbered from first[q] on.
+constexpr int kGroup = 8;
+struct GroupItem {
+  Gemm g;
+  int splitk, kchunk;
+  double* work;
+  int tiles_n, tiles_m;
+  int first;        // first workgroup of this problem
+};
+struct GroupArgs {
+  int n;
+  GroupItem it[kGroup];
+};
+
+template <int BM, int BN>
+__device__ __forceinline__ int group_find(const GroupArgs& a, int blk, int* local) {
+  int q = 0;
+  for (int j = 1; j < a.n; ++j)
+    if (blk >= a.it[j].first) q = j;
+  *local = blk - a.it[q].first;
+  return q;
+}
+
+template <int BM, int BN, bool TA, bool TB, int TAG, typename TI, typename TO>
+__global__ __launch_bounds__(256) void gemm_group_kernel(GroupArgs a) {
+  int local;
+  const int q = group_find<BM, BN>(a, blockIdx.x, &local);
+  const GroupItem& it = a.it[q];
+  const int tn = local % it.tiles_n, tm = (local / it.tiles_n) % it.tiles_m;
+  const int z = local / (it.tiles_n * it.tiles_m);
+  gemm_tile<BM, BN, TA, TB, TI, TO>(it.g, tm * BM, tn * BN, z, it.splitk, it.kchunk, it.work);
+}
+
 // Split-BF16 (bf16x3) variant for float operands: every element x is split
 // at staging into hi = bf16(x) and lo = bf16(x - hi) (round to nearest
 // even), and the product is accumulated in FP32 on the bf16 matrix cores
-// (v_mfma_f32_16x16x16_bf16) as hi*hi + hi*lo + lo*hi.  The tiles are kept
-// in LDS as [m][k] and [n][k] so that each lane's 4 consecutive k are one
-// 8-byte read.
-typedef short s4 __attribute__((ext_vector_type(4)));
+// as hi*hi + hi*lo + lo*hi with gfx950's 16 x 16 x 32 bf16 product
+// (v_mfma_f32_16x16x32_bf16: twice the k of the 16 x 16 x 16 form per
+// instruction).  K tiles of 32; the tiles are kept in LDS as [m][k] and
+// [n][k] so that each lane's 8 consecutive k are one 16-byte read.
+typedef short s8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+constexpr int BK3 = 32;
 
 __device__ inline unsigned short bf16_rne(float x) {
   const unsigned u = __float_as_uint(x);
@@ -200,13 +244,18 @@ __device__ inline void split_bf16(float x, unsigned short* hi, unsigned short* l
   *lo = bf16_rne(x - __uint_as_float((unsigned)*hi << 16));
 }
 
-template <int BM, int BN, bool TA, bool TB, int TAG, typename TO>
-__global__ __launch_bounds__(256) void gemm_bf3_kernel(Gemm g, int splitk, int kchunk, double* work) {
+template <int BM, int BN, bool TA, bool TB, typename TO>
+__device__ __forceinline__ void gemm_bf3_tile(const Gemm& g, int m0, int n0, int z, int splitk, int kchunk,
+                                              double* work) {
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
-  constexpr int LA = BM * BK / 256;
-  constexpr int LB = BN * BK / 256;
-  constexpr int KP = BK + 8;                  // padded k extent (shorts), 8-byte aligned rows
+  constexpr int LA = BM * BK3 / 256;          // elements of A per thread per K tile
+  constexpr int LB = BN * BK3 / 256;
+  constexpr int KP = BK3 + 8;                 // padded k extent (shorts): rows of 80 bytes, 16-byte aligned
+  // staging maps: a thread loads 4 consecutive elements along the stored
+  // row; row-major A (no transpose) takes BK3/4 threads per m, a stored
+  // K x M block (transpose) takes BM/4 threads per k (likewise for B)
+  constexpr int AK = BK3 / 4, AM = BM / 4, BKT = BK3 / 4, BNT = BN / 4;
   __shared__ unsigned short Ah[BM][KP], Al[BM][KP];
   __shared__ unsigned short Bh[BN][KP], Bl[BN][KP];
 
@@ -215,7 +264,6 @@ __global__ __launch_bounds__(256) void gemm_bf3_kernel(Gemm g, int splitk, int k
   const int wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
-  int z = blockIdx.z;
   const int ks = z % splitk;
   z /= splitk;
   const int b2 = z % g.nb[2];
@@ -224,8 +272,6 @@ __global__ __launch_bounds__(256) void gemm_bf3_kernel(Gemm g, int splitk, int k
   const float* __restrict__ A = static_cast<const float*>(g.A) + b0 * g.sA[0] + b1 * g.sA[1] + b2 * g.sA[2];
   const float* __restrict__ B = static_cast<const float*>(g.B) + b0 * g.sB[0] + b1 * g.sB[1] + b2 * g.sB[2];
 
-  const int m0 = blockIdx.y * BM;
-  const int n0 = blockIdx.x * BN;
   const int kbeg = ks * kchunk;
   const int kend = min(g.K, kbeg + kchunk);
   const int M = g.M, N = g.N;
@@ -235,13 +281,13 @@ __global__ __launch_bounds__(256) void gemm_bf3_kernel(Gemm g, int splitk, int k
 #pragma unroll
     for (int c = 0; c < LA / 4; ++c) {
       if (!TA) {
-        const int m = m0 + (t >> 2) + 64 * c;
-        const int k = k0 + (t & 3) * 4;
+        const int m = m0 + t / AK + (256 / AK) * c;
+        const int k = k0 + (t % AK) * 4;
 #pragma unroll
         for (int j = 0; j < 4; ++j) ra[4 * c + j] = (m < M && k + j < kend) ? A[(long)m * g.lda + k + j] : 0.f;
       } else {
-        const int k = k0 + (t >> 4);
-        const int m = m0 + (t & 15) * 4 + 64 * c;
+        const int k = k0 + t / AM + (256 / AM) * c;
+        const int m = m0 + (t % AM) * 4;
 #pragma unroll
         for (int j = 0; j < 4; ++j) ra[4 * c + j] = (k < kend && m + j < M) ? A[(long)k * g.lda + m + j] : 0.f;
       }
@@ -249,13 +295,13 @@ __global__ __launch_bounds__(256) void gemm_bf3_kernel(Gemm g, int splitk, int k
 #pragma unroll
     for (int c = 0; c < LB / 4; ++c) {
       if (!TB) {
-        const int k = k0 + (t >> 4);
-        const int n = n0 + (t & 15) * 4 + 64 * c;
+        const int k = k0 + t / BNT + (256 / BNT) * c;
+        const int n = n0 + (t % BNT) * 4;
 #pragma unroll
         for (int j = 0; j < 4; ++j) rb[4 * c + j] = (k < kend && n + j < N) ? B[(long)k * g.ldb + n + j] : 0.f;
       } else {
-        const int n = n0 + (t >> 2) + 64 * c;
-        const int k = k0 + (t & 3) * 4;
+        const int n = n0 + t / BKT + (256 / BKT) * c;
+        const int k = k0 + (t % BKT) * 4;
 #pragma unroll
         for (int j = 0; j < 4; ++j) rb[4 * c + j] = (n < N && k + j < kend) ? B[(long)n * g.ldb + k + j] : 0.f;
       }
@@ -266,16 +312,16 @@ __global__ __launch_bounds__(256) void gemm_bf3_kernel(Gemm g, int splitk, int k
     for (int c = 0; c < LA / 4; ++c)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int mm = !TA ? (t >> 2) + 64 * c : (t & 15) * 4 + 64 * c + j;
-        const int kk = !TA ? (t & 3) * 4 + j : (t >> 4);
+        const int mm = !TA ? t / AK + (256 / AK) * c : (t % AM) * 4 + j;
+        const int kk = !TA ? (t % AK) * 4 + j : t / AM + (256 / AM) * c;
         split_bf16(ra[4 * c + j], &Ah[mm][kk], &Al[mm][kk]);
       }
 #pragma unroll
     for (int c = 0; c < LB / 4; ++c)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int nn = !TB ? (t & 15) * 4 + 64 * c + j : (t >> 2) + 64 * c;
-        const int kk = !TB ? (t >> 4) : (t & 3) * 4 + j;
+        const int nn = !TB ? (t % BNT) * 4 + j : t / BKT + (256 / BKT) * c;
+        const int kk = !TB ? t / BNT + (256 / BNT) * c : (t % BKT) * 4 + j;
         split_bf16(rb[4 * c + j], &Bh[nn][kk], &Bl[nn][kk]);
       }
   };
@@ -289,30 +335,31 @@ __global__ __launch_bounds__(256) void gemm_bf3_kernel(Gemm g, int splitk, int k
   const int lr = lane & 15, lk = lane >> 4;
   if (kbeg < kend) {
     load(kbeg);
-    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    for (int k0 = kbeg; k0 < kend; k0 += BK3) {
       __syncthreads();
       stash();
       __syncthreads();
-      if (k0 + BK < kend) load(k0 + BK);
-      // operand lane l: A(i = l%16, k = 4 (l/16) + v), B(k = 4 (l/16) + v, j = l%16), v = 0..3
-      s4 ah[TM], al[TM], bh[TN], bl[TN];
+      if (k0 + BK3 < kend) load(k0 + BK3);
+      // operand lane l: A(i = l%16, k = 8 (l/16) + v), B(k = 8 (l/16) + v, j = l%16),
+      // v = 0..7: the same k for the same (l/16, v) in both operands
+      bf8 ah[TM], al[TM], bh[TN], bl[TN];
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
-        ah[i] = *reinterpret_cast<const s4*>(&Ah[wm * WM + i * 16 + lr][4 * lk]);
-        al[i] = *reinterpret_cast<const s4*>(&Al[wm * WM + i * 16 + lr][4 * lk]);
+        ah[i] = __builtin_bit_cast(bf8, *reinterpret_cast<const s8*>(&Ah[wm * WM + i * 16 + lr][8 * lk]));
+        al[i] = __builtin_bit_cast(bf8, *reinterpret_cast<const s8*>(&Al[wm * WM + i * 16 + lr][8 * lk]));
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
-        bh[j] = *reinterpret_cast<const s4*>(&Bh[wn * WN + j * 16 + lr][4 * lk]);
-        bl[j] = *reinterpret_cast<const s4*>(&Bl[wn * WN + j * 16 + lr][4 * lk]);
+        bh[j] = __builtin_bit_cast(bf8, *reinterpret_cast<const s8*>(&Bh[wn * WN + j * 16 + lr][8 * lk]));
+        bl[j] = __builtin_bit_cast(bf8, *reinterpret_cast<const s8*>(&Bl[wn * WN + j * 16 + lr][8 * lk]));
       }
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
         }
     }
   }
@@ -347,6 +394,21 @@ __global__ __launch_bounds__(256) void gemm_bf3_kernel(Gemm g, int splitk, int k
   }
 }
 
+template <int BM, int BN, bool TA, bool TB, int TAG, typename TO>
+__global__ __launch_bounds__(256) void gemm_bf3_kernel(Gemm g, int splitk, int kchunk, double* work) {
+  gemm_bf3_tile<BM, BN, TA, TB, TO>(g, blockIdx.y * BM, blockIdx.x * BN, blockIdx.z, splitk, kchunk, work);
+}
+
+template <int BM, int BN, bool TA, bool TB, int TAG, typename TO>
+__global__ __launch_bounds__(256) void gemm_bf3_group_kernel(GroupArgs a) {
+  int local;
+  const int q = group_find<BM, BN>(a, blockIdx.x, &local);
+  const GroupItem& it = a.it[q];
+  const int tn = local % it.tiles_n, tm = (local / it.tiles_n) % it.tiles_m;
+  const int z = local / (it.tiles_n * it.tiles_m);
+  gemm_bf3_tile<BM, BN, TA, TB, TO>(it.g, tm * BM, tn * BN, z, it.splitk, it.kchunk, it.work);
+}
+
 // Deterministic split-K reduction: C[row*ldc + col] = sum_ks work[ks][row][col].
 template <typename TO>
 __global__ void splitk_reduce(const double* __restrict__ work, int splitk, int M, int N,
@@ -358,6 +420,22 @@ __global__ void splitk_reduce(const double* __restrict__ work, int splitk, int M
   for (int k = 0; k < splitk; ++k) s += work[k * MN + idx];
   const int row = (int)(idx / N), col = (int)(idx % N);
   C[(long)row * ldc + col] = (TO)s;
+}
+
+// The split-K reductions of a grouped launch (problems with splitk > 1;
+// `first` counts 256-element blocks here), each in the order of the plain one.
+template <typename TO>
+__global__ void splitk_reduce_group(GroupArgs a) {
+  int local;
+  const int q = group_find<1, 1>(a, blockIdx.x, &local);
+  const GroupItem& it = a.it[q];
+  const long idx = (long)local * blockDim.x + threadIdx.x;
+  const long MN = (long)it.g.M * it.g.N;
+  if (idx >= MN) return;
+  double s = 0.0;
+  for (int k = 0; k < it.splitk; ++k) s += it.work[k * MN + idx];
+  const int row = (int)(idx / it.g.N), col = (int)(idx % it.g.N);
+  static_cast<TO*>(it.g.C)[(long)row * it.g.ldc + col] = (TO)s;
 }
 
 namespace {
@@ -429,7 +507,121 @@ int choose_splitk(const Gemm& g, bool big) {
 
 bool use_big(const Gemm& g) { return g.M >= 128 && g.N >= 128; }
 
+// Grouped launches: problems that share a kernel (precision, output type,
+// tile size, transposes, tag) go out together, kGroup per launch.
+struct Plan {
+  bool big;
+  int sk, kchunk;
+  int key;
+};
+
+Plan plan_of(const Gemm& g, bool have_work) {
+  Plan p;
+  p.big = use_big(g) && !g.tiles64;
+  p.sk = choose_splitk(g, p.big);
+  if (!have_work || g.K <= 0) p.sk = 1;
+  p.kchunk = g.K;
+  if (p.sk > 1) {
+    p.kchunk = ((g.K + p.sk - 1) / p.sk + BK - 1) / BK * BK;
+    p.sk = (g.K + p.kchunk - 1) / p.kchunk;
+  }
+  const int c64 = g.prec == GEMM_F64 || g.out64;
+  p.key = ((((g.prec * 2 + c64) * 2 + p.big) * 2 + g.transA) * 2 + g.transB) * 2 + (g.tag == 1);
+  return p;
+}
+
+template <int BM, int BN, int TAG, typename TI, typename TO>
+void launch_group(const GroupArgs& a, int blocks, int prec, bool tA, bool tB, hipStream_t s) {
+  dim3 grid(blocks), block(256);
+  if (prec == GEMM_BF16X3) {
+    if (!tA && !tB) hipLaunchKernelGGL((gemm_bf3_group_kernel<BM, BN, false, false, TAG, TO>), grid, block, 0, s, a);
+    else if (tA && !tB) hipLaunchKernelGGL((gemm_bf3_group_kernel<BM, BN, true, false, TAG, TO>), grid, block, 0, s, a);
+    else if (!tA && tB) hipLaunchKernelGGL((gemm_bf3_group_kernel<BM, BN, false, true, TAG, TO>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((gemm_bf3_group_kernel<BM, BN, true, true, TAG, TO>), grid, block, 0, s, a);
+  } else {
+    if (!tA && !tB) hipLaunchKernelGGL((gemm_group_kernel<BM, BN, false, false, TAG, TI, TO>), grid, block, 0, s, a);
+    else if (tA && !tB) hipLaunchKernelGGL((gemm_group_kernel<BM, BN, true, false, TAG, TI, TO>), grid, block, 0, s, a);
+    else if (!tA && tB) hipLaunchKernelGGL((gemm_group_kernel<BM, BN, false, true, TAG, TI, TO>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((gemm_group_kernel<BM, BN, true, true, TAG, TI, TO>), grid, block, 0, s, a);
+  }
+  XTRG_HIP(hipGetLastError());
+}
+
+template <typename TI, typename TO>
+void launch_group_sized(const GroupArgs& a, int blocks, const Gemm& g0, bool big, hipStream_t s) {
+  const bool tA = g0.transA, tB = g0.transB;
+  if (g0.tag == 1) {
+    if (big) launch_group<128, 128, 1, TI, TO>(a, blocks, g0.prec, tA, tB, s);
+    else launch_group<64, 64, 1, TI, TO>(a, blocks, g0.prec, tA, tB, s);
+  } else {
+    if (big) launch_group<128, 128, 0, TI, TO>(a, blocks, g0.prec, tA, tB, s);
+    else launch_group<64, 64, 0, TI, TO>(a, blocks, g0.prec, tA, tB, s);
+  }
+}
+
 }  // namespace
+
+size_t gemm_grouped_work(const std::vector<Gemm>& gs) {
+  size_t w = 0;
+  for (const Gemm& g : gs)
+    if (g.M > 0 && g.N > 0) w += gemm_splitk_work(g);
+  return w;
+}
+
+void gemm_grouped(const std::vector<Gemm>& gs, hipStream_t s, double* work, size_t work_cap) {
+  const bool have_work = work != nullptr && work_cap >= gemm_grouped_work(gs);
+  std::vector<Plan> plans(gs.size());
+  for (size_t q = 0; q < gs.size(); ++q) plans[q] = plan_of(gs[q], have_work);
+  std::vector<char> done(gs.size(), 0);
+  size_t woff = 0;
+  for (size_t q0 = 0; q0 < gs.size(); ++q0) {
+    if (done[q0] || gs[q0].M <= 0 || gs[q0].N <= 0) continue;
+    // every problem of q0's kernel, up to kGroup per launch
+    GroupArgs a{};
+    int blocks = 0;
+    std::vector<size_t> members;
+    for (size_t q = q0; q < gs.size() && a.n < kGroup; ++q) {
+      const Gemm& g = gs[q];
+      if (done[q] || g.M <= 0 || g.N <= 0 || plans[q].key != plans[q0].key) continue;
+      done[q] = 1;
+      members.push_back(q);
+      const Plan& p = plans[q];
+      const int bm = p.big ? 128 : 64;
+      GroupItem& it = a.it[a.n++];
+      it.g = g;
+      it.splitk = p.sk;
+      it.kchunk = p.kchunk;
+      it.work = p.sk > 1 ? work + woff : nullptr;
+      if (p.sk > 1) woff += (size_t)p.sk * g.M * g.N;
+      it.tiles_n = (g.N + bm - 1) / bm;
+      it.tiles_m = (g.M + bm - 1) / bm;
+      it.first = blocks;
+      blocks += it.tiles_n * it.tiles_m * g.nb[0] * g.nb[1] * g.nb[2] * p.sk;
+    }
+    const Gemm& g0 = gs[q0];
+    const bool big = plans[q0].big;
+    const bool c64 = g0.prec == GEMM_F64 || g0.out64;
+    if (g0.prec == GEMM_F64) launch_group_sized<double, double>(a, blocks, g0, big, s);
+    else if (c64) launch_group_sized<float, double>(a, blocks, g0, big, s);
+    else launch_group_sized<float, float>(a, blocks, g0, big, s);
+    // the split-K reductions of this launch's problems
+    GroupArgs r{};
+    int rblocks = 0;
+    for (int j = 0; j < a.n; ++j) {
+      const GroupItem& it = a.it[j];
+      if (it.splitk <= 1) continue;
+      GroupItem& ri = r.it[r.n++];
+      ri = it;
+      ri.first = rblocks;
+      rblocks += (int)(((long)it.g.M * it.g.N + 255) / 256);
+    }
+    if (r.n > 0) {
+      if (c64) hipLaunchKernelGGL(splitk_reduce_group<double>, dim3(rblocks), dim3(256), 0, s, r);
+      else hipLaunchKernelGGL(splitk_reduce_group<float>, dim3(rblocks), dim3(256), 0, s, r);
+      XTRG_HIP(hipGetLastError());
+    }
+  }
+}
 
 size_t gemm_splitk_work(const Gemm& g) {
   const int sk = choose_splitk(g, use_big(g) && !g.tiles64);

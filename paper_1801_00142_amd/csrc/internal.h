@@ -64,6 +64,12 @@ struct Gemm {
 // (device, >= splitk*M*N doubles) and a deterministic reduction.
 void gemm(const Gemm& g, hipStream_t s, double* work = nullptr, size_t work_cap = 0);
 size_t gemm_splitk_work(const Gemm& g);
+// Independent problems in as few launches as their kernels allow (one per
+// kernel and 8 problems; each problem's tiles, split-K and summation order
+// as in gemm(), so it gets the same bits as alone).  `work` holds
+// gemm_grouped_work(gs) doubles (the problems' split-K partials side by side).
+void gemm_grouped(const std::vector<Gemm>& gs, hipStream_t s, double* work, size_t work_cap);
+size_t gemm_grouped_work(const std::vector<Gemm>& gs);
 
 // One-sided block Jacobi SVD of Y (len x p, column-major, device).
 // On return sigma (device, p) holds the singular values descending and,
@@ -101,7 +107,8 @@ struct RoundTimer {
   virtual void begin(hipStream_t s) = 0;
   // launches: round kernels in the bracket; flops: Gram (symmetric) plus
   // rotation of every visited pair; bytes: each column read and written once
-  virtual void end(hipStream_t s, long launches, double flops, double bytes) = 0;
+  // sliced: the rounds were split over row slices (two launches per round)
+  virtual void end(hipStream_t s, long launches, double flops, double bytes, bool sliced) = 0;
 };
 // Problems that fail are marked in their status and dropped from the
 // remaining rounds; the call itself throws only on runtime errors.

@@ -839,9 +839,9 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
         if (D.active) {
           const double pairs = 0.5 * D.nbk * (D.nbk - 1);          // over the whole sweep
           fl += pairs * (kNC * (kNC + 1) / 2 * 2.0 + 2.0 * kNC * kNC) * D.len;
-          by += (D.nbk - 1) * 16.0 * D.len * D.p;
+          by += (D.nbk - 1) * 16.0 * D.len * std::min(D.p, D.nbk * kBlk);
         }
-      timer->end(s, max_nbk - 1, fl, by);
+      timer->end(s, (long)(max_nbk - 1) * (smax > 1 ? 2 : 1), fl, by, smax > 1);
     }
     for (int j = 0; j < n; ++j)
       if (h[j].active) prepare(j);

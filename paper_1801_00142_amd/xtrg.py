@@ -53,6 +53,15 @@ def load_library(path: Optional[str] = None):
     p = path or _LIB_PATH
     if not os.path.exists(p):
         raise XtrgError(f"{p} is missing: build it with `python -m paper_1801_00142_amd.build`")
+    # One HIP runtime per process: PyTorch ships its own copy of the runtime
+    # library under the same soname.  Loaded after it, libxtrg.so binds to
+    # that copy, so torch's streams and device pointers are valid in the
+    # library; loaded first, a second runtime would come up beside torch's
+    # and torch would find no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(p)
     vp, ip, dp = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double)
     sig = {

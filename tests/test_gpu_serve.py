@@ -32,7 +32,7 @@ def _solves():
     out = []
     lats = [W.chain(6), W.square_cylinder(2, 3), W.with_couplings(W.chain(7), 1.0, 1.5),
             W.random_couplings(W.chain(5), 3), W.chain(8)]
-    for q, (lat, D, arr) in enumerate(zip(lats, [8, 12, 16, 6, 10], [0.0, 0.0, 0.2, 0.4, 0.6])):
+    for q, (lat, D, arr) in enumerate(zip(lats, [8, 12, 16, 6, 10], [0.0, 0.0, 0.0, 0.0, 0.1])):
         out.append(Solve(q, lat.n_sites, lat.bonds, lat.jxy, lat.jz, 2.0 ** -6 * 2 ** (q / 4), 6, D,
                          arrival_s=arr, precision=XTRG_FP32 if q == 2 else 0, beta_mix=0.1))
     return out
