@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--serve", type=int, default=0,
                     help="serve N requests of the scaled-down mixed workload instead (p50/p99 latency)")
     ap.add_argument("--serve-rate", type=float, default=2.0)
+    ap.add_argument("--serve-full", action="store_true",
+                    help="the serving workload at its stated size: W in {4,6}, L in [8,16], D in {64,128,256}, "
+                         "15 doublings (default: a scaled-down mix that finishes in about a minute)")
     return ap.parse_args()
 
 
@@ -161,8 +164,13 @@ def serve_main(args):
     import workloads as W
     from paper_1801_00142_amd import Context
     from paper_1801_00142_amd.serve import Server, Solve, percentile
-    reqs = W.serve_requests(args.serve, seed=0, rate_hz=args.serve_rate, widths=(2, 3), lengths=(4, 8),
-                            Ds=(16, 32, 64), n_doublings=10)
+    if args.serve_full:
+        reqs = W.serve_requests(args.serve, seed=0, rate_hz=args.serve_rate)
+        mix = "square XXZ cylinders W 4/6, L 8-16, D 64/128/256, 15 doublings"
+    else:
+        reqs = W.serve_requests(args.serve, seed=0, rate_hz=args.serve_rate, widths=(2, 3), lengths=(4, 8),
+                                Ds=(16, 32, 64), n_doublings=10)
+        mix = "square XXZ cylinders W 2-3, L 4-8, D 16/32/64, 10 doublings"
     solves = [Solve(r.rid, r.lattice.n_sites, r.lattice.bonds, r.lattice.jxy, r.lattice.jz, r.tau0,
                     r.n_doublings, r.D, arrival_s=r.arrival_s) for r in reqs]
     ctx = Context(0)
@@ -184,10 +192,9 @@ def serve_main(args):
         "value": round(flops / dt / 1e12, 4), "unit": "TFLOP/s", "n_gpus": 1, "steps": len(solves),
         "warmup": 0, "ms_per_step": round(dt / len(solves) * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{len(solves)} mixed requests: square XXZ cylinders W 2-3, L 4-8, "
-                               f"D 16/32/64, 10 doublings, Poisson arrivals {args.serve_rate}/s"},
+        "config": {"workload": f"{len(solves)} mixed requests: {mix}, Poisson arrivals {args.serve_rate}/s"},
         "serve": {"p50_latency_s": round(percentile(lat, 50), 3), "p99_latency_s": round(percentile(lat, 99), 3),
-                  "solves_per_s": round(len(solves) / dt, 4), "wall_s": round(dt, 2)},
+                  "solves_per_s": round(len(solves) / dt, 4), "wall_s": round(dt, 2), "failed": len(failed)},
     }
     ctx.close()
     print(json.dumps(out), flush=True)
@@ -217,10 +224,15 @@ def main():
     mixed = {"fp64": XTRG_FP64, "fp32": XTRG_FP32, "bf16x3": XTRG_BF16X3}[args.precision]
     tau = [wl.tau0]
 
+    last_prec = [XTRG_FP64]
+
     def doubling(n_sweeps):
         nonlocal rhos
         # the result reaches beta = 2 tau_{n+1} = 4 tau_n (the schedule of run())
         prec = mixed if 4 * tau[0] >= args.beta_mix else XTRG_FP64
+        if prec != last_prec[0]:
+            ctx.trim()              # the FP64 workspaces of the early doublings are not reused
+            last_prec[0] = prec
         tau[0] *= 2
         if nb == 1:
             new, info = ctx.square_compress(rhos[0], args.D, n_sweeps, precision=prec)
