@@ -112,6 +112,62 @@ def local_sum(op: np.ndarray, n: int) -> List[np.ndarray]:
     return cap(W, np.array([1.0, 0.0]), np.array([0.0, 1.0]))
 
 
+def spin_sum_squared(n: int) -> List[np.ndarray]:
+    """MPO of (sum_i S^z_i)^2 (Sec. IV.D: the D = 3 MPO of the Binder
+    ratio) as the automaton start -> (one S^z placed) -> done: sum over
+    ordered pairs i < j twice, plus the diagonal (S^z_i)^2 = I/4."""
+    W = []
+    for _ in range(n):
+        T = np.zeros((3, 2, 2, 3))
+        for a in range(3):
+            T[a, :, :, a] = I2
+        T[0, :, :, 1] = 2.0 * SZ
+        T[1, :, :, 2] = SZ
+        T[0, :, :, 2] = SZ @ SZ
+        W.append(T)
+    return cap(W, np.array([1.0, 0.0, 0.0]), np.array([0.0, 0.0, 1.0]))
+
+
+def correlation(n: int, center: int, w) -> List[np.ndarray]:
+    """MPO of sum_j w_j S_center . S_j (Sec. III.D, the structure factor's
+    sum) as the sum of the automaton Hamiltonians of the bonds (center, j),
+    j != center, with couplings w_j, plus 3/4 w_center times the identity:
+    built from the Hamiltonian automaton and exact MPO sums, not compact."""
+    bonds = [(min(center, j), max(center, j)) for j in range(n) if j != center]
+    cj = [float(w[j]) for j in range(n) if j != center]
+    Hq = hamiltonian(n, bonds, cj, cj) if bonds else None
+    ident = [np.eye(2).reshape(1, 2, 2, 1).copy() for _ in range(n)]
+    ident[0] = ident[0] * (0.75 * float(w[center]))
+    return mpo_sum(Hq, ident) if Hq is not None else ident
+
+
+def mpo_sum(A: List[np.ndarray], B: List[np.ndarray]) -> List[np.ndarray]:
+    """Exact MPO of A + B (block-diagonal bonds, App. D.2 Eq. MPO:plus)."""
+    n = len(A)
+    out = []
+    for i, (a, b) in enumerate(zip(A, B)):
+        la, _, _, ra = a.shape
+        lb, _, _, rb = b.shape
+        if n == 1:
+            out.append(a + b)
+        elif i == 0:
+            T = np.zeros((1, 2, 2, ra + rb))
+            T[..., :ra] = a
+            T[..., ra:] = b
+            out.append(T)
+        elif i == n - 1:
+            T = np.zeros((la + lb, 2, 2, 1))
+            T[:la] = a
+            T[la:] = b
+            out.append(T)
+        else:
+            T = np.zeros((la + lb, 2, 2, ra + rb))
+            T[:la, :, :, :ra] = a
+            T[la:, :, :, ra:] = b
+            out.append(T)
+    return out
+
+
 def to_dense(W: List[np.ndarray]) -> np.ndarray:
     """Contract an MPO into a dense 2^n x 2^n matrix (brute force)."""
     T = W[0]                                     # (1, s, s', D)

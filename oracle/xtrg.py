@@ -201,13 +201,25 @@ def square_compress(rho: List[np.ndarray], D: int, n_sweeps: int = 4,
     ``svd`` factorises C_E (default: LAPACK gesdd through numpy); the tests
     substitute other factorisations to measure how the result depends on it.
     """
+    return product_compress(rho, rho, D, n_sweeps, deg_rtol, sv_floor, svd)
+
+
+def product_compress(A: List[np.ndarray], B: List[np.ndarray], D: int, n_sweeps: int = 4,
+                     deg_rtol: float = 1e-6, sv_floor: float = 1e-14, svd=None):
+    """C ~ A*B compressed variationally to bond <= D (App. D.1, Eq.
+    MPO:prod with two different factors): the cross products
+    rho_{n,n'} = rho_{n-1} rho_{n'-1} of the interleaved grids (Sec. II.B)
+    and the steps H (H^{k-1} rho) of the pointwise expansion (Sec. II.C,
+    Eq. Tay).  The initial guess is B, which must be right-canonical (its
+    sites 1..L-1 isometric, as every output of this function and of
+    init_rho is).  Returns the normalised right-canonical C and a
+    CompressInfo with ln c, c = ||C||_F before normalisation."""
     if svd is None:
         svd = lambda a: np.linalg.svd(a, full_matrices=False)
-    n = len(rho)
-    if n < 2:
-        raise ValueError("need at least two sites")
-    A = B = rho
-    C = [w.copy() for w in rho]                         # initial guess
+    n = len(A)
+    if n < 2 or len(B) != n:
+        raise ValueError("need two MPOs of the same length >= 2")
+    C = [w.copy() for w in B]                           # initial guess
     one = np.ones((1, 1, 1))
     L: List[np.ndarray] = [None] * (n + 1)
     R: List[np.ndarray] = [None] * (n + 2)
@@ -305,6 +317,31 @@ def observables(rho: List[np.ndarray], lam: float, tau: float, H: List[np.ndarra
                        c=b * b * (g2 - g1 * g1) / n_sites, norm2=nrm, herm_resid=herm,
                        sz_tot=M.trace_of_product(SZ, rt, rho) / nrm, su2_resid=(x2 - z2) / max(z2, 1.0))
     return out
+
+
+def expectation(rho: List[np.ndarray], ops) -> Dict[str, float]:
+    """<O_1 ... O_n> at beta = tau (Tr(O.. rho)/Tr rho) and at beta = 2 tau
+    (Tr(O.. rho^T rho)/Tr(rho^T rho), Sec. II.B) by MPO sandwiches."""
+    rt = M.transpose(rho)
+    return {"tau": M.trace_of_product(*ops, rho) / M.trace(rho),
+            "2tau": M.trace_of_product(*ops, rt, rho) / M.inner(rho, rho)}
+
+
+def binder_ratio(rho: List[np.ndarray]) -> Dict[str, float]:
+    """U_4 = <M^2>^2 / <M^4>, M = S^z_tot (Sec. IV.D, Eq. Binder), from the
+    exact MPO of M^2 (<M^4> = <M^2 M^2>)."""
+    M2 = M.spin_sum_squared(len(rho))
+    m2 = expectation(rho, [M2])
+    m4 = expectation(rho, [M2, M2])
+    return {k: m2[k] ** 2 / m4[k] for k in m2}
+
+
+def structure_factor(rho: List[np.ndarray], positions, q, center: int) -> Dict[str, float]:
+    """Re S(q) = sum_j cos(q . r_0j) <S_0 . S_j> with site 0 = `center`
+    (Sec. III.D)."""
+    r = np.asarray(positions, dtype=float)
+    w = np.cos((r - r[center]) @ np.asarray(q, dtype=float))
+    return expectation(rho, [M.correlation(len(rho), center, w)])
 
 
 def entanglement(rho: List[np.ndarray]) -> np.ndarray:
