@@ -149,6 +149,19 @@ typedef struct {
 int xtrg_square_compress(xtrg_ctx ctx, xtrg_mpo rho_in, const xtrg_compress_opts* opts,
                          xtrg_mpo* rho_out, xtrg_compress_info* info);
 
+/* Product of two different MPOs, out ~ A B / c compressed to bond <= D_max by
+ * the same variational sweeps (App. D.1, Eq. MPO:prod): the cross products
+ * rho_{n,n'} = rho_{n-1} rho_{n'-1} of the interleaved temperature grids
+ * (Sec. II.B) and the steps H (H^{k-1} rho) of the pointwise expansion
+ * (Sec. II.C, Eq. Tay).  B is the initial guess and must be right-canonical
+ * (sites 1..L-1 isometric, as every output of xtrg_init_rho and of the
+ * compressions is); A is any MPO of the same length (an H from
+ * xtrg_hamiltonian_xxz included).  The result is normalised and
+ * right-canonical, info->dlog_norm = ln c with c = ||C||_F before
+ * normalisation.  With A == B it is xtrg_square_compress. */
+int xtrg_product_compress(xtrg_ctx ctx, xtrg_mpo A, xtrg_mpo B, const xtrg_compress_opts* opts,
+                          xtrg_mpo* out, xtrg_compress_info* info);
+
 /* The same doubling for n independent chains at once, e.g. the interleaved
  * temperature grids tau0 = 2^(z-1) tau0' of the z-shift average (Sec. II.B, Eq. zshift),
  * other couplings, lengths or bond budgets.  Chain q runs with opts[q]; the
@@ -199,6 +212,23 @@ typedef struct {
 int xtrg_observables(xtrg_ctx ctx, xtrg_mpo rho, double log_norm, double tau_n, xtrg_mpo H,
                      int n_sites, xtrg_obs* at_tau, xtrg_obs* at_2tau, double* S_E_per_bond);
 
+/* Small operator MPOs and their thermal expectation values, for the
+ * observables the paper evaluates by MPO sandwiches (Sec. IV.D, Eq. Binder:
+ * the Binder ratio U_4 = <M^2>^2 / <M^4> of M = S^z_tot from the exact MPOs
+ * of M and M^2; Sec. III.D: the static structure factor
+ * S(q) = sum_j e^{-i q r_0j} <S_0 . S_j> from one MPO).
+ * xtrg_spin_sum_mpo: (sum_i S^z_i)^power, power 1 (bond 2) or 2 (bond 3).
+ * xtrg_correlation_mpo: sum_j weights[j] S_center . S_j (L weights, the
+ *   j = center term 3/4 weights[center]; bond 5).  With weights
+ *   cos(q r_0j) its expectation value is the real part of S(q).
+ * xtrg_expectation: <O_1 ... O_n> for n = 1 or 2 operators of rho's length:
+ *   at_tau = Tr(O_1..O_n rho)/Tr rho (beta = tau_n), at_2tau =
+ *   Tr(O_1..O_n rho^T rho)/Tr(rho^T rho) (beta = 2 tau_n); either may be NULL.
+ *   <M^4> = <M^2 M^2> takes the M^2 MPO twice. */
+int xtrg_spin_sum_mpo(xtrg_ctx ctx, int L, int power, xtrg_mpo* out);
+int xtrg_correlation_mpo(xtrg_ctx ctx, int L, int center, const double* weights, xtrg_mpo* out);
+int xtrg_expectation(xtrg_ctx ctx, xtrg_mpo rho, int n_ops, const xtrg_mpo* ops, double* at_tau, double* at_2tau);
+
 /* Serving (continuous batching of thermal solves, Sec. II.B: independent
  * runs such as the z-shifted grids of Eq. (zshift) advance together).
  *
@@ -227,7 +257,9 @@ int xtrg_observables(xtrg_ctx ctx, xtrg_mpo rho, double log_norm, double tau_n, 
  * XTRG_EBUSY; submit and poll may be called from any thread.
  * Errors: XTRG_EINVAL for malformed requests (nothing queued).
  *
- * xtrg_serve_poll: XTRG_EBUSY while the run is queued or running, XTRG_EINVAL
+ * xtrg_serve_poll: XTRG_EBUSY while the run is queued or running (result_json
+ * then holds {"id", "state": "queued"|"running", "doublings"}: its progress
+ * at the last batch step), XTRG_EINVAL
  * for an unknown id or a buffer (cap bytes) too small; otherwise XTRG_OK
  * and the result JSON:
  *   {"id", "status" (XTRG_OK or the code that stopped the run), "error",

@@ -472,15 +472,17 @@ std::vector<Step> schedule(int n, int n_sweeps) {
 struct Doubler {
   xtrg_ctx c;
   int L;
-  std::vector<int> Da;                  // bonds of A = B = rho
+  std::vector<int> Da;                  // bonds of A (the left factor; rho in a doubling)
+  std::vector<int> Db;                  // bonds of B (the right factor; rho in a doubling)
   std::vector<int> Dc;                  // bonds of C
   std::vector<int> cap;                 // largest possible bond of C
   // Working precision of the contractions: GEMM_F64, or GEMM_F32 with FP32
   // copies of rho, the environments, the blocks and C (the SVD, the split
   // and the output sites stay FP64).
   int prec = xtrg::GEMM_F64;
-  std::vector<const void*> A;           // rho sites (working precision)
-  std::vector<void*> Bp;                // rho sites with the physical indices swapped
+  std::vector<const void*> A;           // sites of A (working precision)
+  std::vector<const void*> B;           // sites of B (working precision)
+  std::vector<void*> Bp;                // sites of B with the physical indices swapped
   std::string tag;                      // suffix of the chain's workspace names
   std::vector<Site> C;                  // output sites, FP64 (capacity at cap)
   std::vector<void*> Cw;                // working-precision copies of C (C itself in FP64)
@@ -500,16 +502,16 @@ struct Doubler {
     return plain(M, N, K, A_, lda, tA, B_, ldb, tB, C_, ldc, prec, 0);
   }
 
-  // Slot i holds Lb_i (4 cap_i Da_{i+1}^2) or Rb_i (Da_i^2 4 cap_{i+1}).
+  // Slot i holds Lb_i (4 cap_i Da_{i+1} Db_{i+1}) or Rb_i (Da_i Db_i 4 cap_{i+1}).
   void* slot_need(int i) {
-    const size_t n = std::max((size_t)4 * cap[i] * Da[i + 1] * Da[i + 1], (size_t)Da[i] * Da[i] * 4 * cap[i + 1]);
+    const size_t n = std::max((size_t)4 * cap[i] * Da[i + 1] * Db[i + 1], (size_t)Da[i] * Db[i] * 4 * cap[i + 1]);
     return slot[i] = needw("slot" + std::to_string(i) + tag, n);
   }
 
-  // Lb[(c,s,s'')][(a',b')] = sum_{a,b,s'} E[c][a][b] A_i[a][s][s'][a'] A_i[b][s'][s''][b']:
+  // Lb[(c,s,s'')][(a',b')] = sum_{a,b,s'} E[c][a][b] A_i[a][s][s'][a'] B_i[b][s'][s''][b']:
   // two batched GEMMs, the second reading the first's output X (the chain's own)
   std::pair<Gemm, Gemm> left_block_gemms(int i, const void* E, void* out) {
-    const int dc = Dc[i], da = Da[i], db = Da[i], da2 = Da[i + 1], db2 = Da[i + 1];
+    const int dc = Dc[i], da = Da[i], db = Db[i], da2 = Da[i + 1], db2 = Db[i + 1];
     void* X = needw("X" + tag, (size_t)dc * 4 * db * da2);
     Gemm g1;
     g1.prec = prec; g1.out64 = 0;   // X[c][s][b][(s',a')] = sum_a E[c][a][b] A[a][s][(s',a')]   batch (c, s)
@@ -526,7 +528,7 @@ struct Doubler {
     //         Lb[c][s][s''][a'][b'] = sum_{(b,s')} X[c][s][(b,s')][a'] B[(b,s')][s''][b']  batch (c,s,s'')
     g2.M = da2; g2.N = db2; g2.K = 2 * db;
     g2.transA = 1; g2.A = X; g2.lda = da2;
-    g2.B = A[i]; g2.ldb = 2 * db2;
+    g2.B = B[i]; g2.ldb = 2 * db2;
     g2.C = out; g2.ldc = db2;
     g2.nb[0] = dc; g2.nb[1] = 2; g2.nb[2] = 2;
     g2.sA[0] = 4L * db * da2; g2.sA[1] = 2L * db * da2;
@@ -535,9 +537,9 @@ struct Doubler {
     return {g1, g2};
   }
 
-  // Rb[(a,b)][(t,t'',c'')] = sum_{a'',b'',t'} A_j[a][t][t'][a''] A_j[b][t'][t''][b''] F[a''][b''][c'']
+  // Rb[(a,b)][(t,t'',c'')] = sum_{a'',b'',t'} A_j[a][t][t'][a''] B_j[b][t'][t''][b''] F[a''][b''][c'']
   std::pair<Gemm, Gemm> right_block_gemms(int j, const void* F, void* out) {
-    const int da = Da[j], db = Da[j], da2 = Da[j + 1], db2 = Da[j + 1], dc2 = Dc[j + 1];
+    const int da = Da[j], db = Db[j], da2 = Da[j + 1], db2 = Db[j + 1], dc2 = Dc[j + 1];
     void* Z = needw("X" + tag, (size_t)4 * da * db2 * dc2);
     const Gemm g1 = wplain(4 * da, db2 * dc2, da2, A[j], da2, false, F, (long)db2 * dc2, false, Z, (long)db2 * dc2);
     Gemm g;
@@ -619,12 +621,13 @@ void check_opts(const xtrg_compress_opts& o) {
     throw Error(XTRG_EINVAL, "precision must be XTRG_FP64, XTRG_FP32 or XTRG_BF16X3");
 }
 
-// Set up chain q: initial guess C = rho, swapped copies of rho's sites, and
-// the static right blocks Rb_j, j = L-1 .. 1 (the first left-to-right
-// half-sweep reads Rb_{i+1} for every bond i).
-void chain_setup(xtrg_ctx c, Chain& C, xtrg_mpo in, int q) {
+// Set up chain q of C ~ A B: initial guess C = B (right-canonical), working
+// copies of A's and B's sites (B also with its physical indices swapped),
+// and the static right blocks Rb_j, j = L-1 .. 1 (the first left-to-right
+// half-sweep reads Rb_{i+1} for every bond i).  A doubling is A = B = rho.
+void chain_setup(xtrg_ctx c, Chain& C, xtrg_mpo ina, xtrg_mpo inb, int q) {
   hipStream_t s = c->stream;
-  const int L = in->L;
+  const int L = inb->L;
   Doubler& d = C.d;
   C.tag = q == 0 ? "" : "#" + std::to_string(q);
   C.sched = schedule(L, C.o.n_sweeps);
@@ -642,46 +645,57 @@ void chain_setup(xtrg_ctx c, Chain& C, xtrg_mpo in, int q) {
   d.prec = C.o.precision == XTRG_FP32     ? xtrg::GEMM_F32
            : C.o.precision == XTRG_BF16X3 ? xtrg::GEMM_BF16X3
                                           : xtrg::GEMM_F64;
-  d.Da = in->dims;
-  d.Dc = in->dims;                         // initial guess C = rho (right-canonical)
+  const bool same = ina == inb;
+  d.Da = ina->dims;
+  d.Db = inb->dims;
+  d.Dc = inb->dims;                        // initial guess C = B (right-canonical)
   d.cap.resize(L + 1);
   for (int i = 0; i <= L; ++i) {
     double cp = 1.0;
     for (int k = 0; k < std::min(i, L - i) && cp < 1e9; ++k) cp *= 4.0;
-    d.cap[i] = (int)std::min<double>(cp, (double)std::max(C.o.D_max, in->dims[i]));
+    d.cap[i] = (int)std::min<double>(cp, (double)std::max(C.o.D_max, inb->dims[i]));
   }
   d.A.resize(L);
+  d.B.resize(L);
   d.Bp.resize(L);
   d.C.resize(L);
   d.Cw.resize(L);
   const bool f32 = d.prec != xtrg::GEMM_F64;
   for (int i = 0; i < L; ++i) {
     const std::string si = std::to_string(i) + C.tag;
-    const size_t ne = in->elems(i);
+    const size_t na = ina->elems(i), nb = inb->elems(i);
     d.C[i].n = (size_t)d.cap[i] * 4 * d.cap[i + 1];
     d.C[i].p = c->need("C" + si, d.C[i].n);
-    xtrg::copy(d.C[i].p, in->site[i].p, ne, s);
+    xtrg::copy(d.C[i].p, inb->site[i].p, nb, s);
     if (!f32) {
-      d.A[i] = in->site[i].p;
-      double* bp = c->need("Bp" + si, ne);
-      xtrg::swap_phys(bp, in->site[i].p, in->dims[i], in->dims[i + 1], s);
+      d.A[i] = ina->site[i].p;
+      d.B[i] = inb->site[i].p;
+      double* bp = c->need("Bp" + si, nb);
+      xtrg::swap_phys(bp, inb->site[i].p, inb->dims[i], inb->dims[i + 1], s);
       d.Bp[i] = bp;
       d.Cw[i] = d.C[i].p;
     } else {
-      float* a32 = static_cast<float*>(d.needw("A" + si, ne));
-      xtrg::to_f32(a32, in->site[i].p, ne, s);
+      float* a32 = static_cast<float*>(d.needw("A" + si, na));
+      xtrg::to_f32(a32, ina->site[i].p, na, s);
       d.A[i] = a32;
-      double* tmp = c->need("Bp_swap", ne);
-      xtrg::swap_phys(tmp, in->site[i].p, in->dims[i], in->dims[i + 1], s);
-      float* b32 = static_cast<float*>(d.needw("Bp" + si, ne));
-      xtrg::to_f32(b32, tmp, ne, s);
-      d.Bp[i] = b32;
+      if (same) {
+        d.B[i] = a32;
+      } else {
+        float* b32 = static_cast<float*>(d.needw("B" + si, nb));
+        xtrg::to_f32(b32, inb->site[i].p, nb, s);
+        d.B[i] = b32;
+      }
+      double* tmp = c->need("Bp_swap", nb);
+      xtrg::swap_phys(tmp, inb->site[i].p, inb->dims[i], inb->dims[i + 1], s);
+      float* bp32 = static_cast<float*>(d.needw("Bp" + si, nb));
+      xtrg::to_f32(bp32, tmp, nb, s);
+      d.Bp[i] = bp32;
       d.Cw[i] = d.needw("Cw" + si, d.C[i].n);
-      d.sync_cw(i, ne);
+      d.sync_cw(i, nb);
     }
   }
   size_t env_max = 1;
-  for (int i = 0; i <= L; ++i) env_max = std::max(env_max, (size_t)d.cap[i] * d.Da[i] * d.Da[i]);
+  for (int i = 0; i <= L; ++i) env_max = std::max(env_max, (size_t)d.cap[i] * d.Da[i] * d.Db[i]);
   C.E = d.needw("E" + C.tag, env_max);
   C.F = d.needw("F" + C.tag, env_max);
   if (!f32) {
@@ -701,7 +715,7 @@ void chain_setup(xtrg_ctx c, Chain& C, xtrg_mpo in, int q) {
     if (j == 1) break;
     const int mR = 4 * d.Dc[j + 1];
     const int k = d.Dc[j];
-    gemm(c, d.wplain(d.Da[j] * d.Da[j], k, mR, Rb, mR, false, d.Cw[j], mR, true, C.F, k));
+    gemm(c, d.wplain(d.Da[j] * d.Db[j], k, mR, Rb, mR, false, d.Cw[j], mR, true, C.F, k));
   }
 }
 
@@ -1006,7 +1020,7 @@ void chain_truncate_split(xtrg_ctx c, Chain& C) {
     }
     Timed tm(c, P_ENV, 2.0 * k * (double)Kt * mR, 8.0 * ((double)mR * Kt + (double)k * Kt));
     d.sync_cw(i + 1, (size_t)k * mR);
-    gemm(c, d.wplain(d.Da[i + 1] * d.Da[i + 1], k, mR, C.Rb, mR, false, d.Cw[i + 1], mR, true, C.F, k));  // F_{i+1}
+    gemm(c, d.wplain(d.Da[i + 1] * d.Db[i + 1], k, mR, C.Rb, mR, false, d.Cw[i + 1], mR, true, C.F, k));  // F_{i+1}
   }
   d.Dc[i + 1] = k;
   if (!C.o.no_warm_start && C.revisit[C.st]) {
@@ -1038,13 +1052,17 @@ void per_chain(Chain& C, F&& f) {
 // whose numbers turn non-finite or whose memory the budget refuses stops
 // with its own status (outs[q] = NULL, infos[q].status); the others finish.
 // Returns the number of chains that failed.
+// insb: the right factors and initial guesses (NULL: insb = ins, a doubling).
 int square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_compress_opts* opts,
-                         xtrg_mpo* outs, xtrg_compress_info* infos, std::string* first_err) {
+                         xtrg_mpo* outs, xtrg_compress_info* infos, std::string* first_err,
+                         const xtrg_mpo* insb = nullptr) {
   if (n < 1) throw Error(XTRG_EINVAL, "need at least one chain");
+  if (!insb) insb = ins;
   for (int q = 0; q < n; ++q) {
-    if (!ins[q]) throw Error(XTRG_EINVAL, "null input MPO");
-    if (ins[q]->ctx != c) throw Error(XTRG_EINVAL, "input MPO belongs to another context");
-    if (ins[q]->L < 2) throw Error(XTRG_EINVAL, "square_compress needs at least two sites");
+    if (!ins[q] || !insb[q]) throw Error(XTRG_EINVAL, "null input MPO");
+    if (ins[q]->ctx != c || insb[q]->ctx != c) throw Error(XTRG_EINVAL, "input MPO belongs to another context");
+    if (ins[q]->L < 2) throw Error(XTRG_EINVAL, "the compression needs at least two sites");
+    if (insb[q]->L != ins[q]->L) throw Error(XTRG_EINVAL, "the two factors differ in length");
     check_opts(opts[q]);
   }
   hipStream_t s = c->stream;
@@ -1052,7 +1070,7 @@ int square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_comp
   size_t n_steps = 0;
   for (int q = 0; q < n; ++q) {
     ch[q].o = opts[q];
-    per_chain(ch[q], [&] { chain_setup(c, ch[q], ins[q], q); });
+    per_chain(ch[q], [&] { chain_setup(c, ch[q], ins[q], insb[q], q); });
     n_steps = std::max(n_steps, ch[q].sched.size());
   }
 
@@ -1079,11 +1097,11 @@ int square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_comp
         const auto& d = C->d;
         const int i = C->i;
         if (C->sched[st].dir > 0)
-          fb += 8.0 * d.Dc[i] * d.Da[i] * (double)d.Da[i] * d.Da[i + 1] +
-                16.0 * d.Dc[i] * d.Da[i + 1] * (double)d.Da[i] * d.Da[i + 1];
+          fb += 8.0 * d.Dc[i] * d.Da[i] * (double)d.Db[i] * d.Da[i + 1] +
+                16.0 * d.Dc[i] * d.Da[i + 1] * (double)d.Db[i] * d.Db[i + 1];
         else
-          fb += 8.0 * d.Dc[i + 2] * d.Da[i + 2] * (double)d.Da[i + 2] * d.Da[i + 1] +
-                16.0 * d.Dc[i + 2] * d.Da[i + 1] * (double)d.Da[i + 2] * d.Da[i + 1];
+          fb += 8.0 * d.Dc[i + 2] * d.Da[i + 2] * (double)d.Db[i + 2] * d.Da[i + 1] +
+                16.0 * d.Dc[i + 2] * d.Da[i + 1] * (double)d.Db[i + 2] * d.Db[i + 1];
       }
       Timed tm(c, P_BLOCK, fb, 0.0);
       std::vector<Gemm> g1, g2;   // the two substeps of every chain, each stage one grouped launch
@@ -1115,7 +1133,7 @@ int square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_comp
         const int i = C->i;
         C->mL = 4 * d.Dc[i];
         C->mR = 4 * d.Dc[i + 2];
-        C->Kt = d.Da[i + 1] * d.Da[i + 1];
+        C->Kt = d.Da[i + 1] * d.Db[i + 1];
         C->len = C->gauge_right ? C->mL : C->mR;
         C->p = C->gauge_right ? C->mR : C->mL;
         fth += 2.0 * C->mL * (double)C->mR * C->Kt;
@@ -1127,7 +1145,7 @@ int square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_comp
         per_chain(*C, [&] {
           const auto& d = C->d;
           const int i = C->i;
-          C->flops += Doubler::step_flops(d.Dc[i], d.Da[i], d.Da[i], d.Da[i + 1], d.Da[i + 1], d.Dc[i + 2]);
+          C->flops += Doubler::step_flops(d.Dc[i], d.Da[i], d.Db[i], d.Da[i + 1], d.Db[i + 1], d.Dc[i + 2]);
           C->th = c->need("theta" + C->tag, (size_t)C->mL * C->mR);
           const int pr = C->d.prec;   // FP64 output in every precision: the SVD is FP64
           Gemm g = C->gauge_right
@@ -1285,31 +1303,104 @@ struct Named {
   }
 };
 
-// out (row-major in `outd` order) = sum over `sum` of T * W
-void contract_named(const Named& T, const double* Tp, const Named& W, const double* Wp, const Named& outd,
-                    double* outp, const std::vector<std::string>& sum, hipStream_t s) {
-  xtrg::Contract k;
-  k.n_out = (int)outd.name.size();
-  if (k.n_out > 6 || sum.size() > 3) throw Error(XTRG_EINVAL, "internal: contraction too wide");
-  for (int d = 0; d < k.n_out; ++d) {
-    k.oe[d] = outd.ext[d];
-    k.ots[d] = T.stride(outd.name[d]);
-    k.ows[d] = W.stride(outd.name[d]);
+// out (row-major in `outd` order) = sum over `sum` of T * W, as a batched
+// GEMM on the matrix cores: T is gathered into [batch][M][K] and W into
+// [batch][K][N] (batch: output indices of both, M / N: of one only, K: the
+// summed ones; an index missing from one tensor has stride 0 there, and a
+// repeated index is a diagonal), then C[batch][M][N] = T' W', scattered
+// into the order of `outd`.
+void contract_named(xtrg_ctx c, const Named& T, const double* Tp, const Named& W, const double* Wp,
+                    const Named& outd, double* outp, const std::vector<std::string>& sum, hipStream_t s) {
+  auto has = [](const Named& X, const std::string& nm) {
+    return std::find(X.name.begin(), X.name.end(), nm) != X.name.end();
+  };
+  struct Dim {
+    long e, st_t, st_w;
+    int out_pos;
+  };
+  std::vector<Dim> bat, mm, nn, kk;
+  for (size_t d = 0; d < outd.name.size(); ++d) {
+    const std::string& nm = outd.name[d];
+    const bool it = has(T, nm), iw = has(W, nm);
+    if (!it && !iw) throw Error(XTRG_EINVAL, "internal: output index in neither factor");
+    Dim x{outd.ext[d], it ? T.stride(nm) : 0, iw ? W.stride(nm) : 0, (int)d};
+    (it && iw ? bat : it ? mm : nn).push_back(x);
   }
-  k.n_c = (int)sum.size();
-  for (size_t q = 0; q < sum.size(); ++q) {
-    int e = 0;
-    for (size_t d = 0; d < T.name.size(); ++d)
-      if (T.name[d] == sum[q]) e = T.ext[d];
-    if (!e) e = W.extent(sum[q]);
-    k.ce[q] = e;
-    k.cts[q] = T.stride(sum[q]);
-    k.cws[q] = W.stride(sum[q]);
+  for (const std::string& nm : sum) {
+    const long e = has(T, nm) ? T.extent(nm) : W.extent(nm);
+    kk.push_back(Dim{e, has(T, nm) ? T.stride(nm) : 0, has(W, nm) ? W.stride(nm) : 0, -1});
   }
-  k.T = Tp;
-  k.W = Wp;
-  k.out = outp;
-  xtrg::contract(k, s);
+  auto prod = [](const std::vector<Dim>& v) {
+    long n = 1;
+    for (const Dim& x : v) n *= x.e;
+    return n;
+  };
+  const long nb = prod(bat), nm_ = prod(mm), nn_ = prod(nn), nk = prod(kk);
+  if (bat.size() + mm.size() + kk.size() > 8 || bat.size() + kk.size() + nn.size() > 8)
+    throw Error(XTRG_EINVAL, "internal: contraction too wide");
+  auto gather = [&](const double* src, const std::vector<const std::vector<Dim>*>& groups, bool t_side,
+                    double* dst) {
+    xtrg::Permute p;
+    for (const auto* g : groups)
+      for (const Dim& x : *g) {
+        p.e[p.n] = x.e;
+        p.st[p.n] = t_side ? x.st_t : x.st_w;
+        ++p.n;
+      }
+    p.src = src;
+    p.out = dst;
+    xtrg::permute(p, s);
+  };
+  double* Tg = c->need("ct_T", (size_t)std::max(nb * nm_ * nk, 1L));
+  double* Wg = c->need("ct_W", (size_t)std::max(nb * nk * nn_, 1L));
+  gather(Tp, {&bat, &mm, &kk}, true, Tg);
+  gather(Wp, {&bat, &kk, &nn}, false, Wg);
+  // the GEMM's row-major [batch][M][N] is the requested order when the
+  // output indices come batch first, then T's, then W's
+  bool direct = true;
+  {
+    int pos = 0;
+    for (const auto* g : {&bat, &mm, &nn})
+      for (const Dim& x : *g) direct &= x.out_pos == pos++;
+  }
+  double* Cg = direct ? outp : c->need("ct_C", (size_t)std::max(nb * nm_ * nn_, 1L));
+  Gemm g;
+  g.M = (int)nm_;
+  g.N = (int)nn_;
+  g.K = (int)nk;
+  g.A = Tg;
+  g.lda = nk;
+  g.B = Wg;
+  g.ldb = nn_;
+  g.C = Cg;
+  g.ldc = nn_;
+  g.nb[0] = (int)nb;
+  g.sA[0] = nm_ * nk;
+  g.sB[0] = nk * nn_;
+  g.sC[0] = nm_ * nn_;
+  gemm(c, g);
+  if (direct) return;
+  // scatter: output position d reads C' at the row-major stride of its index there
+  xtrg::Permute p;
+  std::vector<long> cst(outd.name.size(), 0);
+  {
+    long st = 1;
+    std::vector<const Dim*> order;
+    for (const auto* grp : {&bat, &mm, &nn})
+      for (const Dim& x : *grp) order.push_back(&x);
+    for (int q = (int)order.size() - 1; q >= 0; --q) {
+      cst[order[q]->out_pos] = st;
+      st *= order[q]->e;
+    }
+  }
+  for (size_t d = 0; d < outd.name.size(); ++d) {
+    p.e[p.n] = outd.ext[d];
+    p.st[p.n] = cst[d];
+    ++p.n;
+  }
+  p.src = Cg;
+  p.out = outp;
+  xtrg::permute(p, s);
 }
 
 // Tr(M_1 M_2 ... M_k) for k <= 4; trans[j]: use M_j^T.
@@ -1368,10 +1459,7 @@ double trace_chain(xtrg_ctx c, const std::vector<xtrg_mpo>& M, const std::vector
         O.name.push_back(si);
         O.ext.push_back(2);
       }
-      if (j == 0 && k > 1) {
-        // s0 is an output index of W_0 here, not summed
-      }
-      contract_named(T, cur, W, M[j]->site[i].p, O, nxt, sum, s);
+      contract_named(c, T, cur, W, M[j]->site[i].p, O, nxt, sum, s);
       std::swap(cur, nxt);
       T = O;
     }
@@ -1404,6 +1492,84 @@ std::unique_ptr<xtrg_mpo_s> local_sum_mpo(xtrg_ctx c, int L, const double O[2][2
             T[(((size_t)a * 2 + s1) * 2 + s2) * Dr + b] = v;
           }
       }
+    upload(c, m->site[i].p, T.data(), T.size());
+  }
+  return m;
+}
+
+// MPO of (sum_i S^z_i)^power for power 1 (bond 2) or 2 (bond 3): virtual
+// states 0 (no S^z placed yet), 1 (one placed), 2 (done); for the square,
+// 0 -> 1 carries 2 S^z (each unordered pair i < j once, times 2), 1 -> 2
+// S^z, 0 -> 2 (S^z)^2 = I/4 (the diagonal terms i = j).
+std::unique_ptr<xtrg_mpo_s> spin_sum_mpo(xtrg_ctx c, int L, int power) {
+  const double Sz[2][2] = {{0.5, 0.0}, {0.0, -0.5}};
+  if (power == 1) return local_sum_mpo(c, L, Sz);
+  const int nv = 3;
+  std::vector<int> dims(L + 1, nv);
+  dims[0] = dims[L] = 1;
+  auto m = new_mpo(c, dims);
+  for (int i = 0; i < L; ++i) {
+    const int Dl = dims[i], Dr = dims[i + 1];
+    std::vector<double> T((size_t)Dl * 4 * Dr, 0.0);
+    auto put = [&](int a, int b, const double (*op)[2], double cf) {
+      for (int s1 = 0; s1 < 2; ++s1)
+        for (int s2 = 0; s2 < 2; ++s2) T[(((size_t)a * 2 + s1) * 2 + s2) * Dr + b] += cf * op[s1][s2];
+    };
+    const double Id[2][2] = {{1.0, 0.0}, {0.0, 1.0}};
+    for (int a = 0; a < Dl; ++a)
+      for (int b = 0; b < Dr; ++b) {
+        const int ga = i == 0 ? 0 : a, gb = i == L - 1 ? 2 : b;   // left edge in 0, right edge in 2
+        if (ga == gb) put(a, b, Id, 1.0);
+        else if (ga == 0 && gb == 1) put(a, b, Sz, 2.0);
+        else if (ga == 1 && gb == 2) put(a, b, Sz, 1.0);
+        else if (ga == 0 && gb == 2) put(a, b, Id, 0.25);
+      }
+    upload(c, m->site[i].p, T.data(), T.size());
+  }
+  return m;
+}
+
+// MPO of sum_j w_j S_c . S_j (real form S+S-/2 + S-S+/2 + SzSz; j = c gives
+// w_c S_c . S_c = 3/4 w_c): bond 5 with states start, done and one per
+// spin component of the one spin already placed.  A spin placed before c
+// carries its weight; at c the partner closes it, or c's own spin opens a
+// channel that a later site j closes with weight w_j.
+std::unique_ptr<xtrg_mpo_s> correlation_mpo(xtrg_ctx c, int L, int center, const double* w) {
+  const double Sp[2][2] = {{0, 1}, {0, 0}}, Sm[2][2] = {{0, 0}, {1, 0}}, Sz[2][2] = {{0.5, 0}, {0, -0.5}};
+  const double Id[2][2] = {{1, 0}, {0, 1}};
+  const double (*open_op[3])[2] = {Sp, Sm, Sz};
+  const double (*close_op[3])[2] = {Sm, Sp, Sz};
+  const double half[3] = {0.5, 0.5, 1.0};
+  std::vector<int> dims(L + 1, 5);
+  dims[0] = dims[L] = 1;
+  auto m = new_mpo(c, dims);
+  for (int i = 0; i < L; ++i) {
+    const int Dl = dims[i], Dr = dims[i + 1];
+    std::vector<double> T((size_t)Dl * 4 * Dr, 0.0);
+    // state index: 0 start, 1 done, 2 + a open channel of component a
+    auto idx_l = [&](int st) { return i == 0 ? (st == 0 ? 0 : -1) : st; };
+    auto idx_r = [&](int st) { return i == L - 1 ? (st == 1 ? 0 : -1) : st; };
+    auto put = [&](int sa, int sb, const double (*op)[2], double cf) {
+      const int a = idx_l(sa), b = idx_r(sb);
+      if (a < 0 || b < 0 || cf == 0.0) return;
+      for (int s1 = 0; s1 < 2; ++s1)
+        for (int s2 = 0; s2 < 2; ++s2) T[(((size_t)a * 2 + s1) * 2 + s2) * Dr + b] += cf * op[s1][s2];
+    };
+    put(0, 0, Id, 1.0);
+    put(1, 1, Id, 1.0);
+    // an open channel passes every site but the centre, where it must close
+    // (else a pair j < c < j' would be picked up)
+    if (i != center)
+      for (int a = 0; a < 3; ++a) put(2 + a, 2 + a, Id, 1.0);
+    if (i < center) {
+      for (int a = 0; a < 3; ++a) put(0, 2 + a, open_op[a], w[i]);           // S_i^a, weight w_i
+    } else if (i == center) {
+      for (int a = 0; a < 3; ++a) put(2 + a, 1, close_op[a], half[a]);       // closes j < c
+      for (int a = 0; a < 3; ++a) put(0, 2 + a, open_op[a], 1.0);            // opens for j > c
+      put(0, 1, Id, 0.75 * w[i]);                                            // S_c . S_c = 3/4
+    } else {
+      for (int a = 0; a < 3; ++a) put(2 + a, 1, close_op[a], half[a] * w[i]); // closes c with weight w_j
+    }
     upload(c, m->site[i].p, T.data(), T.size());
   }
   return m;
@@ -1692,6 +1858,18 @@ int xtrg_square_compress(xtrg_ctx c, xtrg_mpo rho_in, const xtrg_compress_opts* 
   });
 }
 
+int xtrg_product_compress(xtrg_ctx c, xtrg_mpo A, xtrg_mpo B, const xtrg_compress_opts* opts, xtrg_mpo* out,
+                          xtrg_compress_info* info) {
+  if (!c || !A || !B || !opts || !out) return XTRG_EINVAL;
+  return guarded(c, [&] {
+    set_device(c);
+    std::string err;
+    xtrg_compress_info tmp{};
+    xtrg_compress_info* inf = info ? info : &tmp;
+    if (square_compress_impl(c, 1, &A, opts, out, inf, &err, &B) > 0) throw Error(inf->status, err);
+  });
+}
+
 int xtrg_square_compress_batched(xtrg_ctx c, int n, const xtrg_mpo* rho_in, const xtrg_compress_opts* opts,
                                  xtrg_mpo* rho_out, xtrg_compress_info* info) {
   if (!c || n < 1 || !rho_in || !opts || !rho_out) return XTRG_EINVAL;
@@ -1728,6 +1906,57 @@ int xtrg_observables(xtrg_ctx c, xtrg_mpo rho, double log_norm, double tau_n, xt
   return guarded(c, [&] {
     set_device(c);
     observables_impl(c, rho, log_norm, tau_n, H, n_sites, at_tau, at_2tau, S_E_per_bond);
+  });
+}
+
+int xtrg_spin_sum_mpo(xtrg_ctx c, int L, int power, xtrg_mpo* out) {
+  if (!c || !out || L < 1 || (power != 1 && power != 2)) return XTRG_EINVAL;
+  return guarded(c, [&] {
+    set_device(c);
+    auto m = spin_sum_mpo(c, L, power);
+    XTRG_HIP(hipStreamSynchronize(c->stream));
+    *out = m.release();
+  });
+}
+
+int xtrg_correlation_mpo(xtrg_ctx c, int L, int center, const double* weights, xtrg_mpo* out) {
+  if (!c || !out || !weights || L < 1 || center < 0 || center >= L) return XTRG_EINVAL;
+  return guarded(c, [&] {
+    set_device(c);
+    auto m = correlation_mpo(c, L, center, weights);
+    XTRG_HIP(hipStreamSynchronize(c->stream));
+    *out = m.release();
+  });
+}
+
+int xtrg_expectation(xtrg_ctx c, xtrg_mpo rho, int n_ops, const xtrg_mpo* ops, double* at_tau, double* at_2tau) {
+  if (!c || !rho || n_ops < 1 || n_ops > 2 || !ops) return XTRG_EINVAL;
+  for (int k = 0; k < n_ops; ++k)
+    if (!ops[k] || ops[k]->L != rho->L) return XTRG_EINVAL;
+  return guarded(c, [&] {
+    set_device(c);
+    std::vector<xtrg_mpo> m(ops, ops + n_ops);
+    std::vector<bool> tr(n_ops, false);
+    if (at_tau) {
+      const double z = trace_chain(c, {rho}, {false});
+      if (!(z > 0)) throw Error(XTRG_ENUMERIC, "Tr rho <= 0");
+      auto mm = m;
+      auto tt = tr;
+      mm.push_back(rho);
+      tt.push_back(false);
+      *at_tau = trace_chain(c, mm, tt) / z;
+    }
+    if (at_2tau) {
+      const double z = trace_chain(c, {rho, rho}, {true, false});
+      if (!(z > 0)) throw Error(XTRG_ENUMERIC, "||rho|| = 0");
+      auto mm = m;
+      auto tt = tr;
+      mm.push_back(rho);
+      tt.push_back(true);
+      mm.push_back(rho);
+      tt.push_back(false);
+      *at_2tau = trace_chain(c, mm, tt) / z;
+    }
   });
 }
 

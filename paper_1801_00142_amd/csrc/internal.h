@@ -201,5 +201,15 @@ struct Contract {
   double* out = nullptr;
 };
 void contract(const Contract& c, hipStream_t s);
+// Strided gather into a row-major block: out[i_0..i_{n-1}] = src[sum_d i_d st[d]]
+// (a stride may cover a repeated index: a diagonal).
+struct Permute {
+  int n = 0;                // <= 8 dims
+  long e[8] = {1, 1, 1, 1, 1, 1, 1, 1};
+  long st[8] = {0};
+  const double* src = nullptr;
+  double* out = nullptr;
+};
+void permute(const Permute& p, hipStream_t s);
 
 }  // namespace xtrg

@@ -275,6 +275,27 @@ void phys_trace(double* out, const double* W, int Dl, int Dr, hipStream_t s) {
   XTRG_HIP(hipGetLastError());
 }
 
+// out (row-major over the n dims, extents e) = src at offset sum_d i_d st_d.
+__global__ void k_permute(Permute p, long n_total) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n_total; i += (long)gridDim.x * blockDim.x) {
+    long q = i, off = 0;
+    for (int d = p.n - 1; d >= 0; --d) {
+      const long v = q % p.e[d];
+      q /= p.e[d];
+      off += v * p.st[d];
+    }
+    p.out[i] = p.src[off];
+  }
+}
+
+void permute(const Permute& p, hipStream_t s) {
+  long n = 1;
+  for (int d = 0; d < p.n; ++d) n *= p.e[d];
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_permute, grid_for((size_t)n), dim3(kT), 0, s, p, n);
+  XTRG_HIP(hipGetLastError());
+}
+
 void contract(const Contract& c, hipStream_t s) {
   long n = 1;
   for (int d = 0; d < c.n_out; ++d) n *= c.oe[d];

@@ -209,6 +209,8 @@ struct Request {
   int n_doublings = 0, D = 0, n_sweeps = 2, order = 1, precision = XTRG_FP64;
   // state
   bool done = false;       // visible to poll (set under the server lock)
+  bool admitted = false;   // likewise: admitted to the batch
+  int progress = 0;        // likewise: doublings completed
   bool finished = false;   // set by the worker when the run ends
   int status = XTRG_OK;
   std::string err;
@@ -384,6 +386,10 @@ struct Server {
         std::unique_lock<std::mutex> lk(mu);
         for (Request* r : finished_now) r->done = true;
         finished_now.clear();
+        for (Request* r : active) {
+          r->admitted = true;
+          r->progress = r->n_done;
+        }
         if (stop || (pending.empty() && active.empty())) {
           running = false;
           c->serving.store(false);
@@ -555,7 +561,12 @@ int xtrg_serve_poll(xtrg_ctx c, unsigned long long id, char* result_json, size_t
     auto it = S->all.find(id);
     if (it == S->all.end()) return XTRG_EINVAL;
     const xtrg::Request& r = *it->second;
-    if (!r.done) return XTRG_EBUSY;
+    if (!r.done) {   // progress: the state and the doublings completed so far
+      out = xtrg::fmt("{\"id\":%llu,\"state\":\"%s\",\"doublings\":%d}", r.id,
+                      r.admitted ? "running" : "queued", r.progress);
+      if (out.size() + 1 <= cap) std::memcpy(result_json, out.c_str(), out.size() + 1);
+      return XTRG_EBUSY;
+    }
     const double sub = S->secs(r.t_submit), adm = S->secs(r.t_admit), fin = S->secs(r.t_finish);
     out = xtrg::fmt("{\"id\":%llu,\"status\":%d,\"error\":\"", r.id, r.status) + xtrg::json_escape(r.err) +
           xtrg::fmt("\",\"submitted_s\":%.9g,\"admitted_s\":%.9g,\"finished_s\":%.9g,\"latency_s\":%.9g,"

@@ -78,6 +78,7 @@ class Server:
         pending = sorted(solves, key=lambda r: r.arrival_s)
         ids: Dict[int, int] = {}
         out: Dict[int, dict] = {}
+        progress: Dict[int, int] = {}
         t0 = clock()
         while pending or len(out) < len(ids):
             now = clock() - t0
@@ -90,6 +91,11 @@ class Server:
                 if rid in out:
                     continue
                 res = self.ctx.serve_poll(lid)
+                if res is not None and res.get("busy"):
+                    if log and res["doublings"] != progress.get(rid):
+                        progress[rid] = res["doublings"]
+                        log(f"t={clock() - t0:.2f}s request {rid}: {res['state']}, {res['doublings']} doublings done")
+                    continue
                 if res is not None:
                     res["arrival_s"] = next(s.arrival_s for s in solves if s.rid == rid)
                     out[rid] = res

@@ -78,6 +78,8 @@ def load_library(path: Optional[str] = None):
         "xtrg_init_rho": (C.c_int, [vp, vp, C.c_double, C.c_int, C.c_int, C.POINTER(vp), dp]),
         "xtrg_square_compress": (C.c_int, [vp, vp, C.POINTER(CompressOpts), C.POINTER(vp),
                                            C.POINTER(CompressInfo)]),
+        "xtrg_product_compress": (C.c_int, [vp, vp, vp, C.POINTER(CompressOpts), C.POINTER(vp),
+                                            C.POINTER(CompressInfo)]),
         "xtrg_square_compress_batched": (C.c_int, [vp, C.c_int, C.POINTER(vp), C.POINTER(CompressOpts),
                                                    C.POINTER(vp), C.POINTER(CompressInfo)]),
         "xtrg_observables": (C.c_int, [vp, vp, C.c_double, C.c_double, vp, C.c_int, C.POINTER(Obs),
@@ -93,6 +95,9 @@ def load_library(path: Optional[str] = None):
         "xtrg_dsvd_left": (C.c_int, [vp, C.c_int, C.c_int, vp, vp, C.c_int, vp]),
         "xtrg_dsvd_left_qr": (C.c_int, [vp, C.c_int, C.c_int, vp, vp, C.c_int, vp, ip]),
         "xtrg_dqrcp": (C.c_int, [vp, C.c_int, C.c_int, vp, C.c_double, vp, vp, ip]),
+        "xtrg_spin_sum_mpo": (C.c_int, [vp, C.c_int, C.c_int, C.POINTER(vp)]),
+        "xtrg_correlation_mpo": (C.c_int, [vp, C.c_int, C.c_int, dp, C.POINTER(vp)]),
+        "xtrg_expectation": (C.c_int, [vp, vp, C.c_int, C.POINTER(vp), dp, dp]),
         "xtrg_serve_submit": (C.c_int, [vp, C.c_char_p, C.POINTER(C.c_ulonglong)]),
         "xtrg_serve_poll": (C.c_int, [vp, C.c_ulonglong, C.c_char_p, C.c_size_t]),
         "xtrg_profile_enable": (C.c_int, [vp, C.c_int]),
@@ -109,8 +114,8 @@ def load_library(path: Optional[str] = None):
 def exported_symbols() -> List[str]:
     return ["xtrg_ctx_create", "xtrg_ctx_destroy", "xtrg_last_error", "xtrg_ctx_bytes", "xtrg_ctx_trim",
             "xtrg_hamiltonian_xxz", "xtrg_mpo_from_host", "xtrg_mpo_shape", "xtrg_mpo_to_host",
-            "xtrg_mpo_destroy", "xtrg_init_rho", "xtrg_square_compress", "xtrg_square_compress_batched", "xtrg_observables",
-            "xtrg_dgemm", "xtrg_dgemm_noalloc", "xtrg_sgemm", "xtrg_gemm_bf16x3", "xtrg_dsvd_left", "xtrg_dsvd_left_qr", "xtrg_dqrcp", "xtrg_serve_submit", "xtrg_serve_poll", "xtrg_profile_enable",
+            "xtrg_mpo_destroy", "xtrg_init_rho", "xtrg_square_compress", "xtrg_product_compress", "xtrg_square_compress_batched", "xtrg_observables",
+            "xtrg_dgemm", "xtrg_dgemm_noalloc", "xtrg_sgemm", "xtrg_gemm_bf16x3", "xtrg_dsvd_left", "xtrg_dsvd_left_qr", "xtrg_dqrcp", "xtrg_spin_sum_mpo", "xtrg_correlation_mpo", "xtrg_expectation", "xtrg_serve_submit", "xtrg_serve_poll", "xtrg_profile_enable",
             "xtrg_profile_report"]
 
 
@@ -240,6 +245,18 @@ class Context:
             out["sv"] = buf
         return MPO(self, h), out
 
+    def product_compress(self, A: MPO, B: MPO, D_max: int, n_sweeps: int = 4, degen_rtol: float = 1e-6,
+                         sv_floor: float = 1e-14, precision: int = XTRG_FP64, warm_start: bool = True,
+                         qr_start: bool = True):
+        """out ~ A B / c (B: the right-canonical initial guess); returns (MPO, info)."""
+        o = CompressOpts(D_max, n_sweeps, precision, degen_rtol, sv_floor, int(not warm_start), int(not qr_start))
+        info = CompressInfo()
+        h = C.c_void_p()
+        _check(self, _lib.xtrg_product_compress(self.h, A.h, B.h, C.byref(o), C.byref(h), C.byref(info)))
+        return MPO(self, h), dict(dlog_norm=info.dlog_norm, trunc_err_max=info.trunc_err_max,
+                                  sweeps=info.sweeps_done, D_kept_max=info.D_kept_max, steps=info.steps,
+                                  flops=info.flops)
+
     def square_compress_batched(self, rhos: Sequence[MPO], D_max, n_sweeps=4,
                                 degen_rtol: float = 1e-6, sv_floor: float = 1e-14, sv_stride: int = 0,
                                 precision=XTRG_FP64, warm_start: bool = True, qr_start: bool = True):
@@ -306,6 +323,47 @@ class Context:
             out["S_E"] = se[: L - 1]
         return out
 
+    # small operator MPOs and expectation values (Binder ratio, structure factor)
+    def spin_sum_mpo(self, L: int, power: int = 1) -> MPO:
+        h = C.c_void_p()
+        _check(self, _lib.xtrg_spin_sum_mpo(self.h, L, power, C.byref(h)))
+        return MPO(self, h)
+
+    def correlation_mpo(self, L: int, center: int, weights: Sequence[float]) -> MPO:
+        w = np.ascontiguousarray(np.array(weights, dtype=np.float64))
+        if w.shape != (L,):
+            raise ValueError("one weight per site")
+        h = C.c_void_p()
+        _check(self, _lib.xtrg_correlation_mpo(self.h, L, center, w.ctypes.data_as(C.POINTER(C.c_double)),
+                                               C.byref(h)))
+        return MPO(self, h)
+
+    def expectation(self, rho: MPO, ops: Sequence[MPO]):
+        """(<O_1..O_n> at beta = tau_n, at beta = 2 tau_n) for n = 1 or 2 operators."""
+        arr = (C.c_void_p * len(ops))(*[o.h for o in ops])
+        a, b = C.c_double(), C.c_double()
+        _check(self, _lib.xtrg_expectation(self.h, rho.h, len(ops), arr, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def binder_ratio(self, rho: MPO):
+        """U_4 = <M^2>^2 / <M^4> of M = S^z_tot (Eq. Binder) at beta = tau_n and 2 tau_n."""
+        L = rho.shape()[0]
+        M2 = self.spin_sum_mpo(L, 2)
+        m2 = self.expectation(rho, [M2])
+        m4 = self.expectation(rho, [M2, M2])
+        M2.close()
+        return tuple(x * x / y for x, y in zip(m2, m4))
+
+    def structure_factor(self, rho: MPO, positions, q, center: int):
+        """Re S(q) = sum_j cos(q . (r_j - r_center)) <S_center . S_j> (Sec. III.D)
+        at beta = tau_n and 2 tau_n; positions: one coordinate vector per site."""
+        r = np.asarray(positions, dtype=np.float64)
+        w = np.cos((r - r[center]) @ np.asarray(q, dtype=np.float64))
+        O = self.correlation_mpo(len(r), center, w)
+        out = self.expectation(rho, [O])
+        O.close()
+        return out
+
     # serving: the library's continuous-batching loop (include/xtrg.h)
     def serve_submit(self, request: dict) -> int:
         """Queue one XTRG run (the JSON fields of xtrg_serve_submit); returns its id."""
@@ -315,12 +373,14 @@ class Context:
         return rid.value
 
     def serve_poll(self, rid: int, cap: int = 1 << 20):
-        """The run's result dict once it is finished (or failed), else None."""
+        """The run's result dict once it is finished (or failed); while it is
+        queued or running, {"busy": True, "state", "doublings"} (its progress)."""
         import json
         buf = C.create_string_buffer(cap)
         rc = _lib.xtrg_serve_poll(self.h, rid, buf, cap)
         if rc == -5:                               # XTRG_EBUSY: queued or running
-            return None
+            d = json.loads(buf.value.decode()) if buf.value else {}
+            return {"busy": True, "state": d.get("state", "queued"), "doublings": d.get("doublings", 0)}
         if rc != 0 and cap < (1 << 26):
             return self.serve_poll(rid, cap * 8)   # grow the buffer for long runs
         _check(self, rc)
