@@ -21,6 +21,7 @@ Prints one JSON line.  Only one GPU is used: --gpus above 1 exits.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import os
@@ -31,6 +32,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
+PEAK_FP32_MFMA_TFLOPS = 157.3  # dense FP32 matrix
+PEAK_BF16_MFMA_TFLOPS = 2500.0  # dense bf16 matrix
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per Jacobi round of a 1024 x 1024 SVD in the row-sliced form
 # (Gram + rotate launches, 32 block pairs x 4 slices), from rocprofv3
@@ -62,10 +65,29 @@ def parse():
     ap.add_argument("--serve", type=int, default=0,
                     help="serve N requests of the scaled-down mixed workload instead (p50/p99 latency)")
     ap.add_argument("--serve-rate", type=float, default=2.0)
+    ap.add_argument("--serve-slice", default=None,
+                    help="a:b: serve only requests a..b-1 of the seeded stream, their arrivals shifted so that "
+                         "request a arrives at 0 (a long stream in parts; per-request latencies are printed)")
     ap.add_argument("--serve-full", action="store_true",
                     help="the serving workload at its stated size: W in {4,6}, L in [8,16], D in {64,128,256}, "
                          "15 doublings (default: a scaled-down mix that finishes in about a minute)")
     return ap.parse_args()
+
+
+def theta_roofline(prec, achieved, launches, avg_s, flops):
+    """The two-site overlap C_E against the matrix-core peak of the precision
+    it ran in (the last timed doubling's): FP64, FP32, or bf16x3, whose three
+    bf16 products per multiply-add are priced against the dense bf16 peak."""
+    from paper_1801_00142_amd import XTRG_BF16X3, XTRG_FP32
+    if prec == XTRG_FP32:
+        kern, peak, work = "gemm_kernel<128,128,...,1,float,double>", PEAK_FP32_MFMA_TFLOPS, achieved
+    elif prec == XTRG_BF16X3:
+        kern, peak, work = "gemm_bf3_kernel<128,128,...,1,double>", PEAK_BF16_MFMA_TFLOPS, 3.0 * achieved
+    else:
+        kern, peak, work = "gemm_kernel<128,128,...,1,double,double>", PEAK_FP64_TFLOPS, achieved
+    return {"bound": "mfma", "kernel": f"two-site overlap C_E ({kern})", "achieved": round(achieved, 3),
+            "peak": peak, "unit": "TFLOP/s", "frac": round(work / peak, 4), "launches": launches,
+            "avg_launch_ms": round(avg_s * 1e3, 4), "flops_per_launch": flops}
 
 
 def cpu_baseline(sites, D, n_steps):
@@ -171,6 +193,11 @@ def serve_main(args):
         reqs = W.serve_requests(args.serve, seed=0, rate_hz=args.serve_rate, widths=(2, 3), lengths=(4, 8),
                                 Ds=(16, 32, 64), n_doublings=10)
         mix = "square XXZ cylinders W 2-3, L 4-8, D 16/32/64, 10 doublings"
+    n_stream = len(reqs)
+    if args.serve_slice:
+        a, b = (int(x) for x in args.serve_slice.split(":"))
+        t_a = reqs[a].arrival_s
+        reqs = [dataclasses.replace(r, arrival_s=r.arrival_s - t_a) for r in reqs[a:b]]
     solves = [Solve(r.rid, r.lattice.n_sites, r.lattice.bonds, r.lattice.jxy, r.lattice.jz, r.tau0,
                     r.n_doublings, r.D, arrival_s=r.arrival_s) for r in reqs]
     ctx = Context(0)
@@ -192,10 +219,13 @@ def serve_main(args):
         "value": round(flops / dt / 1e12, 4), "unit": "TFLOP/s", "n_gpus": 1, "steps": len(solves),
         "warmup": 0, "ms_per_step": round(dt / len(solves) * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{len(solves)} mixed requests: {mix}, Poisson arrivals {args.serve_rate}/s"},
+        "config": {"workload": f"{len(solves)} mixed requests: {mix}, Poisson arrivals {args.serve_rate}/s"
+                               + (f", requests {args.serve_slice} of a stream of {n_stream}" if args.serve_slice else "")},
         "serve": {"p50_latency_s": round(percentile(lat, 50), 3), "p99_latency_s": round(percentile(lat, 99), 3),
                   "solves_per_s": round(len(solves) / dt, 4), "wall_s": round(dt, 2), "failed": len(failed)},
     }
+    if args.serve_slice:
+        out["serve"]["latencies_s"] = {str(k): round(v["latency_s"], 3) for k, v in sorted(res.items())}
     ctx.close()
     print(json.dumps(out), flush=True)
 
@@ -320,8 +350,11 @@ def main():
                f"tau0=2^{math.log2(wl.tau0):g}, D={args.D}, {args.sweeps} sweeps/doubling")
     if nb > 1:
         wl_name += f", {nb} z-shifted chains batched"
+    # the headline metric (its serve-latency half is measured by --serve N --serve-full)
+    metric = ("TFLOP/s in MPO product-compression sweeps at D=256; p50/p99 serve latency" if args.D == 256
+              else f"TFLOP/s in MPO product-compression sweeps at D={args.D}")
     out = {
-        "metric": "TFLOP/s in MPO product-compression sweeps at D=256",
+        "metric": metric,
         "value": round(value, 4),
         "unit": "TFLOP/s",
         "n_gpus": 1,
@@ -359,11 +392,7 @@ def main():
                      "traffic_note": "rocprofv3 FETCH_SIZE + WRITE_SIZE of the 1024-column round, copy-scaled, "
                                      "scaled to this run's mean algorithmic bytes per round",
                      "rounds": n_rounds, "avg_round_us": round(round_us, 3), "bytes_per_round": round_bytes},
-        "roofline_theta": {"bound": "mfma", "kernel": "two-site overlap C_E (gemm_kernel<128,128,...,1,double,double>)",
-                           "achieved": round(th_achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                           "frac": round(th_achieved / PEAK_FP64_TFLOPS, 4),
-                           "launches": th["calls"], "avg_launch_ms": round(th_avg_s * 1e3, 4),
-                           "flops_per_launch": th_flops},
+        "roofline_theta": theta_roofline(last_prec[0], th_achieved, th["calls"], th_avg_s, th_flops),
     }
     if side:
         out["value_2_sweeps"] = side
