@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--batch", type=int, default=1)
+    ap.add_argument("--batch-leg", type=int, default=4,
+                    help="after the single-chain figures, also time one saturated doubling of this many "
+                         "z-shifted chains through the batched doubling (0: skip)")
     ap.add_argument("--precision", choices=["fp64", "fp32", "bf16x3"], default="fp64",
                     help="contraction precision of the doublings that reach beta >= --beta-mix")
     ap.add_argument("--beta-mix", type=float, default=1.0)
@@ -72,6 +75,50 @@ def parse():
                     help="the serving workload at its stated size: W in {4,6}, L in [8,16], D in {64,128,256}, "
                          "15 doublings (default: a scaled-down mix that finishes in about a minute)")
     return ap.parse_args()
+
+
+def batch_leg(ctx, H, wl, args, mixed):
+    """One saturated doubling of n z-shifted chains (tau0 2^(i/n), Sec. II.B)
+    through the batched doubling: the chains are grown to the bond budget in
+    the batched path, then one doubling is timed (whole-batch flops over its
+    wall time)."""
+    import torch
+    from paper_1801_00142_amd import XTRG_FP64
+    n = args.batch_leg
+    taus = [wl.tau0 * 2.0 ** (i / n) for i in range(n)]
+    rhos = [ctx.init_rho(H, t, wl.init_order)[0] for t in taus]
+    tau = wl.tau0
+    done = 0
+
+    def step():
+        nonlocal rhos, tau
+        prec = mixed if 4 * tau >= args.beta_mix else XTRG_FP64
+        tau *= 2
+        news, infos = ctx.square_compress_batched(rhos, args.D, args.sweeps, precision=prec)
+        for r in rhos:
+            r.close()
+        rhos = news
+        return infos
+
+    while done < wl.n_doublings:
+        infos = step()
+        done += 1
+        dmin = min(i["D_kept_max"] for i in infos)
+        print(f"batch leg warm-up doubling {done}: smallest max bond {dmin}", file=sys.stderr, flush=True)
+        if dmin >= args.D:
+            break
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    flops = sum(i["flops"] for i in infos)
+    print("batch leg timed doubling done", file=sys.stderr, flush=True)
+    for r in rhos:
+        r.close()
+    return {"chains": n, "value": round(flops / dt / 1e12, 4), "unit": "TFLOP/s", "ms_per_step": round(dt * 1e3, 3),
+            "warmup_doublings": done, "note": "one saturated doubling of the z-shifted chains through the "
+                                              "batched doubling (grouped GEMM launches, grouped Jacobi rounds)"}
 
 
 def theta_roofline(prec, achieved, launches, avg_s, flops):
@@ -415,6 +462,9 @@ def main():
             out["accuracy"]["svd_centre"] = svd_accuracy(ctx, th_c, S_c, args.D)
     for r in rhos:
         r.close()
+    if args.batch_leg > 1 and nb == 1:
+        ctx.trim()                  # the single chain's workspaces
+        out["batch_leg"] = batch_leg(ctx, H, wl, args, mixed)
     H.close()
     ctx.close()
     print(json.dumps(out), flush=True)
