@@ -239,21 +239,28 @@ int xtrg_expectation(xtrg_ctx ctx, xtrg_mpo rho, int n_ops, const xtrg_mpo* ops,
  *    "beta_mix": 1.0}
  * (the last five optional, with these defaults; precision applies to the
  * doublings that reach beta >= beta_mix, earlier ones run in FP64) and
- * returns its id.  A worker thread owned by the context admits queued runs
+ * returns its id.  The runs are served in lanes (xtrg_serve_set_lanes,
+ * default 2): a run goes to lane k if its work per doubling (sites x D^4)
+ * is 8^k times below the largest seen so far (the last lane takes the rest),
+ * so runs of very different size do not wait on each other's doublings.
+ * Each lane is a worker thread with its own stream (lane 0 on the
+ * context's, the others on contexts of their own on the same device), and
+ * the lanes run concurrently on the device.  A lane admits its queued runs
  * in arrival order whenever their device-memory estimates fit the budget
  * (the context's hbm_budget, or 85% of the free device memory when the
- * worker starts if that is 0), after the context's shared workspaces
- * (64 MiB plus 128 (4D)^2 bytes for the largest D admitted); per run
+ * first worker starts if that is 0; shared by all lanes), after the lane's
+ * shared workspaces (64 MiB plus 128 (4D)^2 bytes for the largest D it
+ * admitted) and what the other lanes hold; per run
  * 8 [4 D^3 (L-1) + (4D)(4D+32)(L+9) + 16 D^2 L + 6 D^3 + (4D+32)^2] bytes
  * plus 4 MiB.  A run that could not fit even alone fails with XTRG_ENOMEM.
  * The allocator enforces the same budget, so an estimate that falls short
- * fails that run with XTRG_ENOMEM, not the others.  It advances all admitted runs by one doubling per batch
+ * fails that run with XTRG_ENOMEM, not the others.  A lane advances all its admitted runs by one doubling per batch
  * step with xtrg_square_compress_batched, accumulates lambda and the
  * observables after every doubling, and retires finished runs at once;
  * runs submitted meanwhile join at the next step.  A run whose numbers turn
  * non-finite or whose memory the budget refuses fails alone.  Each run's
  * records equal those of the same run served alone.
- * While the worker has work, the context's other compute calls return
+ * While a lane has work, the context's other compute calls return
  * XTRG_EBUSY; submit and poll may be called from any thread.
  * Errors: XTRG_EINVAL for malformed requests (nothing queued).
  *
@@ -264,12 +271,18 @@ int xtrg_expectation(xtrg_ctx ctx, xtrg_mpo rho, int n_ops, const xtrg_mpo* ops,
  * and the result JSON:
  *   {"id", "status" (XTRG_OK or the code that stopped the run), "error",
  *    "submitted_s", "admitted_s", "finished_s", "latency_s" (seconds on the
- *    server's clock), "doublings", "records": [{"n", "tau", "lam",
- *    "bond_dims", "f_tau", "u_tau", "c_tau", "f_2tau", "u_2tau", "c_2tau",
- *    "herm_resid", "sz_tot", "su2_resid", "trunc_err"}, ...]}
- * with one record for rho(tau0) and one per completed doubling. */
+ *    server's clock), "doublings", "flops" (algorithmic flops of its
+ *    doublings), "records": [{"n", "tau", "lam", "bond_dims", "f_tau",
+ *    "u_tau", "c_tau", "f_2tau", "u_2tau", "c_2tau", "herm_resid", "sz_tot",
+ *    "su2_resid", "trunc_err", "flops"}, ...]}
+ * with one record for rho(tau0) and one per completed doubling.
+ *
+ * xtrg_serve_set_lanes: the number of lanes (1 to 4; 1 serves every run in
+ * one lockstep batch).  XTRG_EBUSY while a lane has work; the results of
+ * earlier runs stay available to xtrg_serve_poll. */
 int xtrg_serve_submit(xtrg_ctx ctx, const char* request_json, unsigned long long* id);
 int xtrg_serve_poll(xtrg_ctx ctx, unsigned long long id, char* result_json, size_t cap);
+int xtrg_serve_set_lanes(xtrg_ctx ctx, int n_lanes);
 
 /* Timing of the doubling's phases (two-site overlap GEMM, left/right block
  * GEMMs, environment GEMMs, SVD, split/projection) with HIP events on the

@@ -58,6 +58,7 @@ struct xtrg_ctx_s {
   // it runs; the compute calls of the ABI then return XTRG_EBUSY.
   xtrg::Server* server = nullptr;
   std::atomic<bool> serving{false};
+  int serve_lanes = 2;      // lanes of the serving loop (xtrg_serve_set_lanes)
 
   double* alloc(size_t n) {
     std::lock_guard<std::mutex> lk(mem_mu);

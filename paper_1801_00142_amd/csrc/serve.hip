@@ -217,6 +217,7 @@ struct Request {
   std::unique_ptr<xtrg_mpo_s> H, rho;
   double lam = 0.0, tau = 0.0;
   int n_done = 0;
+  double flops = 0.0;      // algorithmic flops of its doublings
   size_t footprint = 0;
   std::string records;    // JSON array body
   Clock::time_point t_submit, t_admit, t_finish;
@@ -270,73 +271,108 @@ std::string json_escape(const std::string& s) {
 
 }  // namespace
 
+// One lane of the server: a worker thread with its own context (and stream)
+// that advances its admitted requests in lockstep, one doubling per batch
+// step.  Lanes run concurrently on the device: the Jacobi rounds of a
+// single batch leave most compute units idle, so a second batch of
+// requests of a different size overlaps them instead of waiting behind the
+// larger requests' doublings.
+struct Lane {
+  xtrg_ctx c = nullptr;       // lane 0: the server's context; others owned by the lane
+  hipStream_t stream = nullptr;
+  bool owned = false;
+  std::thread worker;
+  bool running = false;       // the worker thread is in its loop
+  std::deque<Request*> pending;
+  std::vector<Request*> active;
+  // Requests finished since the loop last held the lock: they are marked
+  // done there, together with the decision to leave the loop, so that a
+  // client that sees its last result done also finds the lane idle.
+  std::vector<Request*> finished_now;
+  size_t used = 0, shared = 0;   // admitted footprints and the lane's shared reserve (under the server lock)
+};
+
 struct Server {
   xtrg_ctx c = nullptr;
   std::mutex mu;
-  std::thread worker;
-  bool running = false;      // the worker thread is in its loop
   bool stop = false;         // context teardown: finish the batch step, then leave
   unsigned long long next_id = 1;
-  std::deque<Request*> pending;
-  std::vector<Request*> active;
+  std::vector<std::unique_ptr<Lane>> lanes;
   std::map<unsigned long long, std::unique_ptr<Request>> all;
   size_t budget = 0;
   int max_chains = 64;
+  double max_cost = 0.0;     // largest per-doubling cost proxy seen
   Clock::time_point t0 = Clock::now();
 
   double secs(Clock::time_point t) const { return std::chrono::duration<double>(t - t0).count(); }
 
-  void record(Request& r, const xtrg_compress_info* info) {
+  // Work of one doubling at saturation, up to a constant: sites x D^4.
+  static double cost(const Request& r) { return (double)r.n_sites * std::pow((double)r.D, 4.0); }
+
+  // Lane of a new request: 0 for the largest class, k for requests
+  // 8^k times cheaper than the largest seen so far (the last lane takes the rest).
+  int route(const Request& r) {
+    const double w = cost(r);
+    max_cost = std::max(max_cost, w);
+    int k = 0;
+    while (k + 1 < (int)lanes.size() && w * std::pow(8.0, k + 1) <= max_cost) ++k;
+    return k;
+  }
+
+  bool any_running() const {
+    for (const auto& l : lanes)
+      if (l->running) return true;
+    return false;
+  }
+
+  void record(Lane& ln, Request& r, const xtrg_compress_info* info) {
     xtrg_obs a{}, b{};
-    xtrg_impl::observables(c, r.rho.get(), r.lam, r.tau, r.H.get(), r.n_sites, &a, &b, nullptr);
+    xtrg_impl::observables(ln.c, r.rho.get(), r.lam, r.tau, r.H.get(), r.n_sites, &a, &b, nullptr);
     std::string dims = "[";
     for (size_t i = 0; i < r.rho->dims.size(); ++i) dims += (i ? "," : "") + std::to_string(r.rho->dims[i]);
     dims += "]";
+    if (info) r.flops += info->flops;
     if (!r.records.empty()) r.records += ",";
     r.records += fmt("{\"n\":%d,\"tau\":%.17g,\"lam\":%.17g,", r.n_done, r.tau, r.lam) + "\"bond_dims\":" + dims +
                  fmt(",\"f_tau\":%.17g,\"u_tau\":%.17g,\"c_tau\":%.17g,\"f_2tau\":%.17g,\"u_2tau\":%.17g,"
-                     "\"c_2tau\":%.17g,\"herm_resid\":%.17g,\"sz_tot\":%.17g,\"su2_resid\":%.17g,\"trunc_err\":%.17g}",
+                     "\"c_2tau\":%.17g,\"herm_resid\":%.17g,\"sz_tot\":%.17g,\"su2_resid\":%.17g,\"trunc_err\":%.17g,"
+                     "\"flops\":%.17g}",
                      a.f, a.u, a.c, b.f, b.u, b.c, b.herm_resid, b.sz_tot, b.su2_resid,
-                     info ? info->trunc_err_max : 0.0);
+                     info ? info->trunc_err_max : 0.0, info ? info->flops : 0.0);
   }
 
-  // Requests finished since the loop last held the lock: they are marked
-  // done there, together with the decision to leave the loop, so that a
-  // client that sees its last result done also finds the context idle.
-  std::vector<Request*> finished_now;
-
-  void finish(Request& r, int status, const std::string& err) {
+  void finish(Lane& ln, Request& r, int status, const std::string& err) {
     r.finished = true;
     r.status = status;
     r.err = err;
     r.t_finish = Clock::now();
     r.rho.reset();
     r.H.reset();
-    finished_now.push_back(&r);
+    ln.finished_now.push_back(&r);
   }
 
   // Build H and rho(tau0) of an admitted request, with its first record.
-  void admit(Request& r) {
+  void admit(Lane& ln, Request& r) {
     r.t_admit = Clock::now();
     try {
-      r.H = xtrg_impl::hamiltonian(c, r.n_sites, (int)r.jxy.size(), r.bonds.data(), r.jxy.data(), r.jz.data());
-      r.rho = xtrg_impl::init_rho(c, r.H.get(), r.tau0, r.order, 0, &r.lam);
+      r.H = xtrg_impl::hamiltonian(ln.c, r.n_sites, (int)r.jxy.size(), r.bonds.data(), r.jxy.data(), r.jz.data());
+      r.rho = xtrg_impl::init_rho(ln.c, r.H.get(), r.tau0, r.order, 0, &r.lam);
       r.tau = r.tau0;
-      record(r, nullptr);
+      record(ln, r, nullptr);
     } catch (const Error& e) {
       if (e.code == XTRG_EDEVICE) throw;
-      finish(r, e.code, e.what());
+      finish(ln, r, e.code, e.what());
     }
   }
 
-  // One batch step: every active request advances by one doubling.
-  void step() {
-    const int n = (int)active.size();
+  // One batch step of a lane: every active request advances by one doubling.
+  void step(Lane& ln) {
+    const int n = (int)ln.active.size();
     std::vector<xtrg_mpo> ins(n), outs(n, nullptr);
     std::vector<xtrg_compress_opts> opts(n);
     std::vector<xtrg_compress_info> infos(n);
     for (int q = 0; q < n; ++q) {
-      Request& r = *active[q];
+      Request& r = *ln.active[q];
       ins[q] = r.rho.get();
       xtrg_compress_opts o{};
       o.D_max = r.D;
@@ -350,14 +386,14 @@ struct Server {
       infos[q] = xtrg_compress_info{};
     }
     std::string err;
-    xtrg_impl::square_compress(c, n, ins.data(), opts.data(), outs.data(), infos.data(), &err);
+    xtrg_impl::square_compress(ln.c, n, ins.data(), opts.data(), outs.data(), infos.data(), &err);
     std::vector<Request*> still;
     for (int q = 0; q < n; ++q) {
-      Request& r = *active[q];
+      Request& r = *ln.active[q];
       if (!outs[q]) {
-        finish(r, infos[q].status, "doubling " + std::to_string(r.n_done + 1) + ": " +
-                                       (infos[q].status == XTRG_ENOMEM ? "device memory refused by the budget"
-                                                                       : "non-finite numbers in the compression"));
+        finish(ln, r, infos[q].status, "doubling " + std::to_string(r.n_done + 1) + ": " +
+                                           (infos[q].status == XTRG_ENOMEM ? "device memory refused by the budget"
+                                                                           : "non-finite numbers in the compression"));
         continue;
       }
       r.rho.reset(outs[q]);
@@ -365,49 +401,60 @@ struct Server {
       r.tau *= 2.0;
       r.n_done += 1;
       try {
-        record(r, &infos[q]);
+        record(ln, r, &infos[q]);
       } catch (const Error& e) {
         if (e.code == XTRG_EDEVICE) throw;
-        finish(r, e.code, e.what());
+        finish(ln, r, e.code, e.what());
         continue;
       }
-      if (r.n_done >= r.n_doublings) finish(r, XTRG_OK, "");
+      if (r.n_done >= r.n_doublings) finish(ln, r, XTRG_OK, "");
       else still.push_back(&r);
     }
-    if ((int)still.size() < n) xtrg_impl::trim(c);   // workspaces sized for the chains that left
-    active = still;
+    if ((int)still.size() < n) xtrg_impl::trim(ln.c);   // workspaces sized for the chains that left
+    ln.active = still;
   }
 
-  void loop() {
+  // Memory the other lanes hold (footprints and shared reserves), under the lock.
+  size_t used_elsewhere(const Lane& ln) const {
+    size_t u = 0;
+    for (const auto& l : lanes)
+      if (l.get() != &ln) u += l->used + l->shared;
+    return u;
+  }
+
+  void loop(Lane& ln) {
     (void)hipSetDevice(c->device);
     for (;;) {
       std::vector<Request*> admit_now;
       {
         std::unique_lock<std::mutex> lk(mu);
-        for (Request* r : finished_now) r->done = true;
-        finished_now.clear();
-        for (Request* r : active) {
+        for (Request* r : ln.finished_now) r->done = true;
+        ln.finished_now.clear();
+        for (Request* r : ln.active) {
           r->admitted = true;
           r->progress = r->n_done;
         }
-        if (stop || (pending.empty() && active.empty())) {
-          running = false;
-          c->serving.store(false);
+        if (stop || (ln.pending.empty() && ln.active.empty())) {
+          ln.running = false;
+          ln.used = ln.shared = 0;
+          if (!any_running()) c->serving.store(false);
           return;
         }
-        // admission in arrival order while the estimate fits the budget
-        // (the context's shared workspaces for the largest bond budget first)
+        // admission in arrival order while the estimate fits the budget left
+        // by the other lanes (this lane's shared workspaces for its largest
+        // bond budget first)
+        const size_t other = used_elsewhere(ln);
         size_t used = 0;
         int dmax = 0;
-        for (Request* r : active) {
+        for (Request* r : ln.active) {
           used += r->footprint;
           dmax = std::max(dmax, r->D);
         }
-        while (!pending.empty() && (int)(active.size() + admit_now.size()) < max_chains) {
-          Request* r = pending.front();
+        while (!ln.pending.empty() && (int)(ln.active.size() + admit_now.size()) < max_chains) {
+          Request* r = ln.pending.front();
           const size_t shared = shared_bytes(std::max(dmax, r->D));
           if (r->footprint + shared > budget) {   // would never fit: fail now
-            pending.pop_front();
+            ln.pending.pop_front();
             r->status = XTRG_ENOMEM;
             r->err = "device-memory estimate " + std::to_string(r->footprint) + " B exceeds the serving budget " +
                      std::to_string(budget) + " B";
@@ -415,28 +462,81 @@ struct Server {
             r->done = true;
             continue;
           }
-          if (used + r->footprint + shared > budget) break;   // wait for memory to free up
+          if (other + used + r->footprint + shared > budget) break;   // wait for memory to free up
           used += r->footprint;
           dmax = std::max(dmax, r->D);
-          pending.pop_front();
+          ln.pending.pop_front();
           admit_now.push_back(r);
         }
+        ln.used = used;
+        ln.shared = (ln.active.empty() && admit_now.empty()) ? 0 : shared_bytes(dmax);
       }
       try {
         for (Request* r : admit_now) {
-          admit(*r);
-          if (r->rho) active.push_back(r);   // else it failed at its start and is finished
+          admit(ln, *r);
+          if (r->rho) ln.active.push_back(r);   // else it failed at its start and is finished
         }
-        if (!active.empty()) step();
+        if (!ln.active.empty()) step(ln);
+        else if (admit_now.empty()) {
+          // nothing admitted and nothing running: the pending front waits for
+          // memory that other lanes hold; look again shortly
+          std::this_thread::sleep_for(std::chrono::milliseconds(20));
+        }
       } catch (const std::exception& e) {
-        // a runtime error ends every request in flight
+        // a runtime error ends every request in flight on this lane
         const int code = dynamic_cast<const Error*>(&e) ? static_cast<const Error&>(e).code : XTRG_EDEVICE;
-        for (Request* r : active) finish(*r, code, e.what());
+        for (Request* r : ln.active) finish(ln, *r, code, e.what());
         for (Request* r : admit_now)
-          if (!r->finished) finish(*r, code, e.what());
-        active.clear();
+          if (!r->finished) finish(ln, *r, code, e.what());
+        ln.active.clear();
       }
     }
+  }
+
+  // Lanes are set up at the first request: lane 0 on the server's context,
+  // the others on contexts of their own (same device and budget, each with
+  // a stream of its own at the default priority).
+  void make_lanes(int n) {
+    for (int k = 0; k < n; ++k) {
+      auto ln = std::make_unique<Lane>();
+      if (k == 0) {
+        ln->c = c;
+      } else {
+        XTRG_HIP(hipSetDevice(c->device));
+        XTRG_HIP(hipStreamCreateWithFlags(&ln->stream, hipStreamNonBlocking));
+        const int rc = xtrg_ctx_create(c->device, ln->stream, c->budget, &ln->c);
+        if (rc != XTRG_OK) {
+          (void)hipStreamDestroy(ln->stream);
+          throw Error(rc, "serving lane: context creation failed");
+        }
+        ln->owned = true;
+      }
+      lanes.push_back(std::move(ln));
+    }
+  }
+
+  // Replace the lanes (none running; under the lock).  The requests and
+  // their results stay.
+  void relane(int n) {
+    for (auto& ln : lanes) {
+      if (ln->worker.joinable()) ln->worker.join();
+      if (ln->owned) {
+        (void)xtrg_ctx_destroy(ln->c);
+        (void)hipStreamDestroy(ln->stream);
+      }
+    }
+    lanes.clear();
+    max_cost = 0.0;
+    make_lanes(n);
+  }
+
+  void start(Lane& ln) {
+    if (ln.running) return;
+    if (ln.worker.joinable()) ln.worker.join();   // the previous worker has left its loop
+    ln.running = true;
+    c->serving.store(true);
+    Lane* lp = &ln;
+    ln.worker = std::thread([this, lp] { loop(*lp); });
   }
 };
 
@@ -447,10 +547,17 @@ void server_shutdown(xtrg_ctx c) {
     std::lock_guard<std::mutex> lk(S->mu);
     S->stop = true;
   }
-  if (S->worker.joinable()) S->worker.join();
-  for (Request* r : S->active) {
-    r->rho.reset();
-    r->H.reset();
+  for (auto& ln : S->lanes)
+    if (ln->worker.joinable()) ln->worker.join();
+  for (auto& ln : S->lanes) {
+    for (Request* r : ln->active) {
+      r->rho.reset();
+      r->H.reset();
+    }
+    if (ln->owned) {
+      (void)xtrg_ctx_destroy(ln->c);
+      (void)hipStreamDestroy(ln->stream);
+    }
   }
   delete S;
   c->server = nullptr;
@@ -516,30 +623,28 @@ int xtrg_serve_submit(xtrg_ctx c, const char* request_json, unsigned long long* 
     r->t_submit = xtrg::Clock::now();
 
     if (!c->server) {
-      c->server = new xtrg::Server();
-      c->server->c = c;
+      auto S0 = std::make_unique<xtrg::Server>();
+      S0->c = c;
+      S0->make_lanes(c->serve_lanes);
+      c->server = S0.release();
     }
     xtrg::Server* S = c->server;
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->stop) throw Error(XTRG_EINVAL, "context is being destroyed");
+    if (S->budget == 0) {
+      size_t fr = 0, tot = 0;
+      if (c->budget) S->budget = c->budget;
+      else if (hipSetDevice(c->device) == hipSuccess && hipMemGetInfo(&fr, &tot) == hipSuccess)
+        S->budget = (size_t)(0.85 * (double)fr);
+      else
+        throw Error(XTRG_EDEVICE, "hipMemGetInfo failed");
+    }
     r->id = S->next_id++;
     *id = r->id;
-    S->pending.push_back(r.get());
+    xtrg::Lane& ln = *S->lanes[S->route(*r)];
+    ln.pending.push_back(r.get());
     S->all[r->id] = std::move(r);
-    if (!S->running) {
-      if (S->worker.joinable()) S->worker.join();   // the previous worker has left its loop
-      if (S->budget == 0) {
-        size_t fr = 0, tot = 0;
-        if (c->budget) S->budget = c->budget;
-        else if (hipSetDevice(c->device) == hipSuccess && hipMemGetInfo(&fr, &tot) == hipSuccess)
-          S->budget = (size_t)(0.85 * (double)fr);
-        else
-          throw Error(XTRG_EDEVICE, "hipMemGetInfo failed");
-      }
-      S->running = true;
-      c->serving.store(true);
-      S->worker = std::thread([S] { S->loop(); });
-    }
+    S->start(ln);
     c->err.clear();
     return XTRG_OK;
   } catch (const Error& e) {
@@ -548,6 +653,25 @@ int xtrg_serve_submit(xtrg_ctx c, const char* request_json, unsigned long long* 
   } catch (const std::exception& e) {
     c->err = e.what();
     return XTRG_EINVAL;
+  }
+}
+
+int xtrg_serve_set_lanes(xtrg_ctx c, int n_lanes) {
+  if (!c || n_lanes < 1 || n_lanes > 4) return XTRG_EINVAL;
+  try {
+    xtrg::Server* S = c->server;
+    if (!S) {
+      c->serve_lanes = n_lanes;
+      return XTRG_OK;
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->any_running()) return XTRG_EBUSY;
+    c->serve_lanes = n_lanes;
+    S->relane(n_lanes);
+    return XTRG_OK;
+  } catch (const Error& e) {
+    c->err = e.what();
+    return e.code;
   }
 }
 
@@ -570,8 +694,8 @@ int xtrg_serve_poll(xtrg_ctx c, unsigned long long id, char* result_json, size_t
     const double sub = S->secs(r.t_submit), adm = S->secs(r.t_admit), fin = S->secs(r.t_finish);
     out = xtrg::fmt("{\"id\":%llu,\"status\":%d,\"error\":\"", r.id, r.status) + xtrg::json_escape(r.err) +
           xtrg::fmt("\",\"submitted_s\":%.9g,\"admitted_s\":%.9g,\"finished_s\":%.9g,\"latency_s\":%.9g,"
-                    "\"doublings\":%d,\"records\":[",
-                    sub, adm, fin, fin - sub, r.n_done) +
+                    "\"doublings\":%d,\"flops\":%.17g,\"records\":[",
+                    sub, adm, fin, fin - sub, r.n_done, r.flops) +
           r.records + "]}";
   }
   if (out.size() + 1 > cap) return XTRG_EINVAL;

@@ -11,6 +11,11 @@
     python -m paper_1801_00142_amd.microbench copy GIB
         one device-to-device copy of GIB GiB: the reference for scaling the
         HBM byte counters (FETCH_SIZE, WRITE_SIZE) of other kernels.
+    python -m paper_1801_00142_amd.microbench peaks [N]
+        measured ceilings beside the published peaks: the library's N x N x N
+        GEMM in FP64, FP32 and bf16x3 (xtrg_dgemm, xtrg_sgemm,
+        xtrg_gemm_bf16x3; N = 8192 by default) and a timed 4 GiB
+        device-to-device copy (read + write bytes over its time).
 """
 import sys
 import time
@@ -73,6 +78,44 @@ def copy(gib: float) -> None:
     print(f"copied {n * 8} bytes", flush=True)
 
 
+def peaks(n: int = 8192) -> None:
+    import torch
+    from . import Context
+    ctx = Context(0)
+    g = torch.Generator(device="cpu").manual_seed(0)
+    A = torch.rand((n, n), generator=g, dtype=torch.float64).cuda()
+    B = torch.rand((n, n), generator=g, dtype=torch.float64).cuda()
+    C = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    A32, B32 = A.float(), B.float()
+    flops = 2.0 * n ** 3
+    calls = [("fp64", 78.6, lambda: ctx.dgemm(n, n, n, 0, 0, A.data_ptr(), n, B.data_ptr(), n, C.data_ptr(), n)),
+             ("fp32", 157.3, lambda: ctx.sgemm(n, n, n, 0, 0, A32.data_ptr(), n, B32.data_ptr(), n, C.data_ptr(), n)),
+             ("bf16x3", 2500.0 / 3, lambda: ctx.gemm_bf16x3(n, n, n, 0, 0, A32.data_ptr(), n, B32.data_ptr(), n,
+                                                          C.data_ptr(), n))]
+    for name, peak, f in calls:
+        f()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            f()
+        torch.cuda.synchronize()
+        tf = 3 * flops / (time.perf_counter() - t) / 1e12
+        print(f"gemm {name} {n}^3: {tf:.1f} TFLOP/s (published dense peak {peak:.1f}{' / 3 products' if name == 'bf16x3' else ''}, "
+              f"{tf / peak:.2f})", flush=True)
+    m = (4 << 30) // 8
+    a = torch.ones(m, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    gbs = 5 * 2 * m * 8 / (time.perf_counter() - t) / 1e9
+    print(f"copy 4 GiB: {gbs:.0f} GB/s read + write (published HBM peak 8000, {gbs / 8000:.2f})", flush=True)
+    ctx.close()
+
+
 if __name__ == "__main__":
     if len(sys.argv) >= 4 and sys.argv[1] == "svd":
         svd(int(sys.argv[2]), float(sys.argv[3]), int(sys.argv[4]) if len(sys.argv) > 4 else 2)
@@ -80,6 +123,8 @@ if __name__ == "__main__":
         qr(int(sys.argv[2]), int(sys.argv[3]) if len(sys.argv) > 3 else 3)
     elif len(sys.argv) == 3 and sys.argv[1] == "copy":
         copy(float(sys.argv[2]))
+    elif len(sys.argv) >= 2 and sys.argv[1] == "peaks":
+        peaks(int(sys.argv[2]) if len(sys.argv) > 2 else 8192)
     else:
         print(__doc__)
         sys.exit(2)

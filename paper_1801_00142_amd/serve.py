@@ -1,10 +1,10 @@
 """Client of the library's serving loop (xtrg_serve_submit / xtrg_serve_poll).
 
-The continuous batching itself runs inside libxtrg.so: a worker thread
-admits queued thermal solves as device memory allows, advances all admitted
-solves by one doubling per batch step through the batched doubling, keeps
-lambda and the observables of every doubling, and retires finished solves
-(include/xtrg.h).  This module only submits requests at their arrival times
+The continuous batching itself runs inside libxtrg.so: worker threads (one
+per lane; a solve's lane follows its size) admit queued thermal solves as
+device memory allows, advance their admitted solves by one doubling per
+batch step through the batched doubling, keep lambda and the observables of
+every doubling, and retire finished solves (include/xtrg.h).  This module only submits requests at their arrival times
 and polls for results.
 """
 from __future__ import annotations
@@ -63,12 +63,14 @@ def shared_bytes(D_max: int) -> int:
 
 class Server:
     """Submits solves at their arrival times to the library's serving loop
-    on `ctx` (whose hbm_budget, if set, is the admission budget) and
-    collects the results."""
+    on `ctx` (whose hbm_budget, if set, is the admission budget; `lanes`, if
+    given, sets the number of concurrent lanes) and collects the results."""
 
-    def __init__(self, ctx: Context, poll_s: float = 0.005):
+    def __init__(self, ctx: Context, poll_s: float = 0.005, lanes: Optional[int] = None):
         self.ctx = ctx
         self.poll_s = poll_s
+        if lanes is not None:
+            ctx.serve_set_lanes(lanes)
 
     def run(self, solves: Sequence[Solve], clock: Callable[[], float] = time.perf_counter,
             log: Optional[Callable[[str], None]] = None) -> Dict[int, dict]:

@@ -100,6 +100,7 @@ def load_library(path: Optional[str] = None):
         "xtrg_expectation": (C.c_int, [vp, vp, C.c_int, C.POINTER(vp), dp, dp]),
         "xtrg_serve_submit": (C.c_int, [vp, C.c_char_p, C.POINTER(C.c_ulonglong)]),
         "xtrg_serve_poll": (C.c_int, [vp, C.c_ulonglong, C.c_char_p, C.c_size_t]),
+        "xtrg_serve_set_lanes": (C.c_int, [vp, C.c_int]),
         "xtrg_profile_enable": (C.c_int, [vp, C.c_int]),
         "xtrg_profile_report": (C.c_int, [vp, C.c_char_p, C.c_size_t]),
     }
@@ -115,7 +116,7 @@ def exported_symbols() -> List[str]:
     return ["xtrg_ctx_create", "xtrg_ctx_destroy", "xtrg_last_error", "xtrg_ctx_bytes", "xtrg_ctx_trim",
             "xtrg_hamiltonian_xxz", "xtrg_mpo_from_host", "xtrg_mpo_shape", "xtrg_mpo_to_host",
             "xtrg_mpo_destroy", "xtrg_init_rho", "xtrg_square_compress", "xtrg_product_compress", "xtrg_square_compress_batched", "xtrg_observables",
-            "xtrg_dgemm", "xtrg_dgemm_noalloc", "xtrg_sgemm", "xtrg_gemm_bf16x3", "xtrg_dsvd_left", "xtrg_dsvd_left_qr", "xtrg_dqrcp", "xtrg_spin_sum_mpo", "xtrg_correlation_mpo", "xtrg_expectation", "xtrg_serve_submit", "xtrg_serve_poll", "xtrg_profile_enable",
+            "xtrg_dgemm", "xtrg_dgemm_noalloc", "xtrg_sgemm", "xtrg_gemm_bf16x3", "xtrg_dsvd_left", "xtrg_dsvd_left_qr", "xtrg_dqrcp", "xtrg_spin_sum_mpo", "xtrg_correlation_mpo", "xtrg_expectation", "xtrg_serve_submit", "xtrg_serve_poll", "xtrg_serve_set_lanes", "xtrg_profile_enable",
             "xtrg_profile_report"]
 
 
@@ -365,6 +366,10 @@ class Context:
         return out
 
     # serving: the library's continuous-batching loop (include/xtrg.h)
+    def serve_set_lanes(self, n: int) -> None:
+        """Lanes of the serving loop (1 to 4; not while a lane has work)."""
+        _check(self, _lib.xtrg_serve_set_lanes(self.h, int(n)))
+
     def serve_submit(self, request: dict) -> int:
         """Queue one XTRG run (the JSON fields of xtrg_serve_submit); returns its id."""
         import json

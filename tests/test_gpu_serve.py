@@ -77,6 +77,42 @@ def test_serve_results_equal_alone():
         _same_records(alone, mixed[s.rid])
 
 
+def test_serve_lanes_overlap_and_keep_results():
+    """Two lanes: a large run (chain L = 12, D = 48) and two small ones
+    (D = 8, about 400 times less work per doubling) submitted together.  The
+    small runs go to the second lane and finish while the large one is
+    still doubling; with one lane all three advance in lockstep.  Every
+    run's records are bit-identical either way."""
+    from paper_1801_00142_amd.serve import Solve
+    big = W.chain(12)
+    small = [W.chain(6), W.with_couplings(W.chain(6), 1.0, 1.3)]
+    solves = [Solve(0, big.n_sites, big.bonds, big.jxy, big.jz, 2.0 ** -6, 8, 48)]
+    for q, lat in enumerate(small, start=1):
+        solves.append(Solve(q, lat.n_sites, lat.bonds, lat.jxy, lat.jz, 2.0 ** -6 * 2 ** (q / 4), 8, 8))
+    from paper_1801_00142_amd import Context
+    from paper_1801_00142_amd.serve import Server
+    out = {}
+    for lanes in (1, 2):
+        with Context(0) as c:
+            out[lanes] = Server(c, lanes=lanes).run(solves)
+    for s in solves:
+        for lanes in (1, 2):
+            assert out[lanes][s.rid]["status"] == 0, out[lanes][s.rid]["error"]
+        _same_records(out[1][s.rid], out[2][s.rid])
+    two = out[2]
+    assert max(two[q]["finished_s"] for q in (1, 2)) < 0.5 * two[0]["finished_s"]
+    one = out[1]
+    assert min(one[q]["finished_s"] for q in (1, 2)) > 0.9 * one[0]["finished_s"]
+
+
+def test_serve_set_lanes_rejects_bad_counts(ctx):
+    from paper_1801_00142_amd import XtrgError
+    for n in (0, 5):
+        with pytest.raises(XtrgError):
+            ctx.serve_set_lanes(n)
+    ctx.serve_set_lanes(2)
+
+
 def test_serve_failures_stay_with_their_run():
     """T10: a run with a NaN coupling fails with XTRG_ENUMERIC and a run
     whose memory estimate exceeds the budget fails with XTRG_ENOMEM; the
