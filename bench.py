@@ -387,9 +387,13 @@ def main():
     # after every doubling), timed once
     torch.cuda.synchronize()
     t_obs = time.perf_counter()
-    ctx.observables(rhos[0], 0.0, tau[0], H, lat.n_sites, entropy=False)
+    obs = ctx.observables(rhos[0], 0.0, tau[0], H, lat.n_sites, entropy=False)
     torch.cuda.synchronize()
     obs_s = time.perf_counter() - t_obs
+    # properties of the exact state that hold at any size: a check of the
+    # final compressed state where no oracle run reaches (beta = 2 tau_n)
+    inv = {k: obs["2tau"][k] for k in ("herm_resid", "sz_tot", "su2_resid")}
+    inv["beta"] = obs["2tau"]["beta"]
 
     wl_name = (f"{lat.name} {'Heisenberg' if set(lat.jz) == set(lat.jxy) == {1.0} else 'XXZ'}, "
                f"tau0=2^{math.log2(wl.tau0):g}, D={args.D}, {args.sweeps} sweeps/doubling")
@@ -417,6 +421,7 @@ def main():
                    "warmup_doublings": n_done, "saturated_after": saturated_at},
         "sweeps_per_s": round(nb * args.steps * args.sweeps / dt, 4),
         "observables_s": round(obs_s, 3),
+        "invariants": inv,
         "phase_share": shares,
         "svd_sweeps_avg": round(svd_sweeps / max(svd_calls, 1), 2),
         "svd_warm": {"calls": svd_calls, "warm_started": warm_stats["warm_used"],
