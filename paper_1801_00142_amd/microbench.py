@@ -11,6 +11,10 @@
     python -m paper_1801_00142_amd.microbench copy GIB
         one device-to-device copy of GIB GiB: the reference for scaling the
         HBM byte counters (FETCH_SIZE, WRITE_SIZE) of other kernels.
+    python -m paper_1801_00142_amd.microbench gemm M N K [REPS]
+        the library's FP64 GEMM (xtrg_dgemm, A M x K and B K x N row-major,
+        seeded uniform entries) REPS times; prints TFLOP/s.  M = N = 1024,
+        K = 65536 is the two-site overlap C_E at D = 256.
     python -m paper_1801_00142_amd.microbench peaks [N]
         measured ceilings beside the published peaks: the library's N x N x N
         GEMM in FP64, FP32 and bf16x3 (xtrg_dgemm, xtrg_sgemm,
@@ -78,6 +82,24 @@ def copy(gib: float) -> None:
     print(f"copied {n * 8} bytes", flush=True)
 
 
+def gemm(m: int, n: int, k: int, reps: int = 5) -> None:
+    import torch
+    from . import Context
+    ctx = Context(0)
+    g = torch.Generator(device="cpu").manual_seed(0)
+    A = torch.rand((m, k), generator=g, dtype=torch.float64).cuda()
+    B = torch.rand((k, n), generator=g, dtype=torch.float64).cuda()
+    C = torch.empty((m, n), dtype=torch.float64, device="cuda")
+    ctx.dgemm(m, n, k, 0, 0, A.data_ptr(), k, B.data_ptr(), n, C.data_ptr(), n)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        ctx.dgemm(m, n, k, 0, 0, A.data_ptr(), k, B.data_ptr(), n, C.data_ptr(), n)
+    torch.cuda.synchronize()
+    print(f"dgemm {m}x{n}x{k}: {reps * 2.0 * m * n * k / (time.perf_counter() - t) / 1e12:.1f} TFLOP/s", flush=True)
+    ctx.close()
+
+
 def peaks(n: int = 8192) -> None:
     import torch
     from . import Context
@@ -123,6 +145,8 @@ if __name__ == "__main__":
         qr(int(sys.argv[2]), int(sys.argv[3]) if len(sys.argv) > 3 else 3)
     elif len(sys.argv) == 3 and sys.argv[1] == "copy":
         copy(float(sys.argv[2]))
+    elif len(sys.argv) >= 5 and sys.argv[1] == "gemm":
+        gemm(int(sys.argv[2]), int(sys.argv[3]), int(sys.argv[4]), int(sys.argv[5]) if len(sys.argv) > 5 else 5)
     elif len(sys.argv) >= 2 and sys.argv[1] == "peaks":
         peaks(int(sys.argv[2]) if len(sys.argv) > 2 else 8192)
     else:
