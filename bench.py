@@ -376,7 +376,12 @@ def main():
         ctx.profile(False)
         return flops, steps_2site, dt, prof
 
+    # the timed steps' window on the kernel tracer's clock (CLOCK_BOOTTIME),
+    # for per-kernel statistics of exactly these steps from a trace
+    torch.cuda.synchronize()
+    win0 = time.clock_gettime_ns(time.CLOCK_BOOTTIME)
     flops, steps_2site, dt, prof = timed(args.steps, args.sweeps, "timed")
+    win1 = time.clock_gettime_ns(time.CLOCK_BOOTTIME)
     value = flops / dt / 1e12
     side = None
     if args.side_sweeps > 0 and args.sweeps != 2:
@@ -444,6 +449,7 @@ def main():
                    "chains": nb, "two_site_steps_per_doubling": steps_2site // max(args.steps, 1),
                    "warmup_doublings": n_done, "saturated_after": saturated_at,
                    "doublings_in_workload": wl.n_doublings, "state_restores": state["restores"]},
+        "timed_window_ns": [win0, win1],
         "sweeps_per_s": round(nb * args.steps * args.sweeps / dt, 4),
         "observables_s": round(obs_s, 3),
         "invariants": inv,
