@@ -6,7 +6,8 @@ Test infrastructure: see the package docstring.  Follows, in order:
   tau_n = 2^n tau0, starting from rho(tau0) at tiny tau0.
 * Sec. II.C, Eq. (RhoTau) and App. C.2: rho(tau0) as the truncated
   Maclaurin series sum_k (-tau0)^k/k! H^k; order 1 is I - tau0 H, exact at
-  the bond dimension of H.
+  the bond dimension of H; the series start (settn_init) builds H^k by
+  compressed products and stops at an expansion error below 1e-15.
 * Sec. II.D: truncate by a fixed number of kept states, never by discarded
   weight.
 * App. D.1, Eqs. (MPO:prod), (LSEProd), Fig. VMPO: minimise
@@ -120,6 +121,81 @@ def init_rho(n, bonds, jxy, jz, tau0: float, order: int, rel_floor: float = 1e-1
     nrm = float(np.linalg.norm(W[0]))                 # right-canonical: norm on site 0
     W[0] = W[0] / nrm
     return W, math.log(nrm)
+
+
+def identity(n: int) -> List[np.ndarray]:
+    """The identity operator as a normalised, right-canonical MPO of bond 1:
+    every site I/sqrt(2), so ||I||_F = 2^(n/2) is carried by the log-norm."""
+    return [(np.eye(2) / math.sqrt(2.0)).reshape(1, 2, 2, 1) for _ in range(n)]
+
+
+def sum_compress(terms: Sequence[List[np.ndarray]], coefs: Sequence[float], D: int,
+                 deg_rtol: float = 1e-6, sv_floor: float = 1e-14) -> List[np.ndarray]:
+    """sum_k coefs[k] * terms[k] as one MPO of bond <= D: the exact sum
+    (block-diagonal bonds, App. D.2 Eq. MPO:plus) compressed by the direct
+    route of App. D.1 (left-canonicalise, then a right-to-left SVD sweep),
+    each bond cut by the keep rule of the doublings (keep_count: at most D
+    values, multiplet-safe, numerically zero values dropped)."""
+    S = None
+    for W, a in zip(terms, coefs):
+        X = [w.copy() for w in W]
+        X[0] = X[0] * a
+        S = X if S is None else M.mpo_sum(S, X)
+    W = M.left_canonicalize(S)
+    for i in range(len(W) - 1, 0, -1):
+        Dl, d1, d2, Dr = W[i].shape
+        Mi = W[i].reshape(Dl, d1 * d2 * Dr)
+        U, Sv, Vt = np.linalg.svd(Mi, full_matrices=False)
+        k = keep_count(Sv, D, deg_rtol, sv_floor, noise_floor(Mi))
+        W[i] = Vt[:k].reshape(k, d1, d2, Dr)
+        W[i - 1] = np.einsum("astb,bk->astk", W[i - 1], U[:, :k] * Sv[:k])
+    return W
+
+
+def settn_init(H: List[np.ndarray], tau0: float, D: int, n_sweeps: int = 2, tol: float = 1e-15,
+               k_max: int = 80, deg_rtol: float = 1e-6, sv_floor: float = 1e-14, svd=None):
+    """rho(tau0) by the series expansion of Sec. II.C, Eq. (RhoTau), with the
+    cutoff order chosen automatically.
+
+    The terms H^k are built one from the other, H^k = H (H^(k-1)), each
+    product compressed to bond <= D by product_compress (App. D.1; the same
+    sweeps as a doubling, the initial guess the previous term).  The
+    recursion starts from H itself, compressed without loss: from the
+    identity (bond 1) as the initial guess, the sweeps would only see the
+    parts of H whose other sites project onto the identity, and the traceless
+    couplings project to zero.  Every term
+    is kept normalised with its log-norm l_k, so that
+    omega_k H^k = omega_k e^(l_k) Hhat_k with omega_k = (-tau0)^k / k!.  The
+    expansion stops at the first order N_c whose term is below tol relative
+    to the identity term, |omega_k| e^(l_k - l_0) <= tol (an expansion error
+    below 1e-15, as the paper asks; l_0 = ln ||I||_F).  The sum of the
+    N_c + 1 terms is compressed by sum_compress.  Returns (rhohat, lambda_0,
+    N_c) with rho(tau0) = e^(lambda_0) rhohat, ||rhohat||_F = 1 and rhohat
+    right-canonical."""
+    n = len(H)
+    l0 = 0.5 * n * math.log(2.0)
+    terms, coefs = [identity(n)], [1.0]
+    P = M.svd_compress(H, D=10 ** 9, rel_floor=sv_floor)       # H itself, canonical
+    h = float(np.linalg.norm(P[0]))
+    P[0] = P[0] / h
+    l = math.log(h)
+    omega = 1.0
+    nc = 0
+    for k in range(1, k_max + 1):
+        if k > 1:
+            P, info = product_compress(H, P, D, n_sweeps, deg_rtol, sv_floor, svd=svd)
+            l += info.dlog_norm
+        omega *= -tau0 / k
+        a = omega * math.exp(l - l0)
+        terms.append(P)
+        coefs.append(a)
+        nc = k
+        if abs(a) <= tol:
+            break
+    W = sum_compress(terms, coefs, D, deg_rtol, sv_floor)
+    nrm = float(np.linalg.norm(W[0]))
+    W[0] = W[0] / nrm
+    return W, l0 + math.log(nrm), nc
 
 
 # --------------------------------------------------------------------------
