@@ -5,6 +5,7 @@
 #include "xtrg.h"
 
 #include <algorithm>
+#include <limits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -400,9 +401,11 @@ void left_sweep(xtrg_mpo m, double floor, std::vector<std::vector<double>>* sv) 
 }
 
 // Right-to-left: site i = V^T (right-isometric), U S pushed into site i-1.
-// Keeps at most Dmax (if > 0) and drops values <= floor * s_1.  Records the
-// singular values of every bond (bond i-1 | i) in sv (indexed by bond).
-void right_sweep(xtrg_mpo m, double floor, int Dmax, std::vector<std::vector<double>>* sv) {
+// Keeps at most Dmax (if > 0; with degen > 0 backing off as the keep rule
+// of the doubling does, so that a multiplet is not split) and drops values
+// <= floor * s_1.  Records the singular values of every bond (bond i-1 | i)
+// in sv (indexed by bond).
+void right_sweep(xtrg_mpo m, double floor, int Dmax, std::vector<std::vector<double>>* sv, double degen = 0.0) {
   xtrg_ctx c = m->ctx;
   hipStream_t s = c->stream;
   if (sv) sv->assign(std::max(m->L - 1, 0), {});
@@ -414,11 +417,7 @@ void right_sweep(xtrg_mpo m, double floor, int Dmax, std::vector<std::vector<dou
     std::vector<double> S = read_vec(c, xtrg::svd_sorted_values(work, len, Dl), Dl);
     S.resize(std::min(len, Dl));
     const double nf = noise_floor(c, work, len, Dl);
-    int k = 0;
-    for (double v : S)
-      if (v > floor * S[0] && v > nf && v > 0) ++k;
-    k = std::max(k, 1);
-    if (Dmax > 0) k = std::min(k, Dmax);
+    const int k = keep_count(S, Dmax > 0 ? Dmax : std::numeric_limits<int>::max(), degen, floor, nf);
     if (sv) (*sv)[i - 1] = S;
     double* V = c->need("cs_V", (size_t)len * k);
     xtrg::svd_gather(len, Dl, work, k, V, len, 0, s);                 // V col-major = V^T row-major [k][len]
@@ -1705,6 +1704,105 @@ std::unique_ptr<xtrg_mpo_s> init_rho(xtrg_ctx c, xtrg_mpo H, double tau0, int or
   return fin;
 }
 
+// The series start of Sec. II.C, Eq. (RhoTau): rho(tau0) = sum_k omega_k H^k,
+// omega_k = (-tau0)^k / k!, with the cutoff order chosen by the expansion
+// error.  H^k = H (H^(k-1)) by the compressed product of App. D.1 (the
+// doubling's sweeps with A = H and the previous term as B and initial
+// guess); the recursion starts from H itself, compressed without loss (from
+// the bond-1 identity as the initial guess the sweeps would see only the
+// parts of H that project onto the identity elsewhere, and the traceless
+// couplings project to zero).  Every term is kept normalised with its
+// log-norm; the expansion stops at the first order whose term, relative to
+// the identity term, is at most tol.  The terms are summed exactly
+// (block-diagonal bonds, App. D.2 Eq. MPO:plus) and the sum compressed by
+// the direct route of App. D.1: a left-to-right SVD sweep that drops the
+// numerical zeros, then a right-to-left sweep with the keep rule of the
+// doublings.
+std::unique_ptr<xtrg_mpo_s> settn_init(xtrg_ctx c, xtrg_mpo H, double tau0, int D, int n_sweeps, double tol,
+                                       double* log_norm, int* n_terms) {
+  constexpr int kMaxOrder = 80;
+  if (!(tau0 > 0) || !std::isfinite(tau0) || D < 1 || n_sweeps < 1 || !(tol > 0))
+    throw Error(XTRG_EINVAL, "settn_init: tau0 > 0, D >= 1, n_sweeps >= 1, tol > 0");
+  hipStream_t s = c->stream;
+  const int L = H->L;
+  const double l0 = 0.5 * L * std::log(2.0);            // ln ||I||_F
+  std::vector<std::unique_ptr<xtrg_mpo_s>> terms;
+  std::vector<double> coef;
+  {
+    auto I = new_mpo(c, std::vector<int>(L + 1, 1));  // I / sqrt(2) on every site: norm 1, right-canonical
+    const double v[4] = {std::sqrt(0.5), 0.0, 0.0, std::sqrt(0.5)};
+    for (int i = 0; i < L; ++i) upload(c, I->site[i].p, v, 4);
+    terms.push_back(std::move(I));
+    coef.push_back(1.0);
+  }
+  auto P = clone(H);
+  left_sweep(P.get(), 1e-14, nullptr);
+  right_sweep(P.get(), 1e-14, 0, nullptr);
+  const double h = site_norm(P.get(), 0);
+  if (!(h > 0) || !std::isfinite(h)) throw Error(XTRG_ENUMERIC, "settn_init: ||H|| is zero or not finite");
+  xtrg::scale(P->site[0].p, 1.0 / h, P->elems(0), s);
+  double l = std::log(h);
+  xtrg_compress_opts o{};
+  o.D_max = D;
+  o.n_sweeps = n_sweeps;
+  o.precision = XTRG_FP64;
+  o.degen_rtol = 1e-6;
+  o.sv_floor = 1e-14;
+  double omega = 1.0;
+  int nc = 0;
+  for (int k = 1; k <= kMaxOrder; ++k) {
+    if (k > 1) {
+      xtrg_mpo A = H, B = terms.back().get();
+      xtrg_mpo out = nullptr;
+      xtrg_compress_info info{};
+      std::string err;
+      if (square_compress_impl(c, 1, &A, &o, &out, &info, &err, &B) > 0) throw Error(info.status, err);
+      P.reset(out);
+      l += info.dlog_norm;
+    }
+    omega *= -tau0 / k;
+    const double a = omega * std::exp(l - l0);
+    terms.push_back(std::move(P));
+    coef.push_back(a);
+    nc = k;
+    if (std::fabs(a) <= tol) break;
+  }
+  // the exact sum: site 0 concatenates the terms' columns (scaled by their
+  // coefficients), the last site their rows, the sites between are block
+  // diagonal
+  std::vector<int> dims(L + 1, 0);
+  dims[0] = dims[L] = 1;
+  std::vector<std::vector<int>> off(terms.size(), std::vector<int>(L + 1, 0));
+  for (size_t t = 0; t < terms.size(); ++t)
+    for (int b = 1; b < L; ++b) {
+      off[t][b] = dims[b];
+      dims[b] += terms[t]->dims[b];
+    }
+  auto S = new_mpo(c, dims);
+  for (int i = 0; i < L; ++i) xtrg::fill(S->site[i].p, 0.0, S->elems(i), s);
+  for (size_t t = 0; t < terms.size(); ++t) {
+    xtrg_mpo T = terms[t].get();
+    xtrg::scale(T->site[0].p, coef[t], T->elems(0), s);
+    for (int i = 0; i < L; ++i) {
+      const int Dl = T->dims[i], Dr = T->dims[i + 1], Drs = dims[i + 1];
+      double* dst = S->site[i].p + (size_t)off[t][i] * 4 * Drs + off[t][i + 1];
+      XTRG_HIP(hipMemcpy2DAsync(dst, (size_t)Drs * sizeof(double), T->site[i].p, (size_t)Dr * sizeof(double),
+                                (size_t)Dr * sizeof(double), (size_t)Dl * 4, hipMemcpyDeviceToDevice, s));
+    }
+  }
+  terms.clear();
+  left_sweep(S.get(), 1e-14, nullptr);
+  right_sweep(S.get(), 1e-14, D, nullptr, 1e-6);
+  const double nrm = site_norm(S.get(), 0);
+  if (!(nrm > 0) || !std::isfinite(nrm)) throw Error(XTRG_ENUMERIC, "settn_init: the series has zero norm");
+  xtrg::scale(S->site[0].p, 1.0 / nrm, S->elems(0), s);
+  *log_norm = l0 + std::log(nrm);
+  *n_terms = nc;
+  auto fin = clone(S.get());
+  XTRG_HIP(hipStreamSynchronize(s));
+  return fin;
+}
+
 int square_compress(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_compress_opts* opts, xtrg_mpo* outs,
                     xtrg_compress_info* infos, std::string* first_err) {
   return square_compress_impl(c, n, ins, opts, outs, infos, first_err);
@@ -1843,6 +1941,18 @@ int xtrg_init_rho(xtrg_ctx c, xtrg_mpo H, double tau0, int order, int D0_max, xt
   return guarded(c, [&] {
     set_device(c);
     *rho_out = xtrg_impl::init_rho(c, H, tau0, order, D0_max, log_norm).release();
+  });
+}
+
+int xtrg_settn_init(xtrg_ctx c, xtrg_mpo H, double tau0, int D_max, int n_sweeps, double tol, xtrg_mpo* rho_out,
+                    double* log_norm, int* n_terms) {
+  if (!c || !H || !rho_out || !log_norm) return XTRG_EINVAL;
+  *rho_out = nullptr;
+  return guarded(c, [&] {
+    set_device(c);
+    int nt = 0;
+    *rho_out = xtrg_impl::settn_init(c, H, tau0, D_max, n_sweeps, tol, log_norm, &nt).release();
+    if (n_terms) *n_terms = nt;
   });
 }
 

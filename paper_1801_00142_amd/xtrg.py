@@ -101,6 +101,7 @@ def load_library(path: Optional[str] = None):
         "xtrg_serve_submit": (C.c_int, [vp, C.c_char_p, C.POINTER(C.c_ulonglong)]),
         "xtrg_serve_poll": (C.c_int, [vp, C.c_ulonglong, C.c_char_p, C.c_size_t]),
         "xtrg_serve_set_lanes": (C.c_int, [vp, C.c_int]),
+        "xtrg_settn_init": (C.c_int, [vp, vp, C.c_double, C.c_int, C.c_int, C.c_double, C.POINTER(vp), dp, ip]),
         "xtrg_profile_enable": (C.c_int, [vp, C.c_int]),
         "xtrg_profile_report": (C.c_int, [vp, C.c_char_p, C.c_size_t]),
     }
@@ -116,7 +117,7 @@ def exported_symbols() -> List[str]:
     return ["xtrg_ctx_create", "xtrg_ctx_destroy", "xtrg_last_error", "xtrg_ctx_bytes", "xtrg_ctx_trim",
             "xtrg_hamiltonian_xxz", "xtrg_mpo_from_host", "xtrg_mpo_shape", "xtrg_mpo_to_host",
             "xtrg_mpo_destroy", "xtrg_init_rho", "xtrg_square_compress", "xtrg_product_compress", "xtrg_square_compress_batched", "xtrg_observables",
-            "xtrg_dgemm", "xtrg_dgemm_noalloc", "xtrg_sgemm", "xtrg_gemm_bf16x3", "xtrg_dsvd_left", "xtrg_dsvd_left_qr", "xtrg_dqrcp", "xtrg_spin_sum_mpo", "xtrg_correlation_mpo", "xtrg_expectation", "xtrg_serve_submit", "xtrg_serve_poll", "xtrg_serve_set_lanes", "xtrg_profile_enable",
+            "xtrg_dgemm", "xtrg_dgemm_noalloc", "xtrg_sgemm", "xtrg_gemm_bf16x3", "xtrg_dsvd_left", "xtrg_dsvd_left_qr", "xtrg_dqrcp", "xtrg_spin_sum_mpo", "xtrg_correlation_mpo", "xtrg_expectation", "xtrg_serve_submit", "xtrg_serve_poll", "xtrg_serve_set_lanes", "xtrg_settn_init", "xtrg_profile_enable",
             "xtrg_profile_report"]
 
 
@@ -225,6 +226,16 @@ class Context:
         lam = C.c_double()
         _check(self, _lib.xtrg_init_rho(self.h, H.h, tau0, order, D0_max, C.byref(h), C.byref(lam)))
         return MPO(self, h), lam.value
+
+    def settn_init(self, H: MPO, tau0: float, D_max: int, n_sweeps: int = 2, tol: float = 1e-15):
+        """rho(tau0) by the series expansion with automatic cutoff order:
+        (rho_hat, log_norm, cutoff order)."""
+        h = C.c_void_p()
+        lam = C.c_double()
+        nt = C.c_int()
+        _check(self, _lib.xtrg_settn_init(self.h, H.h, tau0, D_max, n_sweeps, tol, C.byref(h), C.byref(lam),
+                                          C.byref(nt)))
+        return MPO(self, h), lam.value, nt.value
 
     def square_compress(self, rho: MPO, D_max: int, n_sweeps: int = 4, degen_rtol: float = 1e-6,
                         sv_floor: float = 1e-14, sv_stride: int = 0, precision: int = XTRG_FP64,
