@@ -206,6 +206,7 @@ struct Request {
   std::vector<int> bonds;
   std::vector<double> jxy, jz;
   double tau0 = 0.0, beta_mix = 1.0;
+  double series_tol = 0.0;   // > 0: the series start to this expansion error instead of order 1 / 2
   int n_doublings = 0, D = 0, n_sweeps = 2, order = 1, precision = XTRG_FP64;
   // state
   bool done = false;       // visible to poll (set under the server lock)
@@ -356,7 +357,12 @@ struct Server {
     r.t_admit = Clock::now();
     try {
       r.H = xtrg_impl::hamiltonian(ln.c, r.n_sites, (int)r.jxy.size(), r.bonds.data(), r.jxy.data(), r.jz.data());
-      r.rho = xtrg_impl::init_rho(ln.c, r.H.get(), r.tau0, r.order, 0, &r.lam);
+      if (r.series_tol > 0) {
+        int nt = 0;
+        r.rho = xtrg_impl::settn_init(ln.c, r.H.get(), r.tau0, r.D, 2, r.series_tol, &r.lam, &nt);
+      } else {
+        r.rho = xtrg_impl::init_rho(ln.c, r.H.get(), r.tau0, r.order, 0, &r.lam);
+      }
       r.tau = r.tau0;
       record(ln, r, nullptr);
     } catch (const Error& e) {
@@ -582,6 +588,7 @@ int xtrg_serve_submit(xtrg_ctx c, const char* request_json, unsigned long long* 
     r->n_sweeps = xtrg::int_field(v, "n_sweeps", 2);
     r->order = xtrg::int_field(v, "order", 1);
     r->beta_mix = xtrg::num_field(v, "beta_mix", 1.0);
+    r->series_tol = xtrg::num_field(v, "series_tol", 0.0);
     if (const xtrg::JVal* pv = v.get("precision")) {
       if (pv->kind != xtrg::JVal::STR) throw Error(XTRG_EINVAL, "request: precision is fp64, fp32 or bf16x3");
       if (pv->str == "fp64") r->precision = XTRG_FP64;
@@ -615,7 +622,7 @@ int xtrg_serve_submit(xtrg_ctx c, const char* request_json, unsigned long long* 
     couplings("jxy", r->jxy);
     couplings("jz", r->jz);
     if (r->n_sites < 2 || !(r->tau0 > 0) || r->n_doublings < 0 || r->D < 1 || r->n_sweeps < 1 || r->order < 1 ||
-        r->order > 2)
+        r->order > 2 || !(r->series_tol >= 0))
       throw Error(XTRG_EINVAL, "request: n_sites >= 2, tau0 > 0, n_doublings >= 0, D >= 1, n_sweeps >= 1, order 1 or 2");
     for (int b : r->bonds)
       if (b < 0 || b >= r->n_sites) throw Error(XTRG_EINVAL, "request: bond index out of range");

@@ -34,12 +34,16 @@ class Solve:
     order: int = 1
     precision: int = 0          # XTRG_FP64, XTRG_FP32 or XTRG_BF16X3
     beta_mix: float = 1.0
+    series_tol: float = 0.0     # > 0: the series start (xtrg_settn_init) to this expansion error
 
     def request(self) -> dict:
-        return dict(n_sites=self.n_sites, bonds=[list(b) for b in self.bonds], jxy=list(self.jxy),
-                    jz=list(self.jz), tau0=self.tau0, n_doublings=self.n_doublings, D=self.D,
-                    n_sweeps=self.n_sweeps, order=self.order, precision=_PREC[self.precision],
-                    beta_mix=self.beta_mix)
+        r = dict(n_sites=self.n_sites, bonds=[list(b) for b in self.bonds], jxy=list(self.jxy),
+                 jz=list(self.jz), tau0=self.tau0, n_doublings=self.n_doublings, D=self.D,
+                 n_sweeps=self.n_sweeps, order=self.order, precision=_PREC[self.precision],
+                 beta_mix=self.beta_mix)
+        if self.series_tol > 0:
+            r["series_tol"] = self.series_tol
+        return r
 
 
 def footprint_bytes(n_sites: int, D: int) -> int:

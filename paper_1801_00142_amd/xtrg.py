@@ -450,16 +450,23 @@ class Context:
 
 def run(ctx: Context, n_sites: int, bonds, jxy, jz, tau0: float, n_doublings: int, D: int, order: int = 1,
         n_sweeps: int = 4, degen_rtol: float = 1e-6, sv_floor: float = 1e-14, observe: bool = True,
-        entropy: bool = False, precision: int = XTRG_FP64, beta_mix: float = 1.0):
+        entropy: bool = False, precision: int = XTRG_FP64, beta_mix: float = 1.0, series_tol: float = 0.0):
     """Full XTRG run through the library: rho(tau0), then n_doublings doublings;
     returns per-doubling records (observables at beta = tau_n and 2 tau_n).
+
+    rho(tau0) is the fixed-order start of xtrg_init_rho (order 1 or 2), or,
+    with series_tol > 0, the series start of xtrg_settn_init to an expansion
+    error below series_tol (bond <= D), which permits a larger tau0.
 
     precision != XTRG_FP64 applies from the doubling whose result reaches
     beta = 2 tau_{n+1} >= beta_mix; earlier doublings run in FP64.  The
     relative error a doubling leaves in ln Z enters f = -ln Z/(N beta) divided
     by beta, so the high-temperature doublings need the most precision."""
     H = ctx.hamiltonian_xxz(n_sites, bonds, jxy, jz)
-    rho, lam = ctx.init_rho(H, tau0, order)
+    if series_tol > 0:
+        rho, lam, _ = ctx.settn_init(H, tau0, D, 2, series_tol)
+    else:
+        rho, lam = ctx.init_rho(H, tau0, order)
     tau = tau0
     recs = []
 
