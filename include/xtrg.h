@@ -116,7 +116,9 @@ int xtrg_init_rho(xtrg_ctx ctx, xtrg_mpo H, double tau0, int order, int D0_max,
  * xtrg_hamiltonian_xxz or xtrg_mpo_from_host); at most 80 orders.
  * Result: right-canonical and normalised, rho(tau0) = exp(*log_norm) *
  * rho_out; n_terms (may be NULL) receives the cutoff order.
- * Errors: XTRG_EINVAL for tau0 <= 0, D_max < 1, n_sweeps < 1 or tol <= 0. */
+ * The exact sum's bond (the sum of the terms' bonds) is limited to 4096.
+ * Errors: XTRG_EINVAL for tau0 <= 0, D_max < 1, n_sweeps < 1, tol <= 0, or
+ * a sum beyond that bond. */
 int xtrg_settn_init(xtrg_ctx ctx, xtrg_mpo H, double tau0, int D_max, int n_sweeps, double tol,
                     xtrg_mpo* rho_out, double* log_norm, int* n_terms);
 

@@ -1778,6 +1778,13 @@ std::unique_ptr<xtrg_mpo_s> settn_init(xtrg_ctx c, xtrg_mpo H, double tau0, int 
       off[t][b] = dims[b];
       dims[b] += terms[t]->dims[b];
     }
+  // the left sweep below factorises (4 Dl) x Dr site matrices, Dr a bond of
+  // the exact sum: at most 4096 columns
+  for (int b = 1; b < L; ++b)
+    if (dims[b] > 4096)
+      throw Error(XTRG_EINVAL, "settn_init: the exact sum of the " + std::to_string(terms.size()) +
+                                   " terms has bond " + std::to_string(dims[b]) +
+                                   " > 4096 (lower D_max or tau0)");
   auto S = new_mpo(c, dims);
   for (int i = 0; i < L; ++i) xtrg::fill(S->site[i].p, 0.0, S->elems(i), s);
   for (size_t t = 0; t < terms.size(); ++t) {

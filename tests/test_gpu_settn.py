@@ -124,3 +124,8 @@ def test_series_start_rejects_bad_arguments(ctx):
             ctx.settn_init(H, *args)
     with pytest.raises(XtrgError):
         ctx.settn_init(H, 0.1, 8, tol=0.0)
+    # L = 8 at tau0 = 1: 28 terms of centre bond up to 256, an exact sum of
+    # centre bond ~5400, beyond the 4096 columns the sweeps take: rejected
+    H8 = _h(ctx, W.chain(8))
+    with pytest.raises(XtrgError, match="exact sum"):
+        ctx.settn_init(H8, 1.0, 256)
