@@ -110,15 +110,14 @@ int xtrg_init_rho(xtrg_ctx ctx, xtrg_mpo H, double tau0, int order, int D0_max,
  * below tol.  The powers H^k = H (H^(k-1)) are compressed products (the
  * sweeps of xtrg_product_compress at bond <= D_max with n_sweeps sweeps,
  * starting from H itself), each kept normalised with its log-norm; the
- * terms are then summed exactly and the sum compressed by SVD sweeps to
- * bond <= D_max with the keep rule of the doublings (App. D.1 direct
- * route, App. D.2 Eq. MPO:plus).  H is any MPO (from
- * xtrg_hamiltonian_xxz or xtrg_mpo_from_host); at most 80 orders.
+ * terms are then added one at a time, each exact sum of two MPOs
+ * compressed by SVD sweeps to bond <= D_max with the keep rule of the
+ * doublings (App. D.1 direct route, App. D.2 Eq. MPO:plus).  H is any MPO
+ * (from xtrg_hamiltonian_xxz or xtrg_mpo_from_host); at most 80 orders.
  * Result: right-canonical and normalised, rho(tau0) = exp(*log_norm) *
  * rho_out; n_terms (may be NULL) receives the cutoff order.
- * The exact sum's bond (the sum of the terms' bonds) is limited to 4096.
- * Errors: XTRG_EINVAL for tau0 <= 0, D_max < 1, n_sweeps < 1, tol <= 0, or
- * a sum beyond that bond. */
+ * Errors: XTRG_EINVAL for tau0 <= 0, D_max < 1, n_sweeps < 1 or tol <= 0,
+ * or a two-term sum beyond bond 4096 (D_max above 2048). */
 int xtrg_settn_init(xtrg_ctx ctx, xtrg_mpo H, double tau0, int D_max, int n_sweeps, double tol,
                     xtrg_mpo* rho_out, double* log_norm, int* n_terms);
 

@@ -129,18 +129,10 @@ def identity(n: int) -> List[np.ndarray]:
     return [(np.eye(2) / math.sqrt(2.0)).reshape(1, 2, 2, 1) for _ in range(n)]
 
 
-def sum_compress(terms: Sequence[List[np.ndarray]], coefs: Sequence[float], D: int,
-                 deg_rtol: float = 1e-6, sv_floor: float = 1e-14) -> List[np.ndarray]:
-    """sum_k coefs[k] * terms[k] as one MPO of bond <= D: the exact sum
-    (block-diagonal bonds, App. D.2 Eq. MPO:plus) compressed by the direct
-    route of App. D.1 (left-canonicalise, then a right-to-left SVD sweep),
-    each bond cut by the keep rule of the doublings (keep_count: at most D
-    values, multiplet-safe, numerically zero values dropped)."""
-    S = None
-    for W, a in zip(terms, coefs):
-        X = [w.copy() for w in W]
-        X[0] = X[0] * a
-        S = X if S is None else M.mpo_sum(S, X)
+def _compress_direct(S: List[np.ndarray], D: int, deg_rtol: float, sv_floor: float) -> List[np.ndarray]:
+    """The direct route of App. D.1: left-canonicalise, then a right-to-left
+    SVD sweep, each bond cut by the keep rule of the doublings (keep_count:
+    at most D values, multiplet-safe, numerically zero values dropped)."""
     W = M.left_canonicalize(S)
     for i in range(len(W) - 1, 0, -1):
         Dl, d1, d2, Dr = W[i].shape
@@ -150,6 +142,21 @@ def sum_compress(terms: Sequence[List[np.ndarray]], coefs: Sequence[float], D: i
         W[i] = Vt[:k].reshape(k, d1, d2, Dr)
         W[i - 1] = np.einsum("astb,bk->astk", W[i - 1], U[:, :k] * Sv[:k])
     return W
+
+
+def sum_compress(terms: Sequence[List[np.ndarray]], coefs: Sequence[float], D: int,
+                 deg_rtol: float = 1e-6, sv_floor: float = 1e-14) -> List[np.ndarray]:
+    """sum_k coefs[k] * terms[k] as one MPO of bond <= D, added one term at a
+    time: S <- compress(S + coefs[k] terms[k]), each exact sum of two MPOs
+    (block-diagonal bonds, App. D.2 Eq. MPO:plus) compressed by the direct
+    route (_compress_direct).  Exact when nothing is cut; the exact sums
+    stay at bond <= D + bond(terms[k])."""
+    S = None
+    for W, a in zip(terms, coefs):
+        X = [w.copy() for w in W]
+        X[0] = X[0] * a
+        S = _compress_direct(X if S is None else M.mpo_sum(S, X), D, deg_rtol, sv_floor)
+    return S
 
 
 def settn_init(H: List[np.ndarray], tau0: float, D: int, n_sweeps: int = 2, tol: float = 1e-15,
@@ -168,10 +175,10 @@ def settn_init(H: List[np.ndarray], tau0: float, D: int, n_sweeps: int = 2, tol:
     omega_k H^k = omega_k e^(l_k) Hhat_k with omega_k = (-tau0)^k / k!.  The
     expansion stops at the first order N_c whose term is below tol relative
     to the identity term, |omega_k| e^(l_k - l_0) <= tol (an expansion error
-    below 1e-15, as the paper asks; l_0 = ln ||I||_F).  The sum of the
-    N_c + 1 terms is compressed by sum_compress.  Returns (rhohat, lambda_0,
-    N_c) with rho(tau0) = e^(lambda_0) rhohat, ||rhohat||_F = 1 and rhohat
-    right-canonical."""
+    below 1e-15, as the paper asks; l_0 = ln ||I||_F).  The N_c + 1 terms
+    are summed by sum_compress (one term at a time).  Returns (rhohat,
+    lambda_0, N_c) with rho(tau0) = e^(lambda_0) rhohat, ||rhohat||_F = 1 and
+    rhohat right-canonical."""
     n = len(H)
     l0 = 0.5 * n * math.log(2.0)
     terms, coefs = [identity(n)], [1.0]

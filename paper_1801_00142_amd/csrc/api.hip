@@ -1704,6 +1704,38 @@ std::unique_ptr<xtrg_mpo_s> init_rho(xtrg_ctx c, xtrg_mpo H, double tau0, int or
   return fin;
 }
 
+// The exact sum of MPOs of one length (App. D.2, Eq. MPO:plus): site 0
+// concatenates the terms' columns, the last site their rows, the sites
+// between are block diagonal.  The bonds add up; the site matrices the SVD
+// sweeps factorise afterwards must stay within 4096 columns.
+std::unique_ptr<xtrg_mpo_s> block_sum(xtrg_ctx c, const std::vector<xtrg_mpo>& terms) {
+  hipStream_t s = c->stream;
+  const int L = terms[0]->L;
+  std::vector<int> dims(L + 1, 0);
+  dims[0] = dims[L] = 1;
+  std::vector<std::vector<int>> off(terms.size(), std::vector<int>(L + 1, 0));
+  for (size_t t = 0; t < terms.size(); ++t)
+    for (int b = 1; b < L; ++b) {
+      off[t][b] = dims[b];
+      dims[b] += terms[t]->dims[b];
+    }
+  for (int b = 1; b < L; ++b)
+    if (dims[b] > 4096)
+      throw Error(XTRG_EINVAL, "MPO sum: bond " + std::to_string(dims[b]) + " > 4096 (lower the bond budget)");
+  auto S = new_mpo(c, dims);
+  for (int i = 0; i < L; ++i) xtrg::fill(S->site[i].p, 0.0, S->elems(i), s);
+  for (size_t t = 0; t < terms.size(); ++t) {
+    xtrg_mpo T = terms[t];
+    for (int i = 0; i < L; ++i) {
+      const int Dl = T->dims[i], Dr = T->dims[i + 1], Drs = dims[i + 1];
+      double* dst = S->site[i].p + (size_t)off[t][i] * 4 * Drs + off[t][i + 1];
+      XTRG_HIP(hipMemcpy2DAsync(dst, (size_t)Drs * sizeof(double), T->site[i].p, (size_t)Dr * sizeof(double),
+                                (size_t)Dr * sizeof(double), (size_t)Dl * 4, hipMemcpyDeviceToDevice, s));
+    }
+  }
+  return S;
+}
+
 // The series start of Sec. II.C, Eq. (RhoTau): rho(tau0) = sum_k omega_k H^k,
 // omega_k = (-tau0)^k / k!, with the cutoff order chosen by the expansion
 // error.  H^k = H (H^(k-1)) by the compressed product of App. D.1 (the
@@ -1713,11 +1745,11 @@ std::unique_ptr<xtrg_mpo_s> init_rho(xtrg_ctx c, xtrg_mpo H, double tau0, int or
 // parts of H that project onto the identity elsewhere, and the traceless
 // couplings project to zero).  Every term is kept normalised with its
 // log-norm; the expansion stops at the first order whose term, relative to
-// the identity term, is at most tol.  The terms are summed exactly
-// (block-diagonal bonds, App. D.2 Eq. MPO:plus) and the sum compressed by
-// the direct route of App. D.1: a left-to-right SVD sweep that drops the
+// the identity term, is at most tol.  The terms are added one at a time,
+// each exact sum of two MPOs (App. D.2 Eq. MPO:plus) compressed by the
+// direct route of App. D.1: a left-to-right SVD sweep that drops the
 // numerical zeros, then a right-to-left sweep with the keep rule of the
-// doublings.
+// doublings (exact when nothing is cut; the sums stay at bond <= 2 D).
 std::unique_ptr<xtrg_mpo_s> settn_init(xtrg_ctx c, xtrg_mpo H, double tau0, int D, int n_sweeps, double tol,
                                        double* log_norm, int* n_terms) {
   constexpr int kMaxOrder = 80;
@@ -1767,39 +1799,17 @@ std::unique_ptr<xtrg_mpo_s> settn_init(xtrg_ctx c, xtrg_mpo H, double tau0, int 
     nc = k;
     if (std::fabs(a) <= tol) break;
   }
-  // the exact sum: site 0 concatenates the terms' columns (scaled by their
-  // coefficients), the last site their rows, the sites between are block
-  // diagonal
-  std::vector<int> dims(L + 1, 0);
-  dims[0] = dims[L] = 1;
-  std::vector<std::vector<int>> off(terms.size(), std::vector<int>(L + 1, 0));
-  for (size_t t = 0; t < terms.size(); ++t)
-    for (int b = 1; b < L; ++b) {
-      off[t][b] = dims[b];
-      dims[b] += terms[t]->dims[b];
-    }
-  // the left sweep below factorises (4 Dl) x Dr site matrices, Dr a bond of
-  // the exact sum: at most 4096 columns
-  for (int b = 1; b < L; ++b)
-    if (dims[b] > 4096)
-      throw Error(XTRG_EINVAL, "settn_init: the exact sum of the " + std::to_string(terms.size()) +
-                                   " terms has bond " + std::to_string(dims[b]) +
-                                   " > 4096 (lower D_max or tau0)");
-  auto S = new_mpo(c, dims);
-  for (int i = 0; i < L; ++i) xtrg::fill(S->site[i].p, 0.0, S->elems(i), s);
-  for (size_t t = 0; t < terms.size(); ++t) {
-    xtrg_mpo T = terms[t].get();
-    xtrg::scale(T->site[0].p, coef[t], T->elems(0), s);
-    for (int i = 0; i < L; ++i) {
-      const int Dl = T->dims[i], Dr = T->dims[i + 1], Drs = dims[i + 1];
-      double* dst = S->site[i].p + (size_t)off[t][i] * 4 * Drs + off[t][i + 1];
-      XTRG_HIP(hipMemcpy2DAsync(dst, (size_t)Drs * sizeof(double), T->site[i].p, (size_t)Dr * sizeof(double),
-                                (size_t)Dr * sizeof(double), (size_t)Dl * 4, hipMemcpyDeviceToDevice, s));
-    }
+  // the sum, one term at a time: S <- compress(S + a_k T_k), each exact sum
+  // of two MPOs compressed by the direct route
+  for (size_t t = 0; t < terms.size(); ++t) xtrg::scale(terms[t]->site[0].p, coef[t], terms[t]->elems(0), s);
+  std::unique_ptr<xtrg_mpo_s> S = std::move(terms[0]);
+  for (size_t t = 1; t < terms.size(); ++t) {
+    S = block_sum(c, {S.get(), terms[t].get()});
+    terms[t].reset();
+    left_sweep(S.get(), 1e-14, nullptr);
+    right_sweep(S.get(), 1e-14, D, nullptr, 1e-6);
   }
   terms.clear();
-  left_sweep(S.get(), 1e-14, nullptr);
-  right_sweep(S.get(), 1e-14, D, nullptr, 1e-6);
   const double nrm = site_norm(S.get(), 0);
   if (!(nrm > 0) || !std::isfinite(nrm)) throw Error(XTRG_ENUMERIC, "settn_init: the series has zero norm");
   xtrg::scale(S->site[0].p, 1.0 / nrm, S->elems(0), s);

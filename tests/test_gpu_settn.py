@@ -68,8 +68,13 @@ def test_truncated_series_start_matches_oracle(ctx, D):
 
 def test_doublings_from_the_series_start_match_ed(ctx):
     """XTRG through the library from the series start at tau0 = 1/8: five
-    untruncated doublings of the L = 8 chain, f within 1e-12 of exact
-    diagonalisation at both estimators of every doubling."""
+    untruncated doublings of the L = 8 chain, f within 5e-12 of exact
+    diagonalisation at both estimators of every doubling.  The bound: the
+    ~10 terms are added one at a time and every partial sum is compressed,
+    each time to the FP64 noise floor (~1e-13 of the sum), so rho(tau0)
+    carries ~1e-12; an error delta in rho(tau0) reaches f = -ln Z/(N beta)
+    as about delta / (N tau0) at every doubling (Z ~ rho(tau0)^(2^n)),
+    i.e. ~1e-12 here (measured 1.6e-12)."""
     lat = W.chain(8)
     H = _h(ctx, lat)
     E = np.linalg.eigvalsh(M.to_dense(M.hamiltonian(lat.n_sites, lat.bonds, lat.jxy, lat.jz)))
@@ -90,14 +95,14 @@ def test_doublings_from_the_series_start_match_ed(ctx):
         obs = ctx.observables(rho, lam, tau, H, n, entropy=False)
         for beta, key in ((tau, "tau"), (2 * tau, "2tau")):
             ref = f_ed(beta)
-            assert abs(obs[key]["f"] - ref) < 1e-12 * abs(ref), (tau, key)
+            assert abs(obs[key]["f"] - ref) < 5e-12 * abs(ref), (tau, key)
 
 
 def test_series_start_in_run_and_serving(ctx):
     """run(..., series_tol) and a served request with "series_tol" start from
     the same rho(tau0) and give the same records bit for bit; f matches ED
-    at tau0 = 1/4 after four doublings (the linear start would be off by
-    its tau0^2 error)."""
+    to 5e-12 at tau0 = 1/4 after four doublings (the bound of the test
+    above; the linear start would be off by its tau0^2 error)."""
     from paper_1801_00142_amd import Context, run
     from paper_1801_00142_amd.serve import Server, Solve
     lat = W.chain(8)
@@ -113,7 +118,7 @@ def test_series_start_in_run_and_serving(ctx):
     e0 = E.min()
     beta = 2 * recs[-1]["tau"]
     ref = (e0 - math.log(np.sum(np.exp(-beta * (E - e0)))) / beta) / lat.n_sites
-    assert abs(recs[-1]["obs"]["2tau"]["f"] - ref) < 1e-12 * abs(ref)
+    assert abs(recs[-1]["obs"]["2tau"]["f"] - ref) < 5e-12 * abs(ref)
 
 
 def test_series_start_rejects_bad_arguments(ctx):
@@ -124,8 +129,9 @@ def test_series_start_rejects_bad_arguments(ctx):
             ctx.settn_init(H, *args)
     with pytest.raises(XtrgError):
         ctx.settn_init(H, 0.1, 8, tol=0.0)
-    # L = 8 at tau0 = 1: 28 terms of centre bond up to 256, an exact sum of
-    # centre bond ~5400, beyond the 4096 columns the sweeps take: rejected
+    # a large tau0 with many orders: the terms are added one at a time, so
+    # the sums stay within the sweeps' limits (L = 8, tau0 = 1, 28 orders
+    # of centre bond up to 256 would be a one-shot sum of bond ~5400)
     H8 = _h(ctx, W.chain(8))
-    with pytest.raises(XtrgError, match="exact sum"):
-        ctx.settn_init(H8, 1.0, 256)
+    rho, lam, nc = ctx.settn_init(H8, 1.0, 256)
+    assert nc > 20 and max(rho.bond_dims) <= 256
