@@ -121,6 +121,20 @@ int xtrg_init_rho(xtrg_ctx ctx, xtrg_mpo H, double tau0, int order, int D0_max,
 int xtrg_settn_init(xtrg_ctx ctx, xtrg_mpo H, double tau0, int D_max, int n_sweeps, double tol,
                     xtrg_mpo* rho_out, double* log_norm, int* n_terms);
 
+/* One pointwise expansion step of Sec. II.C, Eq. (Tay):
+ * rho(tau + dtau) = sum_k (-dtau)^k/k! H^k rho(tau), with the terms
+ * H^k rho = H (H^(k-1) rho) built and summed as in xtrg_settn_init, up to
+ * the first order whose term is at most tol relative to rho (the series
+ * start is this step from rho = I, tau = 0).  rho must be normalised and
+ * right-canonical (every output of this library is); the result is too:
+ * rho(tau + dtau) = exp(lambda + *dlog_norm) * rho_out for
+ * rho(tau) = exp(lambda) * rho.  Steps on the exponential grid
+ * (dtau = tau) reach the same temperatures as the doublings.
+ * Errors: XTRG_EINVAL for a non-finite dtau, D_max < 1, n_sweeps < 1,
+ * tol <= 0, or H and rho of different lengths. */
+int xtrg_taylor_step(xtrg_ctx ctx, xtrg_mpo H, xtrg_mpo rho, double dtau, int D_max, int n_sweeps, double tol,
+                     xtrg_mpo* rho_out, double* dlog_norm, int* n_terms);
+
 /* Options of one doubling. */
 typedef struct {
   int D_max;         /* bond dimension budget D (> 0) */

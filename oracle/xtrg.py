@@ -205,6 +205,37 @@ def settn_init(H: List[np.ndarray], tau0: float, D: int, n_sweeps: int = 2, tol:
     return W, l0 + math.log(nrm), nc
 
 
+def taylor_step(H: List[np.ndarray], rho: List[np.ndarray], dtau: float, D: int, n_sweeps: int = 2,
+                tol: float = 1e-15, k_max: int = 80, deg_rtol: float = 1e-6, sv_floor: float = 1e-14, svd=None):
+    """One pointwise expansion step, Sec. II.C Eq. (Tay):
+    rho(tau + dtau) = sum_k (-dtau)^k / k! H^k rho(tau), for the normalised
+    right-canonical rhohat of rho(tau).  The terms H^k rhohat = H (H^(k-1)
+    rhohat) are compressed products (product_compress, the previous term as
+    B and initial guess), each normalised with its log-norm; the expansion
+    stops at the first order whose term is at most tol relative to the
+    k = 0 term (rhohat, norm 1), and the terms are added one at a time by
+    sum_compress.  Returns (rhohat', dlog, N_c) with
+    rho(tau + dtau) = e^(lambda + dlog) rhohat' for rho(tau) = e^lambda rhohat."""
+    terms, coefs = [[w.copy() for w in rho]], [1.0]
+    P, l = terms[0], 0.0
+    omega = 1.0
+    nc = 0
+    for k in range(1, k_max + 1):
+        P, info = product_compress(H, P, D, n_sweeps, deg_rtol, sv_floor, svd=svd)
+        l += info.dlog_norm
+        omega *= -dtau / k
+        a = omega * math.exp(l)
+        terms.append(P)
+        coefs.append(a)
+        nc = k
+        if abs(a) <= tol:
+            break
+    W = sum_compress(terms, coefs, D, deg_rtol, sv_floor)
+    nrm = float(np.linalg.norm(W[0]))
+    W[0] = W[0] / nrm
+    return W, math.log(nrm), nc
+
+
 # --------------------------------------------------------------------------
 # Environments (Fig. VMPO(a), (c))
 # --------------------------------------------------------------------------

@@ -1736,54 +1736,42 @@ std::unique_ptr<xtrg_mpo_s> block_sum(xtrg_ctx c, const std::vector<xtrg_mpo>& t
   return S;
 }
 
-// The series start of Sec. II.C, Eq. (RhoTau): rho(tau0) = sum_k omega_k H^k,
-// omega_k = (-tau0)^k / k!, with the cutoff order chosen by the expansion
-// error.  H^k = H (H^(k-1)) by the compressed product of App. D.1 (the
-// doubling's sweeps with A = H and the previous term as B and initial
-// guess); the recursion starts from H itself, compressed without loss (from
-// the bond-1 identity as the initial guess the sweeps would see only the
-// parts of H that project onto the identity elsewhere, and the traceless
-// couplings project to zero).  Every term is kept normalised with its
-// log-norm; the expansion stops at the first order whose term, relative to
-// the identity term, is at most tol.  The terms are added one at a time,
-// each exact sum of two MPOs (App. D.2 Eq. MPO:plus) compressed by the
-// direct route of App. D.1: a left-to-right SVD sweep that drops the
+// sum_{k=0}^{N_c} x^k / k! H^k X for a normalised, right-canonical X, the
+// series of Sec. II.C (Eq. RhoTau for X = I, Eq. Tay for X = rho_n with
+// x = tau_n - tau_{n+1}).  H^k X = H (H^(k-1) X) by the compressed product
+// of App. D.1 (the doubling's sweeps with A = H and the previous term as B
+// and initial guess); HX, if given, is the first term already (normalised,
+// log-norm l_hx relative to X).  Every term is kept normalised with its
+// log-norm l_k; the expansion stops at the first order whose term,
+// |x^k / k!| e^(l_k), is at most tol relative to X.  The terms are added one
+// at a time, each exact sum of two MPOs (App. D.2 Eq. MPO:plus) compressed
+// by the direct route of App. D.1: a left-to-right SVD sweep that drops the
 // numerical zeros, then a right-to-left sweep with the keep rule of the
 // doublings (exact when nothing is cut; the sums stay at bond <= 2 D).
-std::unique_ptr<xtrg_mpo_s> settn_init(xtrg_ctx c, xtrg_mpo H, double tau0, int D, int n_sweeps, double tol,
-                                       double* log_norm, int* n_terms) {
+// Returns the normalised sum and, in *dlog, the log of its norm.
+std::unique_ptr<xtrg_mpo_s> expand_series(xtrg_ctx c, xtrg_mpo H, std::unique_ptr<xtrg_mpo_s> X,
+                                          std::unique_ptr<xtrg_mpo_s> HX, double l_hx, double x, int D,
+                                          int n_sweeps, double tol, double* dlog, int* n_terms) {
   constexpr int kMaxOrder = 80;
-  if (!(tau0 > 0) || !std::isfinite(tau0) || D < 1 || n_sweeps < 1 || !(tol > 0))
-    throw Error(XTRG_EINVAL, "settn_init: tau0 > 0, D >= 1, n_sweeps >= 1, tol > 0");
   hipStream_t s = c->stream;
-  const int L = H->L;
-  const double l0 = 0.5 * L * std::log(2.0);            // ln ||I||_F
   std::vector<std::unique_ptr<xtrg_mpo_s>> terms;
   std::vector<double> coef;
-  {
-    auto I = new_mpo(c, std::vector<int>(L + 1, 1));  // I / sqrt(2) on every site: norm 1, right-canonical
-    const double v[4] = {std::sqrt(0.5), 0.0, 0.0, std::sqrt(0.5)};
-    for (int i = 0; i < L; ++i) upload(c, I->site[i].p, v, 4);
-    terms.push_back(std::move(I));
-    coef.push_back(1.0);
-  }
-  auto P = clone(H);
-  left_sweep(P.get(), 1e-14, nullptr);
-  right_sweep(P.get(), 1e-14, 0, nullptr);
-  const double h = site_norm(P.get(), 0);
-  if (!(h > 0) || !std::isfinite(h)) throw Error(XTRG_ENUMERIC, "settn_init: ||H|| is zero or not finite");
-  xtrg::scale(P->site[0].p, 1.0 / h, P->elems(0), s);
-  double l = std::log(h);
+  terms.push_back(std::move(X));
+  coef.push_back(1.0);
   xtrg_compress_opts o{};
   o.D_max = D;
   o.n_sweeps = n_sweeps;
   o.precision = XTRG_FP64;
   o.degen_rtol = 1e-6;
   o.sv_floor = 1e-14;
-  double omega = 1.0;
+  double l = 0.0, omega = 1.0;
   int nc = 0;
   for (int k = 1; k <= kMaxOrder; ++k) {
-    if (k > 1) {
+    std::unique_ptr<xtrg_mpo_s> P;
+    if (k == 1 && HX) {
+      P = std::move(HX);
+      l = l_hx;
+    } else {
       xtrg_mpo A = H, B = terms.back().get();
       xtrg_mpo out = nullptr;
       xtrg_compress_info info{};
@@ -1792,16 +1780,15 @@ std::unique_ptr<xtrg_mpo_s> settn_init(xtrg_ctx c, xtrg_mpo H, double tau0, int 
       P.reset(out);
       l += info.dlog_norm;
     }
-    omega *= -tau0 / k;
-    const double a = omega * std::exp(l - l0);
+    omega *= x / k;
+    const double a = omega * std::exp(l);
     terms.push_back(std::move(P));
     coef.push_back(a);
     nc = k;
     if (std::fabs(a) <= tol) break;
   }
-  // the sum, one term at a time: S <- compress(S + a_k T_k), each exact sum
-  // of two MPOs compressed by the direct route
-  for (size_t t = 0; t < terms.size(); ++t) xtrg::scale(terms[t]->site[0].p, coef[t], terms[t]->elems(0), s);
+  // the sum, one term at a time: S <- compress(S + a_k T_k)
+  for (size_t t = 1; t < terms.size(); ++t) xtrg::scale(terms[t]->site[0].p, coef[t], terms[t]->elems(0), s);
   std::unique_ptr<xtrg_mpo_s> S = std::move(terms[0]);
   for (size_t t = 1; t < terms.size(); ++t) {
     S = block_sum(c, {S.get(), terms[t].get()});
@@ -1811,13 +1798,52 @@ std::unique_ptr<xtrg_mpo_s> settn_init(xtrg_ctx c, xtrg_mpo H, double tau0, int 
   }
   terms.clear();
   const double nrm = site_norm(S.get(), 0);
-  if (!(nrm > 0) || !std::isfinite(nrm)) throw Error(XTRG_ENUMERIC, "settn_init: the series has zero norm");
+  if (!(nrm > 0) || !std::isfinite(nrm)) throw Error(XTRG_ENUMERIC, "series: the sum has zero norm");
   xtrg::scale(S->site[0].p, 1.0 / nrm, S->elems(0), s);
-  *log_norm = l0 + std::log(nrm);
+  *dlog = std::log(nrm);
   *n_terms = nc;
   auto fin = clone(S.get());
   XTRG_HIP(hipStreamSynchronize(s));
   return fin;
+}
+
+// The series start of Sec. II.C, Eq. (RhoTau): rho(tau0) = sum_k (-tau0)^k / k! H^k
+// with the cutoff order chosen by the expansion error (expand_series with
+// X = I / 2^(L/2)).  The first term is H itself, compressed without loss:
+// from the bond-1 identity as the initial guess the product's sweeps would
+// see only the parts of H that project onto the identity elsewhere, and
+// the traceless couplings project to zero.
+std::unique_ptr<xtrg_mpo_s> settn_init(xtrg_ctx c, xtrg_mpo H, double tau0, int D, int n_sweeps, double tol,
+                                       double* log_norm, int* n_terms) {
+  if (!(tau0 > 0) || !std::isfinite(tau0) || D < 1 || n_sweeps < 1 || !(tol > 0))
+    throw Error(XTRG_EINVAL, "settn_init: tau0 > 0, D >= 1, n_sweeps >= 1, tol > 0");
+  hipStream_t s = c->stream;
+  const int L = H->L;
+  const double l0 = 0.5 * L * std::log(2.0);            // ln ||I||_F
+  auto I = new_mpo(c, std::vector<int>(L + 1, 1));     // I / sqrt(2) on every site: norm 1, right-canonical
+  const double v[4] = {std::sqrt(0.5), 0.0, 0.0, std::sqrt(0.5)};
+  for (int i = 0; i < L; ++i) upload(c, I->site[i].p, v, 4);
+  auto P = clone(H);
+  left_sweep(P.get(), 1e-14, nullptr);
+  right_sweep(P.get(), 1e-14, 0, nullptr);
+  const double h = site_norm(P.get(), 0);
+  if (!(h > 0) || !std::isfinite(h)) throw Error(XTRG_ENUMERIC, "settn_init: ||H|| is zero or not finite");
+  xtrg::scale(P->site[0].p, 1.0 / h, P->elems(0), s);
+  double dl = 0.0;
+  auto out = expand_series(c, H, std::move(I), std::move(P), std::log(h) - l0, -tau0, D, n_sweeps, tol, &dl,
+                           n_terms);
+  *log_norm = l0 + dl;
+  return out;
+}
+
+// One step of Eq. (Tay): rho(tau + dtau) from the normalised, right-canonical
+// rho(tau) (expand_series with X = rho, x = -dtau).
+std::unique_ptr<xtrg_mpo_s> taylor_step(xtrg_ctx c, xtrg_mpo H, xtrg_mpo rho, double dtau, int D, int n_sweeps,
+                                        double tol, double* dlog, int* n_terms) {
+  if (!std::isfinite(dtau) || D < 1 || n_sweeps < 1 || !(tol > 0))
+    throw Error(XTRG_EINVAL, "taylor_step: finite dtau, D >= 1, n_sweeps >= 1, tol > 0");
+  if (H->L != rho->L) throw Error(XTRG_EINVAL, "taylor_step: H and rho differ in length");
+  return expand_series(c, H, clone(rho), nullptr, 0.0, -dtau, D, n_sweeps, tol, dlog, n_terms);
 }
 
 int square_compress(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_compress_opts* opts, xtrg_mpo* outs,
@@ -1969,6 +1995,18 @@ int xtrg_settn_init(xtrg_ctx c, xtrg_mpo H, double tau0, int D_max, int n_sweeps
     set_device(c);
     int nt = 0;
     *rho_out = xtrg_impl::settn_init(c, H, tau0, D_max, n_sweeps, tol, log_norm, &nt).release();
+    if (n_terms) *n_terms = nt;
+  });
+}
+
+int xtrg_taylor_step(xtrg_ctx c, xtrg_mpo H, xtrg_mpo rho, double dtau, int D_max, int n_sweeps, double tol,
+                     xtrg_mpo* rho_out, double* dlog_norm, int* n_terms) {
+  if (!c || !H || !rho || !rho_out || !dlog_norm) return XTRG_EINVAL;
+  *rho_out = nullptr;
+  return guarded(c, [&] {
+    set_device(c);
+    int nt = 0;
+    *rho_out = xtrg_impl::taylor_step(c, H, rho, dtau, D_max, n_sweeps, tol, dlog_norm, &nt).release();
     if (n_terms) *n_terms = nt;
   });
 }

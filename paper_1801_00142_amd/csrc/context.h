@@ -127,6 +127,8 @@ std::unique_ptr<xtrg_mpo_s> init_rho(xtrg_ctx c, xtrg_mpo H, double tau0, int or
                                      double* log_norm);
 std::unique_ptr<xtrg_mpo_s> settn_init(xtrg_ctx c, xtrg_mpo H, double tau0, int D, int n_sweeps, double tol,
                                        double* log_norm, int* n_terms);
+std::unique_ptr<xtrg_mpo_s> taylor_step(xtrg_ctx c, xtrg_mpo H, xtrg_mpo rho, double dtau, int D, int n_sweeps,
+                                        double tol, double* dlog, int* n_terms);
 // Returns the number of chains that stopped (their outs[q] = NULL, infos[q].status).
 int square_compress(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_compress_opts* opts, xtrg_mpo* outs,
                     xtrg_compress_info* infos, std::string* first_err);

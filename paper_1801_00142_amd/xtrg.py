@@ -102,6 +102,8 @@ def load_library(path: Optional[str] = None):
         "xtrg_serve_poll": (C.c_int, [vp, C.c_ulonglong, C.c_char_p, C.c_size_t]),
         "xtrg_serve_set_lanes": (C.c_int, [vp, C.c_int]),
         "xtrg_settn_init": (C.c_int, [vp, vp, C.c_double, C.c_int, C.c_int, C.c_double, C.POINTER(vp), dp, ip]),
+        "xtrg_taylor_step": (C.c_int, [vp, vp, vp, C.c_double, C.c_int, C.c_int, C.c_double, C.POINTER(vp), dp,
+                                       ip]),
         "xtrg_profile_enable": (C.c_int, [vp, C.c_int]),
         "xtrg_profile_report": (C.c_int, [vp, C.c_char_p, C.c_size_t]),
     }
@@ -117,7 +119,7 @@ def exported_symbols() -> List[str]:
     return ["xtrg_ctx_create", "xtrg_ctx_destroy", "xtrg_last_error", "xtrg_ctx_bytes", "xtrg_ctx_trim",
             "xtrg_hamiltonian_xxz", "xtrg_mpo_from_host", "xtrg_mpo_shape", "xtrg_mpo_to_host",
             "xtrg_mpo_destroy", "xtrg_init_rho", "xtrg_square_compress", "xtrg_product_compress", "xtrg_square_compress_batched", "xtrg_observables",
-            "xtrg_dgemm", "xtrg_dgemm_noalloc", "xtrg_sgemm", "xtrg_gemm_bf16x3", "xtrg_dsvd_left", "xtrg_dsvd_left_qr", "xtrg_dqrcp", "xtrg_spin_sum_mpo", "xtrg_correlation_mpo", "xtrg_expectation", "xtrg_serve_submit", "xtrg_serve_poll", "xtrg_serve_set_lanes", "xtrg_settn_init", "xtrg_profile_enable",
+            "xtrg_dgemm", "xtrg_dgemm_noalloc", "xtrg_sgemm", "xtrg_gemm_bf16x3", "xtrg_dsvd_left", "xtrg_dsvd_left_qr", "xtrg_dqrcp", "xtrg_spin_sum_mpo", "xtrg_correlation_mpo", "xtrg_expectation", "xtrg_serve_submit", "xtrg_serve_poll", "xtrg_serve_set_lanes", "xtrg_settn_init", "xtrg_taylor_step", "xtrg_profile_enable",
             "xtrg_profile_report"]
 
 
@@ -236,6 +238,16 @@ class Context:
         _check(self, _lib.xtrg_settn_init(self.h, H.h, tau0, D_max, n_sweeps, tol, C.byref(h), C.byref(lam),
                                           C.byref(nt)))
         return MPO(self, h), lam.value, nt.value
+
+    def taylor_step(self, H: MPO, rho: MPO, dtau: float, D_max: int, n_sweeps: int = 2, tol: float = 1e-15):
+        """rho(tau + dtau) by the pointwise expansion (Eq. Tay):
+        (rho_hat', dlog_norm, cutoff order)."""
+        h = C.c_void_p()
+        dl = C.c_double()
+        nt = C.c_int()
+        _check(self, _lib.xtrg_taylor_step(self.h, H.h, rho.h, dtau, D_max, n_sweeps, tol, C.byref(h), C.byref(dl),
+                                           C.byref(nt)))
+        return MPO(self, h), dl.value, nt.value
 
     def square_compress(self, rho: MPO, D_max: int, n_sweeps: int = 4, degen_rtol: float = 1e-6,
                         sv_floor: float = 1e-14, sv_stride: int = 0, precision: int = XTRG_FP64,

@@ -1,6 +1,6 @@
-"""Oracle pins of the series start (Sec. II.C, Eq. RhoTau) and of the
-compressed MPO sum it ends with (App. D.2, Eq. MPO:plus; App. D.1 direct
-route).
+"""Oracle pins of the series start (Sec. II.C, Eq. RhoTau), of the
+pointwise expansion step (Eq. Tay) and of the compressed MPO sum both end
+with (App. D.2, Eq. MPO:plus; App. D.1 direct route).
 
 The series start is exact up to its stopping rule when no term is
 truncated, so it is pinned against the dense exponential exp(-tau0 H) of
@@ -144,3 +144,24 @@ def test_doublings_from_the_series_start_match_ed():
             worst_lin = max(worst_lin, abs(OX.observables(lin, llin, tau, H, n)[key]["f"] - ref) / abs(ref))
     assert worst_settn < 1e-12, worst_settn
     assert worst_lin > 1e-4, worst_lin
+
+
+def test_taylor_steps_follow_the_exponential():
+    """Pointwise expansion steps (Eq. Tay) on the exponential grid from the
+    series start: rho(0.1) -> rho(0.2) -> ... -> rho(1.6), untruncated,
+    equal to exp(-tau H) to 1e-12 at every step on a random-coupling chain
+    and a 2x3 cylinder; a step of dtau = 0 returns rho itself."""
+    for lat in (W.random_couplings(W.chain(6), 4), W.square_cylinder(2, 3)):
+        H = _h(lat)
+        Hd = M.to_dense(H)
+        rho, lam, _ = OX.settn_init(H, 0.1, 10 ** 4)
+        tau = 0.1
+        for _ in range(4):
+            rho, dl, nc = OX.taylor_step(H, rho, tau, 10 ** 4)
+            lam += dl
+            tau *= 2.0
+            ex = sl.expm(-tau * Hd)
+            assert np.linalg.norm(_dense_rho(rho, lam) - ex) < 1e-12 * np.linalg.norm(ex), (lat.name, tau)
+        same, dl, nc = OX.taylor_step(H, rho, 0.0, 10 ** 4)
+        assert nc == 1 and abs(dl) < 1e-14
+        assert np.linalg.norm(M.to_dense(same) - M.to_dense(rho)) < 1e-13
