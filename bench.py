@@ -201,11 +201,12 @@ def svd_accuracy(ctx, th, S_ref, D):
     return out
 
 
-def parity_leg(ctx, name="chain12_D256"):
+def parity_leg(ctx, name="chain12_D256", precision=0, beta_mix=1.0):
     """The stored FP64 oracle run of the L=12 chain at D=256 (two-site
     tensors of 1024 x 1024, 11 doublings, 2 sweeps) rerun through the
-    library: largest relative deviation of f, u, c over both estimators and
-    every beta, and whether every doubling kept the same bond dimensions."""
+    library in the bench's contraction precision and schedule: largest
+    relative deviation of f, u, c over both estimators and every beta, and
+    whether every doubling kept the same bond dimensions."""
     import json
     import workloads as W
     from paper_1801_00142_amd import run
@@ -214,7 +215,7 @@ def parity_leg(ctx, name="chain12_D256"):
     lat = W.workload(ref["workload"], ref["D"]).lattice
     t0 = time.perf_counter()
     gpu = run(ctx, lat.n_sites, lat.bonds, lat.jxy, lat.jz, ref["tau0"], ref["n_doublings"], ref["D"],
-              order=ref["order"], n_sweeps=ref["n_sweeps"])
+              order=ref["order"], n_sweeps=ref["n_sweeps"], precision=precision, beta_mix=beta_mix)
     dt = time.perf_counter() - t0
     err = {"f": 0.0, "u": 0.0, "c": 0.0}
     same = True
@@ -224,8 +225,10 @@ def parity_leg(ctx, name="chain12_D256"):
             for q, floor in (("f", 0.0), ("u", 1e-3), ("c", 1e-3)):
                 vo = o[okey][q]
                 err[q] = max(err[q], abs(g["obs"][key][q] - vo) / max(abs(vo), floor))
+    pname = {0: "FP64", 1: "FP32", 2: "bf16x3"}[precision]
     return {"workload": f"{name}: chain L=12, D={ref['D']}, {ref['n_doublings']} doublings, "
-                        f"{ref['n_sweeps']} sweeps, vs the stored FP64 oracle run",
+                        f"{ref['n_sweeps']} sweeps, {pname} contractions"
+                        + (f" from beta >= {beta_mix}" if precision else "") + ", vs the stored FP64 oracle run",
             "max_rel_df": err["f"], "max_rel_du": err["u"], "max_rel_dc": err["c"],
             "bond_dims_equal": bool(same), "seconds": round(dt, 2)}
 
@@ -482,7 +485,7 @@ def main():
         sites = rhos[0].to_host()
     if not args.no_accuracy:
         print("accuracy: stored-oracle parity run", file=sys.stderr, flush=True)
-        out["accuracy"] = {"parity": parity_leg(ctx)}
+        out["accuracy"] = {"parity": parity_leg(ctx, precision=mixed, beta_mix=args.beta_mix)}
     if not args.no_cpu_baseline:
         tf, cdt, cfl, threads, (th_c, S_c) = cpu_baseline(sites, args.D, args.cpu_steps)
         out["cpu_baseline"] = {"value": round(tf, 5), "unit": "TFLOP/s",
