@@ -39,7 +39,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import Dict, List, Sequence
+from typing import Dict, List, Optional, Sequence
 
 import numpy as np
 
@@ -299,6 +299,7 @@ class CompressInfo:
     discarded: List[float]
     steps: int
     flops: float
+    charges: Optional[List[np.ndarray]] = None   # S^z charge of every bond index (u1 route)
 
     @property
     def trunc_err_max(self) -> float:
@@ -306,7 +307,7 @@ class CompressInfo:
 
 
 def square_compress(rho: List[np.ndarray], D: int, n_sweeps: int = 4,
-                    deg_rtol: float = 1e-6, sv_floor: float = 1e-14, svd=None):
+                    deg_rtol: float = 1e-6, sv_floor: float = 1e-14, svd=None, u1: bool = False):
     """One doubling: C ~ rho*rho, compressed variationally to bond <= D.
 
     ``rho`` must be right-canonical with ||rho||_F = 1.  Returns the new
@@ -314,12 +315,14 @@ def square_compress(rho: List[np.ndarray], D: int, n_sweeps: int = 4,
     c = ||C||_F before normalisation, so lambda_{n+1} = 2 lambda_n + ln c.
     ``svd`` factorises C_E (default: LAPACK gesdd through numpy); the tests
     substitute other factorisations to measure how the result depends on it.
+    ``u1``: factorise C_E by charge blocks (block_svd); rho must have
+    charge-definite bonds (bond_charges), and so has the result.
     """
-    return product_compress(rho, rho, D, n_sweeps, deg_rtol, sv_floor, svd)
+    return product_compress(rho, rho, D, n_sweeps, deg_rtol, sv_floor, svd, u1)
 
 
 def product_compress(A: List[np.ndarray], B: List[np.ndarray], D: int, n_sweeps: int = 4,
-                     deg_rtol: float = 1e-6, sv_floor: float = 1e-14, svd=None):
+                     deg_rtol: float = 1e-6, sv_floor: float = 1e-14, svd=None, u1: bool = False):
     """C ~ A*B compressed variationally to bond <= D (App. D.1, Eq.
     MPO:prod with two different factors): the cross products
     rho_{n,n'} = rho_{n-1} rho_{n'-1} of the interleaved grids (Sec. II.B)
@@ -327,13 +330,23 @@ def product_compress(A: List[np.ndarray], B: List[np.ndarray], D: int, n_sweeps:
     Eq. Tay).  The initial guess is B, which must be right-canonical (its
     sites 1..L-1 isometric, as every output of this function and of
     init_rho is).  Returns the normalised right-canonical C and a
-    CompressInfo with ln c, c = ||C||_F before normalisation."""
+    CompressInfo with ln c, c = ||C||_F before normalisation.
+
+    With u1, A and B must conserve S^z_tot in charge-definite bond bases
+    (bond_charges); C_E is then block-diagonal in the charge of the bond
+    being cut, it is factorised block by block (block_svd), and the kept
+    singular vectors carry their block's charge into C's bond, so C is
+    charge-definite too (info.charges).  The cut is the same keep rule on
+    the merged values of all blocks."""
     if svd is None:
         svd = lambda a: np.linalg.svd(a, full_matrices=False)
     n = len(A)
     if n < 2 or len(B) != n:
         raise ValueError("need two MPOs of the same length >= 2")
     C = [w.copy() for w in B]                           # initial guess
+    if u1:
+        bond_charges(A)                                 # raises unless A conserves S^z in its basis
+        qc = bond_charges(B)                            # charges of C's bonds (C = B)
     one = np.ones((1, 1, 1))
     L: List[np.ndarray] = [None] * (n + 1)
     R: List[np.ndarray] = [None] * (n + 2)
@@ -352,8 +365,13 @@ def product_compress(A: List[np.ndarray], B: List[np.ndarray], D: int, n_sweeps:
         Rb = right_block(R[i + 2], A[i + 1], B[i + 1])
         th = two_site_overlap(Lb, Rb)
         flops += _step_flops(L[i].shape, A[i].shape[3], B[i].shape[3], R[i + 2].shape)
-        U, S, Vt = svd(th)
+        if u1:
+            U, S, Vt, qs = block_svd(th, theta_row_charges(qc[i]), theta_col_charges(qc[i + 2]), svd)
+        else:
+            U, S, Vt = svd(th)
         k = keep_count(S, D, deg_rtol, sv_floor, noise_floor(th))
+        if u1:
+            qc[i + 1] = qs[:k].copy()
         tot = float(np.sum(S * S))
         sv[i] = S.copy()
         kept[i] = k
@@ -374,7 +392,7 @@ def product_compress(A: List[np.ndarray], B: List[np.ndarray], D: int, n_sweeps:
         S_last = S[:k]
     c = float(np.sqrt(np.sum(S_last * S_last)))
     C[0] = C[0] / c
-    return C, CompressInfo(math.log(c), sv, kept, disc, len(sched), flops)
+    return C, CompressInfo(math.log(c), sv, kept, disc, len(sched), flops, qc if u1 else None)
 
 
 def _step_flops(Lshape, Da2, Db2, Rshape) -> float:
@@ -389,6 +407,132 @@ def _step_flops(Lshape, Da2, Db2, Rshape) -> float:
     th = 2.0 * (Dc * d * d) * (Da2 * Db2) * (d * d * Dc2)
     k3 = 2.0 * Da2 * Db2 * (Dc * d * d) * Dc
     return k1 + k2 + th + k3
+
+
+# --------------------------------------------------------------------------
+# U(1) charge sectors (Sec. II.A: the models conserve S^z_tot, and the
+# paper's tensors are blocked by it; App. B.2).  The tensors stay dense
+# here: the charges label the bond indices, and the factorisations run
+# block by block.
+# --------------------------------------------------------------------------
+
+def bond_charges(W: List[np.ndarray]) -> List[np.ndarray]:
+    """S^z charge of every bond index of an MPO whose operator commutes with
+    S^z_tot, written in a basis in which every index has a definite charge.
+
+    Site index s = 0 is up (S^z = +1/2), s = 1 down; the entry W[a, s, s', b]
+    multiplies |s><s'|, which raises S^z by s' - s.  In a charge-definite
+    basis an entry can be non-zero only if q_b = q_a + (s' - s), with q = 0
+    at the left end, so the charges follow from the non-zero entries, site
+    by site.  An index that no non-zero entry reaches from the left end
+    (a state of a redundant MPO that never occurs, such as a product of
+    automata in which one factor has stopped before the other started)
+    contributes nothing to the operator: its own entries are ignored, and
+    it gets charge 0.  Raises ValueError if two entries of one index imply
+    different charges (the operator does not conserve S^z, or the basis
+    mixes charges)."""
+    q = [np.zeros(W[0].shape[0], dtype=np.int64)]
+    known = np.ones(W[0].shape[0], dtype=bool)
+    for i, w in enumerate(W):
+        a, s, t, b = np.nonzero(w)
+        use = known[a]
+        a, s, t, b = a[use], s[use], t[use], b[use]
+        v = q[i][a] + (t - s)
+        Dr = w.shape[3]
+        lo = np.full(Dr, np.iinfo(np.int64).max)
+        hi = np.full(Dr, np.iinfo(np.int64).min)
+        np.minimum.at(lo, b, v)
+        np.maximum.at(hi, b, v)
+        known = hi >= lo
+        if np.any(known & (hi != lo)):
+            raise ValueError(f"site {i}: a bond index carries two S^z charges")
+        q.append(np.where(known, lo, 0))
+    return q
+
+
+def theta_row_charges(q_left: np.ndarray) -> np.ndarray:
+    """Charges of the rows (c, s, s'') of C_E: q_c + (s'' - s)."""
+    d = np.arange(2)
+    return (q_left[:, None, None] + (d[None, None, :] - d[None, :, None])).reshape(-1)
+
+
+def theta_col_charges(q_right: np.ndarray) -> np.ndarray:
+    """Charges of the columns (t, t'', c'') of C_E: the charge a row must
+    carry to connect to them, q_c'' - (t'' - t)."""
+    d = np.arange(2)
+    return (d[:, None, None] - d[None, :, None] + q_right[None, None, :]).reshape(-1)
+
+
+def block_svd(th: np.ndarray, q_row: np.ndarray, q_col: np.ndarray, svd=None):
+    """SVD of a matrix whose entries vanish unless the row and the column
+    charge agree.  Sorted by charge it is block-diagonal, so its singular
+    triples are those of its blocks, each block factorised on its own.
+    Returns U, S, Vt, q: S descending over all blocks (equal values in
+    increasing charge), U and Vt zero outside their block, q the charge of
+    each triple.  Raises ValueError if an entry between different charges
+    is non-zero."""
+    if svd is None:
+        svd = lambda a: np.linalg.svd(a, full_matrices=False)
+    m, n = th.shape
+    if np.any(th[q_row[:, None] != q_col[None, :]] != 0):
+        raise ValueError("non-zero entry between different S^z charges")
+    Us, Ss, Vs, qs = [], [], [], []
+    for qv in np.intersect1d(q_row, q_col):
+        r = np.nonzero(q_row == qv)[0]
+        c = np.nonzero(q_col == qv)[0]
+        u, s, vt = svd(th[np.ix_(r, c)])
+        U = np.zeros((m, s.size))
+        U[r] = u
+        V = np.zeros((s.size, n))
+        V[:, c] = vt
+        Us.append(U)
+        Ss.append(s)
+        Vs.append(V)
+        qs.append(np.full(s.size, qv, dtype=np.int64))
+    if not Ss:
+        raise ValueError("no charge is shared by the rows and the columns")
+    S = np.concatenate(Ss)
+    q = np.concatenate(qs)
+    order = np.lexsort((q, -S))
+    return np.concatenate(Us, axis=1)[:, order], S[order], np.concatenate(Vs, axis=0)[order], q[order]
+
+
+def canonical_u1(W: List[np.ndarray], rel_floor: float = 1e-14) -> List[np.ndarray]:
+    """Lossless canonical form with charge-definite bonds: a left-to-right
+    sweep of block SVDs (U stays, S V^T moves right), then a right-to-left
+    one (V^T stays, U S moves left), each dropping only the values at or
+    below rel_floor * s_1 or the rounding noise (the exact zeros of a
+    redundant MPO such as the automaton's).  The result is right-canonical,
+    the operator is unchanged."""
+    W = [w.copy() for w in W]
+    q = bond_charges(W)
+    n = len(W)
+    for i in range(n - 1):
+        Dl, d1, d2, Dr = W[i].shape
+        Mi = W[i].reshape(Dl * d1 * d2, Dr)
+        U, S, Vt, qs = block_svd(Mi, theta_row_charges(q[i]), q[i + 1])
+        k = keep_count(S, 10 ** 9, 0.0, rel_floor, noise_floor(Mi))
+        W[i] = U[:, :k].reshape(Dl, d1, d2, k)
+        W[i + 1] = np.einsum("kb,bstc->kstc", S[:k, None] * Vt[:k], W[i + 1])
+        q[i + 1] = qs[:k]
+    for i in range(n - 1, 0, -1):
+        Dl, d1, d2, Dr = W[i].shape
+        Mi = W[i].reshape(Dl, d1 * d2 * Dr)
+        U, S, Vt, qs = block_svd(Mi, q[i], theta_col_charges(q[i + 1]))
+        k = keep_count(S, 10 ** 9, 0.0, rel_floor, noise_floor(Mi))
+        W[i] = Vt[:k].reshape(k, d1, d2, Dr)
+        W[i - 1] = np.einsum("astb,bk->astk", W[i - 1], U[:, :k] * S[:k])
+        q[i] = qs[:k]
+    return W
+
+
+def init_rho_u1(n, bonds, jxy, jz, tau0: float, order: int, rel_floor: float = 1e-14):
+    """init_rho with charge-definite bonds (canonical_u1 in place of the QR
+    and SVD sweeps): the same operator, normalised and right-canonical."""
+    W = canonical_u1(series_rho(n, bonds, jxy, jz, tau0, order), rel_floor)
+    nrm = float(np.linalg.norm(W[0]))
+    W[0] = W[0] / nrm
+    return W, math.log(nrm)
 
 
 # --------------------------------------------------------------------------
@@ -483,10 +627,11 @@ def entanglement(rho: List[np.ndarray]) -> np.ndarray:
 
 def run(n, bonds, jxy, jz, tau0: float, n_doublings: int, D: int, order: int = 1,
         n_sweeps: int = 4, deg_rtol: float = 1e-6, sv_floor: float = 1e-14,
-        with_entropy: bool = False, keep_states: bool = False, svd=None):
-    """Full XTRG run; returns a list of per-doubling records."""
+        with_entropy: bool = False, keep_states: bool = False, svd=None, u1: bool = False):
+    """Full XTRG run; returns a list of per-doubling records.  u1: the start
+    and every doubling keep charge-definite bonds (init_rho_u1, block_svd)."""
     H = M.hamiltonian(n, bonds, jxy, jz)
-    rho, lam = init_rho(n, bonds, jxy, jz, tau0, order)
+    rho, lam = (init_rho_u1 if u1 else init_rho)(n, bonds, jxy, jz, tau0, order)
     recs = []
     tau = tau0
     rec = dict(n=0, tau=tau, lam=lam, obs=observables(rho, lam, tau, H, n), bond_dims=M.bond_dims(rho))
@@ -496,7 +641,7 @@ def run(n, bonds, jxy, jz, tau0: float, n_doublings: int, D: int, order: int = 1
         rec["rho"] = rho
     recs.append(rec)
     for k in range(1, n_doublings + 1):
-        rho, info = square_compress(rho, D, n_sweeps, deg_rtol, sv_floor, svd=svd)
+        rho, info = square_compress(rho, D, n_sweeps, deg_rtol, sv_floor, svd=svd, u1=u1)
         lam = 2 * lam + info.dlog_norm
         tau = 2 * tau
         rec = dict(n=k, tau=tau, lam=lam, obs=observables(rho, lam, tau, H, n),
