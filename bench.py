@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "fp32", "bf16x3"], default="fp64",
                     help="contraction precision of the doublings that reach beta >= --beta-mix")
     ap.add_argument("--beta-mix", type=float, default=1.0)
+    ap.add_argument("--u1", action="store_true",
+                    help="U(1) charge sectors: charge-definite start, every two-site tensor factorised by "
+                         "S^z charge blocks")
     ap.add_argument("--serve", type=int, default=0,
                     help="serve N requests of the scaled-down mixed workload instead (p50/p99 latency)")
     ap.add_argument("--serve-rate", type=float, default=2.0)
@@ -91,7 +94,7 @@ def batch_leg(ctx, H, wl, args, mixed):
     from paper_1801_00142_amd import XTRG_FP64
     n = args.batch_leg
     taus = [wl.tau0 * 2.0 ** (i / n) for i in range(n)]
-    rhos = [ctx.init_rho(H, t, wl.init_order)[0] for t in taus]
+    rhos = [ctx.init_rho(H, t, wl.init_order, u1=args.u1)[0] for t in taus]
     tau = wl.tau0
     done = 0
 
@@ -99,7 +102,7 @@ def batch_leg(ctx, H, wl, args, mixed):
         nonlocal rhos, tau
         prec = mixed if 4 * tau >= args.beta_mix else XTRG_FP64
         tau *= 2
-        news, infos = ctx.square_compress_batched(rhos, args.D, args.sweeps, precision=prec)
+        news, infos = ctx.square_compress_batched(rhos, args.D, args.sweeps, precision=prec, u1=args.u1)
         for r in rhos:
             r.close()
         rhos = news
@@ -201,7 +204,7 @@ def svd_accuracy(ctx, th, S_ref, D):
     return out
 
 
-def parity_leg(ctx, name="chain12_D256", precision=0, beta_mix=1.0):
+def parity_leg(ctx, name="chain12_D256", precision=0, beta_mix=1.0, u1=False):
     """The stored FP64 oracle run of the L=12 chain at D=256 (two-site
     tensors of 1024 x 1024, 11 doublings, 2 sweeps) rerun through the
     library in the bench's contraction precision and schedule: largest
@@ -215,7 +218,7 @@ def parity_leg(ctx, name="chain12_D256", precision=0, beta_mix=1.0):
     lat = W.workload(ref["workload"], ref["D"]).lattice
     t0 = time.perf_counter()
     gpu = run(ctx, lat.n_sites, lat.bonds, lat.jxy, lat.jz, ref["tau0"], ref["n_doublings"], ref["D"],
-              order=ref["order"], n_sweeps=ref["n_sweeps"], precision=precision, beta_mix=beta_mix)
+              order=ref["order"], n_sweeps=ref["n_sweeps"], precision=precision, beta_mix=beta_mix, u1=u1)
     dt = time.perf_counter() - t0
     err = {"f": 0.0, "u": 0.0, "c": 0.0}
     same = True
@@ -228,7 +231,8 @@ def parity_leg(ctx, name="chain12_D256", precision=0, beta_mix=1.0):
     pname = {0: "FP64", 1: "FP32", 2: "bf16x3"}[precision]
     return {"workload": f"{name}: chain L=12, D={ref['D']}, {ref['n_doublings']} doublings, "
                         f"{ref['n_sweeps']} sweeps, {pname} contractions"
-                        + (f" from beta >= {beta_mix}" if precision else "") + ", vs the stored FP64 oracle run",
+                        + (f" from beta >= {beta_mix}" if precision else "")
+                        + (", U(1) charge blocks" if u1 else "") + ", vs the stored FP64 oracle run",
             "max_rel_df": err["f"], "max_rel_du": err["u"], "max_rel_dc": err["c"],
             "bond_dims_equal": bool(same), "seconds": round(dt, 2)}
 
@@ -299,7 +303,7 @@ def main():
     taus = W.zshift_tau0(wl.tau0, nb)
     ctx = Context(0)
     H = ctx.hamiltonian_xxz(lat.n_sites, lat.bonds, lat.jxy, lat.jz)
-    rhos = [ctx.init_rho(H, t, wl.init_order)[0] for t in taus]
+    rhos = [ctx.init_rho(H, t, wl.init_order, u1=args.u1)[0] for t in taus]
 
     from paper_1801_00142_amd import XTRG_BF16X3, XTRG_FP32, XTRG_FP64
     mixed = {"fp64": XTRG_FP64, "fp32": XTRG_FP32, "bf16x3": XTRG_BF16X3}[args.precision]
@@ -316,10 +320,10 @@ def main():
             last_prec[0] = prec
         tau[0] *= 2
         if nb == 1:
-            new, info = ctx.square_compress(rhos[0], args.D, n_sweeps, precision=prec)
+            new, info = ctx.square_compress(rhos[0], args.D, n_sweeps, precision=prec, u1=args.u1)
             news, infos = [new], [info]
         else:
-            news, infos = ctx.square_compress_batched(rhos, args.D, n_sweeps, precision=prec)
+            news, infos = ctx.square_compress_batched(rhos, args.D, n_sweeps, precision=prec, u1=args.u1)
         for r in rhos:
             r.close()
         rhos = news
@@ -352,6 +356,9 @@ def main():
         for r in rhos:
             r.close()
         rhos = [ctx.mpo_from_host(x) for x in snap[0]]
+        if args.u1:
+            for r in rhos:
+                r.label_charges()
         tau[0] = snap[1]
         state["n"] = snap[2]
         state["restores"] += 1
@@ -431,6 +438,8 @@ def main():
                f"tau0=2^{math.log2(wl.tau0):g}, D={args.D}, {args.sweeps} sweeps/doubling")
     if nb > 1:
         wl_name += f", {nb} z-shifted chains batched"
+    if args.u1:
+        wl_name += ", U(1) charge sectors (two-site tensors factorised by S^z blocks)"
     # the headline metric (its serve-latency half is measured by --serve N --serve-full)
     metric = ("TFLOP/s in MPO product-compression sweeps at D=256; p50/p99 serve latency" if args.D == 256
               else f"TFLOP/s in MPO product-compression sweeps at D={args.D}")
@@ -485,7 +494,8 @@ def main():
         sites = rhos[0].to_host()
     if not args.no_accuracy:
         print("accuracy: stored-oracle parity run", file=sys.stderr, flush=True)
-        out["accuracy"] = {"parity": parity_leg(ctx, precision=mixed, beta_mix=args.beta_mix)}
+        out["accuracy"] = {"parity": parity_leg(ctx, "chain12_D256_u1" if args.u1 else "chain12_D256",
+                                                precision=mixed, beta_mix=args.beta_mix, u1=args.u1)}
     if not args.no_cpu_baseline:
         tf, cdt, cfl, threads, (th_c, S_c) = cpu_baseline(sites, args.D, args.cpu_steps)
         out["cpu_baseline"] = {"value": round(tf, 5), "unit": "TFLOP/s",

@@ -103,6 +103,25 @@ int xtrg_mpo_destroy(xtrg_mpo mpo);
  * rho(tau0) = exp(*log_norm) * rho_out with ||rho_out||_F = 1. */
 int xtrg_init_rho(xtrg_ctx ctx, xtrg_mpo H, double tau0, int order, int D0_max,
                   xtrg_mpo* rho_out, double* log_norm);
+/* xtrg_init_rho with S^z charges on every bond (Sec. II.A; App. B.2): the
+ * same operator, normalised and right-canonical, compressed by block SVD
+ * sweeps, so that every bond index has a definite charge (a dense SVD mixes
+ * degenerate values of different charges); the handle carries the charges
+ * for doublings with opts.u1 = 1.  The charges of H's automaton states are
+ * read from its non-zero entries. */
+int xtrg_init_rho_u1(xtrg_ctx ctx, xtrg_mpo H, double tau0, int order, int D0_max,
+                     xtrg_mpo* rho_out, double* log_norm);
+/* Attach S^z charges to an MPO whose bond bases are charge-definite (e.g. one
+ * uploaded with xtrg_mpo_from_host), read from its non-zero entries: site
+ * index 0 is up, W[a][s][s'][b] != 0 requires q_b = q_a + (s' - s), q = 0 at
+ * the left end; an index that no non-zero entry reaches from the left gets
+ * charge 0.  Downloads the sites (host work O(sum_i D_i D_{i+1})).
+ * XTRG_EINVAL if some index would need two charges. */
+int xtrg_mpo_label_charges(xtrg_mpo mpo);
+/* The charges of every bond, bond 0 first (sum of the L+1 bond dimensions
+ * ints, caller-sized).  XTRG_EINVAL if the MPO carries none. */
+int xtrg_mpo_charges(xtrg_mpo mpo, int* charges);
+
 
 /* The series start of Sec. II.C, Eq. (RhoTau), for larger tau0: the series
  * sum_k (-tau0)^k/k! H^k up to the first order whose term is at most tol
@@ -152,6 +171,17 @@ typedef struct {
                         singular values are those of R, the left singular vectors Q W
                         (same result to rounding, fewer Jacobi sweeps);
                         1: such SVDs run the Jacobi on the two-site tensor itself */
+  int u1;            /* 0: C_E is factorised as one dense matrix.  1: U(1) charge sectors
+                        (Sec. II.A: the XXZ models conserve S^z_tot; App. B.2): the
+                        input MPOs must carry S^z charges on their bonds (xtrg_init_rho_u1,
+                        xtrg_mpo_label_charges, or an earlier u1 doubling); C_E, block
+                        diagonal in the charge of the bond being cut, is factorised block by
+                        block (one grouped Jacobi launch per round over all blocks; the
+                        warm and QR starts are not used), the keep rule runs on the merged
+                        values of all blocks, and every kept singular vector carries its
+                        block's charge into the output's bond, which is charge-definite
+                        too.  The tensors stay dense.  XTRG_EINVAL if an input has no
+                        charges or C_E has weight between different charges. */
 } xtrg_compress_opts;
 
 /* Diagnostics of one doubling. */

@@ -353,6 +353,221 @@ void orthonormalize(xtrg_ctx c, double* U, int len, int k, bool rowmajor) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// U(1) charge sectors (Sec. II.A: the XXZ models conserve S^z_tot, and the
+// paper's tensors are blocked by it; App. B.2).  The tensors stay dense; the
+// S^z charges label the bond indices, and a matrix that conserves the charge
+// is factorised block by block.
+// ---------------------------------------------------------------------------
+
+// Charges of the rows (c, s, s'') of a site matrix or two-site tensor from
+// the charges q of its left bond: q_c + (s'' - s) (index 0 is up).
+std::vector<int> row_charges(const std::vector<int>& q) {
+  std::vector<int> out(q.size() * 4);
+  for (size_t c = 0; c < q.size(); ++c)
+    for (int s = 0; s < 2; ++s)
+      for (int u = 0; u < 2; ++u) out[c * 4 + s * 2 + u] = q[c] + (u - s);
+  return out;
+}
+
+// Charge a left index must carry to connect to the column (t, t'', c) of a
+// site matrix or two-site tensor: q_c - (t'' - t).
+std::vector<int> col_charges(const std::vector<int>& q) {
+  const size_t D = q.size();
+  std::vector<int> out(4 * D);
+  for (int t = 0; t < 2; ++t)
+    for (int u = 0; u < 2; ++u)
+      for (size_t c = 0; c < D; ++c) out[(t * 2 + u) * D + c] = q[c] - (u - t);
+  return out;
+}
+
+// Charges of every bond index from the non-zero entries of host copies of
+// the sites ([Dl][2][2][Dr] each): the entry W[a][s][t][b] fixes
+// q_b = q_a + (t - s), starting from q = 0 at the left end.  An index that
+// no non-zero entry reaches from an index of known charge contributes
+// nothing to the operator; it gets charge 0.
+std::vector<std::vector<int>> infer_charges(const std::vector<std::vector<double>>& W, const std::vector<int>& dims) {
+  const int L = (int)W.size();
+  std::vector<std::vector<int>> q(L + 1);
+  q[0].assign(dims[0], 0);
+  std::vector<char> known(dims[0], 1);
+  for (int i = 0; i < L; ++i) {
+    const int Dl = dims[i], Dr = dims[i + 1];
+    std::vector<int> lo(Dr, std::numeric_limits<int>::max()), hi(Dr, std::numeric_limits<int>::min());
+    for (int a = 0; a < Dl; ++a) {
+      if (!known[a]) continue;
+      for (int st = 0; st < 4; ++st) {
+        const double* row = W[i].data() + ((size_t)a * 4 + st) * Dr;
+        const int v = q[i][a] + ((st & 1) - (st >> 1));
+        for (int b = 0; b < Dr; ++b)
+          if (row[b] != 0.0) {
+            lo[b] = std::min(lo[b], v);
+            hi[b] = std::max(hi[b], v);
+          }
+      }
+    }
+    q[i + 1].assign(Dr, 0);
+    known.assign(Dr, 0);
+    for (int b = 0; b < Dr; ++b) {
+      if (hi[b] < lo[b]) continue;
+      if (hi[b] != lo[b])
+        throw Error(XTRG_EINVAL, "site " + std::to_string(i) + ": a bond index carries two S^z charges");
+      known[b] = 1;
+      q[i + 1][b] = lo[b];
+    }
+  }
+  return q;
+}
+
+// Factorisation of a len x p column-major matrix Y whose entries vanish
+// unless the charge of the row (ql) equals that of the column (qp): sorted by
+// charge it is block diagonal, and its singular triples are those of its
+// blocks.  Every block is one problem of a grouped Jacobi SVD.
+struct BlockSvd {
+  struct Blk {
+    int q = 0, len = 0, p = 0;
+    std::vector<int> idx;   // rows, then columns, then the merged positions of the kept triples
+    int* d_idx = nullptr;
+    double* Y = nullptr;
+    double* work = nullptr;
+    int kept = 0;
+  };
+  std::vector<Blk> b;
+  const double* Y = nullptr;
+  int len = 0, p = 0;
+  double* chk = nullptr;          // device: ||Y||_F^2, then 1024 partials
+  // after merge(): the values of all blocks, descending (equal values in
+  // increasing charge), with their charge, block and rank in the block
+  std::vector<double> S;
+  std::vector<int> qs, from, rank;
+  double fro2 = 0.0;              // sum of the blocks' ||Y_q||_F^2
+};
+
+// Split Y into its charge blocks and append one SVD problem per block to
+// jobs.  `tag` names the workspaces (one set per concurrent factorisation).
+void bsvd_prepare(xtrg_ctx c, const std::string& tag, const double* Y, int len, int p, const std::vector<int>& ql,
+                  const std::vector<int>& qp, BlockSvd& B, std::vector<xtrg::SvdJob>& jobs) {
+  if ((int)ql.size() != len || (int)qp.size() != p) throw Error(XTRG_EINVAL, "charge lists do not match the tensor");
+  hipStream_t s = c->stream;
+  std::map<int, std::pair<std::vector<int>, std::vector<int>>> g;
+  for (int r = 0; r < len; ++r) g[ql[r]].first.push_back(r);
+  for (int j = 0; j < p; ++j) g[qp[j]].second.push_back(j);
+  B = BlockSvd{};
+  B.Y = Y;
+  B.len = len;
+  B.p = p;
+  for (auto& kv : g) {
+    auto& rc = kv.second;
+    if (rc.first.empty() || rc.second.empty()) continue;
+    BlockSvd::Blk k;
+    k.q = kv.first;
+    k.len = (int)rc.first.size();
+    k.p = (int)rc.second.size();
+    k.idx = rc.first;
+    k.idx.insert(k.idx.end(), rc.second.begin(), rc.second.end());
+    k.idx.resize(k.idx.size() + std::min(k.len, k.p), 0);
+    B.b.push_back(std::move(k));
+  }
+  if (B.b.empty()) throw Error(XTRG_EINVAL, "no S^z charge is shared by the rows and the columns");
+  B.chk = c->need("u1_chk" + tag, 1026);
+  xtrg::sumsq(Y, (size_t)len * p, B.chk, B.chk + 2, s);
+  for (size_t t = 0; t < B.b.size(); ++t) {
+    auto& k = B.b[t];
+    const std::string nm = tag + "/" + std::to_string(t);
+    k.d_idx = reinterpret_cast<int*>(c->need("u1_idx" + nm, k.idx.size() / 2 + 1));
+    XTRG_HIP(hipMemcpyAsync(k.d_idx, k.idx.data(), sizeof(int) * (k.len + k.p), hipMemcpyHostToDevice, s));
+    k.Y = c->need("u1_Y" + nm, (size_t)k.len * k.p);
+    xtrg::gather_block(k.Y, Y, len, k.d_idx, k.len, k.d_idx + k.len, k.p, s);
+    k.work = c->need("u1_svd" + nm, xtrg::svd_work(k.len, k.p));
+    jobs.push_back(xtrg::SvdJob{k.len, k.p, k.Y, k.work, 0, svd_gram(c, "u1" + nm, k.p)});
+  }
+}
+
+// After the grouped SVD: the values of all blocks, merged and sorted; throws
+// if Y has weight between different charges (beyond rounding).
+void bsvd_merge(xtrg_ctx c, const std::string& tag, BlockSvd& B) {
+  hipStream_t s = c->stream;
+  size_t n = 1;
+  for (auto& k : B.b) n += 1 + std::min(k.len, k.p);
+  double* st = c->need("u1_vals" + tag, n);
+  XTRG_HIP(hipMemcpyAsync(st, B.chk, sizeof(double), hipMemcpyDeviceToDevice, s));
+  size_t o = 1;
+  for (auto& k : B.b) {
+    const int r = std::min(k.len, k.p);
+    XTRG_HIP(hipMemcpyAsync(st + o, xtrg::svd_fro2(k.work, k.len, k.p), sizeof(double), hipMemcpyDeviceToDevice, s));
+    XTRG_HIP(hipMemcpyAsync(st + o + 1, xtrg::svd_sorted_values(k.work, k.len, k.p), sizeof(double) * r,
+                            hipMemcpyDeviceToDevice, s));
+    o += 1 + r;
+  }
+  const std::vector<double> h = read_vec(c, st, n);
+  struct E { double v; int q, blk, rank; };
+  std::vector<E> e;
+  B.fro2 = 0.0;
+  o = 1;
+  for (size_t t = 0; t < B.b.size(); ++t) {
+    const auto& k = B.b[t];
+    const int r = std::min(k.len, k.p);
+    B.fro2 += h[o];
+    for (int j = 0; j < r; ++j) {
+      const double v = h[o + 1 + j];
+      if (!std::isfinite(v)) throw Error(XTRG_ENUMERIC, "non-finite singular value");
+      e.push_back({v, k.q, (int)t, j});
+    }
+    o += 1 + r;
+  }
+  const double full = h[0];
+  if (!std::isfinite(full)) throw Error(XTRG_ENUMERIC, "non-finite entries in the two-site tensor");
+  if (std::fabs(full - B.fro2) > 1e-10 * full)
+    throw Error(XTRG_EINVAL, "the tensor has weight between different S^z charges: the inputs do not conserve "
+                             "S^z in their bond bases");
+  // blocks come in increasing charge and each block's values descending, so a
+  // stable sort by value keeps both orders among equal values
+  std::stable_sort(e.begin(), e.end(), [](const E& a, const E& b) { return a.v > b.v; });
+  B.S.resize(e.size());
+  B.qs.resize(e.size());
+  B.from.resize(e.size());
+  B.rank.resize(e.size());
+  for (size_t j = 0; j < e.size(); ++j) {
+    B.S[j] = e[j].v;
+    B.qs[j] = e[j].q;
+    B.from[j] = e[j].blk;
+    B.rank[j] = e[j].rank;
+  }
+}
+
+// The first k merged singular vectors as a dense len x k matrix: dst[r*k + j]
+// (rowmajor) or dst[j*len + r]; zero outside each vector's block.
+void bsvd_scatter(xtrg_ctx c, const std::string& tag, BlockSvd& B, int k, double* dst, int rowmajor) {
+  hipStream_t s = c->stream;
+  xtrg::fill(dst, 0.0, (size_t)B.len * k, s);
+  for (auto& blk : B.b) blk.kept = 0;
+  for (int j = 0; j < k; ++j) {
+    auto& blk = B.b[B.from[j]];
+    if (B.rank[j] != blk.kept) throw Error(XTRG_EINVAL, "block SVD: kept values out of order");
+    blk.idx[blk.len + blk.p + blk.kept] = j;
+    blk.kept += 1;
+  }
+  for (auto& blk : B.b) {
+    if (blk.kept == 0) continue;
+    int* pos = blk.d_idx + blk.len + blk.p;
+    XTRG_HIP(hipMemcpyAsync(pos, blk.idx.data() + blk.len + blk.p, sizeof(int) * blk.kept, hipMemcpyHostToDevice, s));
+    double* tmp = c->need("u1_vec" + tag, (size_t)blk.len * blk.kept);
+    xtrg::svd_gather(blk.len, blk.p, blk.work, blk.kept, tmp, blk.len, 0, s);
+    xtrg::scatter_cols(dst, B.len, k, rowmajor, tmp, blk.len, blk.kept, blk.d_idx, pos, s);
+  }
+}
+
+// One block factorisation on its own (the canonical sweeps of the start).
+void bsvd_run(xtrg_ctx c, const std::string& tag, const double* Y, int len, int p, const std::vector<int>& ql,
+              const std::vector<int>& qp, BlockSvd& B) {
+  std::vector<xtrg::SvdJob> jobs;
+  bsvd_prepare(c, tag, Y, len, p, ql, qp, B, jobs);
+  xtrg::svd_batched(jobs, svd_desc(c, (int)jobs.size()), c->stream);
+  for (const auto& j : jobs)
+    if (j.status != 0) throw Error(XTRG_ENUMERIC, "block SVD: non-finite entries or no convergence");
+  bsvd_merge(c, tag, B);
+}
+
 // Replace site i's buffer by a new one of n doubles.
 double* reshape_site(xtrg_mpo m, int i, size_t n) {
   xtrg_ctx c = m->ctx;
@@ -432,6 +647,71 @@ void right_sweep(xtrg_mpo m, double floor, int Dmax, std::vector<std::vector<dou
   }
 }
 
+// left_sweep and right_sweep with charge-definite bonds: every site matrix
+// is factorised by charge blocks (m->charges labels its bonds and is kept up
+// to date), so the new bond indices carry their block's charge.
+void left_sweep_u1(xtrg_mpo m, double floor) {
+  xtrg_ctx c = m->ctx;
+  hipStream_t s = c->stream;
+  auto& q = m->charges;
+  BlockSvd B;
+  for (int i = 0; i + 1 < m->L; ++i) {
+    const int Dl = m->dims[i], Dr = m->dims[i + 1], Dn = m->dims[i + 2];
+    const int rows = Dl * 4;
+    double* Y = c->need("cs_Y", (size_t)rows * Dr);
+    xtrg::transpose(Y, rows, m->site[i].p, Dr, Dr, rows, s);          // Y col-major (rows x Dr)
+    bsvd_run(c, "cs", Y, rows, Dr, row_charges(q[i]), q[i + 1], B);
+    const double nf = xtrg::svd_keep_rel(rows, Dr) * std::sqrt(B.fro2);
+    int k = 0;
+    for (double v : B.S)
+      if (v > floor * B.S[0] && v > nf && v > 0) ++k;
+    k = std::max(k, 1);
+    double* U = c->need("cs_U", (size_t)rows * k);
+    bsvd_scatter(c, "cs", B, k, U, 1);                                 // U row-major [rows][k]
+    orthonormalize(c, U, rows, k, true);
+    double* R = c->need("cs_R", (size_t)k * Dr);
+    gemm(c, plain(k, Dr, rows, U, k, true, m->site[i].p, Dr, false, R, Dr));   // R = U^T M
+    double* Nn = c->need("cs_N", (size_t)k * 4 * Dn);
+    gemm(c, plain(k, 4 * Dn, Dr, R, Dr, false, m->site[i + 1].p, 4 * Dn, false, Nn, 4 * Dn));
+    xtrg::copy(reshape_site(m, i, (size_t)rows * k), U, (size_t)rows * k, s);
+    xtrg::copy(reshape_site(m, i + 1, (size_t)k * 4 * Dn), Nn, (size_t)k * 4 * Dn, s);
+    m->dims[i + 1] = k;
+    q[i + 1].assign(B.qs.begin(), B.qs.begin() + k);
+  }
+}
+
+void right_sweep_u1(xtrg_mpo m, double floor, int Dmax) {
+  xtrg_ctx c = m->ctx;
+  hipStream_t s = c->stream;
+  auto& q = m->charges;
+  BlockSvd B;
+  for (int i = m->L - 1; i >= 1; --i) {
+    const int Dl = m->dims[i], Dr = m->dims[i + 1], Dp = m->dims[i - 1];
+    const int len = 4 * Dr;
+    bsvd_run(c, "cs", m->site[i].p, len, Dl, col_charges(q[i + 1]), q[i], B);
+    const double nf = xtrg::svd_keep_rel(len, Dl) * std::sqrt(B.fro2);
+    const int k = keep_count(B.S, Dmax > 0 ? Dmax : std::numeric_limits<int>::max(), 0.0, floor, nf);
+    double* V = c->need("cs_V", (size_t)len * k);
+    bsvd_scatter(c, "cs", B, k, V, 0);                                 // V^T row-major [k][len]
+    orthonormalize(c, V, len, k, false);
+    double* US = c->need("cs_R", (size_t)Dl * k);
+    gemm(c, plain(Dl, k, len, m->site[i].p, len, false, V, len, true, US, k));   // U S = M V
+    double* Pn = c->need("cs_N", (size_t)Dp * 4 * k);
+    gemm(c, plain(Dp * 4, k, Dl, m->site[i - 1].p, Dl, false, US, k, false, Pn, k));
+    xtrg::copy(reshape_site(m, i, (size_t)k * len), V, (size_t)k * len, s);
+    xtrg::copy(reshape_site(m, i - 1, (size_t)Dp * 4 * k), Pn, (size_t)Dp * 4 * k, s);
+    m->dims[i] = k;
+    q[i].assign(B.qs.begin(), B.qs.begin() + k);
+  }
+}
+
+// Host copies of the sites.
+std::vector<std::vector<double>> download_sites(xtrg_mpo m) {
+  std::vector<std::vector<double>> W(m->L);
+  for (int i = 0; i < m->L; ++i) W[i] = read_vec(m->ctx, m->site[i].p, m->elems(i));
+  return W;
+}
+
 double site_norm(xtrg_mpo m, int i) {
   xtrg_ctx c = m->ctx;
   xtrg::sumsq(m->site[i].p, m->elems(i), c->scratch, c->scratch + 1024, c->stream);
@@ -441,6 +721,7 @@ double site_norm(xtrg_mpo m, int i) {
 std::unique_ptr<xtrg_mpo_s> clone(xtrg_mpo src) {
   auto m = new_mpo(src->ctx, src->dims);
   for (int i = 0; i < src->L; ++i) xtrg::copy(m->site[i].p, src->site[i].p, src->elems(i), src->ctx->stream);
+  m->charges = src->charges;
   return m;
 }
 
@@ -611,6 +892,11 @@ struct Chain {
   bool warm_now = false;                  // this step's SVD input was rotated by a warm basis
   int status = 0;                         // XTRG_OK, or the code that stopped this chain
   std::string err;                        // and its message
+  // U(1) charge sectors: charges of C's bonds, and the block factorisation
+  // of the current step
+  bool u1 = false;
+  std::vector<std::vector<int>> qc;
+  BlockSvd bs;
 
 };
 
@@ -645,6 +931,12 @@ void chain_setup(xtrg_ctx c, Chain& C, xtrg_mpo ina, xtrg_mpo inb, int q) {
            : C.o.precision == XTRG_BF16X3 ? xtrg::GEMM_BF16X3
                                           : xtrg::GEMM_F64;
   const bool same = ina == inb;
+  C.u1 = C.o.u1 != 0;
+  if (C.u1) {
+    if (ina->charges.empty() || inb->charges.empty())
+      throw Error(XTRG_EINVAL, "u1: the input MPOs carry no S^z charges (xtrg_init_rho_u1, xtrg_mpo_label_charges)");
+    C.qc = inb->charges;                   // C = B
+  }
   d.Da = ina->dims;
   d.Db = inb->dims;
   d.Dc = inb->dims;                        // initial guess C = B (right-canonical)
@@ -981,12 +1273,20 @@ void chain_truncate_split(xtrg_ctx c, Chain& C) {
   auto& d = C.d;
   const int i = C.i;
   const int mL = C.mL, mR = C.mR, Kt = C.Kt, len = C.len, p = C.p, pw = C.psvd;
-  std::vector<double> S = read_vec(c, xtrg::svd_sorted_values(C.work, len, pw), pw);
-  for (double v : S)
-    if (!std::isfinite(v)) throw Error(XTRG_ENUMERIC, "non-finite singular value");
-  const std::vector<double> S_all = S;
-  S.resize(std::min(mL, mR));
-  const double kf = noise_floor(c, C.work, len, pw, p);
+  std::vector<double> S, S_all;
+  double kf = 0.0;
+  if (C.u1) {
+    bsvd_merge(c, C.tag, C.bs);
+    S = C.bs.S;
+    kf = xtrg::svd_keep_rel(len, p) * std::sqrt(C.bs.fro2);
+  } else {
+    S = read_vec(c, xtrg::svd_sorted_values(C.work, len, pw), pw);
+    for (double v : S)
+      if (!std::isfinite(v)) throw Error(XTRG_ENUMERIC, "non-finite singular value");
+    S_all = S;
+    S.resize(std::min(mL, mR));
+    kf = noise_floor(c, C.work, len, pw, p);
+  }
   const int k = keep_count(S, C.o.D_max, C.o.degen_rtol, C.o.sv_floor, kf);
   double tot = 0.0, kw = 0.0;
   for (size_t q = 0; q < S.size(); ++q) {
@@ -1003,7 +1303,10 @@ void chain_truncate_split(xtrg_ctx c, Chain& C) {
   if (C.gauge_right) {
     {
       Timed tm(c, P_SPLIT, 2.0 * k * (double)mL * mR, 0.0);
-      xtrg::svd_gather(len, pw, C.work, k, Ci, k, 1, s);                              // C_i = U [mL][k]
+      if (C.u1)
+        bsvd_scatter(c, C.tag, C.bs, k, Ci, 1);
+      else
+        xtrg::svd_gather(len, pw, C.work, k, Ci, k, 1, s);                            // C_i = U [mL][k]
       orthonormalize(c, Ci, mL, k, true);
       gemm(c, plain(k, mR, mL, Ci, k, true, C.th, mL, true, Cn, mR));                 // C_{i+1} = U^T theta
     }
@@ -1013,7 +1316,10 @@ void chain_truncate_split(xtrg_ctx c, Chain& C) {
   } else {
     {
       Timed tm(c, P_SPLIT, 2.0 * k * (double)mL * mR, 0.0);
-      xtrg::svd_gather(len, pw, C.work, k, Cn, len, 0, s);                            // C_{i+1} = V^T [k][mR]
+      if (C.u1)
+        bsvd_scatter(c, C.tag, C.bs, k, Cn, 0);
+      else
+        xtrg::svd_gather(len, pw, C.work, k, Cn, len, 0, s);                          // C_{i+1} = V^T [k][mR]
       orthonormalize(c, Cn, mR, k, false);
       gemm(c, plain(mL, k, mR, C.th, mR, false, Cn, mR, true, Ci, k));                // C_i = theta V
     }
@@ -1022,7 +1328,8 @@ void chain_truncate_split(xtrg_ctx c, Chain& C) {
     gemm(c, d.wplain(d.Da[i + 1] * d.Db[i + 1], k, mR, C.Rb, mR, false, d.Cw[i + 1], mR, true, C.F, k));  // F_{i+1}
   }
   d.Dc[i + 1] = k;
-  if (!C.o.no_warm_start && C.revisit[C.st]) {
+  if (C.u1) C.qc[i + 1].assign(C.bs.qs.begin(), C.bs.qs.begin() + k);
+  if (!C.u1 && !C.o.no_warm_start && C.revisit[C.st]) {
     Timed tm(c, P_WARM, 0.0, 0.0);
     build_warm(c, C, S_all, kf, 0x5EEDull + 7919ull * (unsigned long long)i);
   }
@@ -1159,7 +1466,8 @@ int square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_comp
       double fw = 0.0;
       for (Chain* C : act) {
         const auto& w = C->warm[C->i];
-        if (C->status == XTRG_OK && !C->o.no_warm_start && C->p >= kWarmMin && w.side == (C->gauge_right ? 1 : 0) &&
+        if (C->status == XTRG_OK && !C->u1 && !C->o.no_warm_start && C->p >= kWarmMin &&
+            w.side == (C->gauge_right ? 1 : 0) &&
             w.dim == C->p)
           fw += 2.0 * C->len * (double)C->p * w.cols;
       }
@@ -1173,7 +1481,7 @@ int square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_comp
           C->warm_now = false;
           const auto& w = C->warm[C->i];
           const int need_side = C->gauge_right ? 1 : 0;   // the column index of Y
-          if (!C->o.no_warm_start && C->p >= kWarmMin && w.side == need_side && w.dim == C->p) {
+          if (!C->u1 && !C->o.no_warm_start && C->p >= kWarmMin && w.side == need_side && w.dim == C->p) {
             const double* Q = c->need("wq" + std::to_string(C->i) + C->tag, (size_t)C->p * w.cols);
             double* Yw = c->need("svd_in" + C->tag, (size_t)C->len * w.cols);
             gw.push_back(plain(w.cols, C->len, C->p, Q, C->p, false, C->th, C->len, false, Yw, C->len));   // Y [Q0 X]
@@ -1182,7 +1490,7 @@ int square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_comp
             C->warm_now = true;
             c->warm_used += 1;
           }
-          C->work = c->need("svd" + C->tag, xtrg::svd_work(C->len, C->psvd));
+          if (!C->u1) C->work = c->need("svd" + C->tag, xtrg::svd_work(C->len, C->psvd));
         });
       gemm_group(c, gw);
     }
@@ -1191,7 +1499,7 @@ int square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_comp
       for (Chain* C : act)
         // first visits only: a warm basis (square when the previous visit's
         // spectrum was all above the noise) already gives a cheap Jacobi
-        if (C->status == XTRG_OK && !C->warm_now && !C->o.no_warm_start && !C->o.no_qr_start &&
+        if (C->status == XTRG_OK && !C->u1 && !C->warm_now && !C->o.no_warm_start && !C->o.no_qr_start &&
             C->p >= kQrMin && C->len >= kQrMin && C->len <= xtrg::kQrMaxLen && C->p <= 2048)
           pre.push_back(C);
       if (!pre.empty()) {
@@ -1215,6 +1523,26 @@ int square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_comp
       job_chain.clear();
       for (Chain* C : act) {
         if (C->status != XTRG_OK || C->svd_done) continue;
+        if (C->u1) {
+          // one problem per charge block of C_E (len side: the index that
+          // takes the isometry)
+          const int i = C->i;
+          const auto qr = row_charges(C->qc[i]), qcol = col_charges(C->qc[i + 2]);
+          const size_t j0 = jobs.size();
+          per_chain(*C, [&] {
+            bsvd_prepare(c, C->tag, C->th, C->len, C->p, C->gauge_right ? qr : qcol, C->gauge_right ? qcol : qr,
+                         C->bs, jobs);
+          });
+          if (C->status != XTRG_OK) {   // its workspaces refused by the budget
+            jobs.resize(j0);
+            continue;
+          }
+          for (size_t j = j0; j < jobs.size(); ++j) {
+            job_chain.push_back(C);
+            bs += 8.0 * jobs[j].len * (double)jobs[j].p;
+          }
+          continue;
+        }
         jobs.push_back(xtrg::SvdJob{C->len, C->psvd, C->Y, C->work, 0, svd_gram(c, C->tag, C->psvd)});
         job_chain.push_back(C);
         bs += 8.0 * C->len * (double)C->psvd;
@@ -1244,6 +1572,7 @@ int square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_comp
       xtrg::scale(d.C[0].p, 1.0 / ch[q].last_norm, (size_t)4 * d.Dc[1], s);
       res[q] = new_mpo(c, d.Dc);
       for (int i = 0; i < d.L; ++i) xtrg::copy(res[q]->site[i].p, d.C[i].p, res[q]->elems(i), s);
+      if (ch[q].u1) res[q]->charges = ch[q].qc;
     });
   XTRG_HIP(hipStreamSynchronize(s));
   int failed = 0;
@@ -1653,7 +1982,7 @@ std::unique_ptr<xtrg_mpo_s> hamiltonian(xtrg_ctx c, int n_sites, int n_bonds, co
 }
 
 std::unique_ptr<xtrg_mpo_s> init_rho(xtrg_ctx c, xtrg_mpo H, double tau0, int order, int D0_max,
-                                   double* log_norm) {
+                                   double* log_norm, bool u1) {
   if (!H->has_open || order < 1 || order > 2 || !(tau0 > 0))
   throw Error(XTRG_EINVAL, "init_rho: H from xtrg_hamiltonian_xxz, order 1 or 2, tau0 > 0");
   hipStream_t s = c->stream;
@@ -1691,8 +2020,29 @@ std::unique_ptr<xtrg_mpo_s> init_rho(xtrg_ctx c, xtrg_mpo H, double tau0, int or
     gemm(c, plain(Dl * Dl * 4, 1, 4, prod, 4, false, rv, 1, false, m->site[L - 1].p, 1));
   }
   // lossless compression to canonical form: exact zeros dropped
-  left_sweep(m.get(), 1e-14, nullptr);
-  right_sweep(m.get(), 1e-14, D0_max, nullptr);
+  if (u1) {
+    // charges of the automaton states from H's entries; the product of two
+    // automata carries q_a + q_b on its state (a, b)
+    if (H->charges.empty()) H->charges = infer_charges(download_sites(H), H->dims);
+    auto& q = m->charges;
+    q.assign(L + 1, {});
+    for (int i = 0; i <= L; ++i) {
+      const auto& h = H->charges[i];
+      if (i == L) {
+        q[i].assign(m->dims[L], 0);
+      } else if (order == 1) {
+        q[i] = h;
+      } else {
+        for (int a = 0; a < (int)h.size(); ++a)
+          for (int b = 0; b < (int)h.size(); ++b) q[i].push_back(h[a] + h[b]);
+      }
+    }
+    left_sweep_u1(m.get(), 1e-14);
+    right_sweep_u1(m.get(), 1e-14, D0_max);
+  } else {
+    left_sweep(m.get(), 1e-14, nullptr);
+    right_sweep(m.get(), 1e-14, D0_max, nullptr);
+  }
   const double nrm = site_norm(m.get(), 0);
   if (!(nrm > 0) || !std::isfinite(nrm)) throw Error(XTRG_ENUMERIC, "rho(tau0) has zero norm");
   xtrg::scale(m->site[0].p, 1.0 / nrm, m->elems(0), s);
@@ -1985,6 +2335,32 @@ int xtrg_init_rho(xtrg_ctx c, xtrg_mpo H, double tau0, int order, int D0_max, xt
     set_device(c);
     *rho_out = xtrg_impl::init_rho(c, H, tau0, order, D0_max, log_norm).release();
   });
+}
+
+int xtrg_init_rho_u1(xtrg_ctx c, xtrg_mpo H, double tau0, int order, int D0_max, xtrg_mpo* rho_out,
+                     double* log_norm) {
+  if (!c || !H || !rho_out || !log_norm || !(tau0 > 0) || order < 1 || order > 2) return XTRG_EINVAL;
+  if (!H->has_open) return XTRG_EINVAL;
+  return guarded(c, [&] {
+    set_device(c);
+    *rho_out = xtrg_impl::init_rho(c, H, tau0, order, D0_max, log_norm, true).release();
+  });
+}
+
+int xtrg_mpo_label_charges(xtrg_mpo m) {
+  if (!m) return XTRG_EINVAL;
+  return guarded(m->ctx, [&] {
+    set_device(m->ctx);
+    m->charges = infer_charges(download_sites(m), m->dims);
+  });
+}
+
+int xtrg_mpo_charges(xtrg_mpo m, int* charges) {
+  if (!m || !charges || m->charges.empty()) return XTRG_EINVAL;
+  size_t o = 0;
+  for (const auto& q : m->charges)
+    for (int v : q) charges[o++] = v;
+  return XTRG_OK;
 }
 
 int xtrg_settn_init(xtrg_ctx c, xtrg_mpo H, double tau0, int D_max, int n_sweeps, double tol, xtrg_mpo* rho_out,

@@ -110,6 +110,11 @@ struct xtrg_mpo_s {
   // last index: start, stop) on the host for the series start.
   bool has_open = false;
   std::vector<double> open_last;
+  // S^z charge of every bond index (L+1 lists, bond i has dims[i] entries),
+  // or empty: the MPO's bond bases are not known to be charge-definite.
+  // Index s = 0 of a site is up; the entry W[a][s][s'][b] is non-zero only
+  // if q_b = q_a + (s' - s).
+  std::vector<std::vector<int>> charges;
 
   ~xtrg_mpo_s() {
     for (auto& s : site) ctx->release(s.p, s.n);
@@ -124,7 +129,7 @@ namespace xtrg_impl {
 std::unique_ptr<xtrg_mpo_s> hamiltonian(xtrg_ctx c, int n_sites, int n_bonds, const int* bonds, const double* jxy,
                                         const double* jz);
 std::unique_ptr<xtrg_mpo_s> init_rho(xtrg_ctx c, xtrg_mpo H, double tau0, int order, int D0_max,
-                                     double* log_norm);
+                                     double* log_norm, bool u1 = false);
 std::unique_ptr<xtrg_mpo_s> settn_init(xtrg_ctx c, xtrg_mpo H, double tau0, int D, int n_sweeps, double tol,
                                        double* log_norm, int* n_terms);
 std::unique_ptr<xtrg_mpo_s> taylor_step(xtrg_ctx c, xtrg_mpo H, xtrg_mpo rho, double dtau, int D, int n_sweeps,

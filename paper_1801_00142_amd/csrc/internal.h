@@ -185,6 +185,15 @@ void sumsq(const double* x, size_t n, double* out, double* part, hipStream_t s);
 // C[(a,b), s, u, (a',b')] = sum_t A[a,s,t,a'] B[b,t,u,b'] (exact MPO product site)
 void site_product(double* C, const double* A, int Dla, int Dra, const double* B, int Dlb, int Drb,
                   hipStream_t s);
+// dst (rows x cols, column-major) = src[ri[i] + ci[j]*ld]: the rows ri and
+// columns ci of a column-major matrix (index arrays on the device).
+void gather_block(double* dst, const double* src, long ld, const int* ri, int rows, const int* ci, int cols,
+                  hipStream_t s);
+// Column t of src (rows x cols, column-major) into column pos[t] of a dense
+// len x k matrix at rows ri: dst[ri[i]*k + pos[t]] (rowmajor) or
+// dst[pos[t]*len + ri[i]]; other entries of dst are left as they are.
+void scatter_cols(double* dst, int len, int k, int rowmajor, const double* src, int rows, int cols, const int* ri,
+                  const int* pos, hipStream_t s);
 // out[a][a'] = sum_s W[a][s][s][a']
 void phys_trace(double* out, const double* W, int Dl, int Dr, hipStream_t s);
 

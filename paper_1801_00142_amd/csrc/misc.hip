@@ -275,6 +275,29 @@ void phys_trace(double* out, const double* W, int Dl, int Dr, hipStream_t s) {
   XTRG_HIP(hipGetLastError());
 }
 
+// dst[i + j*rows] = src[ri[i] + ci[j]*ld]: one charge block of a matrix.
+__global__ void k_gather_block(double* __restrict__ dst, const double* __restrict__ src, long ld,
+                               const int* __restrict__ ri, int rows, const int* __restrict__ ci, int cols) {
+  const long n = (long)rows * cols;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % rows), j = (int)(e / rows);
+    dst[e] = src[ri[i] + (long)ci[j] * ld];
+  }
+}
+
+// Column t of src (rows x cols, column-major) goes to column pos[t] of a
+// dense len x k matrix, row i to row ri[i]: dst[r*k + j] (rowmajor) or
+// dst[j*len + r].
+__global__ void k_scatter_cols(double* __restrict__ dst, int len, int k, int rowmajor, const double* __restrict__ src,
+                               int rows, int cols, const int* __restrict__ ri, const int* __restrict__ pos) {
+  const long n = (long)rows * cols;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % rows), t = (int)(e / rows);
+    const long r = ri[i], j = pos[t];
+    dst[rowmajor ? r * k + j : j * len + r] = src[e];
+  }
+}
+
 // out (row-major over the n dims, extents e) = src at offset sum_d i_d st_d.
 __global__ void k_permute(Permute p, long n_total) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n_total; i += (long)gridDim.x * blockDim.x) {
@@ -286,6 +309,22 @@ __global__ void k_permute(Permute p, long n_total) {
     }
     p.out[i] = p.src[off];
   }
+}
+
+void gather_block(double* dst, const double* src, long ld, const int* ri, int rows, const int* ci, int cols,
+                  hipStream_t s) {
+  const size_t n = (size_t)rows * cols;
+  if (!n) return;
+  hipLaunchKernelGGL(k_gather_block, grid_for(n), dim3(kT), 0, s, dst, src, ld, ri, rows, ci, cols);
+  XTRG_HIP(hipGetLastError());
+}
+
+void scatter_cols(double* dst, int len, int k, int rowmajor, const double* src, int rows, int cols, const int* ri,
+                  const int* pos, hipStream_t s) {
+  const size_t n = (size_t)rows * cols;
+  if (!n) return;
+  hipLaunchKernelGGL(k_scatter_cols, grid_for(n), dim3(kT), 0, s, dst, len, k, rowmajor, src, rows, cols, ri, pos);
+  XTRG_HIP(hipGetLastError());
 }
 
 void permute(const Permute& p, hipStream_t s) {

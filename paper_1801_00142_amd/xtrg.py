@@ -30,7 +30,7 @@ class XtrgError(RuntimeError):
 class CompressOpts(C.Structure):
     _fields_ = [("D_max", C.c_int), ("n_sweeps", C.c_int), ("precision", C.c_int),
                 ("degen_rtol", C.c_double), ("sv_floor", C.c_double), ("no_warm_start", C.c_int),
-                ("no_qr_start", C.c_int)]
+                ("no_qr_start", C.c_int), ("u1", C.c_int)]
 
 
 class CompressInfo(C.Structure):
@@ -76,6 +76,9 @@ def load_library(path: Optional[str] = None):
         "xtrg_mpo_to_host": (C.c_int, [vp, C.POINTER(dp)]),
         "xtrg_mpo_destroy": (C.c_int, [vp]),
         "xtrg_init_rho": (C.c_int, [vp, vp, C.c_double, C.c_int, C.c_int, C.POINTER(vp), dp]),
+        "xtrg_init_rho_u1": (C.c_int, [vp, vp, C.c_double, C.c_int, C.c_int, C.POINTER(vp), dp]),
+        "xtrg_mpo_label_charges": (C.c_int, [vp]),
+        "xtrg_mpo_charges": (C.c_int, [vp, ip]),
         "xtrg_square_compress": (C.c_int, [vp, vp, C.POINTER(CompressOpts), C.POINTER(vp),
                                            C.POINTER(CompressInfo)]),
         "xtrg_product_compress": (C.c_int, [vp, vp, vp, C.POINTER(CompressOpts), C.POINTER(vp),
@@ -118,7 +121,8 @@ def load_library(path: Optional[str] = None):
 def exported_symbols() -> List[str]:
     return ["xtrg_ctx_create", "xtrg_ctx_destroy", "xtrg_last_error", "xtrg_ctx_bytes", "xtrg_ctx_trim",
             "xtrg_hamiltonian_xxz", "xtrg_mpo_from_host", "xtrg_mpo_shape", "xtrg_mpo_to_host",
-            "xtrg_mpo_destroy", "xtrg_init_rho", "xtrg_square_compress", "xtrg_product_compress", "xtrg_square_compress_batched", "xtrg_observables",
+            "xtrg_mpo_destroy", "xtrg_init_rho", "xtrg_init_rho_u1", "xtrg_mpo_label_charges", "xtrg_mpo_charges",
+            "xtrg_square_compress", "xtrg_product_compress", "xtrg_square_compress_batched", "xtrg_observables",
             "xtrg_dgemm", "xtrg_dgemm_noalloc", "xtrg_sgemm", "xtrg_gemm_bf16x3", "xtrg_dsvd_left", "xtrg_dsvd_left_qr", "xtrg_dqrcp", "xtrg_spin_sum_mpo", "xtrg_correlation_mpo", "xtrg_expectation", "xtrg_serve_submit", "xtrg_serve_poll", "xtrg_serve_set_lanes", "xtrg_settn_init", "xtrg_taylor_step", "xtrg_profile_enable",
             "xtrg_profile_report"]
 
@@ -146,6 +150,20 @@ class MPO:
         ptrs = (C.POINTER(C.c_double) * L)(*[a.ctypes.data_as(C.POINTER(C.c_double)) for a in arrs])
         _check(self.ctx, _lib.xtrg_mpo_to_host(self.h, ptrs))
         return arrs
+
+    def charges(self) -> List[np.ndarray]:
+        """S^z charge of every bond index (L+1 arrays), for MPOs with
+        charge-definite bonds (xtrg_init_rho_u1, label_charges, u1 doublings)."""
+        L, dims = self.shape()
+        buf = (C.c_int * sum(dims))()
+        _check(self.ctx, _lib.xtrg_mpo_charges(self.h, buf))
+        flat = np.frombuffer(buf, dtype=np.int32).astype(np.int64)
+        return list(np.split(flat, np.cumsum(dims)[:-1]))
+
+    def label_charges(self):
+        """Read the charges of the bond indices from the non-zero entries."""
+        _check(self.ctx, _lib.xtrg_mpo_label_charges(self.h))
+        return self
 
     def close(self):
         # an MPO is released before its context; after Context.close() the
@@ -223,10 +241,11 @@ class Context:
         _check(self, _lib.xtrg_mpo_from_host(self.h, L, 2, dims, ptrs, C.byref(h)))
         return MPO(self, h)
 
-    def init_rho(self, H: MPO, tau0: float, order: int = 1, D0_max: int = 0):
+    def init_rho(self, H: MPO, tau0: float, order: int = 1, D0_max: int = 0, u1: bool = False):
         h = C.c_void_p()
         lam = C.c_double()
-        _check(self, _lib.xtrg_init_rho(self.h, H.h, tau0, order, D0_max, C.byref(h), C.byref(lam)))
+        f = _lib.xtrg_init_rho_u1 if u1 else _lib.xtrg_init_rho
+        _check(self, f(self.h, H.h, tau0, order, D0_max, C.byref(h), C.byref(lam)))
         return MPO(self, h), lam.value
 
     def settn_init(self, H: MPO, tau0: float, D_max: int, n_sweeps: int = 2, tol: float = 1e-15):
@@ -251,9 +270,9 @@ class Context:
 
     def square_compress(self, rho: MPO, D_max: int, n_sweeps: int = 4, degen_rtol: float = 1e-6,
                         sv_floor: float = 1e-14, sv_stride: int = 0, precision: int = XTRG_FP64,
-                        warm_start: bool = True, qr_start: bool = True):
+                        warm_start: bool = True, qr_start: bool = True, u1: bool = False):
         o = CompressOpts(D_max, n_sweeps, precision, degen_rtol, sv_floor, int(not warm_start),
-                         int(not qr_start))
+                         int(not qr_start), int(u1))
         info = CompressInfo()
         L = rho.shape()[0]
         buf = None
@@ -271,9 +290,10 @@ class Context:
 
     def product_compress(self, A: MPO, B: MPO, D_max: int, n_sweeps: int = 4, degen_rtol: float = 1e-6,
                          sv_floor: float = 1e-14, precision: int = XTRG_FP64, warm_start: bool = True,
-                         qr_start: bool = True):
+                         qr_start: bool = True, u1: bool = False):
         """out ~ A B / c (B: the right-canonical initial guess); returns (MPO, info)."""
-        o = CompressOpts(D_max, n_sweeps, precision, degen_rtol, sv_floor, int(not warm_start), int(not qr_start))
+        o = CompressOpts(D_max, n_sweeps, precision, degen_rtol, sv_floor, int(not warm_start), int(not qr_start),
+                         int(u1))
         info = CompressInfo()
         h = C.c_void_p()
         _check(self, _lib.xtrg_product_compress(self.h, A.h, B.h, C.byref(o), C.byref(h), C.byref(info)))
@@ -283,7 +303,8 @@ class Context:
 
     def square_compress_batched(self, rhos: Sequence[MPO], D_max, n_sweeps=4,
                                 degen_rtol: float = 1e-6, sv_floor: float = 1e-14, sv_stride: int = 0,
-                                precision=XTRG_FP64, warm_start: bool = True, qr_start: bool = True):
+                                precision=XTRG_FP64, warm_start: bool = True, qr_start: bool = True,
+                                u1: bool = False):
         """One doubling of every chain in `rhos` together.  D_max, n_sweeps and
         precision are one value for all chains or a sequence with one per
         chain.  Returns ([new MPO per chain], [info dict per chain]).  A chain
@@ -299,7 +320,7 @@ class Context:
             return out
         Ds, Ss, Ps = per(D_max, "D_max"), per(n_sweeps, "n_sweeps"), per(precision, "precision")
         o = (CompressOpts * n)(*[CompressOpts(Ds[q], Ss[q], Ps[q], degen_rtol, sv_floor, int(not warm_start),
-                                              int(not qr_start))
+                                              int(not qr_start), int(u1))
                                for q in range(n)])
         infos = (CompressInfo * n)()
         bufs = []
@@ -462,7 +483,8 @@ class Context:
 
 def run(ctx: Context, n_sites: int, bonds, jxy, jz, tau0: float, n_doublings: int, D: int, order: int = 1,
         n_sweeps: int = 4, degen_rtol: float = 1e-6, sv_floor: float = 1e-14, observe: bool = True,
-        entropy: bool = False, precision: int = XTRG_FP64, beta_mix: float = 1.0, series_tol: float = 0.0):
+        entropy: bool = False, precision: int = XTRG_FP64, beta_mix: float = 1.0, series_tol: float = 0.0,
+        u1: bool = False):
     """Full XTRG run through the library: rho(tau0), then n_doublings doublings;
     returns per-doubling records (observables at beta = tau_n and 2 tau_n).
 
@@ -473,12 +495,15 @@ def run(ctx: Context, n_sites: int, bonds, jxy, jz, tau0: float, n_doublings: in
     precision != XTRG_FP64 applies from the doubling whose result reaches
     beta = 2 tau_{n+1} >= beta_mix; earlier doublings run in FP64.  The
     relative error a doubling leaves in ln Z enters f = -ln Z/(N beta) divided
-    by beta, so the high-temperature doublings need the most precision."""
+    by beta, so the high-temperature doublings need the most precision.
+
+    u1: charge-definite bonds throughout (xtrg_init_rho_u1, and every
+    doubling factorises its two-site tensors by S^z charge blocks)."""
     H = ctx.hamiltonian_xxz(n_sites, bonds, jxy, jz)
     if series_tol > 0:
         rho, lam, _ = ctx.settn_init(H, tau0, D, 2, series_tol)
     else:
-        rho, lam = ctx.init_rho(H, tau0, order)
+        rho, lam = ctx.init_rho(H, tau0, order, u1=u1)
     tau = tau0
     recs = []
 
@@ -493,7 +518,7 @@ def run(ctx: Context, n_sites: int, bonds, jxy, jz, tau0: float, n_doublings: in
     recs.append(rec(0))
     for n in range(1, n_doublings + 1):
         prec = precision if 4 * tau >= beta_mix else XTRG_FP64
-        new, info = ctx.square_compress(rho, D, n_sweeps, degen_rtol, sv_floor, precision=prec)
+        new, info = ctx.square_compress(rho, D, n_sweeps, degen_rtol, sv_floor, precision=prec, u1=u1)
         rho.close()
         rho = new
         lam = 2 * lam + info["dlog_norm"]

@@ -23,6 +23,11 @@ CASES = {
     # those budgets): linear start at tau0 = 2^-8, 11 doublings, 2 sweeps
     "chain12_D128": dict(workload="chain12", D=128, n_sweeps=2),
     "chain12_D256": dict(workload="chain12", D=256, n_sweeps=2),
+    # the same runs with charge-definite bonds: the start by block SVD sweeps,
+    # every C_E factorised by S^z charge blocks (oracle u1 route)
+    "chain10_D64_u1": dict(workload="chain10", D=64, n_sweeps=4, u1=True),
+    "chain12_D128_u1": dict(workload="chain12", D=128, n_sweeps=2, u1=True),
+    "chain12_D256_u1": dict(workload="chain12", D=256, n_sweeps=2, u1=True),
 }
 
 
@@ -33,8 +38,9 @@ def main(names):
         lat = wl.lattice
         t0 = time.time()
         recs = xtrg.run(lat.n_sites, lat.bonds, lat.jxy, lat.jz, wl.tau0, wl.n_doublings, wl.D,
-                        order=wl.init_order, n_sweeps=cfg["n_sweeps"])
-        out = dict(case=name, workload=cfg["workload"], D=wl.D, n_sweeps=cfg["n_sweeps"], tau0=wl.tau0,
+                        order=wl.init_order, n_sweeps=cfg["n_sweeps"], u1=cfg.get("u1", False))
+        out = dict(case=name, workload=cfg["workload"], D=wl.D, n_sweeps=cfg["n_sweeps"], u1=cfg.get("u1", False),
+                   tau0=wl.tau0,
                    order=wl.init_order, n_doublings=wl.n_doublings, n_sites=lat.n_sites,
                    seconds=time.time() - t0, records=[])
         for r in recs:

@@ -1,0 +1,176 @@
+"""GPU parity of the U(1) charge-sector route (Sec. II.A: the XXZ models
+conserve S^z_tot; App. B.2) against the oracle's u1 route.
+
+The library keeps the tensors dense and labels every bond index with its
+S^z charge; each two-site tensor C_E is factorised block by block (one
+grouped Jacobi launch per round over all blocks) and the keep rule runs on
+the merged values.  Checked here through the C ABI:
+* the charges the library attaches to its start and to every doubling's
+  output are the ones the oracle reads from the exact zeros of the same
+  downloaded tensors (integers, exact);
+* one doubling from the same charge-definite input as the oracle: ln c,
+  bond dimensions, charge counts per bond and the dense operator;
+* whole runs against stored oracle u1 runs (tests/golden/make_golden.py)
+  at D = 64, 128 and 256: f, u, c at both estimators, lambda, bond
+  dimensions;
+* inputs without charges are refused.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import mpo as M
+from oracle import xtrg as OX
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1801_00142_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _same_charges(gpu_q, ref_q):
+    assert len(gpu_q) == len(ref_q)
+    for i, (g, r) in enumerate(zip(gpu_q, ref_q)):
+        assert np.array_equal(np.asarray(g), np.asarray(r)), i
+
+
+def _counts(q):
+    return [dict(zip(*np.unique(np.asarray(b), return_counts=True))) for b in q]
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_u1_start_charges_and_operator(ctx, order):
+    """xtrg_init_rho_u1 on the L = 8 chain: the charges the library reports
+    are those the oracle infers from the downloaded tensors; the operator,
+    ln ||rho||, the bond dimensions and the charge counts equal the oracle's
+    init_rho_u1."""
+    lat = W.chain(8)
+    tau0 = 2.0 ** -6
+    H = ctx.hamiltonian_xxz(lat.n_sites, lat.bonds, lat.jxy, lat.jz)
+    rho, lam = ctx.init_rho(H, tau0, order, u1=True)
+    Wg = rho.to_host()
+    qg = rho.charges()
+    _same_charges(qg, OX.bond_charges(Wg))
+    Wo, lam_o = OX.init_rho_u1(lat.n_sites, lat.bonds, lat.jxy, lat.jz, tau0, order)
+    assert abs(lam - lam_o) < 1e-13 * max(1.0, abs(lam_o))
+    assert rho.bond_dims == M.bond_dims(Wo)
+    assert _counts(qg) == _counts(OX.bond_charges(Wo))
+    Dg, Do = M.to_dense(Wg), M.to_dense(Wo)
+    assert np.abs(Dg - Do).max() < 1e-13 * np.abs(Do).max()
+
+
+def test_u1_doubling_from_the_oracle_state(ctx):
+    """One u1 doubling from the oracle's charge-definite state of the L = 8
+    chain after three u1 doublings at D = 24 (uploaded, charges read by
+    xtrg_mpo_label_charges): ln c, bond dimensions and charge counts equal
+    the oracle's u1 doubling of the same input, the output's charges are
+    the ones its zeros imply, and the dense operators agree."""
+    lat = W.chain(8)
+    rho, lam = OX.init_rho_u1(lat.n_sites, lat.bonds, lat.jxy, lat.jz, 2.0 ** -4, 1)
+    for _ in range(3):
+        rho, _ = OX.square_compress(rho, 24, 2, u1=True)
+    ref, info = OX.square_compress(rho, 24, 2, u1=True)
+    g = ctx.mpo_from_host(rho).label_charges()
+    _same_charges(g.charges(), OX.bond_charges(rho))
+    out, ginfo = ctx.square_compress(g, 24, 2, u1=True)
+    assert abs(ginfo["dlog_norm"] - info.dlog_norm) < 1e-12
+    assert out.bond_dims == M.bond_dims(ref)
+    Wg = out.to_host()
+    qg = out.charges()
+    _same_charges(qg, OX.bond_charges(Wg))
+    assert _counts(qg) == _counts(info.charges)
+    Dg, Do = M.to_dense(Wg), M.to_dense(ref)
+    assert np.abs(Dg - Do).max() < 1e-11 * np.abs(Do).max()
+
+
+def test_u1_product_of_two_states(ctx):
+    """xtrg_product_compress with u1 (A != B: two temperatures of the same
+    chain) against the oracle's product_compress(u1=True)."""
+    lat = W.chain(8)
+    A, _ = OX.init_rho_u1(lat.n_sites, lat.bonds, lat.jxy, lat.jz, 2.0 ** -3, 1)
+    B, _ = OX.init_rho_u1(lat.n_sites, lat.bonds, lat.jxy, lat.jz, 2.0 ** -2, 2)
+    ref, info = OX.product_compress(A, B, 16, 2, u1=True)
+    gA = ctx.mpo_from_host(A).label_charges()
+    gB = ctx.mpo_from_host(B).label_charges()
+    out, ginfo = ctx.product_compress(gA, gB, 16, 2, u1=True)
+    assert abs(ginfo["dlog_norm"] - info.dlog_norm) < 1e-12
+    assert out.bond_dims == M.bond_dims(ref)
+    Dg, Do = M.to_dense(out.to_host()), M.to_dense(ref)
+    assert np.abs(Dg - Do).max() < 1e-11 * np.abs(Do).max()
+
+
+def test_u1_needs_charges(ctx):
+    """A doubling with u1 on an MPO without charges, or with charges that
+    its tensors do not conserve, is refused with XTRG_EINVAL."""
+    from paper_1801_00142_amd.xtrg import XtrgError
+    lat = W.chain(6)
+    H = ctx.hamiltonian_xxz(lat.n_sites, lat.bonds, lat.jxy, lat.jz)
+    rho, _ = ctx.init_rho(H, 0.01, 1)
+    with pytest.raises(XtrgError):
+        ctx.square_compress(rho, 16, 1, u1=True)
+    with pytest.raises(XtrgError):
+        rho.charges()
+    # a charge-definite state is labelled; with an S^x term added to one
+    # entry its charges are contradictory, and the inference refuses it
+    Wo, _ = OX.init_rho_u1(lat.n_sites, lat.bonds, lat.jxy, lat.jz, 0.01, 1)
+    ctx.mpo_from_host(Wo).label_charges()
+    Wh = [w.copy() for w in Wo]
+    Wh[2][0, 0, 1, 0] += 0.5
+    Wh[2][0, 1, 0, 0] += 0.5
+    bad = ctx.mpo_from_host(Wh)
+    with pytest.raises(XtrgError):
+        bad.label_charges()
+
+
+def _golden(name):
+    path = os.path.join(GOLD, f"oracle_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"stored oracle run {name} missing (tests/golden/make_golden.py)")
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name", ["chain10_D64_u1", "chain12_D128_u1", "chain12_D256_u1"])
+def test_u1_chain_against_stored_oracle(ctx, name):
+    """Whole u1 runs (charge-definite start, every doubling by charge
+    blocks) against the oracle's u1 runs: f and u to 1e-9, c to 1e-7
+    (relative, floor 1e-3), lambda, bond dimensions at every beta."""
+    from paper_1801_00142_amd import run
+    from test_gpu_fullsize import check_against_golden, _errors
+    ref = _golden(name)
+    assert ref.get("u1")
+    lat = W.workload(ref["workload"], ref["D"]).lattice
+    gpu = run(ctx, lat.n_sites, lat.bonds, lat.jxy, lat.jz, ref["tau0"], ref["n_doublings"], ref["D"],
+              order=ref["order"], n_sweeps=ref["n_sweeps"], u1=True)
+    print(name, _errors(gpu, ref))
+    check_against_golden(gpu, ref, 1e-9, 1e-7)
+
+
+def test_u1_batched_equals_single(ctx):
+    """The batched doubling with u1 gives every chain the bits of its single
+    call (the blocks of all chains share the grouped Jacobi launches)."""
+    lat = W.chain(10)
+    H = ctx.hamiltonian_xxz(lat.n_sites, lat.bonds, lat.jxy, lat.jz)
+    rhos = [ctx.init_rho(H, t, 1, u1=True)[0] for t in (2.0 ** -3, 2.0 ** -2.5)]
+    outs, infos = ctx.square_compress_batched(rhos, 32, 2, u1=True)
+    for r, o, inf in zip(rhos, outs, infos):
+        s, sinf = ctx.square_compress(r, 32, 2, u1=True)
+        assert inf["status"] == 0
+        assert sinf["dlog_norm"] == inf["dlog_norm"]
+        assert s.bond_dims == o.bond_dims
+        for a, b in zip(s.to_host(), o.to_host()):
+            assert np.array_equal(a, b)
+        for a, b in zip(s.charges(), o.charges()):
+            assert np.array_equal(a, b)
