@@ -45,6 +45,10 @@ PEAK_HBM_GBS = 8000.0
 # measured: reset to None when they change.
 JACOBI_ROUND_TRAFFIC_1024 = 26.82e6
 JACOBI_ROUND_BYTES_1024 = 16.0 * 1024 * 1024   # algorithmic: every column read and written once
+# The same for the one-launch round (jacobi_round<0>) of the charge blocks of
+# the D = 256 two-site tensors: None until counters are taken on it.
+JACOBI_ROUND0_TRAFFIC = None
+JACOBI_ROUND0_BYTES = None
 
 
 def parse():
@@ -68,9 +72,9 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "fp32", "bf16x3"], default="fp64",
                     help="contraction precision of the doublings that reach beta >= --beta-mix")
     ap.add_argument("--beta-mix", type=float, default=1.0)
-    ap.add_argument("--u1", action="store_true",
-                    help="U(1) charge sectors: charge-definite start, every two-site tensor factorised by "
-                         "S^z charge blocks")
+    ap.add_argument("--dense", action="store_true",
+                    help="factorise every two-site tensor as one dense matrix (default: U(1) charge sectors, "
+                         "a charge-definite start and every two-site tensor factorised by S^z charge blocks)")
     ap.add_argument("--serve", type=int, default=0,
                     help="serve N requests of the scaled-down mixed workload instead (p50/p99 latency)")
     ap.add_argument("--serve-rate", type=float, default=2.0)
@@ -82,7 +86,9 @@ def parse():
     ap.add_argument("--serve-full", action="store_true",
                     help="the serving workload at its stated size: W in {4,6}, L in [8,16], D in {64,128,256}, "
                          "15 doublings (default: a scaled-down mix that finishes in about a minute)")
-    return ap.parse_args()
+    a = ap.parse_args()
+    a.u1 = not a.dense
+    return a
 
 
 def batch_leg(ctx, H, wl, args, mixed):
@@ -409,13 +415,17 @@ def main():
     th_avg_s = th["ms"] / max(th["calls"], 1) / 1e3
     th_flops = th["flops"] / max(th["calls"], 1)
     th_achieved = th_flops / th_avg_s / 1e12 if th_avg_s > 0 else 0.0
-    # the dominant kernel: the Jacobi round split over row slices (a Gram
-    # launch and a rotate launch back to back), timed by event pairs around
+    # the dominant kernel: the Jacobi round, timed by event pairs around
     # each sweep's launches; algorithmic bytes: every active column read and
-    # written once per round
-    n_rounds = max(rounds["calls"] // 2, 1)
-    round_us = rounds["ms"] / n_rounds * 1e3
-    round_bytes = rounds["bytes"] / n_rounds
+    # written once per round.  Dense 1024-row tensors take the round split
+    # over row slices (a Gram launch and a rotate launch back to back); the
+    # charge blocks (a few hundred rows) take the one-launch round, all
+    # blocks of a two-site tensor in one grouped launch.
+    sliced = rounds["ms"] >= rounds_fused["ms"]
+    rr = rounds if sliced else rounds_fused
+    n_rounds = max(rr["calls"] // (2 if sliced else 1), 1)
+    round_us = rr["ms"] / n_rounds * 1e3
+    round_bytes = rr["bytes"] / n_rounds
     round_gbs = round_bytes / (round_us * 1e-6) / 1e9 if round_us > 0 else 0.0
     total_ms = sum(v["ms"] for v in prof.values())
     shares = {k: round(v["ms"] / total_ms, 4) if total_ms else 0.0 for k, v in prof.items()}
@@ -477,13 +487,19 @@ def main():
                          "mean_rows": round(qr_stats["qr_rows"] / max(qr_stats["qr_calls"], 1), 1),
                          "rt_sweeps_avg": round(qr_stats["qr_sweeps"] / max(qr_stats["qr_used"], 1), 2)},
         "roofline": {"bound": "hbm",
-                     "kernel": "jacobi_round<1> + jacobi_round<2> (one block-Jacobi SVD round split over row "
-                               "slices: Gram launch, rotate launch)",
+                     "kernel": ("jacobi_round<1> + jacobi_round<2> (one block-Jacobi SVD round split over row "
+                                "slices: Gram launch, rotate launch)") if sliced else
+                               ("jacobi_round<0> (one block-Jacobi SVD round in one launch; every S^z charge "
+                                "block of the two-site tensor is a problem of the grouped launch)"),
                      "achieved": round(round_gbs, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(round_gbs / PEAK_HBM_GBS, 4),
-                     "traffic": JACOBI_ROUND_TRAFFIC_1024 * round_bytes / JACOBI_ROUND_BYTES_1024,
-                     "traffic_note": "rocprofv3 FETCH_SIZE + WRITE_SIZE of the 1024-column round, copy-scaled, "
-                                     "scaled to this run's mean algorithmic bytes per round",
+                     "traffic": (JACOBI_ROUND_TRAFFIC_1024 * round_bytes / JACOBI_ROUND_BYTES_1024 if sliced else
+                                 JACOBI_ROUND0_TRAFFIC * round_bytes / JACOBI_ROUND0_BYTES
+                                 if JACOBI_ROUND0_TRAFFIC else None),
+                     "traffic_note": ("rocprofv3 FETCH_SIZE + WRITE_SIZE of the " +
+                                      ("1024-column sliced round" if sliced else "one-launch round of the charge "
+                                       "blocks") + ", copy-scaled, scaled to this run's mean algorithmic bytes "
+                                      "per round"),
                      "rounds": n_rounds, "avg_round_us": round(round_us, 3), "bytes_per_round": round_bytes},
         "roofline_theta": theta_roofline(last_prec[0], th_achieved, th["calls"], th_avg_s, th_flops),
     }

@@ -9,6 +9,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
+#include <tuple>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -430,6 +432,8 @@ struct BlockSvd {
     int* d_idx = nullptr;
     double* Y = nullptr;
     double* work = nullptr;
+    int psvd = 0;           // columns of the SVD input (p, or more with a warm basis)
+    std::vector<double> S;  // after merge(): the block's values, descending
     int kept = 0;
   };
   std::vector<Blk> b;
@@ -445,8 +449,13 @@ struct BlockSvd {
 
 // Split Y into its charge blocks and append one SVD problem per block to
 // jobs.  `tag` names the workspaces (one set per concurrent factorisation).
+// warm(q, len_q, p_q, Y_q): the SVD input of block q (Y_q itself, or Y_q
+// rotated into a warm basis) and its column count.
+using WarmHook = std::function<std::pair<const double*, int>(int, int, int, const double*)>;
+
 void bsvd_prepare(xtrg_ctx c, const std::string& tag, const double* Y, int len, int p, const std::vector<int>& ql,
-                  const std::vector<int>& qp, BlockSvd& B, std::vector<xtrg::SvdJob>& jobs) {
+                  const std::vector<int>& qp, BlockSvd& B, std::vector<xtrg::SvdJob>& jobs,
+                  const WarmHook& warm = nullptr) {
   if ((int)ql.size() != len || (int)qp.size() != p) throw Error(XTRG_EINVAL, "charge lists do not match the tensor");
   hipStream_t s = c->stream;
   std::map<int, std::pair<std::vector<int>, std::vector<int>>> g;
@@ -478,8 +487,11 @@ void bsvd_prepare(xtrg_ctx c, const std::string& tag, const double* Y, int len, 
     XTRG_HIP(hipMemcpyAsync(k.d_idx, k.idx.data(), sizeof(int) * (k.len + k.p), hipMemcpyHostToDevice, s));
     k.Y = c->need("u1_Y" + nm, (size_t)k.len * k.p);
     xtrg::gather_block(k.Y, Y, len, k.d_idx, k.len, k.d_idx + k.len, k.p, s);
-    k.work = c->need("u1_svd" + nm, xtrg::svd_work(k.len, k.p));
-    jobs.push_back(xtrg::SvdJob{k.len, k.p, k.Y, k.work, 0, svd_gram(c, "u1" + nm, k.p)});
+    const double* in = k.Y;
+    k.psvd = k.p;
+    if (warm) std::tie(in, k.psvd) = warm(k.q, k.len, k.p, k.Y);
+    k.work = c->need("u1_svd" + nm, xtrg::svd_work(k.len, k.psvd));
+    jobs.push_back(xtrg::SvdJob{k.len, k.psvd, in, k.work, 0, svd_gram(c, "u1" + nm, k.psvd)});
   }
 }
 
@@ -494,8 +506,9 @@ void bsvd_merge(xtrg_ctx c, const std::string& tag, BlockSvd& B) {
   size_t o = 1;
   for (auto& k : B.b) {
     const int r = std::min(k.len, k.p);
-    XTRG_HIP(hipMemcpyAsync(st + o, xtrg::svd_fro2(k.work, k.len, k.p), sizeof(double), hipMemcpyDeviceToDevice, s));
-    XTRG_HIP(hipMemcpyAsync(st + o + 1, xtrg::svd_sorted_values(k.work, k.len, k.p), sizeof(double) * r,
+    XTRG_HIP(hipMemcpyAsync(st + o, xtrg::svd_fro2(k.work, k.len, k.psvd), sizeof(double), hipMemcpyDeviceToDevice,
+                            s));
+    XTRG_HIP(hipMemcpyAsync(st + o + 1, xtrg::svd_sorted_values(k.work, k.len, k.psvd), sizeof(double) * r,
                             hipMemcpyDeviceToDevice, s));
     o += 1 + r;
   }
@@ -505,8 +518,9 @@ void bsvd_merge(xtrg_ctx c, const std::string& tag, BlockSvd& B) {
   B.fro2 = 0.0;
   o = 1;
   for (size_t t = 0; t < B.b.size(); ++t) {
-    const auto& k = B.b[t];
+    auto& k = B.b[t];
     const int r = std::min(k.len, k.p);
+    k.S.assign(h.begin() + o + 1, h.begin() + o + 1 + r);
     B.fro2 += h[o];
     for (int j = 0; j < r; ++j) {
       const double v = h[o + 1 + j];
@@ -552,7 +566,7 @@ void bsvd_scatter(xtrg_ctx c, const std::string& tag, BlockSvd& B, int k, double
     int* pos = blk.d_idx + blk.len + blk.p;
     XTRG_HIP(hipMemcpyAsync(pos, blk.idx.data() + blk.len + blk.p, sizeof(int) * blk.kept, hipMemcpyHostToDevice, s));
     double* tmp = c->need("u1_vec" + tag, (size_t)blk.len * blk.kept);
-    xtrg::svd_gather(blk.len, blk.p, blk.work, blk.kept, tmp, blk.len, 0, s);
+    xtrg::svd_gather(blk.len, blk.psvd, blk.work, blk.kept, tmp, blk.len, 0, s);
     xtrg::scatter_cols(dst, B.len, k, rowmajor, tmp, blk.len, blk.kept, blk.d_idx, pos, s);
   }
 }
@@ -897,6 +911,8 @@ struct Chain {
   bool u1 = false;
   std::vector<std::vector<int>> qc;
   BlockSvd bs;
+  std::map<std::pair<int, int>, WarmQ> wq1;   // warm bases per (bond, charge block)
+  std::string wq1_name(int i, int q) const { return "wq1_" + std::to_string(i) + "_" + std::to_string(q) + tag; }
 
 };
 
@@ -1024,6 +1040,10 @@ void chain_setup(xtrg_ctx c, Chain& C, xtrg_mpo ina, xtrg_mpo inb, int q) {
 // relies on, and it is checked.
 // ---------------------------------------------------------------------------
 constexpr int kWarmMin = 128;   // smallest SVD column count worth a warm start
+// The same for a charge block: the blocks of one two-site tensor share the
+// grouped Jacobi launches until the last of them converges, so a cold small
+// block would add sweeps of its own after the warm large ones are done.
+constexpr int kWarmMinBlock = 64;
 
 // it Newton-Schulz steps X <- X (3I - X^T X)/2 on the columns of X
 // (column-major len x k, sigma_max(X) < sqrt(3)): singular values below 1
@@ -1087,11 +1107,11 @@ constexpr int kWarmExtra = 32;
 // Returns its column count, 0 if none is built (small, or mostly noise), or
 // -1 if it fails the orthogonality check; *m_out: the completion size.
 int build_basis(xtrg_ctx c, double* work, int dim, int pw, const std::vector<double>& S, double keep_floor,
-                unsigned long long seed, double* Q, int* m_out) {
+                unsigned long long seed, double* Q, int* m_out, int min_len = kWarmMin) {
   hipStream_t s = c->stream;
   const int len = dim;
   *m_out = 0;
-  if (len < kWarmMin || pw < 1) return 0;
+  if (len < min_len || pw < 1) return 0;
   int r = 0;
   const int rmax = std::min(len, pw);
   while (r < rmax && S[r] > 0.5 * keep_floor) ++r;
@@ -1329,6 +1349,31 @@ void chain_truncate_split(xtrg_ctx c, Chain& C) {
   }
   d.Dc[i + 1] = k;
   if (C.u1) C.qc[i + 1].assign(C.bs.qs.begin(), C.bs.qs.begin() + k);
+  if (C.u1 && !C.o.no_warm_start && C.revisit[C.st]) {
+    // a basis per charge block for the next visit of the bond (as
+    // build_warm does for the whole tensor)
+    Timed tm(c, P_WARM, 0.0, 0.0);
+    for (const auto& blk : C.bs.b) {
+      const auto key = std::make_pair(i, blk.q);
+      C.wq1.erase(key);
+      if (blk.len < kWarmMinBlock) continue;
+      double* Q = c->need(C.wq1_name(i, blk.q), (size_t)blk.len * (blk.len + kWarmExtra));
+      std::vector<double> Sb = blk.S;
+      Sb.resize(std::max<size_t>(Sb.size(), blk.psvd), 0.0);
+      int m = 0;
+      const unsigned long long seed = 0x5EEDull + 7919ull * (unsigned long long)i + 104729ull * (unsigned)(blk.q + 4096);
+      const int cols = build_basis(c, blk.work, blk.len, blk.psvd, Sb, kf, seed, Q, &m, kWarmMinBlock);
+      c->warm_m += m;
+      if (cols < 0) c->warm_rejected += 1;
+      if (cols <= 0) continue;
+      c->warm_built += 1;
+      Chain::WarmQ w;
+      w.side = C.gauge_right ? 0 : 1;
+      w.dim = blk.len;
+      w.cols = cols;
+      C.wq1[key] = w;
+    }
+  }
   if (!C.u1 && !C.o.no_warm_start && C.revisit[C.st]) {
     Timed tm(c, P_WARM, 0.0, 0.0);
     build_warm(c, C, S_all, kf, 0x5EEDull + 7919ull * (unsigned long long)i);
@@ -1529,9 +1574,24 @@ int square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_comp
           const int i = C->i;
           const auto qr = row_charges(C->qc[i]), qcol = col_charges(C->qc[i + 2]);
           const size_t j0 = jobs.size();
+          // warm start of a block: the basis of the previous visit of the
+          // bond for the same charge block, on the side this visit shares
+          const int need_side = C->gauge_right ? 1 : 0;
+          const WarmHook hook = [&, C, i, need_side](int q, int len_q, int p_q,
+                                                     const double* Yq) -> std::pair<const double*, int> {
+            if (C->o.no_warm_start || p_q < kWarmMinBlock) return {Yq, p_q};
+            const auto it = C->wq1.find({i, q});
+            if (it == C->wq1.end() || it->second.side != need_side || it->second.dim != p_q) return {Yq, p_q};
+            const auto& w = it->second;
+            const double* Q = c->need(C->wq1_name(i, q), (size_t)p_q * w.cols);
+            double* Yw = c->need("u1_in" + C->tag + "/" + std::to_string(q), (size_t)len_q * w.cols);
+            gemm(c, plain(w.cols, len_q, p_q, Q, p_q, false, Yq, len_q, false, Yw, len_q));   // Y_q [Q0 X]
+            c->warm_used += 1;
+            return {Yw, w.cols};
+          };
           per_chain(*C, [&] {
             bsvd_prepare(c, C->tag, C->th, C->len, C->p, C->gauge_right ? qr : qcol, C->gauge_right ? qcol : qr,
-                         C->bs, jobs);
+                         C->bs, jobs, hook);
           });
           if (C->status != XTRG_OK) {   // its workspaces refused by the budget
             jobs.resize(j0);
