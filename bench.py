@@ -45,10 +45,12 @@ PEAK_HBM_GBS = 8000.0
 # measured: reset to None when they change.
 JACOBI_ROUND_TRAFFIC_1024 = 26.82e6
 JACOBI_ROUND_BYTES_1024 = 16.0 * 1024 * 1024   # algorithmic: every column read and written once
-# The same for the one-launch round (jacobi_round<0>) of the charge blocks of
-# the D = 256 two-site tensors: None until counters are taken on it.
-JACOBI_ROUND0_TRAFFIC = None
-JACOBI_ROUND0_BYTES = None
+# The same for the one-launch round (jacobi_round<0>, the round of the S^z
+# charge blocks, a few hundred rows each at D = 256), measured on a 320 x 320
+# SVD (570 rounds): FETCH 502.66 KiB x 2.0 + WRITE 688.55 KiB x 1.0 per
+# round, against 16 * 320 * 320 algorithmic bytes.
+JACOBI_ROUND0_TRAFFIC = (502.655 * 2.0 + 688.550) * 1024.0
+JACOBI_ROUND0_BYTES = 16.0 * 320 * 320
 
 
 def parse():

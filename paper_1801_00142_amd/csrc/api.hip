@@ -2660,7 +2660,8 @@ int xtrg_dsvd_left(xtrg_ctx c, int len, int p, const double* Y, double* sigma, i
     set_device(c);
     double* work = c->need("svd", xtrg::svd_work(len, p));
     int sw = 0;
-    xtrg::svd_left(len, p, Y, sigma, k, U, len, 0, work, svd_desc(c, 1), c->stream, &sw);
+    RoundProf rp(c);
+    xtrg::svd_left(len, p, Y, sigma, k, U, len, 0, work, svd_desc(c, 1), c->stream, &sw, &rp);
     c->svd_calls += 1;
     c->svd_sweeps += sw;
     if (k > 0 && U) orthonormalize(c, U, len, k, false);

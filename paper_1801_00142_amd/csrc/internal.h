@@ -78,8 +78,10 @@ size_t gemm_grouped_work(const std::vector<Gemm>& gs);
 size_t svd_work(int len, int p);
 // desc_dev: device scratch of svd_desc_bytes(n) bytes (n problems).
 size_t svd_desc_bytes(int n);
+struct RoundTimer;
 void svd_left(int len, int p, const double* Y, double* sigma, int k, double* U, long ldu,
-              int u_rowmajor, double* work, void* desc_dev, hipStream_t s, int* sweeps_out);
+              int u_rowmajor, double* work, void* desc_dev, hipStream_t s, int* sweeps_out,
+              RoundTimer* timer = nullptr);
 // Several independent SVDs at once: every Jacobi round of all problems is one
 // grouped launch, so latency-bound rounds of independent chains overlap.
 struct SvdJob {

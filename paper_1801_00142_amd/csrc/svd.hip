@@ -570,24 +570,6 @@ __global__ void column_norms(const double* __restrict__ Y, int len, int glen, in
   if (lane == 0) out[col] = sqrt(s);
 }
 
-// Columns still above the numerical zero: how many of the descending norms
-// have norm^2 > zth / 2 (the margin keeps every column that a Gram diagonal
-// could find above zth; the others are never rotated again).
-__global__ __launch_bounds__(256) void count_alive(const double* __restrict__ sorted, int p,
-                                                   const double* __restrict__ fro2, double zrel2, int* __restrict__ out) {
-  __shared__ int part[256];
-  const double th = 0.5 * zrel2 * fro2[0];
-  int c = 0;
-  for (int i = threadIdx.x; i < p; i += 256) c += sorted[i] * sorted[i] > th;
-  part[threadIdx.x] = c;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *out = part[0];
-}
-
 // *out = sum of x[i]^2 for i < n, one workgroup, a fixed summation order.
 __global__ __launch_bounds__(256) void sum_squares_ordered(const double* __restrict__ x, int n,
                                                            double* __restrict__ out) {
@@ -637,6 +619,84 @@ __global__ __launch_bounds__(1024) void sort_desc(const double* __restrict__ val
     sorted[i] = v[i];
     perm[i] = ix[i];
   }
+}
+
+// The ranking of every active problem of a grouped SVD at once
+// (blockIdx.y, or blockIdx.x for the one-workgroup kernels, selects the
+// problem; per problem the arithmetic of column_norms and sort_desc above,
+// so the same bits): column norms over the Gram rows, their descending
+// order, and how many of them have norm^2 > zth / 2 (the margin keeps every
+// column that a Gram diagonal could find above zth; the others are never
+// rotated again).
+// Problem workspace: Z (len x p), then raw norms, sorted norms, order.
+__global__ void column_norms_group(const JacobiDesc* __restrict__ descs) {
+  const JacobiDesc& D = descs[blockIdx.y];
+  if (!D.active) return;
+  const int col = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (col >= D.p) return;
+  const double* c = D.Z + (long)col * D.len;
+  double s = 0.0;
+  for (int e = lane; e < D.glen; e += 64) s = fma(c[e], c[e], s);
+  s = wave_sum(s);
+  if (lane == 0) D.Z[(long)D.len * D.p + col] = sqrt(s);
+}
+
+__global__ __launch_bounds__(1024) void sort_desc_group(const JacobiDesc* __restrict__ descs) {
+  const JacobiDesc& D = descs[blockIdx.x];
+  if (!D.active) return;
+  extern __shared__ unsigned char sm[];
+  const int p = D.p;
+  const double* val = D.Z + (long)D.len * p;
+  double* sorted = D.Z + (long)D.len * p + p;
+  int* perm = reinterpret_cast<int*>(D.Z + (long)D.len * p + 2 * (long)p);
+  int n = 1;
+  while (n < p) n <<= 1;
+  double* v = reinterpret_cast<double*>(sm);
+  int* ix = reinterpret_cast<int*>(v + n);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    v[i] = i < p ? val[i] : -1.0;
+    ix[i] = i < p ? i : 0x7fffffff;
+  }
+  __syncthreads();
+  for (int k = 2; k <= n; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int l = i ^ j;
+        if (l > i) {
+          const bool desc = (i & k) == 0;
+          const bool i_first = (v[i] > v[l]) || (v[i] == v[l] && ix[i] < ix[l]);
+          if (desc != i_first) {
+            const double tv = v[i]; v[i] = v[l]; v[l] = tv;
+            const int ti = ix[i]; ix[i] = ix[l]; ix[l] = ti;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < p; i += blockDim.x) {
+    sorted[i] = v[i];
+    perm[i] = ix[i];
+  }
+}
+
+__global__ __launch_bounds__(256) void count_alive_group(const JacobiDesc* __restrict__ descs,
+                                                         int* __restrict__ out) {
+  const JacobiDesc& D = descs[blockIdx.x];
+  if (!D.active) return;
+  __shared__ int part[256];
+  const double* sorted = D.Z + (long)D.len * D.p + D.p;
+  const double th = 0.5 * D.zrel2 * D.fro2[0];
+  int c = 0;
+  for (int i = threadIdx.x; i < D.p; i += 256) c += sorted[i] * sorted[i] > th;
+  part[threadIdx.x] = c;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = part[0];
 }
 
 // U column j = Z column perm[j] / sigma[j] (zero if sigma[j] == 0).
@@ -739,24 +799,24 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
   }
   std::vector<int> full_nbk(n), hal(n, 0);
   for (int j = 0; j < n; ++j) full_nbk[j] = h[j].nbk;
-  auto rank_columns = [&](int j) {
-    const SvdJob& J = jobs[j];
-    double* w = J.work;
-    double* raw = w + (size_t)J.len * J.p;
-    hipLaunchKernelGGL(column_norms, dim3((J.p + 3) / 4), dim3(256), 0, s, w, J.len, h[j].glen, J.p, raw);
-    hipLaunchKernelGGL(sort_desc, dim3(1), dim3(1024), (sizeof(double) + sizeof(int)) * n2[j], s, raw, J.p,
-                       sv_sorted(w, J.len, J.p), sv_perm(w, J.len, J.p));
-    XTRG_HIP(hipGetLastError());
-  };
   // Ranks for the next sweep and the count of columns still above the
   // numerical zero: the rest sort last, are never rotated again (a pair is
   // rotated only if both columns are above it, and rotations alone change
   // a column), and are left out of the block schedule.
-  auto prepare = [&](int j) {
-    rank_columns(j);
-    const SvdJob& J = jobs[j];
-    hipLaunchKernelGGL(count_alive, dim3(1), dim3(256), 0, s, sv_sorted(J.work, J.len, J.p), J.p, h[j].fro2,
-                       h[j].zrel2, d_alive + j);
+  // The same for every active problem at once (three grouped launches; the
+  // device descriptors must be current).
+  auto prepare_all = [&](bool count) {
+    int maxp = 0, maxn2 = 1;
+    for (int j = 0; j < n; ++j)
+      if (h[j].active) {
+        maxp = std::max(maxp, h[j].p);
+        maxn2 = std::max(maxn2, n2[j]);
+      }
+    if (maxp == 0) return;
+    hipLaunchKernelGGL(column_norms_group, dim3((maxp + 3) / 4, n), dim3(256), 0, s, d_desc);
+    hipLaunchKernelGGL(sort_desc_group, dim3(n), dim3(1024), (sizeof(double) + sizeof(int)) * maxn2, s, d_desc);
+    if (count) hipLaunchKernelGGL(count_alive_group, dim3(n), dim3(256), 0, s, d_desc, d_alive);
+    XTRG_HIP(hipGetLastError());
   };
   bool dirty = true;
   auto set_nbk = [&](int j) {
@@ -768,8 +828,8 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
       dirty = true;
     }
   };
-  for (int j = 0; j < n; ++j)
-    if (h[j].active) prepare(j);
+  XTRG_HIP(hipMemcpyAsync(d_desc, h.data(), sizeof(JacobiDesc) * n, hipMemcpyHostToDevice, s));
+  prepare_all(true);
   XTRG_HIP(hipMemcpyAsync(hal.data(), d_alive, sizeof(int) * n, hipMemcpyDeviceToHost, s));
   // ||Y||_F^2 must be finite: a NaN or Inf entry, or a norm beyond the
   // double range, would leave every rotation test false
@@ -843,8 +903,7 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
         }
       timer->end(s, (long)(max_nbk - 1) * (smax > 1 ? 2 : 1), fl, by, smax > 1);
     }
-    for (int j = 0; j < n; ++j)
-      if (h[j].active) prepare(j);
+    prepare_all(true);   // the descriptors on the device are those of this sweep
     XTRG_HIP(hipMemcpyAsync(hoff.data(), d_off, sizeof(unsigned long long) * n, hipMemcpyDeviceToHost, s));
     XTRG_HIP(hipMemcpyAsync(hal.data(), d_alive, sizeof(int) * n, hipMemcpyDeviceToHost, s));
     XTRG_HIP(hipStreamSynchronize(s));
@@ -908,15 +967,17 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
     for (int j = 0; j < n; ++j)
       if (h[j].active) set_nbk(j);
   }
-  for (int j = 0; j < n; ++j)
-    if (jobs[j].len > 0 && jobs[j].p > 0 && jobs[j].status == 0) rank_columns(j);
+  // final ranking of every problem that succeeded (also those with one column)
+  for (int j = 0; j < n; ++j) h[j].active = jobs[j].len > 0 && jobs[j].p > 0 && jobs[j].status == 0;
+  XTRG_HIP(hipMemcpyAsync(d_desc, h.data(), sizeof(JacobiDesc) * n, hipMemcpyHostToDevice, s));
+  prepare_all(false);
 }
 
 void svd_left(int len, int p, const double* Y, double* sigma, int k, double* U, long ldu, int u_rowmajor,
-              double* work, void* desc_dev, hipStream_t s, int* sweeps_out) {
+              double* work, void* desc_dev, hipStream_t s, int* sweeps_out, RoundTimer* timer) {
   std::vector<SvdJob> jobs(1);
   jobs[0] = SvdJob{len, p, Y, work, 0};
-  svd_batched(jobs, desc_dev, s);
+  svd_batched(jobs, desc_dev, s, timer);
   if (jobs[0].status != 0)
     throw Error(-4, "svd: non-finite entry, ||Y||_F^2 beyond the double range, or no convergence (len " +
                         std::to_string(len) + ", p " + std::to_string(p) + ")");

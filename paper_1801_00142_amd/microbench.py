@@ -49,6 +49,14 @@ def svd(n: int, decades: float, reps: int = 2) -> None:
     r = ctx.profile_report()
     print(f"sweeps per call {r['svd_sweeps'] / max(r['svd_calls'], 1):.1f}; "
           f"max |sigma - sigma_exact| / sigma_1 = {np.abs(sig.cpu().numpy() - s0).max():.2e}", flush=True)
+    # algorithmic bytes per round (every active column read and written once),
+    # for scaling the HBM counters of the round kernels
+    for key, per in (("svd_rounds_fused", 1), ("svd_rounds", 2)):
+        q = r.get(key, {})
+        if q.get("calls"):
+            n = q["calls"] // per
+            print(f"{key}: {n} rounds, {q['bytes'] / n:.1f} algorithmic bytes per round, "
+                  f"{q['ms'] / n * 1e3:.3f} us per round", flush=True)
     ctx.close()
 
 
