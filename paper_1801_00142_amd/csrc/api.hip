@@ -428,8 +428,8 @@ std::vector<std::vector<int>> infer_charges(const std::vector<std::vector<double
 struct BlockSvd {
   struct Blk {
     int q = 0, len = 0, p = 0;
-    std::vector<int> idx;   // rows, then columns, then the merged positions of the kept triples
-    int* d_idx = nullptr;
+    size_t off = 0;         // its index lists in idx: rows, then columns, then the merged positions of the kept triples
+    int* d_idx = nullptr;   // the same on the device
     double* Y = nullptr;
     double* work = nullptr;
     int psvd = 0;           // columns of the SVD input (p, or more with a warm basis)
@@ -437,6 +437,8 @@ struct BlockSvd {
     int kept = 0;
   };
   std::vector<Blk> b;
+  std::vector<int> idx;           // the index lists of all blocks (one upload each way)
+  int* d_idx = nullptr;
   const double* Y = nullptr;
   int len = 0, p = 0;
   double* chk = nullptr;          // device: ||Y||_F^2, then 1024 partials
@@ -472,19 +474,22 @@ void bsvd_prepare(xtrg_ctx c, const std::string& tag, const double* Y, int len, 
     k.q = kv.first;
     k.len = (int)rc.first.size();
     k.p = (int)rc.second.size();
-    k.idx = rc.first;
-    k.idx.insert(k.idx.end(), rc.second.begin(), rc.second.end());
-    k.idx.resize(k.idx.size() + std::min(k.len, k.p), 0);
+    k.off = B.idx.size();
+    B.idx.insert(B.idx.end(), rc.first.begin(), rc.first.end());
+    B.idx.insert(B.idx.end(), rc.second.begin(), rc.second.end());
+    B.idx.resize(B.idx.size() + std::min(k.len, k.p), 0);
     B.b.push_back(std::move(k));
   }
   if (B.b.empty()) throw Error(XTRG_EINVAL, "no S^z charge is shared by the rows and the columns");
+  // one upload for all blocks (an upload from pageable memory waits for the stream)
+  B.d_idx = reinterpret_cast<int*>(c->need("u1_idx" + tag, B.idx.size() / 2 + 1));
+  XTRG_HIP(hipMemcpyAsync(B.d_idx, B.idx.data(), sizeof(int) * B.idx.size(), hipMemcpyHostToDevice, s));
   B.chk = c->need("u1_chk" + tag, 1026);
   xtrg::sumsq(Y, (size_t)len * p, B.chk, B.chk + 2, s);
   for (size_t t = 0; t < B.b.size(); ++t) {
     auto& k = B.b[t];
     const std::string nm = tag + "/" + std::to_string(t);
-    k.d_idx = reinterpret_cast<int*>(c->need("u1_idx" + nm, k.idx.size() / 2 + 1));
-    XTRG_HIP(hipMemcpyAsync(k.d_idx, k.idx.data(), sizeof(int) * (k.len + k.p), hipMemcpyHostToDevice, s));
+    k.d_idx = B.d_idx + k.off;
     k.Y = c->need("u1_Y" + nm, (size_t)k.len * k.p);
     xtrg::gather_block(k.Y, Y, len, k.d_idx, k.len, k.d_idx + k.len, k.p, s);
     const double* in = k.Y;
@@ -558,13 +563,13 @@ void bsvd_scatter(xtrg_ctx c, const std::string& tag, BlockSvd& B, int k, double
   for (int j = 0; j < k; ++j) {
     auto& blk = B.b[B.from[j]];
     if (B.rank[j] != blk.kept) throw Error(XTRG_EINVAL, "block SVD: kept values out of order");
-    blk.idx[blk.len + blk.p + blk.kept] = j;
+    B.idx[blk.off + blk.len + blk.p + blk.kept] = j;
     blk.kept += 1;
   }
+  XTRG_HIP(hipMemcpyAsync(B.d_idx, B.idx.data(), sizeof(int) * B.idx.size(), hipMemcpyHostToDevice, s));
   for (auto& blk : B.b) {
     if (blk.kept == 0) continue;
     int* pos = blk.d_idx + blk.len + blk.p;
-    XTRG_HIP(hipMemcpyAsync(pos, blk.idx.data() + blk.len + blk.p, sizeof(int) * blk.kept, hipMemcpyHostToDevice, s));
     double* tmp = c->need("u1_vec" + tag, (size_t)blk.len * blk.kept);
     xtrg::svd_gather(blk.len, blk.psvd, blk.work, blk.kept, tmp, blk.len, 0, s);
     xtrg::scatter_cols(dst, B.len, k, rowmajor, tmp, blk.len, blk.kept, blk.d_idx, pos, s);
@@ -1106,8 +1111,36 @@ constexpr int kWarmExtra = 32;
 // values S) into Q (dim x (dim + kWarmExtra) doubles, column-major).
 // Returns its column count, 0 if none is built (small, or mostly noise), or
 // -1 if it fails the orthogonality check; *m_out: the completion size.
+// *dev (device) = max |Q Q^T - I| of the len x cols basis Q.
+void basis_check(xtrg_ctx c, const double* Q, int len, int cols, double* dev) {
+  double* G = c->need("wq_G", (size_t)len * len);
+  gemm(c, plain(len, len, cols, Q, len, true, Q, len, false, G, len));  // Q Q^T
+  xtrg::eye_dev(G, len, dev, c->scratch + 1024, c->stream);
+}
+
+// The Jacobi leaves cosines <= 8 sqrt(len) eps between kept columns; a
+// basis passes when Q Q^T is the identity to 4x that.
+double basis_lim(int len) { return 32.0 * std::sqrt((double)len) * 2.220446049250313e-16; }
+
+// A basis that failed its first check: up to two rounds of further
+// Newton-Schulz steps on its completion (m + o columns after the first
+// len - m), each followed by the check.  Returns cols, or -1.
+int basis_retry(xtrg_ctx c, double* Q, int len, int cols, int m) {
+  if (m == 0) return -1;
+  const int o = cols - len, r = len - m;
+  for (int attempt = 1; attempt <= 2; ++attempt) {
+    ns_steps(c, Q + (size_t)len * r, len, m + o, 3);
+    basis_check(c, Q, len, cols, c->scratch);
+    if (read_scalar(c, c->scratch) <= basis_lim(len)) return cols;
+  }
+  return -1;
+}
+
+// dev_out (device, optional): leave the first orthogonality check there for
+// the caller to read (together with other bases) and return the columns
+// the basis has if it passes; basis_retry then handles one that does not.
 int build_basis(xtrg_ctx c, double* work, int dim, int pw, const std::vector<double>& S, double keep_floor,
-                unsigned long long seed, double* Q, int* m_out, int min_len = kWarmMin) {
+                unsigned long long seed, double* Q, int* m_out, int min_len = kWarmMin, double* dev_out = nullptr) {
   hipStream_t s = c->stream;
   const int len = dim;
   *m_out = 0;
@@ -1138,22 +1171,16 @@ int build_basis(xtrg_ctx c, double* work, int dim, int pw, const std::vector<dou
     xtrg::scale(R, 1.0 / hi, (size_t)len * mo, s);
     polar_ns(c, R, len, mo, 0.5 * lo / hi);
   }
-  // Q Q^T = I on R^len?  The Jacobi leaves cosines <= 8 sqrt(len) eps
-  // between kept columns; a completion whose smallest singular value
+  // Q Q^T = I on R^len?  A completion whose smallest singular value
   // started below the estimate gets up to two rounds of further steps.
-  const double lim = 32.0 * std::sqrt((double)len) * 2.220446049250313e-16;
-  double dev = 0.0;
-  for (int attempt = 0;; ++attempt) {
-    double* G = c->need("wq_G", (size_t)len * len);
-    gemm(c, plain(len, len, cols, Q, len, true, Q, len, false, G, len));  // Q Q^T
-    xtrg::eye_dev(G, len, c->scratch, c->scratch + 1024, s);
-    dev = read_scalar(c, c->scratch);
-    if (dev <= lim || m == 0 || attempt == 2) break;
-    ns_steps(c, Q + (size_t)len * r, len, m + o, 3);
-  }
   *m_out = m;
-  if (!(dev <= lim)) return -1;
-  return cols;
+  if (dev_out) {
+    basis_check(c, Q, len, cols, dev_out);
+    return cols;
+  }
+  basis_check(c, Q, len, cols, c->scratch);
+  if (read_scalar(c, c->scratch) <= basis_lim(len)) return cols;
+  return basis_retry(c, Q, len, cols, m);
 }
 
 void build_warm(xtrg_ctx c, Chain& C, const std::vector<double>& S, double keep_floor, unsigned long long seed) {
@@ -1353,17 +1380,31 @@ void chain_truncate_split(xtrg_ctx c, Chain& C) {
     // a basis per charge block for the next visit of the bond (as
     // build_warm does for the whole tensor)
     Timed tm(c, P_WARM, 0.0, 0.0);
-    for (const auto& blk : C.bs.b) {
-      const auto key = std::make_pair(i, blk.q);
-      C.wq1.erase(key);
+    const size_t nb = C.bs.b.size();
+    std::vector<int> colsv(nb, 0), mv(nb, 0);
+    double* devs = c->need("u1_dev" + C.tag, nb + 1);
+    bool any = false;
+    for (size_t t = 0; t < nb; ++t) {
+      const auto& blk = C.bs.b[t];
+      C.wq1.erase(std::make_pair(i, blk.q));
       if (blk.len < kWarmMinBlock) continue;
       double* Q = c->need(C.wq1_name(i, blk.q), (size_t)blk.len * (blk.len + kWarmExtra));
       std::vector<double> Sb = blk.S;
       Sb.resize(std::max<size_t>(Sb.size(), blk.psvd), 0.0);
-      int m = 0;
       const unsigned long long seed = 0x5EEDull + 7919ull * (unsigned long long)i + 104729ull * (unsigned)(blk.q + 4096);
-      const int cols = build_basis(c, blk.work, blk.len, blk.psvd, Sb, kf, seed, Q, &m, kWarmMinBlock);
-      c->warm_m += m;
+      colsv[t] = build_basis(c, blk.work, blk.len, blk.psvd, Sb, kf, seed, Q, &mv[t], kWarmMinBlock, devs + t);
+      any |= colsv[t] > 0;
+    }
+    // the orthogonality checks of all blocks in one read
+    const std::vector<double> hd = any ? read_vec(c, devs, nb) : std::vector<double>(nb, 0.0);
+    for (size_t t = 0; t < nb; ++t) {
+      const auto& blk = C.bs.b[t];
+      const auto key = std::make_pair(i, blk.q);
+      int cols = colsv[t];
+      if (cols > 0 && !(hd[t] <= basis_lim(blk.len)))
+        cols = basis_retry(c, c->need(C.wq1_name(i, blk.q), (size_t)blk.len * (blk.len + kWarmExtra)), blk.len, cols,
+                           mv[t]);
+      c->warm_m += mv[t];
       if (cols < 0) c->warm_rejected += 1;
       if (cols <= 0) continue;
       c->warm_built += 1;
