@@ -297,11 +297,13 @@ int xtrg_expectation(xtrg_ctx ctx, xtrg_mpo rho, int n_ops, const xtrg_mpo* ops,
  *   {"n_sites": L, "bonds": [[i, j], ...], "jxy": x or [x per bond],
  *    "jz": x or [...], "tau0": t, "n_doublings": n, "D": D,
  *    "n_sweeps": 2, "order": 1, "precision": "fp64"|"fp32"|"bf16x3",
- *    "beta_mix": 1.0, "series_tol": 0}
- * (the last six optional, with these defaults; precision applies to the
+ *    "beta_mix": 1.0, "series_tol": 0, "u1": false}
+ * (the last seven optional, with these defaults; precision applies to the
  * doublings that reach beta >= beta_mix, earlier ones run in FP64;
  * series_tol > 0 starts from xtrg_settn_init at bond <= D with that
- * expansion error instead of the order-1/2 start) and
+ * expansion error instead of the order-1/2 start; u1 = true runs the solve
+ * with S^z charges on its bonds, xtrg_init_rho_u1 and opts.u1, and needs
+ * series_tol = 0) and
  * returns its id.  The runs are served in lanes (xtrg_serve_set_lanes,
  * default 2): a run goes to lane k if its work per doubling (sites x D^4)
  * is 8^k times below the largest seen so far (the last lane takes the rest),

@@ -208,6 +208,7 @@ struct Request {
   double tau0 = 0.0, beta_mix = 1.0;
   double series_tol = 0.0;   // > 0: the series start to this expansion error instead of order 1 / 2
   int n_doublings = 0, D = 0, n_sweeps = 2, order = 1, precision = XTRG_FP64;
+  bool u1 = false;           // U(1) charge sectors: charge-definite start, C_E factorised by S^z blocks
   // state
   bool done = false;       // visible to poll (set under the server lock)
   bool admitted = false;   // likewise: admitted to the batch
@@ -361,7 +362,7 @@ struct Server {
         int nt = 0;
         r.rho = xtrg_impl::settn_init(ln.c, r.H.get(), r.tau0, r.D, 2, r.series_tol, &r.lam, &nt);
       } else {
-        r.rho = xtrg_impl::init_rho(ln.c, r.H.get(), r.tau0, r.order, 0, &r.lam);
+        r.rho = xtrg_impl::init_rho(ln.c, r.H.get(), r.tau0, r.order, 0, &r.lam, r.u1);
       }
       r.tau = r.tau0;
       record(ln, r, nullptr);
@@ -388,6 +389,7 @@ struct Server {
       o.precision = 4.0 * r.tau >= r.beta_mix ? r.precision : XTRG_FP64;
       o.degen_rtol = 1e-6;
       o.sv_floor = 1e-14;
+      o.u1 = r.u1 ? 1 : 0;
       opts[q] = o;
       infos[q] = xtrg_compress_info{};
     }
@@ -596,6 +598,11 @@ int xtrg_serve_submit(xtrg_ctx c, const char* request_json, unsigned long long* 
       else if (pv->str == "bf16x3") r->precision = XTRG_BF16X3;
       else throw Error(XTRG_EINVAL, "request: precision is fp64, fp32 or bf16x3");
     }
+    if (const xtrg::JVal* uv = v.get("u1")) {
+      if (uv->kind != xtrg::JVal::BOOL) throw Error(XTRG_EINVAL, "request: u1 is true or false");
+      r->u1 = uv->b;
+    }
+    if (r->u1 && r->series_tol > 0) throw Error(XTRG_EINVAL, "request: u1 takes the order-1/2 start (series_tol 0)");
     const xtrg::JVal* bv = v.get("bonds");
     if (!bv || bv->kind != xtrg::JVal::ARR) throw Error(XTRG_EINVAL, "request: bonds is a list of [i, j] pairs");
     for (const auto& b : bv->arr) {

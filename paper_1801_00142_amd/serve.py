@@ -35,6 +35,7 @@ class Solve:
     precision: int = 0          # XTRG_FP64, XTRG_FP32 or XTRG_BF16X3
     beta_mix: float = 1.0
     series_tol: float = 0.0     # > 0: the series start (xtrg_settn_init) to this expansion error
+    u1: bool = False            # S^z charges on the bonds, C_E factorised by charge blocks
 
     def request(self) -> dict:
         r = dict(n_sites=self.n_sites, bonds=[list(b) for b in self.bonds], jxy=list(self.jxy),
@@ -43,6 +44,8 @@ class Solve:
                  beta_mix=self.beta_mix)
         if self.series_tol > 0:
             r["series_tol"] = self.series_tol
+        if self.u1:
+            r["u1"] = True
         return r
 
 

@@ -34,7 +34,7 @@ def _solves():
             W.random_couplings(W.chain(5), 3), W.chain(8)]
     for q, (lat, D, arr) in enumerate(zip(lats, [8, 12, 16, 6, 10], [0.0, 0.0, 0.0, 0.0, 0.1])):
         out.append(Solve(q, lat.n_sites, lat.bonds, lat.jxy, lat.jz, 2.0 ** -6 * 2 ** (q / 4), 6, D,
-                         arrival_s=arr, precision=XTRG_FP32 if q == 2 else 0, beta_mix=0.1))
+                         arrival_s=arr, precision=XTRG_FP32 if q == 2 else 0, beta_mix=0.1, u1=q == 4))
     return out
 
 
@@ -55,7 +55,8 @@ def _same_records(a, b):
 
 def test_serve_results_equal_alone():
     """Continuous batching in the library: five runs (one with FP32
-    contractions from beta_mix on, the others FP64) arriving at different
+    contractions from beta_mix on, one with U(1) charge blocks, the others
+    FP64 dense factorisations) arriving at different
     times under a budget that holds two at once.  Some wait for memory; each
     run's records (bond dimensions, lambda, f, u, c at every doubling) are
     bit-identical to the run served alone."""
@@ -162,6 +163,29 @@ def test_serve_matches_run(ctx):
         for key, est in (("tau", "tau"), ("2tau", "2tau")):
             for q in ("f", "u", "c"):
                 assert x[f"{q}_{key}"] == r["obs"][est][q]
+
+
+def test_serve_u1_matches_run(ctx):
+    """A served run with "u1": true reproduces run(u1=True) bit for bit; a
+    u1 request with the series start is refused."""
+    import json
+    from paper_1801_00142_amd import run
+    from paper_1801_00142_amd.serve import Solve
+    from paper_1801_00142_amd.xtrg import XtrgError
+    lat = W.with_couplings(W.square_cylinder(2, 4), 1.0, 1.5)
+    s = Solve(0, lat.n_sites, lat.bonds, lat.jxy, lat.jz, 2.0 ** -6, 6, 12, u1=True)
+    got = _serve(0, [s])[0]
+    assert got["status"] == 0, got["error"]
+    ref = run(ctx, lat.n_sites, lat.bonds, lat.jxy, lat.jz, 2.0 ** -6, 6, 12, n_sweeps=2, u1=True)
+    for x, r in zip(got["records"], ref):
+        assert x["bond_dims"] == r["bond_dims"]
+        assert x["lam"] == r["lam"]
+        for key, est in (("tau", "tau"), ("2tau", "2tau")):
+            for q in ("f", "u", "c"):
+                assert x[f"{q}_{key}"] == r["obs"][est][q]
+    bad = dict(s.request(), series_tol=1e-12)
+    with pytest.raises(XtrgError):
+        ctx.serve_submit(bad)
 
 
 def test_batched_chain_with_nan_fails_alone(ctx):
