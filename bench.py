@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "fp32", "bf16x3"], default="fp64",
                     help="contraction precision of the doublings that reach beta >= --beta-mix")
     ap.add_argument("--beta-mix", type=float, default=1.0)
+    ap.add_argument("--mixed-leg", type=int, default=2,
+                    help="with FP64 contractions: this many doublings timed again with FP32 contractions "
+                         "(the same doubling of the workload, the state restored first), with their accuracy")
     ap.add_argument("--dense", action="store_true",
                     help="factorise every two-site tensor as one dense matrix (default: U(1) charge sectors, "
                          "a charge-definite start and every two-site tensor factorised by S^z charge blocks)")
@@ -318,11 +321,12 @@ def main():
     tau = [wl.tau0]
 
     last_prec = [XTRG_FP64]
+    mode = {"mixed": mixed}
 
     def doubling(n_sweeps):
         nonlocal rhos
         # the result reaches beta = 2 tau_{n+1} = 4 tau_n (the schedule of run())
-        prec = mixed if 4 * tau[0] >= args.beta_mix else XTRG_FP64
+        prec = mode["mixed"] if 4 * tau[0] >= args.beta_mix else XTRG_FP64
         if prec != last_prec[0]:
             ctx.trim()              # the FP64 workspaces of the early doublings are not reused
             last_prec[0] = prec
@@ -401,11 +405,23 @@ def main():
     flops, steps_2site, dt, prof = timed(args.steps, args.sweeps, "timed")
     win1 = time.clock_gettime_ns(time.CLOCK_BOOTTIME)
     value = flops / dt / 1e12
+    main_prec = last_prec[0]          # the contraction precision of the timed doublings
     side = None
     if args.side_sweeps > 0 and args.sweeps != 2:
         f2, s2, d2, _ = timed(args.side_sweeps, 2, "2-sweep")
         side = {"value": round(f2 / d2 / 1e12, 4), "n_sweeps": 2, "doublings": args.side_sweeps,
                 "ms_per_step": round(d2 / args.side_sweeps * 1e3, 3)}
+    mixed_leg = None
+    if args.mixed_leg > 0 and mixed == XTRG_FP64:
+        # the same doubling with FP32 contractions (FP64 SVD, cut and
+        # normalisation), timed after the state is restored
+        restore()
+        mode["mixed"] = XTRG_FP32
+        fm, sm, dm, _ = timed(args.mixed_leg, args.sweeps, "fp32")
+        mode["mixed"] = mixed
+        mixed_leg = {"precision": "f32 contractions, f64 svd", "value": round(fm / dm / 1e12, 4),
+                     "unit": "TFLOP/s", "doublings": args.mixed_leg, "ms_per_step": round(dm / args.mixed_leg * 1e3, 3),
+                     "solves_per_s_vs_fp64": round((dt / args.steps) / (dm / args.mixed_leg), 4)}
 
     svd_calls = prof.pop("svd_calls", 0)
     svd_sweeps = prof.pop("svd_sweeps", 0)
@@ -503,10 +519,12 @@ def main():
                                        "blocks") + ", copy-scaled, scaled to this run's mean algorithmic bytes "
                                       "per round"),
                      "rounds": n_rounds, "avg_round_us": round(round_us, 3), "bytes_per_round": round_bytes},
-        "roofline_theta": theta_roofline(last_prec[0], th_achieved, th["calls"], th_avg_s, th_flops),
+        "roofline_theta": theta_roofline(main_prec, th_achieved, th["calls"], th_avg_s, th_flops),
     }
     if side:
         out["value_2_sweeps"] = side
+    if mixed_leg:
+        out["mixed_leg"] = mixed_leg
     sites = None
     if not args.no_cpu_baseline or not args.no_accuracy:
         sites = rhos[0].to_host()
@@ -514,6 +532,9 @@ def main():
         print("accuracy: stored-oracle parity run", file=sys.stderr, flush=True)
         out["accuracy"] = {"parity": parity_leg(ctx, "chain12_D256_u1" if args.u1 else "chain12_D256",
                                                 precision=mixed, beta_mix=args.beta_mix, u1=args.u1)}
+        if mixed_leg:
+            mixed_leg["accuracy"] = parity_leg(ctx, "chain12_D256_u1" if args.u1 else "chain12_D256",
+                                               precision=XTRG_FP32, beta_mix=args.beta_mix, u1=args.u1)
     if not args.no_cpu_baseline:
         tf, cdt, cfl, threads, (th_c, S_c) = cpu_baseline(sites, args.D, args.cpu_steps)
         out["cpu_baseline"] = {"value": round(tf, 5), "unit": "TFLOP/s",

@@ -174,3 +174,18 @@ def test_u1_batched_equals_single(ctx):
             assert np.array_equal(a, b)
         for a, b in zip(s.charges(), o.charges()):
             assert np.array_equal(a, b)
+
+
+def test_u1_fp32_mix_against_stored_oracle(ctx):
+    """XTRG_FP32 contractions (beta_mix = 1 schedule) on the U(1) route at
+    D = 256: f and u within the mixed-precision target 1e-6 of the oracle's
+    FP64 u1 run at every beta (FP32 rounding may move a value across the cut,
+    so bond dimensions are not compared)."""
+    from paper_1801_00142_amd import XTRG_FP32, run
+    from test_gpu_fullsize import check_against_golden, _errors
+    ref = _golden("chain12_D256_u1")
+    lat = W.workload(ref["workload"], ref["D"]).lattice
+    gpu = run(ctx, lat.n_sites, lat.bonds, lat.jxy, lat.jz, ref["tau0"], ref["n_doublings"], ref["D"],
+              order=ref["order"], n_sweeps=ref["n_sweeps"], precision=XTRG_FP32, beta_mix=1.0, u1=True)
+    print("u1 fp32 mix", _errors(gpu, ref))
+    check_against_golden(gpu, ref, 1e-6, 1e-4, bonds=False)
