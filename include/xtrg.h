@@ -176,9 +176,10 @@ typedef struct {
                         input MPOs must carry S^z charges on their bonds (xtrg_init_rho_u1,
                         xtrg_mpo_label_charges, or an earlier u1 doubling); C_E, block
                         diagonal in the charge of the bond being cut, is factorised block by
-                        block (one grouped Jacobi launch per round over all blocks; the
-                        warm and QR starts are not used), the keep rule runs on the merged
-                        values of all blocks, and every kept singular vector carries its
+                        block (one grouped Jacobi launch per round over all blocks; a block of
+                        at least 64 columns starts from the previous visit's basis of the same
+                        block unless no_warm_start; no QR start), the keep rule runs on the
+                        merged values of all blocks, and every kept singular vector carries its
                         block's charge into the output's bond, which is charge-definite
                         too.  The tensors stay dense.  XTRG_EINVAL if an input has no
                         charges or C_E has weight between different charges. */
