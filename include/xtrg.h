@@ -177,7 +177,7 @@ typedef struct {
                         xtrg_mpo_label_charges, or an earlier u1 doubling); C_E, block
                         diagonal in the charge of the bond being cut, is factorised block by
                         block (one grouped Jacobi launch per round over all blocks; a block of
-                        at least 64 columns starts from the previous visit's basis of the same
+                        at least 32 columns starts from the previous visit's basis of the same
                         block unless no_warm_start; no QR start), the keep rule runs on the
                         merged values of all blocks, and every kept singular vector carries its
                         block's charge into the output's bond, which is charge-definite

@@ -1048,7 +1048,7 @@ constexpr int kWarmMin = 128;   // smallest SVD column count worth a warm start
 // The same for a charge block: the blocks of one two-site tensor share the
 // grouped Jacobi launches until the last of them converges, so a cold small
 // block would add sweeps of its own after the warm large ones are done.
-constexpr int kWarmMinBlock = 64;
+constexpr int kWarmMinBlock = 32;
 
 // it Newton-Schulz steps X <- X (3I - X^T X)/2 on the columns of X
 // (column-major len x k, sigma_max(X) < sqrt(3)): singular values below 1
