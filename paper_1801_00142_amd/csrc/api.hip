@@ -449,12 +449,12 @@ struct BlockSvd {
   double fro2 = 0.0;              // sum of the blocks' ||Y_q||_F^2
 };
 
-// Split Y into its charge blocks and append one SVD problem per block to
-// jobs.  `tag` names the workspaces (one set per concurrent factorisation).
 // warm(q, len_q, p_q, Y_q): the SVD input of block q (Y_q itself, or Y_q
 // rotated into a warm basis) and its column count.
 using WarmHook = std::function<std::pair<const double*, int>(int, int, int, const double*)>;
 
+// Split Y into its charge blocks and append one SVD problem per block to
+// jobs.  `tag` names the workspaces (one set per concurrent factorisation).
 void bsvd_prepare(xtrg_ctx c, const std::string& tag, const double* Y, int len, int p, const std::vector<int>& ql,
                   const std::vector<int>& qp, BlockSvd& B, std::vector<xtrg::SvdJob>& jobs,
                   const WarmHook& warm = nullptr) {
