@@ -507,16 +507,34 @@ void bsvd_merge(xtrg_ctx c, const std::string& tag, BlockSvd& B) {
   size_t n = 1;
   for (auto& k : B.b) n += 1 + std::min(k.len, k.p);
   double* st = c->need("u1_vals" + tag, n);
-  XTRG_HIP(hipMemcpyAsync(st, B.chk, sizeof(double), hipMemcpyDeviceToDevice, s));
-  size_t o = 1;
-  for (auto& k : B.b) {
-    const int r = std::min(k.len, k.p);
-    XTRG_HIP(hipMemcpyAsync(st + o, xtrg::svd_fro2(k.work, k.len, k.psvd), sizeof(double), hipMemcpyDeviceToDevice,
-                            s));
-    XTRG_HIP(hipMemcpyAsync(st + o + 1, xtrg::svd_sorted_values(k.work, k.len, k.psvd), sizeof(double) * r,
-                            hipMemcpyDeviceToDevice, s));
-    o += 1 + r;
+  if (B.b.size() <= (size_t)xtrg::ValGather::kMax) {   // one launch for all blocks
+    xtrg::ValGather g;
+    g.n = (int)B.b.size();
+    g.head = B.chk;
+    g.out = st;
+    size_t o = 1;
+    for (int t = 0; t < g.n; ++t) {
+      const auto& k = B.b[t];
+      g.f2[t] = xtrg::svd_fro2(k.work, k.len, k.psvd);
+      g.v[t] = xtrg::svd_sorted_values(k.work, k.len, k.psvd);
+      g.r[t] = std::min(k.len, k.p);
+      g.off[t] = (int)o;
+      o += 1 + g.r[t];
+    }
+    xtrg::gather_values(g, s);
+  } else {
+    XTRG_HIP(hipMemcpyAsync(st, B.chk, sizeof(double), hipMemcpyDeviceToDevice, s));
+    size_t o = 1;
+    for (auto& k : B.b) {
+      const int r = std::min(k.len, k.p);
+      XTRG_HIP(hipMemcpyAsync(st + o, xtrg::svd_fro2(k.work, k.len, k.psvd), sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+      XTRG_HIP(hipMemcpyAsync(st + o + 1, xtrg::svd_sorted_values(k.work, k.len, k.psvd), sizeof(double) * r,
+                              hipMemcpyDeviceToDevice, s));
+      o += 1 + r;
+    }
   }
+  size_t o = 1;
   const std::vector<double> h = read_vec(c, st, n);
   struct E { double v; int q, blk, rank; };
   std::vector<E> e;

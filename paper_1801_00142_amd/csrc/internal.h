@@ -191,6 +191,20 @@ void site_product(double* C, const double* A, int Dla, int Dra, const double* B,
 // columns ci of a column-major matrix (index arrays on the device).
 void gather_block(double* dst, const double* src, long ld, const int* ri, int rows, const int* ci, int cols,
                   hipStream_t s);
+// out[0] = head[0]; then for every entry e: out[off[e]] = f2[e][0] and
+// out[off[e] + 1 + i] = v[e][i] for i < r[e] (one launch for many small
+// device-to-device copies; the table is passed by value).
+struct ValGather {
+  static constexpr int kMax = 64;
+  int n = 0;
+  const double* f2[kMax] = {};
+  const double* v[kMax] = {};
+  int r[kMax] = {};
+  int off[kMax] = {};
+  const double* head = nullptr;
+  double* out = nullptr;
+};
+void gather_values(const ValGather& g, hipStream_t s);
 // Column t of src (rows x cols, column-major) into column pos[t] of a dense
 // len x k matrix at rows ri: dst[ri[i]*k + pos[t]] (rowmajor) or
 // dst[pos[t]*len + ri[i]]; other entries of dst are left as they are.

@@ -285,6 +285,13 @@ __global__ void k_gather_block(double* __restrict__ dst, const double* __restric
   }
 }
 
+__global__ void k_gather_values(ValGather g) {
+  const int e = blockIdx.x;
+  if (e == 0 && threadIdx.x == 0) g.out[0] = g.head[0];
+  if (threadIdx.x == 0) g.out[g.off[e]] = g.f2[e][0];
+  for (int i = threadIdx.x; i < g.r[e]; i += blockDim.x) g.out[g.off[e] + 1 + i] = g.v[e][i];
+}
+
 // Column t of src (rows x cols, column-major) goes to column pos[t] of a
 // dense len x k matrix, row i to row ri[i]: dst[r*k + j] (rowmajor) or
 // dst[j*len + r].
@@ -316,6 +323,12 @@ void gather_block(double* dst, const double* src, long ld, const int* ri, int ro
   const size_t n = (size_t)rows * cols;
   if (!n) return;
   hipLaunchKernelGGL(k_gather_block, grid_for(n), dim3(kT), 0, s, dst, src, ld, ri, rows, ci, cols);
+  XTRG_HIP(hipGetLastError());
+}
+
+void gather_values(const ValGather& g, hipStream_t s) {
+  if (g.n <= 0) return;
+  hipLaunchKernelGGL(k_gather_values, dim3(g.n), dim3(kT), 0, s, g);
   XTRG_HIP(hipGetLastError());
 }
 

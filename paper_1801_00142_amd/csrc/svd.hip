@@ -682,7 +682,7 @@ __global__ __launch_bounds__(1024) void sort_desc_group(const JacobiDesc* __rest
 }
 
 __global__ __launch_bounds__(256) void count_alive_group(const JacobiDesc* __restrict__ descs,
-                                                         int* __restrict__ out) {
+                                                         int* __restrict__ out, double* __restrict__ f2out) {
   const JacobiDesc& D = descs[blockIdx.x];
   if (!D.active) return;
   __shared__ int part[256];
@@ -696,7 +696,10 @@ __global__ __launch_bounds__(256) void count_alive_group(const JacobiDesc* __res
     if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[blockIdx.x] = part[0];
+  if (threadIdx.x == 0) {
+    out[blockIdx.x] = part[0];
+    f2out[blockIdx.x] = D.fro2[0];   // ||Y||_F^2 of the problem, for the host's finiteness check
+  }
 }
 
 // U column j = Z column perm[j] / sigma[j] (zero if sigma[j] == 0).
@@ -723,9 +726,11 @@ static int* sv_perm(double* work, int len, int p) {
   return reinterpret_cast<int*>(work + (size_t)len * p + 2 * (size_t)p);
 }
 
-// [descs: n][off: n][pad to 256 B][Gram partials: n x kMaxPairs x kMaxSplit x kGramVals doubles]
+// [descs: n][off: n][||Y||_F^2: n doubles][alive: n ints][pad to 256 B]
+// [Gram partials: n x kMaxPairs x kMaxSplit x kGramVals doubles]
 static size_t parts_offset(int n) {
-  return (sizeof(JacobiDesc) * (size_t)n + sizeof(unsigned long long) * (size_t)n + sizeof(int) * (size_t)n + 255) /
+  return (sizeof(JacobiDesc) * (size_t)n + sizeof(unsigned long long) * (size_t)n + sizeof(double) * (size_t)n +
+          sizeof(int) * (size_t)n + 255) /
          256 * 256;
 }
 size_t svd_desc_bytes(int n) {
@@ -747,7 +752,8 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
   if (n == 0) return;
   JacobiDesc* d_desc = reinterpret_cast<JacobiDesc*>(desc_dev);
   unsigned long long* d_off = reinterpret_cast<unsigned long long*>(d_desc + n);
-  int* d_alive = reinterpret_cast<int*>(d_off + n);
+  double* d_f2 = reinterpret_cast<double*>(d_off + n);
+  int* d_alive = reinterpret_cast<int*>(d_f2 + n);
   double* d_parts = reinterpret_cast<double*>(static_cast<char*>(desc_dev) + parts_offset(n));
   std::vector<JacobiDesc> h(n);
   std::vector<int> n2(n);
@@ -815,7 +821,7 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
     if (maxp == 0) return;
     hipLaunchKernelGGL(column_norms_group, dim3((maxp + 3) / 4, n), dim3(256), 0, s, d_desc);
     hipLaunchKernelGGL(sort_desc_group, dim3(n), dim3(1024), (sizeof(double) + sizeof(int)) * maxn2, s, d_desc);
-    if (count) hipLaunchKernelGGL(count_alive_group, dim3(n), dim3(256), 0, s, d_desc, d_alive);
+    if (count) hipLaunchKernelGGL(count_alive_group, dim3(n), dim3(256), 0, s, d_desc, d_alive, d_f2);
     XTRG_HIP(hipGetLastError());
   };
   bool dirty = true;
@@ -833,9 +839,8 @@ void svd_batched(std::vector<SvdJob>& jobs, void* desc_dev, hipStream_t s, Round
   XTRG_HIP(hipMemcpyAsync(hal.data(), d_alive, sizeof(int) * n, hipMemcpyDeviceToHost, s));
   // ||Y||_F^2 must be finite: a NaN or Inf entry, or a norm beyond the
   // double range, would leave every rotation test false
-  std::vector<double> f2(n, 0.0);
-  for (int j = 0; j < n; ++j)
-    if (h[j].active) XTRG_HIP(hipMemcpyAsync(&f2[j], h[j].fro2, sizeof(double), hipMemcpyDeviceToHost, s));
+  std::vector<double> f2(n, 0.0);   // written for the active problems by the count
+  XTRG_HIP(hipMemcpyAsync(f2.data(), d_f2, sizeof(double) * n, hipMemcpyDeviceToHost, s));
   XTRG_HIP(hipStreamSynchronize(s));
   for (int j = 0; j < n; ++j)
     if (h[j].active && !std::isfinite(f2[j])) {   // non-finite entry or ||Y||_F^2 beyond the double range
