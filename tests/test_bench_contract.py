@@ -34,3 +34,11 @@ def test_options_parse():
     assert (a.steps, a.warmup, a.precision, a.D, a.serve, a.serve_slice, a.serve_lanes) == \
         (20, 5, "fp32", 512, 64, "0:11", 2)
     assert a.sweeps == 4 and a.gpus == 1 and a.batch_leg == 0
+    assert a.u1 and a.mixed_leg == 2                       # U(1) charge blocks and the FP32 leg by default
+    old = sys.argv
+    try:
+        sys.argv = ["bench.py", "--dense", "--mixed-leg", "0"]
+        b = bench.parse()
+    finally:
+        sys.argv = old
+    assert not b.u1 and b.mixed_leg == 0
