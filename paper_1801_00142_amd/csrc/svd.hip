@@ -585,10 +585,11 @@ __global__ __launch_bounds__(256) void sum_squares_ordered(const double* __restr
   if (threadIdx.x == 0) *out = part[0];
 }
 
-// Descending bitonic sort of (value, index) in one workgroup, n <= 4096.
-__global__ __launch_bounds__(1024) void sort_desc(const double* __restrict__ val, int p,
-                                                   double* __restrict__ sorted, int* __restrict__ perm) {
-  extern __shared__ unsigned char sm[];
+// Descending bitonic sort of (value, index) in one workgroup, n <= 4096:
+// larger value first, ties by smaller index (deterministic).  sm holds
+// pow2(p) doubles and as many ints.
+__device__ inline void sort_desc_body(const double* __restrict__ val, int p, double* __restrict__ sorted,
+                                      int* __restrict__ perm, unsigned char* sm) {
   int n = 1;
   while (n < p) n <<= 1;
   double* v = reinterpret_cast<double*>(sm);
@@ -604,7 +605,6 @@ __global__ __launch_bounds__(1024) void sort_desc(const double* __restrict__ val
         const int l = i ^ j;
         if (l > i) {
           const bool desc = (i & k) == 0;
-          // order: larger value first; ties by smaller index (deterministic)
           const bool i_first = (v[i] > v[l]) || (v[i] == v[l] && ix[i] < ix[l]);
           if (desc != i_first) {
             const double tv = v[i]; v[i] = v[l]; v[l] = tv;
@@ -619,6 +619,12 @@ __global__ __launch_bounds__(1024) void sort_desc(const double* __restrict__ val
     sorted[i] = v[i];
     perm[i] = ix[i];
   }
+}
+
+__global__ __launch_bounds__(1024) void sort_desc(const double* __restrict__ val, int p,
+                                                   double* __restrict__ sorted, int* __restrict__ perm) {
+  extern __shared__ unsigned char sm[];
+  sort_desc_body(val, p, sorted, perm, sm);
 }
 
 // The ranking of every active problem of a grouped SVD at once
@@ -647,38 +653,8 @@ __global__ __launch_bounds__(1024) void sort_desc_group(const JacobiDesc* __rest
   if (!D.active) return;
   extern __shared__ unsigned char sm[];
   const int p = D.p;
-  const double* val = D.Z + (long)D.len * p;
-  double* sorted = D.Z + (long)D.len * p + p;
-  int* perm = reinterpret_cast<int*>(D.Z + (long)D.len * p + 2 * (long)p);
-  int n = 1;
-  while (n < p) n <<= 1;
-  double* v = reinterpret_cast<double*>(sm);
-  int* ix = reinterpret_cast<int*>(v + n);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    v[i] = i < p ? val[i] : -1.0;
-    ix[i] = i < p ? i : 0x7fffffff;
-  }
-  __syncthreads();
-  for (int k = 2; k <= n; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int l = i ^ j;
-        if (l > i) {
-          const bool desc = (i & k) == 0;
-          const bool i_first = (v[i] > v[l]) || (v[i] == v[l] && ix[i] < ix[l]);
-          if (desc != i_first) {
-            const double tv = v[i]; v[i] = v[l]; v[l] = tv;
-            const int ti = ix[i]; ix[i] = ix[l]; ix[l] = ti;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-  for (int i = threadIdx.x; i < p; i += blockDim.x) {
-    sorted[i] = v[i];
-    perm[i] = ix[i];
-  }
+  double* raw = D.Z + (long)D.len * p;
+  sort_desc_body(raw, p, raw + p, reinterpret_cast<int*>(raw + 2 * (long)p), sm);
 }
 
 __global__ __launch_bounds__(256) void count_alive_group(const JacobiDesc* __restrict__ descs,
