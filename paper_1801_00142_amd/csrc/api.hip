@@ -20,9 +20,13 @@
 
 #include "internal.h"
 #include "context.h"
+#include "host_rules.h"
 
 using xtrg::Error;
 using xtrg::Gemm;
+using xtrg_host::col_charges;
+using xtrg_host::keep_count;
+using xtrg_host::row_charges;
 
 // Device scratch of xtrg_dgemm_noalloc (the split-K partial products):
 // one fixed array per GPU, in the library's code object, held until the
@@ -294,26 +298,6 @@ std::vector<std::vector<double>> cap(const Automaton& A, const double r[2], std:
 // Canonical forms by SVD sweeps (all on device)
 // ---------------------------------------------------------------------------
 
-// Number of kept singular values: the rule of the doubling step.
-// S descending; values <= max(floor * S[0], abs_floor) count as zero.
-int keep_count(const std::vector<double>& S, int D, double deg_rtol, double floor, double abs_floor) {
-  if (S.empty() || !(S[0] > 0)) return 1;
-  const double f = std::max(floor * S[0], abs_floor);
-  int r = 0;
-  for (double v : S)
-    if (v > f) ++r;
-  r = std::max(r, 1);
-  if (r <= D) return r;
-  // a gap separates two multiplets only if it exceeds deg_rtol * S[k-1]
-  // plus the absolute rounding noise abs_floor of the values themselves
-  // (deg_rtol = 0 switches the multiplet protection off: cut at exactly D)
-  if (!(deg_rtol > 0)) return D;
-  const int lo = std::max(1, (D + 1) / 2);
-  for (int k = D; k >= lo; --k)
-    if (S[k - 1] - S[k] > deg_rtol * S[k - 1] + abs_floor) return k;
-  return D;
-}
-
 std::vector<double> read_vec(xtrg_ctx c, const double* d, size_t n) {
   std::vector<double> h(n);
   if (n) {
@@ -362,63 +346,14 @@ void orthonormalize(xtrg_ctx c, double* U, int len, int k, bool rowmajor) {
 // is factorised block by block.
 // ---------------------------------------------------------------------------
 
-// Charges of the rows (c, s, s'') of a site matrix or two-site tensor from
-// the charges q of its left bond: q_c + (s'' - s) (index 0 is up).
-std::vector<int> row_charges(const std::vector<int>& q) {
-  std::vector<int> out(q.size() * 4);
-  for (size_t c = 0; c < q.size(); ++c)
-    for (int s = 0; s < 2; ++s)
-      for (int u = 0; u < 2; ++u) out[c * 4 + s * 2 + u] = q[c] + (u - s);
-  return out;
-}
-
-// Charge a left index must carry to connect to the column (t, t'', c) of a
-// site matrix or two-site tensor: q_c - (t'' - t).
-std::vector<int> col_charges(const std::vector<int>& q) {
-  const size_t D = q.size();
-  std::vector<int> out(4 * D);
-  for (int t = 0; t < 2; ++t)
-    for (int u = 0; u < 2; ++u)
-      for (size_t c = 0; c < D; ++c) out[(t * 2 + u) * D + c] = q[c] - (u - t);
-  return out;
-}
-
 // Charges of every bond index from the non-zero entries of host copies of
-// the sites ([Dl][2][2][Dr] each): the entry W[a][s][t][b] fixes
-// q_b = q_a + (t - s), starting from q = 0 at the left end.  An index that
-// no non-zero entry reaches from an index of known charge contributes
-// nothing to the operator; it gets charge 0.
+// the sites (xtrg_host::infer_charges), with the library's error code.
 std::vector<std::vector<int>> infer_charges(const std::vector<std::vector<double>>& W, const std::vector<int>& dims) {
-  const int L = (int)W.size();
-  std::vector<std::vector<int>> q(L + 1);
-  q[0].assign(dims[0], 0);
-  std::vector<char> known(dims[0], 1);
-  for (int i = 0; i < L; ++i) {
-    const int Dl = dims[i], Dr = dims[i + 1];
-    std::vector<int> lo(Dr, std::numeric_limits<int>::max()), hi(Dr, std::numeric_limits<int>::min());
-    for (int a = 0; a < Dl; ++a) {
-      if (!known[a]) continue;
-      for (int st = 0; st < 4; ++st) {
-        const double* row = W[i].data() + ((size_t)a * 4 + st) * Dr;
-        const int v = q[i][a] + ((st & 1) - (st >> 1));
-        for (int b = 0; b < Dr; ++b)
-          if (row[b] != 0.0) {
-            lo[b] = std::min(lo[b], v);
-            hi[b] = std::max(hi[b], v);
-          }
-      }
-    }
-    q[i + 1].assign(Dr, 0);
-    known.assign(Dr, 0);
-    for (int b = 0; b < Dr; ++b) {
-      if (hi[b] < lo[b]) continue;
-      if (hi[b] != lo[b])
-        throw Error(XTRG_EINVAL, "site " + std::to_string(i) + ": a bond index carries two S^z charges");
-      known[b] = 1;
-      q[i + 1][b] = lo[b];
-    }
+  try {
+    return xtrg_host::infer_charges(W, dims);
+  } catch (const std::invalid_argument& e) {
+    throw Error(XTRG_EINVAL, e.what());
   }
-  return q;
 }
 
 // Factorisation of a len x p column-major matrix Y whose entries vanish
@@ -536,20 +471,19 @@ void bsvd_merge(xtrg_ctx c, const std::string& tag, BlockSvd& B) {
   }
   size_t o = 1;
   const std::vector<double> h = read_vec(c, st, n);
-  struct E { double v; int q, blk, rank; };
-  std::vector<E> e;
   B.fro2 = 0.0;
   o = 1;
+  std::vector<int> qb(B.b.size());
+  std::vector<std::vector<double>> Sb(B.b.size());
   for (size_t t = 0; t < B.b.size(); ++t) {
     auto& k = B.b[t];
     const int r = std::min(k.len, k.p);
     k.S.assign(h.begin() + o + 1, h.begin() + o + 1 + r);
-    B.fro2 += h[o];
-    for (int j = 0; j < r; ++j) {
-      const double v = h[o + 1 + j];
+    for (double v : k.S)
       if (!std::isfinite(v)) throw Error(XTRG_ENUMERIC, "non-finite singular value");
-      e.push_back({v, k.q, (int)t, j});
-    }
+    B.fro2 += h[o];
+    qb[t] = k.q;
+    Sb[t] = k.S;
     o += 1 + r;
   }
   const double full = h[0];
@@ -557,19 +491,11 @@ void bsvd_merge(xtrg_ctx c, const std::string& tag, BlockSvd& B) {
   if (std::fabs(full - B.fro2) > 1e-10 * full)
     throw Error(XTRG_EINVAL, "the tensor has weight between different S^z charges: the inputs do not conserve "
                              "S^z in their bond bases");
-  // blocks come in increasing charge and each block's values descending, so a
-  // stable sort by value keeps both orders among equal values
-  std::stable_sort(e.begin(), e.end(), [](const E& a, const E& b) { return a.v > b.v; });
-  B.S.resize(e.size());
-  B.qs.resize(e.size());
-  B.from.resize(e.size());
-  B.rank.resize(e.size());
-  for (size_t j = 0; j < e.size(); ++j) {
-    B.S[j] = e[j].v;
-    B.qs[j] = e[j].q;
-    B.from[j] = e[j].blk;
-    B.rank[j] = e[j].rank;
-  }
+  xtrg_host::Merged m = xtrg_host::merge_block_values(qb, Sb);
+  B.S = std::move(m.S);
+  B.qs = std::move(m.qs);
+  B.from = std::move(m.from);
+  B.rank = std::move(m.rank);
 }
 
 // The first k merged singular vectors as a dense len x k matrix: dst[r*k + j]
