@@ -395,23 +395,18 @@ void bsvd_prepare(xtrg_ctx c, const std::string& tag, const double* Y, int len, 
                   const WarmHook& warm = nullptr) {
   if ((int)ql.size() != len || (int)qp.size() != p) throw Error(XTRG_EINVAL, "charge lists do not match the tensor");
   hipStream_t s = c->stream;
-  std::map<int, std::pair<std::vector<int>, std::vector<int>>> g;
-  for (int r = 0; r < len; ++r) g[ql[r]].first.push_back(r);
-  for (int j = 0; j < p; ++j) g[qp[j]].second.push_back(j);
   B = BlockSvd{};
   B.Y = Y;
   B.len = len;
   B.p = p;
-  for (auto& kv : g) {
-    auto& rc = kv.second;
-    if (rc.first.empty() || rc.second.empty()) continue;
+  for (const auto& cb : xtrg_host::charge_blocks(ql, qp)) {
     BlockSvd::Blk k;
-    k.q = kv.first;
-    k.len = (int)rc.first.size();
-    k.p = (int)rc.second.size();
+    k.q = cb.q;
+    k.len = (int)cb.rows.size();
+    k.p = (int)cb.cols.size();
     k.off = B.idx.size();
-    B.idx.insert(B.idx.end(), rc.first.begin(), rc.first.end());
-    B.idx.insert(B.idx.end(), rc.second.begin(), rc.second.end());
+    B.idx.insert(B.idx.end(), cb.rows.begin(), cb.rows.end());
+    B.idx.insert(B.idx.end(), cb.cols.begin(), cb.cols.end());
     B.idx.resize(B.idx.size() + std::min(k.len, k.p), 0);
     B.b.push_back(std::move(k));
   }
@@ -692,25 +687,8 @@ std::unique_ptr<xtrg_mpo_s> clone(xtrg_mpo src) {
 // The doubling step (App. D.1, Fig. VMPO)
 // ---------------------------------------------------------------------------
 
-struct Step {
-  int bond;
-  int dir;        // +1 left-to-right, -1 right-to-left
-  bool last;      // last bond of its half-sweep
-};
-
-std::vector<Step> schedule(int n, int n_sweeps) {
-  std::vector<Step> out;
-  for (int h = 0; h < 2 * n_sweeps; ++h) {
-    std::vector<int> bonds;
-    if (h % 2 == 0)
-      for (int b = (h == 0 ? 0 : 1); b <= n - 2; ++b) bonds.push_back(b);
-    else
-      for (int b = n - 3; b >= 0; --b) bonds.push_back(b);
-    for (size_t j = 0; j < bonds.size(); ++j)
-      out.push_back({bonds[j], h % 2 == 0 ? 1 : -1, j + 1 == bonds.size()});
-  }
-  return out;
-}
+using xtrg_host::Step;
+using xtrg_host::schedule;
 
 struct Doubler {
   xtrg_ctx c;
@@ -1421,7 +1399,7 @@ int square_compress_impl(xtrg_ctx c, int n, const xtrg_mpo* ins, const xtrg_comp
       const bool final_step = st + 1 == C.sched.size();
       C.i = sp.bond;
       C.st = st;
-      C.gauge_right = final_step ? false : (sp.dir > 0) != sp.last;
+      C.gauge_right = xtrg_host::gauge_right(sp, final_step);
       act.push_back(&C);
     }
     if (act.empty()) break;

@@ -1,11 +1,13 @@
 // Host-side decision rules of the doubling (plain C++, no device code): the
-// truncation rule, the S^z charge bookkeeping of the U(1) route and the merge
-// of the singular values of charge blocks.  The library calls them on the
-// values and charges it reads back from the device.
+// truncation rule, the sweep schedule and its gauge, the S^z charge
+// bookkeeping of the U(1) route and the merge of the singular values of
+// charge blocks.  The library calls them on the values and charges it reads
+// back from the device.
 #pragma once
 
 #include <algorithm>
 #include <limits>
+#include <map>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -33,6 +35,36 @@ inline int keep_count(const std::vector<double>& S, int D, double deg_rtol, doub
     if (S[k - 1] - S[k] > deg_rtol * S[k - 1] + abs_floor) return k;
   return D;
 }
+
+// The bonds a doubling visits (App. D.1: variational two-site sweeps):
+// n_sweeps full sweeps, each a left-to-right half-sweep over bonds 0 .. n-2
+// (from 1 after the first) and a right-to-left one over n-3 .. 0, so the
+// bond that ends a half-sweep is not optimised twice in a row.
+struct Step {
+  int bond;
+  int dir;        // +1 left-to-right, -1 right-to-left
+  bool last;      // last bond of its half-sweep
+};
+
+inline std::vector<Step> schedule(int n, int n_sweeps) {
+  std::vector<Step> out;
+  for (int h = 0; h < 2 * n_sweeps; ++h) {
+    std::vector<int> bonds;
+    if (h % 2 == 0)
+      for (int b = (h == 0 ? 0 : 1); b <= n - 2; ++b) bonds.push_back(b);
+    else
+      for (int b = n - 3; b >= 0; --b) bonds.push_back(b);
+    for (size_t j = 0; j < bonds.size(); ++j)
+      out.push_back({bonds[j], h % 2 == 0 ? 1 : -1, j + 1 == bonds.size()});
+  }
+  return out;
+}
+
+// Which side of a step keeps the isometry: the left site (the sweep moves
+// right) unless the step ends its half-sweep, where the gauge turns; the
+// final step of the doubling leaves the centre at site 0 (right side
+// isometric), where the result is normalised.
+inline bool gauge_right(const Step& sp, bool final_step) { return final_step ? false : (sp.dir > 0) != sp.last; }
 
 // U(1) charge sectors (Sec. II.A: the XXZ models conserve S^z_tot; App.
 // B.2).  Site index 0 is up; the entry W[a][s][s'][b] of a site tensor
@@ -96,6 +128,25 @@ inline std::vector<std::vector<int>> infer_charges(const std::vector<std::vector
     }
   }
   return q;
+}
+
+// The charge blocks of a matrix whose rows carry the charges ql and columns
+// qp: for every charge present on both sides (increasing), its rows and
+// columns in increasing index order.
+struct ChargeBlock {
+  int q;
+  std::vector<int> rows, cols;
+};
+
+inline std::vector<ChargeBlock> charge_blocks(const std::vector<int>& ql, const std::vector<int>& qp) {
+  std::map<int, std::pair<std::vector<int>, std::vector<int>>> g;
+  for (int r = 0; r < (int)ql.size(); ++r) g[ql[r]].first.push_back(r);
+  for (int j = 0; j < (int)qp.size(); ++j) g[qp[j]].second.push_back(j);
+  std::vector<ChargeBlock> out;
+  for (auto& kv : g)
+    if (!kv.second.first.empty() && !kv.second.second.empty())
+      out.push_back({kv.first, std::move(kv.second.first), std::move(kv.second.second)});
+  return out;
 }
 
 // The singular values of the charge blocks of one matrix merged into one

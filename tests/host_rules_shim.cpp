@@ -52,4 +52,33 @@ void hr_merge(int nb, const int* q, const int* r, const double* vals, double* S,
   }
 }
 
+// The steps of a doubling of n sites with n_sweeps sweeps (arrays of
+// (n - 1) * 2 * n_sweeps entries at most); returns their count.
+int hr_schedule(int n, int n_sweeps, int* bond, int* dir, int* last, int* gauge) {
+  const auto sc = xtrg_host::schedule(n, n_sweeps);
+  for (size_t j = 0; j < sc.size(); ++j) {
+    bond[j] = sc[j].bond;
+    dir[j] = sc[j].dir;
+    last[j] = sc[j].last ? 1 : 0;
+    gauge[j] = xtrg_host::gauge_right(sc[j], j + 1 == sc.size()) ? 1 : 0;
+  }
+  return (int)sc.size();
+}
+
+// The charge blocks of rows ql (nl) and columns qp (np): their charges,
+// sizes, and the rows and columns one block after the other; returns the
+// number of blocks.
+int hr_charge_blocks(int nl, const int* ql, int np, const int* qp, int* q, int* nr, int* nc, int* rows, int* cols) {
+  const auto cb = xtrg_host::charge_blocks(std::vector<int>(ql, ql + nl), std::vector<int>(qp, qp + np));
+  int orr = 0, oc = 0;
+  for (size_t t = 0; t < cb.size(); ++t) {
+    q[t] = cb[t].q;
+    nr[t] = (int)cb[t].rows.size();
+    nc[t] = (int)cb[t].cols.size();
+    for (int r : cb[t].rows) rows[orr++] = r;
+    for (int c : cb[t].cols) cols[oc++] = c;
+  }
+  return (int)cb.size();
+}
+
 }  // extern "C"

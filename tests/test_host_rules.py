@@ -1,10 +1,12 @@
 """The library's host-side decision rules (paper_1801_00142_amd/csrc/
 host_rules.h, compiled here with g++ for the host) against the oracle, on
 the CPU: the truncation rule (Sec. II.D; the multiplet-safe cut and the
-noise floor), the S^z charges read from an MPO's non-zero entries (Sec.
-II.A; App. B.2) and the order in which the values of charge blocks are
-merged.  These rules take integer decisions (a kept count, a charge, an
-order), so library and oracle must agree exactly."""
+noise floor), the sweep schedule and its gauge (App. D.1), the S^z charges
+read from an MPO's non-zero entries and the grouping of a tensor's rows and
+columns by charge (Sec. II.A; App. B.2), and the order in which the values
+of charge blocks are merged.  These rules take integer decisions (a kept
+count, a bond, a side, a charge, an order), so library and oracle must
+agree exactly."""
 import ctypes as C
 import os
 import shutil
@@ -37,6 +39,10 @@ def lib(tmp_path_factory):
     h.hr_infer_charges.argtypes = [C.c_int, ip, dp, ip]
     h.hr_merge.restype = None
     h.hr_merge.argtypes = [C.c_int, ip, ip, dp, dp, ip, ip, ip]
+    h.hr_schedule.restype = C.c_int
+    h.hr_schedule.argtypes = [C.c_int, C.c_int, ip, ip, ip, ip]
+    h.hr_charge_blocks.restype = C.c_int
+    h.hr_charge_blocks.argtypes = [C.c_int, ip, C.c_int, ip, ip, ip, ip, ip, ip]
     return h
 
 
@@ -198,3 +204,45 @@ def test_merge_order_matches_the_oracle_block_svd(lib):
         assert np.array_equal(qo, q_ref)
         for j in range(vals.size):                  # each value's block and rank point back to it
             assert per[fr[j]][rk[j]] == S[j]
+
+
+def test_sweep_schedule_and_gauge_match_the_oracle(lib):
+    """The bonds of every two-site step, their direction, the end of each
+    half-sweep, and which side keeps the isometry (the gauge the split
+    takes), for chains of 2 to 70 sites and 1 to 5 sweeps: the library's
+    schedule is the oracle's step for step."""
+    for n in list(range(2, 12)) + [48, 64, 70]:
+        for ns in range(1, 6):
+            m = 2 * ns * max(n - 1, 1)
+            bond, d, last, gauge = (np.zeros(m, dtype=np.int32) for _ in range(4))
+            k = lib.hr_schedule(n, ns, _ip(bond), _ip(d), _ip(last), _ip(gauge))
+            ref = OX.sweep_schedule(n, ns)
+            assert k == len(ref)
+            for j, (b, dr, ls) in enumerate(ref):
+                go_right = (dr > 0) != (ls and j != len(ref) - 1)
+                if j == len(ref) - 1:
+                    go_right = False
+                assert (bond[j], d[j], bool(last[j]), bool(gauge[j])) == (b, dr, ls, go_right), (n, ns, j)
+
+
+def test_charge_blocks_match_the_oracle(lib):
+    """The grouping of rows and columns by charge that the block
+    factorisation uses: the same charges (present on both sides, increasing)
+    and the same rows and columns per block as the oracle's block_svd
+    (charges drawn from -3..3, some on one side only)."""
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        nl, npc = int(rng.integers(1, 80)), int(rng.integers(1, 80))
+        ql = rng.integers(-3, 4, nl).astype(np.int32)
+        qp = rng.integers(-2, 3, npc).astype(np.int32)
+        q, nr, nc = (np.zeros(16, dtype=np.int32) for _ in range(3))
+        rows, cols = np.zeros(nl, dtype=np.int32), np.zeros(npc, dtype=np.int32)
+        nb = lib.hr_charge_blocks(nl, _ip(ql), npc, _ip(qp), _ip(q), _ip(nr), _ip(nc), _ip(rows), _ip(cols))
+        shared = np.intersect1d(ql, qp)
+        assert nb == shared.size and np.array_equal(q[:nb], shared)
+        orr = oc = 0
+        for t, qv in enumerate(shared):
+            r_ref, c_ref = np.nonzero(ql == qv)[0], np.nonzero(qp == qv)[0]
+            assert np.array_equal(rows[orr:orr + nr[t]], r_ref) and np.array_equal(cols[oc:oc + nc[t]], c_ref)
+            orr += nr[t]
+            oc += nc[t]
