@@ -14,7 +14,9 @@
  *  - Ownership: the library owns all device memory behind xtrg_ctx and
  *    xtrg_mpo handles.  Every *_out handle is newly created and must be
  *    released by the caller with xtrg_mpo_destroy / xtrg_ctx_destroy.
- *    Input handles are never modified.  Host arrays are caller-owned and
+ *    Input handles are never modified (xtrg_mpo_label_charges, which
+ *    attaches charge labels to its argument, is the one exception; the
+ *    tensors stay unchanged).  Host arrays are caller-owned and
  *    are only read or written during the call.
  *  - Threading: a context serialises its work on one HIP stream; use one
  *    context per host thread.

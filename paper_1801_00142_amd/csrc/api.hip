@@ -2046,11 +2046,12 @@ std::unique_ptr<xtrg_mpo_s> init_rho(xtrg_ctx c, xtrg_mpo H, double tau0, int or
   if (u1) {
     // charges of the automaton states from H's entries; the product of two
     // automata carries q_a + q_b on its state (a, b)
-    if (H->charges.empty()) H->charges = infer_charges(download_sites(H), H->dims);
+    const std::vector<std::vector<int>> qH =
+        H->charges.empty() ? infer_charges(download_sites(H), H->dims) : H->charges;
     auto& q = m->charges;
     q.assign(L + 1, {});
     for (int i = 0; i <= L; ++i) {
-      const auto& h = H->charges[i];
+      const auto& h = qH[i];
       if (i == L) {
         q[i].assign(m->dims[L], 0);
       } else if (order == 1) {
